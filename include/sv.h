@@ -1,0 +1,154 @@
+/*
+ * sv.h -- C ABI of libsv, the MI355X (gfx950) swept-volume collision checker.
+ *
+ * Method: Joho, Schwinn, Safronov, "Neural Implicit Swept Volume Models for Fast
+ * Collision Detection" (ICRA 2024).  The library evaluates, on one GPU,
+ *   - the signed distance f_d(x, m) of a point x to the swept volume V_S(m) of a
+ *     motion m (Sec. III, eq. (1)-(4)), exactly, by sampling the motion at T
+ *     configurations, placing the robot's capsules with forward kinematics and
+ *     taking the minimum point-to-capsule distance;
+ *   - the cloud distance d(X, m) = min over x in X and the verdict "free iff
+ *     d(X, m) > eps_S" (Sec. IV-B, Alg. 1);
+ *   - the learned model f_theta(x, q0, q1) (Sec. IV-A) as a softplus MLP, and
+ *     per-point screening with that model in front of the exact check.
+ *
+ * Conventions shared by every entry point:
+ *   - Units are metres and radians.  Distances are signed: negative inside.
+ *   - "dev" pointers are device (HBM) pointers the caller owns; "host" pointers
+ *     are read during the call only.  The library never allocates or frees
+ *     memory and never synchronises: scratch memory comes in through
+ *     (ws, ws_bytes), sized with sv_workspace_size(), and every call is
+ *     asynchronous on `stream` (a hipStream_t; NULL is the default stream).
+ *   - Arguments are validated on the host before anything is launched.  On a
+ *     validation failure the call returns a negative sv_status, launches
+ *     nothing, and sv_last_error() describes the problem.  A HIP launch error
+ *     is returned as SV_ERR_HIP.  Input values must be finite; they are not
+ *     checked.
+ *   - Verdicts: 1 = collision (d <= eps), 0 = free (d > eps).
+ *   - Calls that share a workspace must not overlap in time.
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SV_OK = 0,
+  SV_ERR_ARG = -1,          /* null pointer or value out of range */
+  SV_ERR_SHAPE = -2,        /* inconsistent sizes */
+  SV_ERR_WORKSPACE = -3,    /* workspace missing or too small */
+  SV_ERR_UNSUPPORTED = -4,  /* valid request this build does not implement */
+  SV_ERR_HIP = -5           /* a HIP runtime call failed */
+} sv_status;
+
+#define SV_MAX_DOF 8
+#define SV_MAX_CAPS 16
+
+/* Robot model (host struct, read during the call).
+ * Kinematics: standard Denavit-Hartenberg, frame i = frame i-1 * Rz(q_i + theta_off_i)
+ * Tz(d_i) Tx(a_i) Rx(alpha_i), frame 0 = world.  The paper needs "the sequence of
+ * poses of each link" along a motion (Sec. IV-C); the robot's volume V_R(q)
+ * (Sec. III) is a union of capsules.  Capsule k is the segment between point
+ * cap_p[k][0] fixed in frame cap_frame[k][0] and point cap_p[k][1] fixed in frame
+ * cap_frame[k][1], inflated by radius cap_r[k] >= 0.  Frame indices run 0..dof. */
+typedef struct {
+  int32_t dof;                          /* 1..SV_MAX_DOF */
+  int32_t n_caps;                       /* 1..SV_MAX_CAPS */
+  double dh[SV_MAX_DOF][4];             /* rows (a, alpha, d, theta_off) */
+  int32_t cap_frame[SV_MAX_CAPS][2];
+  double cap_p[SV_MAX_CAPS][2][3];
+  double cap_r[SV_MAX_CAPS];
+} sv_robot;
+
+/* Motion types.  The path c(m, s), s in [0, 1] (Sec. III, eq. (2)) is sampled at
+ * s_t = t / (T - 1), t = 0..T-1 (T = 1: s = 0).
+ *   SV_LINEAR: q_s = q0 + s (q1 - q0) (the paper's linear joint-space motion, Sec. IV-C).
+ *   SV_SPLINE: per joint, the cubic spline through q0, via[0], via[1], q1 at
+ *              s = 0, 1/3, 2/3, 1 with zero end slopes and continuous second
+ *              derivative (a joint-space stand-in for the paper's task-space spline). */
+enum { SV_LINEAR = 0, SV_SPLINE = 1 };
+
+typedef struct {
+  int32_t kind;        /* SV_LINEAR or SV_SPLINE */
+  int32_t T;           /* samples per motion, >= 1 */
+  int64_t n;           /* number of motions M, >= 0 */
+  const float* q0;     /* dev [M][dof] */
+  const float* q1;     /* dev [M][dof] */
+  const float* via;    /* dev [M][2][dof] for SV_SPLINE, else ignored */
+} sv_motions;
+
+/* Point cloud X (Sec. IV-B), structure of arrays. */
+typedef struct {
+  int64_t n;           /* number of points N, >= 0 (indices must fit in int32) */
+  const float* x;      /* dev [N] */
+  const float* y;      /* dev [N] */
+  const float* z;      /* dev [N] */
+} sv_cloud;
+
+/* Per-motion results, all dev [M]; any pointer may be NULL to skip that output. */
+typedef struct {
+  float* min_dist;     /* d(X, m); +inf when N = 0 */
+  int32_t* argmin;     /* index of a point attaining min_dist (the lowest among FP32
+                          ties); -1 when N = 0 */
+  uint8_t* verdict;    /* 1 = collision (d <= eps), 0 = free */
+  int32_t* n_fallback; /* screening only: points sent to the exact check */
+} sv_results;
+
+/* Workspace sizes per operation. */
+enum { SV_OP_EXACT_SDF = 0, SV_OP_CHECK = 1 };
+
+/* Human-readable name of a status code. */
+const char* sv_status_string(int status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char* sv_last_error(void);
+
+/* Bytes of workspace the operation `op` needs for these arguments (host, no launch).
+ * For SV_OP_EXACT_SDF and SV_OP_CHECK only robot, motions and cloud are read
+ * (mlp may be NULL).  Returns SV_OK and writes *bytes. */
+int sv_workspace_size(int op, const sv_robot* robot, const void* mlp, const sv_motions* motions,
+                      const sv_cloud* cloud, size_t* bytes);
+
+/* Forward kinematics (paper Sec. IV-C: the poses of every link along a motion).
+ * q: dev [n_cfg][dof] joint configurations (FP32).
+ * caps: dev [n_cfg][n_caps][8] output; entry = (Ax, Ay, Az, Bx, By, Bz, r, 0), the
+ *       world endpoints and radius of every capsule.
+ * fp64: 0 = FP32 arithmetic, 1 = FP64 arithmetic rounded to FP32 at the end.
+ * No workspace.  n_cfg = 0 is a no-op. */
+int sv_fk(const sv_robot* robot, const float* q, int64_t n_cfg, float* caps, int fp64, void* stream);
+
+/* Exact swept signed distance of every point to every motion (Sec. III, eq. (1)-(4)):
+ *   sdf[m][i] = min over t < T, k < n_caps of ( |x_i - segment_k(q_t)| - r_k ),
+ * computed in FP32.  sdf: dev [M][N] row-major.  Workspace: SV_OP_EXACT_SDF. */
+int sv_exact_sdf(const sv_robot* robot, const sv_motions* motions, const sv_cloud* cloud, float* sdf,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* Exact collision check of M motions against one cloud (Sec. IV-B: d(X, m) and the
+ * safety-margin test of Alg. 1).  Distances are computed in FP32; every motion
+ * whose FP32 distance lies within 1e-5 m of eps is recomputed in FP64 so that
+ * its verdict is the FP64 one (min_dist then holds the FP64 value rounded to
+ * FP32).  mlp must be NULL and screen 0 in this build.  Workspace: SV_OP_CHECK. */
+int sv_check_motions(const sv_robot* robot, const void* mlp, int screen, float eps, float tau,
+                     const sv_motions* motions, const sv_cloud* cloud, sv_results* out, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* ---- measurement support (not part of the method) --------------------------------
+ * When enabled, every later call records a HIP event pair on its stream around each
+ * of its kernel groups ("motion_table", "exact", "exact_sdf", "finalize",
+ * "recheck64", ...).  sv_profile_read waits for the recorded events and returns the
+ * summed elapsed milliseconds and the number of recorded launches of that group
+ * since the last reset.  Do not enable while capturing a HIP graph. */
+int sv_profile_enable(int on);
+void sv_profile_reset(void);
+int sv_profile_read(const char* kernel, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SV_H */

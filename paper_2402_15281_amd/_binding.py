@@ -1,0 +1,222 @@
+"""ctypes binding of libsv (argument marshalling only).
+
+Every function here has the name of the C entry point it wraps and does nothing
+but turn torch device tensors into the pointers and sizes of the C ABI (see
+include/sv.h).  All arithmetic runs in the HIP kernels of libsv.so; if the
+library is missing this module raises at import time rather than fall back to
+anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsv.so")
+
+SV_MAX_DOF = 8
+SV_MAX_CAPS = 16
+SV_LINEAR, SV_SPLINE = 0, 1
+SV_OP_EXACT_SDF, SV_OP_CHECK = 0, 1
+
+_STATUS = {0: "SV_OK", -1: "SV_ERR_ARG", -2: "SV_ERR_SHAPE", -3: "SV_ERR_WORKSPACE",
+           -4: "SV_ERR_UNSUPPORTED", -5: "SV_ERR_HIP"}
+
+
+class SvError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+class sv_robot(ctypes.Structure):
+    _fields_ = [("dof", ctypes.c_int32), ("n_caps", ctypes.c_int32),
+                ("dh", (ctypes.c_double * 4) * SV_MAX_DOF),
+                ("cap_frame", (ctypes.c_int32 * 2) * SV_MAX_CAPS),
+                ("cap_p", ((ctypes.c_double * 3) * 2) * SV_MAX_CAPS),
+                ("cap_r", ctypes.c_double * SV_MAX_CAPS)]
+
+
+class sv_motions(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("T", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("q0", ctypes.c_void_p), ("q1", ctypes.c_void_p), ("via", ctypes.c_void_p)]
+
+
+class sv_cloud(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p)]
+
+
+class sv_results(ctypes.Structure):
+    _fields_ = [("min_dist", ctypes.c_void_p), ("argmin", ctypes.c_void_p), ("verdict", ctypes.c_void_p),
+                ("n_fallback", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libsv.so not built at {LIB_PATH}; run `python -m paper_2402_15281_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.sv_status_string.restype = ctypes.c_char_p
+    lib.sv_status_string.argtypes = [ctypes.c_int]
+    lib.sv_last_error.restype = ctypes.c_char_p
+    lib.sv_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(sv_robot), P, ctypes.POINTER(sv_motions),
+                                      ctypes.POINTER(sv_cloud), ctypes.POINTER(ctypes.c_size_t)]
+    lib.sv_fk.argtypes = [ctypes.POINTER(sv_robot), P, ctypes.c_int64, P, ctypes.c_int, P]
+    lib.sv_exact_sdf.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_motions), ctypes.POINTER(sv_cloud), P,
+                                 P, ctypes.c_size_t, P]
+    lib.sv_check_motions.argtypes = [ctypes.POINTER(sv_robot), P, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                                     ctypes.POINTER(sv_motions), ctypes.POINTER(sv_cloud),
+                                     ctypes.POINTER(sv_results), P, ctypes.c_size_t, P]
+    lib.sv_profile_enable.argtypes = [ctypes.c_int]
+    lib.sv_profile_reset.argtypes = []
+    lib.sv_profile_reset.restype = None
+    lib.sv_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    for fn in ("sv_workspace_size", "sv_fk", "sv_exact_sdf", "sv_check_motions", "sv_profile_enable",
+               "sv_profile_read"):
+        getattr(lib, fn).restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int):
+    if status != 0:
+        raise SvError(status, lib.sv_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------- host structs
+
+def make_robot(arm) -> sv_robot:
+    """sv_robot from an arm description (dh [dof][4], cap_frame [K][2], cap_p [K][2][3], cap_r [K])."""
+    r = sv_robot()
+    dh = np.asarray(arm.dh, np.float64)
+    cf = np.asarray(arm.cap_frame, np.int32)
+    cp = np.asarray(arm.cap_p, np.float64)
+    cr = np.asarray(arm.cap_r, np.float64)
+    r.dof, r.n_caps = dh.shape[0], cr.shape[0]
+    for i in range(dh.shape[0]):
+        for j in range(4):
+            r.dh[i][j] = float(dh[i, j])
+    for k in range(cr.shape[0]):
+        r.cap_frame[k][0], r.cap_frame[k][1] = int(cf[k, 0]), int(cf[k, 1])
+        for e in range(2):
+            for c in range(3):
+                r.cap_p[k][e][c] = float(cp[k, e, c])
+        r.cap_r[k] = float(cr[k])
+    return r
+
+
+class DeviceMotions:
+    """Motions resident in device memory (FP32) plus their sv_motions descriptor."""
+
+    def __init__(self, motions, device="cuda"):
+        self.kind = SV_SPLINE if motions.kind == "spline" else SV_LINEAR
+        self.T = int(motions.T)
+        self.q0 = torch.as_tensor(np.asarray(motions.q0, np.float32), device=device).contiguous()
+        self.q1 = torch.as_tensor(np.asarray(motions.q1, np.float32), device=device).contiguous()
+        self.via = None
+        if motions.via is not None:
+            self.via = torch.as_tensor(np.asarray(motions.via, np.float32), device=device).contiguous()
+        self.n = int(self.q0.shape[0])
+
+    def desc(self) -> sv_motions:
+        return sv_motions(self.kind, self.T, self.n, self.q0.data_ptr() if self.n else None,
+                          self.q1.data_ptr() if self.n else None,
+                          self.via.data_ptr() if self.via is not None and self.n else None)
+
+
+class DeviceCloud:
+    """Point cloud in device memory as structure of arrays (FP32)."""
+
+    def __init__(self, pts, device="cuda"):
+        p = torch.as_tensor(np.asarray(pts, np.float32).reshape(-1, 3).T.copy(), device=device).contiguous()
+        self.xyz = p                      # [3][N]
+        self.n = int(p.shape[1])
+
+    def desc(self) -> sv_cloud:
+        if self.n == 0:
+            return sv_cloud(0, None, None, None)
+        base = self.xyz.data_ptr()
+        return sv_cloud(self.n, base, base + 4 * self.n, base + 8 * self.n)
+
+
+class DeviceResults:
+    def __init__(self, M, device="cuda"):
+        self.min_dist = torch.empty(M, dtype=torch.float32, device=device)
+        self.argmin = torch.empty(M, dtype=torch.int32, device=device)
+        self.verdict = torch.empty(M, dtype=torch.uint8, device=device)
+        self.n_fallback = torch.zeros(M, dtype=torch.int32, device=device)
+
+    def desc(self) -> sv_results:
+        return sv_results(self.min_dist.data_ptr(), self.argmin.data_ptr(), self.verdict.data_ptr(),
+                          self.n_fallback.data_ptr())
+
+
+# ------------------------------------------------------------------ entry points
+
+def sv_workspace_size(op: int, robot: sv_robot, motions: DeviceMotions, cloud: DeviceCloud, mlp=None) -> int:
+    n = ctypes.c_size_t(0)
+    md, cd = motions.desc(), cloud.desc()
+    _check(lib.sv_workspace_size(op, ctypes.byref(robot), mlp, ctypes.byref(md), ctypes.byref(cd), ctypes.byref(n)))
+    return int(n.value)
+
+
+def workspace(nbytes: int, device="cuda"):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def sv_fk(robot: sv_robot, q: torch.Tensor, caps: torch.Tensor, fp64: bool = False, stream=None):
+    """caps[n][n_caps][8] <- FK of q[n][dof] (device tensors, FP32)."""
+    n = int(q.shape[0])
+    _check(lib.sv_fk(ctypes.byref(robot), _ptr(q), n, _ptr(caps), int(bool(fp64)), _stream(stream)))
+
+
+def sv_exact_sdf(robot: sv_robot, motions: DeviceMotions, cloud: DeviceCloud, sdf: torch.Tensor, ws=None,
+                 stream=None):
+    """sdf[M][N] <- exact swept SDF (device FP32)."""
+    md, cd = motions.desc(), cloud.desc()
+    if ws is None:
+        ws = workspace(sv_workspace_size(SV_OP_EXACT_SDF, robot, motions, cloud))
+    _check(lib.sv_exact_sdf(ctypes.byref(robot), ctypes.byref(md), ctypes.byref(cd), _ptr(sdf), _ptr(ws),
+                            ws.numel(), _stream(stream)))
+    return ws
+
+
+def sv_check_motions(robot: sv_robot, motions: DeviceMotions, cloud: DeviceCloud, out: DeviceResults, eps: float,
+                     mlp=None, screen: int = 0, tau: float = 0.0, ws=None, stream=None):
+    """Per-motion min distance, argmin and verdict (exact check)."""
+    md, cd, rd = motions.desc(), cloud.desc(), out.desc()
+    if ws is None:
+        ws = workspace(sv_workspace_size(SV_OP_CHECK, robot, motions, cloud, mlp))
+    _check(lib.sv_check_motions(ctypes.byref(robot), mlp, int(screen), float(eps), float(tau), ctypes.byref(md),
+                                ctypes.byref(cd), ctypes.byref(rd), _ptr(ws), ws.numel(), _stream(stream)))
+    return ws
+
+
+def sv_profile_enable(on: bool = True):
+    _check(lib.sv_profile_enable(int(bool(on))))
+
+
+def sv_profile_reset():
+    lib.sv_profile_reset()
+
+
+def sv_profile_read(kernel: str):
+    """(total milliseconds, launches) recorded for a kernel group since the last reset."""
+    ms, n = ctypes.c_double(0), ctypes.c_int64(0)
+    _check(lib.sv_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return float(ms.value), int(n.value)

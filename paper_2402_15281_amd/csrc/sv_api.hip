@@ -1,0 +1,300 @@
+// C ABI of libsv: argument validation, workspace carving and kernel dispatch.
+// The entry points and their contracts are declared and documented in sv.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sv_internal.h"
+
+namespace sv {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(SV_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+// ---- optional per-kernel timing with HIP events (sv_profile_*)
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::map<std::string, std::pair<double, int64_t>> g_prof_acc;
+
+// Records a HIP event pair around the launches in its scope, on the launch stream.
+struct ProfScope {
+  ProfRec rec{nullptr, nullptr, nullptr};
+  hipStream_t st;
+  ProfScope(const char* name, hipStream_t s) : st(s) {
+    if (!g_prof_on) return;
+    if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess) return;
+    rec.name = name;
+    (void)hipEventRecord(rec.a, st);
+  }
+  ~ProfScope() {
+    if (!rec.name) return;
+    (void)hipEventRecord(rec.b, st);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_pending.push_back(rec);
+  }
+};
+
+void prof_resolve() {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (auto& r : g_prof_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      auto& acc = g_prof_acc[r.name];
+      acc.first += ms;
+      acc.second += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof_pending.clear();
+}
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Sequential carving of the caller's workspace.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+int check_robot(const sv_robot* r) {
+  if (!r) return fail(SV_ERR_ARG, "robot is NULL");
+  if (r->dof < 1 || r->dof > SV_MAX_DOF) return fail(SV_ERR_ARG, "robot dof %d outside 1..%d", r->dof, SV_MAX_DOF);
+  if (r->n_caps < 1 || r->n_caps > SV_MAX_CAPS)
+    return fail(SV_ERR_ARG, "robot n_caps %d outside 1..%d", r->n_caps, SV_MAX_CAPS);
+  for (int k = 0; k < r->n_caps; ++k) {
+    for (int e = 0; e < 2; ++e)
+      if (r->cap_frame[k][e] < 0 || r->cap_frame[k][e] > r->dof)
+        return fail(SV_ERR_ARG, "capsule %d endpoint %d frame %d outside 0..%d", k, e, r->cap_frame[k][e], r->dof);
+    if (!(r->cap_r[k] >= 0.0) || !isfinite(r->cap_r[k]))
+      return fail(SV_ERR_ARG, "capsule %d radius must be finite and >= 0", k);
+  }
+  return SV_OK;
+}
+
+int check_motions(const sv_motions* m, int dof) {
+  if (!m) return fail(SV_ERR_ARG, "motions is NULL");
+  if (m->kind != SV_LINEAR && m->kind != SV_SPLINE) return fail(SV_ERR_ARG, "unknown motion kind %d", m->kind);
+  if (m->T < 1) return fail(SV_ERR_ARG, "T = %d, need T >= 1", m->T);
+  if (m->n < 0) return fail(SV_ERR_SHAPE, "negative motion count");
+  if (m->n > 0 && (!m->q0 || !m->q1)) return fail(SV_ERR_ARG, "motion q0/q1 is NULL");
+  if (m->n > 0 && m->kind == SV_SPLINE && !m->via) return fail(SV_ERR_ARG, "spline motions need via points");
+  if (m->n > (int64_t)0x7fffffff / 2) return fail(SV_ERR_SHAPE, "too many motions");
+  (void)dof;
+  return SV_OK;
+}
+
+int check_cloud(const sv_cloud* c) {
+  if (!c) return fail(SV_ERR_ARG, "cloud is NULL");
+  if (c->n < 0 || c->n > 0x7fffffffLL) return fail(SV_ERR_SHAPE, "cloud size %lld outside 0..2^31-1", (long long)c->n);
+  if (c->n > 0 && (!c->x || !c->y || !c->z)) return fail(SV_ERR_ARG, "cloud coordinate pointer is NULL");
+  return SV_OK;
+}
+
+MotionArgs to_args(const sv_motions& m) {
+  return MotionArgs{m.kind, m.T, m.n, m.q0, m.q1, m.kind == SV_SPLINE ? m.via : nullptr};
+}
+CloudArgs to_args(const sv_cloud& c) { return CloudArgs{(int)c.n, c.x, c.y, c.z}; }
+
+// Workspace layout of the exact check.
+struct CheckWs {
+  CapEntry* table;
+  unsigned long long* keys;
+  int* list;
+  int* count;
+  CapEntry64* table64;
+  unsigned long long* keys64;
+  size_t bytes;
+};
+
+CheckWs carve_check(void* ws, const sv_robot& r, const sv_motions& m) {
+  Carver c(ws);
+  CheckWs w;
+  const size_t entries = (size_t)m.n * r.n_caps * m.T;
+  w.table = c.take<CapEntry>(entries);
+  w.keys = c.take<unsigned long long>(m.n);
+  w.list = c.take<int>(m.n);
+  w.count = c.take<int>(1);
+  w.table64 = c.take<CapEntry64>(entries);
+  w.keys64 = c.take<unsigned long long>(m.n);
+  w.bytes = c.off;
+  return w;
+}
+
+size_t exact_sdf_bytes(const sv_robot& r, const sv_motions& m) {
+  Carver c(nullptr);
+  c.take<CapEntry>((size_t)m.n * r.n_caps * m.T);
+  return c.off;
+}
+
+// Motions whose FP32 cloud distance lies within this band of eps are recomputed in FP64.
+constexpr float kCertBand = 1e-5f;
+
+}  // namespace
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" {
+
+const char* sv_status_string(int s) {
+  switch (s) {
+    case SV_OK: return "ok";
+    case SV_ERR_ARG: return "invalid argument";
+    case SV_ERR_SHAPE: return "inconsistent shape";
+    case SV_ERR_WORKSPACE: return "workspace missing or too small";
+    case SV_ERR_UNSUPPORTED: return "unsupported request";
+    case SV_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* sv_last_error(void) { return g_last_error.c_str(); }
+
+int sv_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_on = on != 0;
+  return SV_OK;
+}
+
+void sv_profile_reset(void) {
+  prof_resolve();
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_acc.clear();
+}
+
+int sv_profile_read(const char* kernel, double* total_ms, int64_t* launches) {
+  if (!kernel || !total_ms || !launches) return fail(SV_ERR_ARG, "NULL argument");
+  prof_resolve();
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  auto it = g_prof_acc.find(kernel);
+  *total_ms = it == g_prof_acc.end() ? 0.0 : it->second.first;
+  *launches = it == g_prof_acc.end() ? 0 : it->second.second;
+  return SV_OK;
+}
+
+int sv_workspace_size(int op, const sv_robot* robot, const void* mlp, const sv_motions* motions,
+                      const sv_cloud* cloud, size_t* bytes) {
+  (void)mlp;
+  if (!bytes) return fail(SV_ERR_ARG, "bytes is NULL");
+  int s;
+  if ((s = check_robot(robot)) || (s = check_motions(motions, robot->dof)) || (s = check_cloud(cloud))) return s;
+  switch (op) {
+    case SV_OP_EXACT_SDF: *bytes = exact_sdf_bytes(*robot, *motions); return SV_OK;
+    case SV_OP_CHECK: *bytes = carve_check(nullptr, *robot, *motions).bytes; return SV_OK;
+    default: return fail(SV_ERR_ARG, "unknown workspace op %d", op);
+  }
+}
+
+int sv_fk(const sv_robot* robot, const float* q, int64_t n_cfg, float* caps, int fp64, void* stream) {
+  int s;
+  if ((s = check_robot(robot))) return s;
+  if (n_cfg < 0) return fail(SV_ERR_SHAPE, "negative configuration count");
+  if (n_cfg > 0 && (!q || !caps)) return fail(SV_ERR_ARG, "q or caps is NULL");
+  hipError_t e = launch_fk_configs(*robot, q, n_cfg, caps, fp64 ? 1 : 0, (hipStream_t)stream);
+  return e == hipSuccess ? SV_OK : hip_fail(e, "sv_fk");
+}
+
+int sv_exact_sdf(const sv_robot* robot, const sv_motions* motions, const sv_cloud* cloud, float* sdf, void* ws,
+                 size_t ws_bytes, void* stream) {
+  int s;
+  if ((s = check_robot(robot)) || (s = check_motions(motions, robot->dof)) || (s = check_cloud(cloud))) return s;
+  if (motions->n == 0 || cloud->n == 0) return SV_OK;
+  if (!sdf) return fail(SV_ERR_ARG, "sdf is NULL");
+  const size_t need = exact_sdf_bytes(*robot, *motions);
+  if (!ws || ws_bytes < need) return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", need, ws_bytes);
+  hipStream_t st = (hipStream_t)stream;
+  CapEntry* table = static_cast<CapEntry*>(ws);
+  const MotionArgs ma = to_args(*motions);
+  hipError_t e;
+  {
+    ProfScope ps("motion_table", st);
+    e = launch_motion_table(*robot, ma, table, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "motion table");
+  ProfScope ps("exact_sdf", st);
+  e = launch_exact(*robot, table, ma, to_args(*cloud), nullptr, nullptr, motions->n, sdf, nullptr,
+                   default_exact_shape(), st);
+  return e == hipSuccess ? SV_OK : hip_fail(e, "exact kernel");
+}
+
+int sv_check_motions(const sv_robot* robot, const void* mlp, int screen, float eps, float tau,
+                     const sv_motions* motions, const sv_cloud* cloud, sv_results* out, void* ws, size_t ws_bytes,
+                     void* stream) {
+  (void)tau;
+  int s;
+  if ((s = check_robot(robot)) || (s = check_motions(motions, robot->dof)) || (s = check_cloud(cloud))) return s;
+  if (!out) return fail(SV_ERR_ARG, "results is NULL");
+  if (!isfinite(eps)) return fail(SV_ERR_ARG, "eps must be finite");
+  if (mlp || screen) return fail(SV_ERR_UNSUPPORTED, "network screening is not available in this call");
+  if (motions->n == 0) return SV_OK;
+  const CheckWs w0 = carve_check(nullptr, *robot, *motions);
+  if (!ws || ws_bytes < w0.bytes)
+    return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", w0.bytes, ws_bytes);
+  const CheckWs w = carve_check(ws, *robot, *motions);
+  hipStream_t st = (hipStream_t)stream;
+  const MotionArgs ma = to_args(*motions);
+  const CloudArgs ca = to_args(*cloud);
+  hipError_t e;
+  if ((e = launch_fill_u64(w.keys, motions->n, ~0ull, st)) != hipSuccess) return hip_fail(e, "init keys");
+  if ((e = launch_fill_i32(w.count, 1, 0, st)) != hipSuccess) return hip_fail(e, "init count");
+  if (cloud->n > 0) {
+    {
+      ProfScope ps("motion_table", st);
+      e = launch_motion_table(*robot, ma, w.table, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "motion table");
+    {
+      ProfScope ps("exact", st);
+      e = launch_exact(*robot, w.table, ma, ca, nullptr, nullptr, motions->n, nullptr, w.keys, default_exact_shape(),
+                       st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "exact kernel");
+  }
+  {
+    ProfScope ps("finalize", st);
+    e = launch_finalize(w.keys, motions->n, eps, kCertBand, *out, w.list, w.count, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "finalize");
+  {
+    ProfScope ps("recheck64", st);
+    e = launch_recheck64(*robot, ma, ca, w.list, w.count, w.table64, w.keys64, eps, *out, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "fp64 recheck");
+  return SV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,497 @@
+// Geometric kernels of the exact swept-volume check (gfx950).
+//
+// Paper: Sec. III (eq. (1)-(4): f_d(x, m) = signed distance of x to the swept volume
+// V_S(m) = union over s of V_R(c(m, s))) and Sec. IV-B (d(X, m) = min over the cloud,
+// free iff d > eps_S).  The continuous union over s is sampled at T configurations
+// s_t = t / (T - 1); V_R(q) is a union of capsules placed by forward kinematics.
+//
+// Kernels:
+//   k_fk_configs   forward kinematics of independent configurations (sv_fk)
+//   k_motion_table per (motion, t): motion sample + FK -> one capsule entry per link
+//   k_exact        per (motion, point tile): min over capsules and samples, FP32 VALU;
+//                  optional per-point output and per-motion (distance, index) min keys
+//   k_finalize     keys -> min distance, argmin, verdict; certified-band list
+//   k_fk64_table / k_exact64 / k_finalize64: FP64 recheck of the band list
+#include <math.h>
+
+#include "sv_internal.h"
+
+namespace sv {
+namespace {
+
+constexpr unsigned long long kKeyEmpty = ~0ull;
+
+// Monotone map of a float onto uint32 so that unsigned order equals float order.
+__device__ __forceinline__ uint32_t ord_f32(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float unord_f32(uint32_t o) {
+  uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+  return __uint_as_float(u);
+}
+__device__ __forceinline__ unsigned long long ord_f64(double f) {
+  unsigned long long u = (unsigned long long)__double_as_longlong(f);
+  return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+__device__ __forceinline__ double unord_f64(unsigned long long o) {
+  unsigned long long u = (o >> 63) ? (o & ~(1ull << 63)) : ~o;
+  return __longlong_as_double((long long)u);
+}
+
+__device__ __forceinline__ void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
+
+// Path parameter of sample t of T.
+template <typename R>
+__device__ __forceinline__ R sample_s(int t, int T) {
+  return T > 1 ? (R)t / (R)(T - 1) : (R)0;
+}
+
+// Joint configuration q_s of one motion (eq. (2)).
+// Linear: q0 + s (q1 - q0).  Spline: per joint, the C2 cubic through (0, q0),
+// (1/3, v1), (2/3, v2), (1, q1) with zero end slopes.  With knot spacing 1/3 the
+// two interior slopes, already multiplied by the spacing, are
+//   h m1 = (4 (v2 - q0) - (q1 - v1)) / 5,   h m2 = (4 (q1 - v1) - (v2 - q0)) / 5,
+// and each segment is a cubic Hermite in u = 3 s - segment.
+template <typename R>
+__device__ __forceinline__ void motion_config(int kind, int dof, const float* q0, const float* q1,
+                                              const float* via, R s, R* q) {
+  if (kind == SV_LINEAR) {
+#pragma unroll
+    for (int j = 0; j < SV_MAX_DOF; ++j)
+      if (j < dof) {
+        R a = (R)q0[j], b = (R)q1[j];
+        q[j] = a + s * (b - a);
+      }
+    return;
+  }
+  R s3 = s * (R)3;
+  int seg = (int)s3;
+  seg = seg > 2 ? 2 : (seg < 0 ? 0 : seg);
+  R u = s3 - (R)seg;
+  R u2 = u * u, u3 = u2 * u;
+  R h00 = (R)2 * u3 - (R)3 * u2 + (R)1;
+  R h10 = u3 - (R)2 * u2 + u;
+  R h01 = (R)3 * u2 - (R)2 * u3;
+  R h11 = u3 - u2;
+#pragma unroll
+  for (int j = 0; j < SV_MAX_DOF; ++j)
+    if (j < dof) {
+      R y0 = (R)q0[j], y1 = (R)via[j], y2 = (R)via[dof + j], y3 = (R)q1[j];
+      R hm1 = ((R)4 * (y2 - y0) - (y3 - y1)) / (R)5;
+      R hm2 = ((R)4 * (y3 - y1) - (y2 - y0)) / (R)5;
+      R ya = seg == 0 ? y0 : (seg == 1 ? y1 : y2);
+      R yb = seg == 0 ? y1 : (seg == 1 ? y2 : y3);
+      R ma = seg == 0 ? (R)0 : (seg == 1 ? hm1 : hm2);
+      R mb = seg == 0 ? hm1 : (seg == 1 ? hm2 : (R)0);
+      q[j] = h00 * ya + h10 * ma + h01 * yb + h11 * mb;
+    }
+}
+
+// World endpoints of every capsule at configuration q (standard DH chain).
+// F holds the running frame [R | p] (3x4, row-major); after joint i it is frame i.
+template <typename R>
+__device__ __forceinline__ void fk_capsules(const RobotT<R>& rb, const R* q, R (&A)[SV_MAX_CAPS][3],
+                                            R (&B)[SV_MAX_CAPS][3]) {
+  R F[12] = {(R)1, (R)0, (R)0, (R)0, (R)0, (R)1, (R)0, (R)0, (R)0, (R)0, (R)1, (R)0};
+  for (int f = 0; f <= rb.dof; ++f) {
+    if (f > 0) {
+      const int i = f - 1;
+      R st, ct, sa, ca;
+      sincos_r(q[i] + rb.dh[i][3], &st, &ct);
+      sincos_r(rb.dh[i][1], &sa, &ca);
+      const R a = rb.dh[i][0], d = rb.dh[i][2];
+      // F <- F * [[ct, -st ca, st sa, a ct], [st, ct ca, -ct sa, a st], [0, sa, ca, d]]
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const R f0 = F[4 * r], f1 = F[4 * r + 1], f2 = F[4 * r + 2], f3 = F[4 * r + 3];
+        const R c0 = f0 * ct + f1 * st;
+        const R s0 = f1 * ct - f0 * st;   // row . (-st, ct, 0)
+        F[4 * r + 0] = c0;
+        F[4 * r + 1] = s0 * ca + f2 * sa;
+        F[4 * r + 2] = f2 * ca - s0 * sa;
+        F[4 * r + 3] = a * c0 + d * f2 + f3;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < SV_MAX_CAPS; ++k) {
+      if (k < rb.n_caps) {
+        if (rb.fa[k] == f)
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+            A[k][r] = F[4 * r] * rb.pa[k][0] + F[4 * r + 1] * rb.pa[k][1] + F[4 * r + 2] * rb.pa[k][2] + F[4 * r + 3];
+        if (rb.fb[k] == f)
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+            B[k][r] = F[4 * r] * rb.pb[k][0] + F[4 * r + 1] * rb.pb[k][1] + F[4 * r + 2] * rb.pb[k][2] + F[4 * r + 3];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- sv_fk
+template <typename R>
+__global__ __launch_bounds__(256) void k_fk_configs(RobotT<R> rb, const float* __restrict__ q, int64_t n,
+                                                    float* __restrict__ caps) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  R qq[SV_MAX_DOF];
+#pragma unroll
+  for (int j = 0; j < SV_MAX_DOF; ++j) qq[j] = j < rb.dof ? (R)q[c * rb.dof + j] : (R)0;
+  R A[SV_MAX_CAPS][3], B[SV_MAX_CAPS][3];
+  fk_capsules<R>(rb, qq, A, B);
+  float* o = caps + c * rb.n_caps * 8;
+#pragma unroll
+  for (int k = 0; k < SV_MAX_CAPS; ++k)
+    if (k < rb.n_caps) {
+      float4 lo = make_float4((float)A[k][0], (float)A[k][1], (float)A[k][2], (float)B[k][0]);
+      float4 hi = make_float4((float)B[k][1], (float)B[k][2], (float)rb.r[k], 0.f);
+      reinterpret_cast<float4*>(o + 8 * k)[0] = lo;
+      reinterpret_cast<float4*>(o + 8 * k)[1] = hi;
+    }
+}
+
+// ------------------------------------------------------- motion tables
+// One thread per (motion, t); writes the entry of every capsule at [m][k][t].
+__global__ __launch_bounds__(256) void k_motion_table(Robot32 rb, MotionArgs mo, CapEntry* __restrict__ table) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= mo.n * mo.T) return;
+  const int64_t m = g / mo.T;
+  const int t = (int)(g - m * mo.T);
+  float q[SV_MAX_DOF];
+  motion_config<float>(mo.kind, rb.dof, mo.q0 + m * rb.dof, mo.q1 + m * rb.dof,
+                       mo.via ? mo.via + m * 2 * rb.dof : nullptr, sample_s<float>(t, mo.T), q);
+  float A[SV_MAX_CAPS][3], B[SV_MAX_CAPS][3];
+  fk_capsules<float>(rb, q, A, B);
+#pragma unroll
+  for (int k = 0; k < SV_MAX_CAPS; ++k)
+    if (k < rb.n_caps) {
+      const float bx = B[k][0] - A[k][0], by = B[k][1] - A[k][1], bz = B[k][2] - A[k][2];
+      const float l2 = bx * bx + by * by + bz * bz;
+      CapEntry e;
+      e.ax = A[k][0]; e.ay = A[k][1]; e.az = A[k][2];
+      e.inv_l2 = l2 > 0.f ? 1.0f / l2 : 0.f;
+      e.bx = bx; e.by = by; e.bz = bz; e.r = rb.r[k];
+      table[(m * rb.n_caps + k) * mo.T + t] = e;
+    }
+}
+
+// ------------------------------------------------------------ exact check
+// Capsule entries are uniform across a wave: read them through the constant
+// address space so that they arrive in scalar registers (s_load).
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(4))) const vf4* ConstF4Ptr;
+
+__device__ __forceinline__ CapEntry load_entry(ConstF4Ptr p, size_t idx) {
+  const vf4 lo = p[2 * idx], hi = p[2 * idx + 1];
+  CapEntry e;
+  e.ax = lo.x; e.ay = lo.y; e.az = lo.z; e.inv_l2 = lo.w;
+  e.bx = hi.x; e.by = hi.y; e.bz = hi.z; e.r = hi.w;
+  return e;
+}
+
+// Squared distance from (x, y, z) to the segment of entry e.  The closest-point
+// parameter is clamped to [0, 1]; the residual is formed explicitly (never as
+// |ap|^2 - dot^2 / |ab|^2, which cancels near the segment's axis).
+__device__ __forceinline__ float seg_d2(const CapEntry& e, float x, float y, float z) {
+  const float px = x - e.ax, py = y - e.ay, pz = z - e.az;
+  const float dot = px * e.bx + py * e.by + pz * e.bz;
+  const float u = __builtin_amdgcn_fmed3f(dot * e.inv_l2, 0.0f, 1.0f);
+  const float ex = px - u * e.bx, ey = py - u * e.by, ez = pz - u * e.bz;
+  return ex * ex + ey * ey + ez * ez;
+}
+
+// grid: one block per (motion slot, tile of NT*P points), tile fastest.
+// Lanes own points base + p*NT + tid.  For every capsule k: running min over t of
+// the squared distance, then sqrt - r; the point's distance is the min over k.
+template <int P, int NT>
+__global__ __launch_bounds__(NT) void k_exact(const CapEntry* __restrict__ table, int T, int K,
+                                              const float* __restrict__ px, const float* __restrict__ py,
+                                              const float* __restrict__ pz, int N, int tiles,
+                                              const int* __restrict__ mlist, const int* __restrict__ mcount,
+                                              float* __restrict__ sdf, unsigned long long* __restrict__ keys) {
+  const int slot = blockIdx.x / tiles;
+  const int tile = blockIdx.x - slot * tiles;
+  if (mcount && slot >= *mcount) return;
+  const int m = mlist ? mlist[slot] : slot;
+  const int base = tile * (NT * P) + threadIdx.x;
+
+  float x[P], y[P], z[P], best[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int i = base + p * NT;
+    const bool ok = i < N;
+    x[p] = ok ? px[i] : 0.f;
+    y[p] = ok ? py[i] : 0.f;
+    z[p] = ok ? pz[i] : 0.f;
+    best[p] = INFINITY;
+  }
+  ConstF4Ptr tab = (ConstF4Ptr)table;
+  for (int k = 0; k < K; ++k) {
+    const size_t e = ((size_t)m * K + k) * T;
+    float m2[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) m2[p] = INFINITY;
+    int t = 0;
+    for (; t + 1 < T; t += 2) {
+      const CapEntry a = load_entry(tab, e + t);
+      const CapEntry b = load_entry(tab, e + t + 1);
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const float da = seg_d2(a, x[p], y[p], z[p]);
+        const float db = seg_d2(b, x[p], y[p], z[p]);
+        m2[p] = fminf(m2[p], fminf(da, db));
+      }
+    }
+    if (t < T) {
+      const CapEntry a = load_entry(tab, e + t);
+#pragma unroll
+      for (int p = 0; p < P; ++p) m2[p] = fminf(m2[p], seg_d2(a, x[p], y[p], z[p]));
+    }
+    const float r = load_entry(tab, e).r;
+#pragma unroll
+    for (int p = 0; p < P; ++p) best[p] = fminf(best[p], sqrtf(m2[p]) - r);
+  }
+
+  if (sdf) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int i = base + p * NT;
+      if (i < N) sdf[(size_t)m * N + i] = best[p];
+    }
+  }
+  if (keys) {
+    unsigned long long key = kKeyEmpty;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int i = base + p * NT;
+      if (i < N) {
+        const unsigned long long kk = ((unsigned long long)ord_f32(best[p]) << 32) | (uint32_t)i;
+        key = kk < key ? kk : key;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(key, off, 64);
+      key = o < key ? o : key;
+    }
+    __shared__ unsigned long long wmin[NT / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) wmin[wid] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long k2 = wmin[0];
+#pragma unroll
+      for (int w = 1; w < NT / 64; ++w) k2 = wmin[w] < k2 ? wmin[w] : k2;
+      if (k2 != kKeyEmpty) atomicMin(keys + m, k2);
+    }
+  }
+}
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n, unsigned long long v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_i32(int* __restrict__ p, int64_t n, int v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_finalize(const unsigned long long* __restrict__ keys, int64_t M, float eps, float band,
+                           sv_results out, int* __restrict__ list, int* __restrict__ count) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const unsigned long long key = keys[m];
+  float d;
+  int arg;
+  if (key == kKeyEmpty) {
+    d = INFINITY;
+    arg = -1;
+  } else {
+    d = unord_f32((uint32_t)(key >> 32));
+    arg = (int)(uint32_t)(key & 0xffffffffu);
+  }
+  if (out.min_dist) out.min_dist[m] = d;
+  if (out.argmin) out.argmin[m] = arg;
+  if (out.verdict) out.verdict[m] = (uint8_t)(d <= eps);
+  if (list && fabsf(d - eps) <= band) list[atomicAdd(count, 1)] = (int)m;
+}
+
+// --------------------------------------------------------- FP64 recheck
+// Grid-stride over (slot, t) for the slots listed by k_finalize.
+__global__ __launch_bounds__(256) void k_fk64_table(Robot64 rb, MotionArgs mo, const int* __restrict__ list,
+                                                    const int* __restrict__ count, CapEntry64* __restrict__ table) {
+  const int64_t work = (int64_t)(*count) * mo.T;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < work; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t slot = g / mo.T;
+    const int t = (int)(g - slot * mo.T);
+    const int64_t m = list[slot];
+    double q[SV_MAX_DOF];
+    motion_config<double>(mo.kind, rb.dof, mo.q0 + m * rb.dof, mo.q1 + m * rb.dof,
+                          mo.via ? mo.via + m * 2 * rb.dof : nullptr, sample_s<double>(t, mo.T), q);
+    double A[SV_MAX_CAPS][3], B[SV_MAX_CAPS][3];
+    fk_capsules<double>(rb, q, A, B);
+#pragma unroll
+    for (int k = 0; k < SV_MAX_CAPS; ++k)
+      if (k < rb.n_caps) {
+        CapEntry64 e;
+        e.ax = A[k][0]; e.ay = A[k][1]; e.az = A[k][2];
+        e.bx = B[k][0] - A[k][0]; e.by = B[k][1] - A[k][1]; e.bz = B[k][2] - A[k][2];
+        e.l2 = e.bx * e.bx + e.by * e.by + e.bz * e.bz;
+        e.r = rb.r[k];
+        table[(slot * rb.n_caps + k) * mo.T + t] = e;
+      }
+  }
+}
+
+__device__ __forceinline__ double seg_d2_64(const CapEntry64& e, double x, double y, double z) {
+  const double px = x - e.ax, py = y - e.ay, pz = z - e.az;
+  double u = 0.0;
+  if (e.l2 > 0.0) {
+    u = (px * e.bx + py * e.by + pz * e.bz) / e.l2;
+    u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
+  }
+  const double ex = px - u * e.bx, ey = py - u * e.by, ez = pz - u * e.bz;
+  return ex * ex + ey * ey + ez * ez;
+}
+
+// Grid-stride over (slot, tile of 256 points); per-slot min of the FP64 distance.
+__global__ __launch_bounds__(256) void k_exact64(const CapEntry64* __restrict__ table, int T, int K,
+                                                 CloudArgs c, int tiles, const int* __restrict__ count,
+                                                 unsigned long long* __restrict__ keys64) {
+  const int64_t work = (int64_t)(*count) * tiles;
+  __shared__ unsigned long long wmin[4];
+  for (int64_t w = blockIdx.x; w < work; w += gridDim.x) {
+    const int64_t slot = w / tiles;
+    const int tile = (int)(w - slot * tiles);
+    const int i = tile * 256 + threadIdx.x;
+    double best = INFINITY;
+    if (i < c.n) {
+      const double x = c.x[i], y = c.y[i], z = c.z[i];
+      const CapEntry64* e0 = table + (size_t)slot * K * T;
+      for (int k = 0; k < K; ++k) {
+        double m2 = INFINITY;
+        for (int t = 0; t < T; ++t) m2 = fmin(m2, seg_d2_64(e0[(size_t)k * T + t], x, y, z));
+        best = fmin(best, sqrt(m2) - e0[(size_t)k * T].r);
+      }
+    }
+    unsigned long long key = i < c.n ? ord_f64(best) : kKeyEmpty;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(key, off, 64);
+      key = o < key ? o : key;
+    }
+    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long k2 = wmin[0];
+      for (int q = 1; q < 4; ++q) k2 = wmin[q] < k2 ? wmin[q] : k2;
+      if (k2 != kKeyEmpty) atomicMin(keys64 + slot, k2);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_finalize64(const int* __restrict__ list, const int* __restrict__ count,
+                             const unsigned long long* __restrict__ keys64, float eps, sv_results out) {
+  const int n = *count;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+    const int m = list[s];
+    const double d = unord_f64(keys64[s]);
+    if (out.min_dist) out.min_dist[m] = (float)d;
+    if (out.verdict) out.verdict[m] = (uint8_t)(d <= (double)eps);
+  }
+}
+
+inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+template <int P, int NT>
+hipError_t launch_exact_t(const CapEntry* table, const MotionArgs& m, const CloudArgs& c, int K, const int* mlist,
+                          const int* mcount, int64_t n_slots, float* sdf, unsigned long long* keys,
+                          hipStream_t st) {
+  const int tiles = (c.n + NT * P - 1) / (NT * P);
+  const int64_t blocks = n_slots * tiles;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_exact<P, NT>), dim3((unsigned)blocks), dim3(NT), 0, st, table, m.T, K, c.x, c.y, c.z, c.n,
+                     tiles, mlist, mcount, sdf, keys);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+ExactShape default_exact_shape() { return ExactShape{2, 256}; }
+
+hipError_t launch_fk_configs(const sv_robot& rb, const float* q, int64_t n, float* caps, int fp64,
+                             hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (fp64)
+    hipLaunchKernelGGL(k_fk_configs<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, robot_to_dev<double>(rb), q, n,
+                       caps);
+  else
+    hipLaunchKernelGGL(k_fk_configs<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, robot_to_dev<float>(rb), q, n,
+                       caps);
+  return hipGetLastError();
+}
+
+hipError_t launch_motion_table(const sv_robot& rb, const MotionArgs& m, CapEntry* table, hipStream_t st) {
+  const int64_t n = m.n * m.T;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_motion_table, dim3(grid_for(n, 256)), dim3(256), 0, st, robot_to_dev<float>(rb), m, table);
+  return hipGetLastError();
+}
+
+hipError_t launch_exact(const sv_robot& rb, const CapEntry* table, const MotionArgs& m, const CloudArgs& c,
+                        const int* mlist, const int* mcount, int64_t n_slots, float* sdf, unsigned long long* keys,
+                        ExactShape s, hipStream_t st) {
+  const int K = rb.n_caps;
+#define SV_EXACT_CASE(P, NT) \
+  if (s.ppl == P && s.threads == NT) return launch_exact_t<P, NT>(table, m, c, K, mlist, mcount, n_slots, sdf, keys, st);
+  SV_EXACT_CASE(1, 64) SV_EXACT_CASE(1, 128) SV_EXACT_CASE(1, 256)
+  SV_EXACT_CASE(2, 64) SV_EXACT_CASE(2, 128) SV_EXACT_CASE(2, 256)
+  SV_EXACT_CASE(4, 64) SV_EXACT_CASE(4, 128) SV_EXACT_CASE(4, 256)
+#undef SV_EXACT_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const unsigned long long* keys, int64_t M, float eps, float band, sv_results out,
+                           int* list, int* count, hipStream_t st) {
+  if (M == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3(grid_for(M, 256)), dim3(256), 0, st, keys, M, eps, band, out, list, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_recheck64(const sv_robot& rb, const MotionArgs& m, const CloudArgs& c, const int* list,
+                            const int* count, CapEntry64* table64, unsigned long long* keys64, float eps,
+                            sv_results out, hipStream_t st) {
+  if (m.n == 0) return hipSuccess;
+  hipError_t e = launch_fill_u64(keys64, m.n, kKeyEmpty, st);
+  if (e != hipSuccess) return e;
+  const int64_t fk_work = m.n * m.T;
+  hipLaunchKernelGGL(k_fk64_table, dim3((unsigned)std::min<int64_t>(grid_for(fk_work, 256), 1024)), dim3(256), 0, st,
+                     robot_to_dev<double>(rb), m, list, count, table64);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int tiles = (c.n + 255) / 256;
+  if (tiles > 0) {
+    hipLaunchKernelGGL(k_exact64, dim3((unsigned)std::min<int64_t>(m.n * tiles, 2048)), dim3(256), 0, st, table64,
+                       m.T, rb.n_caps, c, tiles, count, keys64);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_finalize64, dim3(4), dim3(256), 0, st, list, count, keys64, eps, out);
+  return hipGetLastError();
+}
+
+}  // namespace sv

@@ -1,0 +1,96 @@
+// Internal declarations shared by the libsv translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sv.h"
+
+namespace sv {
+
+// Robot model in the precision of the kernel that reads it; passed by value as a
+// kernel argument.  fa/fb: frame of each capsule endpoint; pa/pb: endpoint in it.
+template <typename R>
+struct RobotT {
+  int dof, n_caps;
+  R dh[SV_MAX_DOF][4];
+  int fa[SV_MAX_CAPS], fb[SV_MAX_CAPS];
+  R pa[SV_MAX_CAPS][3], pb[SV_MAX_CAPS][3];
+  R r[SV_MAX_CAPS];
+};
+using Robot32 = RobotT<float>;
+using Robot64 = RobotT<double>;
+
+template <typename R>
+RobotT<R> robot_to_dev(const sv_robot& in) {
+  RobotT<R> o{};
+  o.dof = in.dof;
+  o.n_caps = in.n_caps;
+  for (int i = 0; i < SV_MAX_DOF; ++i)
+    for (int j = 0; j < 4; ++j) o.dh[i][j] = (R)in.dh[i][j];
+  for (int k = 0; k < SV_MAX_CAPS; ++k) {
+    o.fa[k] = in.cap_frame[k][0];
+    o.fb[k] = in.cap_frame[k][1];
+    for (int c = 0; c < 3; ++c) {
+      o.pa[k][c] = (R)in.cap_p[k][0][c];
+      o.pb[k][c] = (R)in.cap_p[k][1][c];
+    }
+    o.r[k] = (R)in.cap_r[k];
+  }
+  return o;
+}
+
+// Motion description for kernels (device pointers).
+struct MotionArgs {
+  int kind, T;
+  int64_t n;
+  const float* q0;
+  const float* q1;
+  const float* via;
+};
+
+struct CloudArgs {
+  int n;
+  const float* x;
+  const float* y;
+  const float* z;
+};
+
+// Capsule-sample table entry of the FP32 exact check: segment start A, 1/|AB|^2
+// (0 for a sphere), segment vector AB, radius.  Layout [motion][capsule][t].
+struct alignas(32) CapEntry {
+  float ax, ay, az, inv_l2;
+  float bx, by, bz, r;
+};
+// FP64 entry for the certified-band recheck: A, |AB|^2, AB, radius.
+struct alignas(64) CapEntry64 {
+  double ax, ay, az, l2;
+  double bx, by, bz, r;
+};
+
+// Tunable launch shape of the exact kernel: points per lane and threads per block.
+struct ExactShape {
+  int ppl;      // 1, 2, 4
+  int threads;  // 64, 128, 256
+};
+
+// ---- launchers (sv_geom.hip) ------------------------------------------------------
+hipError_t launch_fk_configs(const sv_robot& rb, const float* q, int64_t n, float* caps, int fp64,
+                             hipStream_t st);
+hipError_t launch_motion_table(const sv_robot& rb, const MotionArgs& m, CapEntry* table, hipStream_t st);
+hipError_t launch_exact(const sv_robot& rb, const CapEntry* table, const MotionArgs& m, const CloudArgs& c,
+                        const int* mlist, const int* mcount, int64_t n_slots, float* sdf,
+                        unsigned long long* keys, ExactShape shape, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);
+hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
+// Decode FP32 keys into results; motions within `band` of eps are appended to
+// (list, count) for the FP64 recheck.
+hipError_t launch_finalize(const unsigned long long* keys, int64_t M, float eps, float band, sv_results out,
+                           int* list, int* count, hipStream_t st);
+hipError_t launch_recheck64(const sv_robot& rb, const MotionArgs& m, const CloudArgs& c, const int* list,
+                            const int* count, CapEntry64* table64, unsigned long long* keys64, float eps,
+                            sv_results out, hipStream_t st);
+
+ExactShape default_exact_shape();
+
+}  // namespace sv

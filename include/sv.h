@@ -99,8 +99,36 @@ typedef struct {
   int32_t* n_fallback; /* screening only: points sent to the exact check */
 } sv_results;
 
+/* Swept-volume network f_theta(x, q0, q1) -> delta_hat (Sec. IV-A): a plain MLP with
+ * softplus activations, h_0 = [x; q0; q1] (in that order, the inputs of Fig. 1),
+ * h_l = softplus(W_l h_{l-1} + b_l) for l = 1..L, delta_hat = w_out . h_L + b_out.
+ * softplus(z) = max(z, 0) + log(1 + exp(-|z|)).  The network applies to linear
+ * motions only: (q0, q1) determines a linear motion but not a spline (Sec. IV-C). */
+typedef struct {
+  int32_t in_dim;      /* 3 + 2 * dof */
+  int32_t width;       /* hidden width W: FP32 path W % 64 == 0, W <= 1024; BF16 path 128, 256 or 512 */
+  int32_t n_hidden;    /* L >= 1 softplus layers */
+  const float* params; /* dev FP32, flat: W_1 [W][in_dim], b_1 [W], then for l = 2..L: W_l [W][W], b_l [W];
+                          then w_out [W], b_out [1].  Weights row-major [out][in]. */
+} sv_mlp;
+
+/* Arithmetic of the network evaluation. */
+enum {
+  SV_FP32 = 0,  /* FP32 throughout */
+  SV_BF16 = 1   /* hidden layers: BF16 weights and activations (round to nearest even) on MFMA with
+                   FP32 accumulation; first and output layers in FP32 */
+};
+
+/* Screening modes of sv_check_motions.  A point is sent to the exact check iff the
+ * network predicts delta_hat < tau (the network is a proxy for the exact distance,
+ * Sec. IV-B).  SV_SCREEN_TRUST: a motion collides iff a sent point has exact distance
+ * <= eps; SV_SCREEN_CERTIFIED: as TRUST, and every motion without such a witness is
+ * checked exactly over all its points, so that verdicts equal the exact check's (as
+ * Alg. 1 confirms with the geometric checker every motion it reports free). */
+enum { SV_SCREEN_NONE = 0, SV_SCREEN_TRUST = 1, SV_SCREEN_CERTIFIED = 2 };
+
 /* Workspace sizes per operation. */
-enum { SV_OP_EXACT_SDF = 0, SV_OP_CHECK = 1 };
+enum { SV_OP_EXACT_SDF = 0, SV_OP_CHECK = 1, SV_OP_NN_SDF = 2 };
 
 /* Human-readable name of a status code. */
 const char* sv_status_string(int status);
@@ -109,10 +137,11 @@ const char* sv_status_string(int status);
 const char* sv_last_error(void);
 
 /* Bytes of workspace the operation `op` needs for these arguments (host, no launch).
- * For SV_OP_EXACT_SDF and SV_OP_CHECK only robot, motions and cloud are read
- * (mlp may be NULL).  Returns SV_OK and writes *bytes. */
-int sv_workspace_size(int op, const sv_robot* robot, const void* mlp, const sv_motions* motions,
-                      const sv_cloud* cloud, size_t* bytes);
+ * SV_OP_EXACT_SDF: robot, motions, cloud.  SV_OP_CHECK: robot, motions, cloud and mlp
+ * (NULL = exact only).  SV_OP_NN_SDF: mlp, motions, cloud and `precision` (robot may be
+ * NULL).  Returns SV_OK and writes *bytes. */
+int sv_workspace_size(int op, const sv_robot* robot, const sv_mlp* mlp, int precision,
+                      const sv_motions* motions, const sv_cloud* cloud, size_t* bytes);
 
 /* Forward kinematics (paper Sec. IV-C: the poses of every link along a motion).
  * q: dev [n_cfg][dof] joint configurations (FP32).
@@ -128,12 +157,25 @@ int sv_fk(const sv_robot* robot, const float* q, int64_t n_cfg, float* caps, int
 int sv_exact_sdf(const sv_robot* robot, const sv_motions* motions, const sv_cloud* cloud, float* sdf,
                  void* ws, size_t ws_bytes, void* stream);
 
-/* Exact collision check of M motions against one cloud (Sec. IV-B: d(X, m) and the
- * safety-margin test of Alg. 1).  Distances are computed in FP32; every motion
- * whose FP32 distance lies within 1e-5 m of eps is recomputed in FP64 so that
- * its verdict is the FP64 one (min_dist then holds the FP64 value rounded to
- * FP32).  mlp must be NULL and screen 0 in this build.  Workspace: SV_OP_CHECK. */
-int sv_check_motions(const sv_robot* robot, const void* mlp, int screen, float eps, float tau,
+/* Network prediction delta_hat = f_theta(x_i, q0_m, q1_m) for every (motion, point):
+ * sdf_hat dev [M][N] row-major.  Linear motions only (T is ignored).
+ * precision: SV_FP32 or SV_BF16.  Workspace: SV_OP_NN_SDF (0 bytes for SV_FP32). */
+int sv_nn_sdf(const sv_mlp* mlp, int precision, const sv_motions* motions, const sv_cloud* cloud, float* sdf_hat,
+              void* ws, size_t ws_bytes, void* stream);
+
+/* Collision check of M motions against one cloud (Sec. IV-B: d(X, m) and the
+ * safety-margin test of Alg. 1).
+ *   mlp == NULL, screen == SV_SCREEN_NONE: exact check of every (motion, point).
+ *   mlp != NULL, screen TRUST or CERTIFIED: the BF16 network screens every (motion,
+ *     point) first and only points with delta_hat < tau go to the exact check (linear
+ *     motions; mlp->width 128, 256 or 512).  n_fallback[m] counts them.  min_dist of a
+ *     motion decided by a witness is the minimum over the sent points; of any other
+ *     motion it is the minimum over all points (CERTIFIED) or over the sent points,
+ *     +inf if none (TRUST).
+ * Exact distances are FP32; every motion whose FP32 distance lies within 1e-5 m of eps
+ * is recomputed in FP64 over all its points so that its verdict is the FP64 one
+ * (min_dist then holds the FP64 value rounded to FP32).  Workspace: SV_OP_CHECK. */
+int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float eps, float tau,
                      const sv_motions* motions, const sv_cloud* cloud, sv_results* out, void* ws,
                      size_t ws_bytes, void* stream);
 

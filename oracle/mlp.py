@@ -156,3 +156,36 @@ def screened_verdicts(delta_hat, delta, eps, tau, certified=True):
     else:
         verdict = witness
     return verdict.astype(np.uint8), sent.sum(axis=1)
+
+
+def round_bf16(a):
+    """Round FP32 values to the nearest BF16 (ties to even), returned as float64.
+
+    BF16 keeps the top 16 bits of an FP32 word; rounding adds half an ulp of the
+    kept part (0x7FFF plus the lowest kept bit, for ties to even) before truncating.
+    Inputs are first rounded to FP32.
+    """
+    f = np.ascontiguousarray(np.asarray(a, np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def forward_bf16(flat, in_dim, width, n_hidden, H0):
+    """Debugging aid: the network with the BF16 path's rounding points, otherwise FP64.
+
+    The first layer uses FP32-exact weights and unrounded inputs; its activations,
+    like those of every hidden layer except the last, are rounded to BF16 before
+    they feed a matrix product; the weights of layers 2..L are rounded to BF16; the
+    last hidden activations and the output layer stay unrounded, except for a
+    single-layer network, whose output layer reads BF16 activations.
+    """
+    layers = unpack(flat, in_dim, width, n_hidden)
+    h = np.asarray(H0, np.float64)
+    for l, (W, b) in enumerate(layers[:-1]):
+        Wr = W if l == 0 else round_bf16(W)
+        h = softplus(h @ Wr.T + b)
+        if l + 1 < n_hidden or n_hidden == 1:
+            h = round_bf16(h)
+    W, b = layers[-1]
+    return (h @ W.T + b)[:, 0]

@@ -20,7 +20,9 @@ LIB_PATH = os.path.join(_HERE, "libsv.so")
 SV_MAX_DOF = 8
 SV_MAX_CAPS = 16
 SV_LINEAR, SV_SPLINE = 0, 1
-SV_OP_EXACT_SDF, SV_OP_CHECK = 0, 1
+SV_OP_EXACT_SDF, SV_OP_CHECK, SV_OP_NN_SDF = 0, 1, 2
+SV_FP32, SV_BF16 = 0, 1
+SV_SCREEN_NONE, SV_SCREEN_TRUST, SV_SCREEN_CERTIFIED = 0, 1, 2
 
 _STATUS = {0: "SV_OK", -1: "SV_ERR_ARG", -2: "SV_ERR_SHAPE", -3: "SV_ERR_WORKSPACE",
            -4: "SV_ERR_UNSUPPORTED", -5: "SV_ERR_HIP"}
@@ -49,6 +51,11 @@ class sv_cloud(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p)]
 
 
+class sv_mlp(ctypes.Structure):
+    _fields_ = [("in_dim", ctypes.c_int32), ("width", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
+                ("params", ctypes.c_void_p)]
+
+
 class sv_results(ctypes.Structure):
     _fields_ = [("min_dist", ctypes.c_void_p), ("argmin", ctypes.c_void_p), ("verdict", ctypes.c_void_p),
                 ("n_fallback", ctypes.c_void_p)]
@@ -62,19 +69,23 @@ def _load():
     lib.sv_status_string.restype = ctypes.c_char_p
     lib.sv_status_string.argtypes = [ctypes.c_int]
     lib.sv_last_error.restype = ctypes.c_char_p
-    lib.sv_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(sv_robot), P, ctypes.POINTER(sv_motions),
-                                      ctypes.POINTER(sv_cloud), ctypes.POINTER(ctypes.c_size_t)]
+    lib.sv_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(sv_robot), ctypes.POINTER(sv_mlp), ctypes.c_int,
+                                      ctypes.POINTER(sv_motions), ctypes.POINTER(sv_cloud),
+                                      ctypes.POINTER(ctypes.c_size_t)]
+    lib.sv_nn_sdf.argtypes = [ctypes.POINTER(sv_mlp), ctypes.c_int, ctypes.POINTER(sv_motions),
+                              ctypes.POINTER(sv_cloud), P, P, ctypes.c_size_t, P]
     lib.sv_fk.argtypes = [ctypes.POINTER(sv_robot), P, ctypes.c_int64, P, ctypes.c_int, P]
     lib.sv_exact_sdf.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_motions), ctypes.POINTER(sv_cloud), P,
                                  P, ctypes.c_size_t, P]
-    lib.sv_check_motions.argtypes = [ctypes.POINTER(sv_robot), P, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+    lib.sv_check_motions.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_mlp), ctypes.c_int, ctypes.c_float,
+                                     ctypes.c_float,
                                      ctypes.POINTER(sv_motions), ctypes.POINTER(sv_cloud),
                                      ctypes.POINTER(sv_results), P, ctypes.c_size_t, P]
     lib.sv_profile_enable.argtypes = [ctypes.c_int]
     lib.sv_profile_reset.argtypes = []
     lib.sv_profile_reset.restype = None
     lib.sv_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
-    for fn in ("sv_workspace_size", "sv_fk", "sv_exact_sdf", "sv_check_motions", "sv_profile_enable",
+    for fn in ("sv_workspace_size", "sv_fk", "sv_exact_sdf", "sv_nn_sdf", "sv_check_motions", "sv_profile_enable",
                "sv_profile_read"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
@@ -154,6 +165,20 @@ class DeviceCloud:
         return sv_cloud(self.n, base, base + 4 * self.n, base + 8 * self.n)
 
 
+class DeviceMLP:
+    """Flat FP32 network parameters in device memory plus their sv_mlp descriptor."""
+
+    def __init__(self, params, in_dim: int, width: int, n_hidden: int, device="cuda"):
+        if isinstance(params, torch.Tensor):
+            self.params = params.to(device=device, dtype=torch.float32).contiguous()
+        else:
+            self.params = torch.as_tensor(np.asarray(params, np.float32), device=device).contiguous()
+        self.in_dim, self.width, self.n_hidden = int(in_dim), int(width), int(n_hidden)
+
+    def desc(self) -> sv_mlp:
+        return sv_mlp(self.in_dim, self.width, self.n_hidden, self.params.data_ptr())
+
+
 class DeviceResults:
     def __init__(self, M, device="cuda"):
         self.min_dist = torch.empty(M, dtype=torch.float32, device=device)
@@ -168,10 +193,20 @@ class DeviceResults:
 
 # ------------------------------------------------------------------ entry points
 
-def sv_workspace_size(op: int, robot: sv_robot, motions: DeviceMotions, cloud: DeviceCloud, mlp=None) -> int:
+def _mlp_ref(mlp):
+    if mlp is None:
+        return None, None
+    d = mlp.desc()
+    return d, ctypes.byref(d)
+
+
+def sv_workspace_size(op: int, robot, motions: DeviceMotions, cloud: DeviceCloud, mlp=None,
+                      precision: int = SV_BF16) -> int:
     n = ctypes.c_size_t(0)
     md, cd = motions.desc(), cloud.desc()
-    _check(lib.sv_workspace_size(op, ctypes.byref(robot), mlp, ctypes.byref(md), ctypes.byref(cd), ctypes.byref(n)))
+    keep, mref = _mlp_ref(mlp)
+    rref = ctypes.byref(robot) if robot is not None else None
+    _check(lib.sv_workspace_size(op, rref, mref, int(precision), ctypes.byref(md), ctypes.byref(cd), ctypes.byref(n)))
     return int(n.value)
 
 
@@ -196,13 +231,26 @@ def sv_exact_sdf(robot: sv_robot, motions: DeviceMotions, cloud: DeviceCloud, sd
     return ws
 
 
+def sv_nn_sdf(mlp: DeviceMLP, precision: int, motions: DeviceMotions, cloud: DeviceCloud, sdf_hat: torch.Tensor,
+              ws=None, stream=None):
+    """sdf_hat[M][N] <- network prediction for every (motion, point) (device FP32)."""
+    md, cd = motions.desc(), cloud.desc()
+    keep, mref = _mlp_ref(mlp)
+    if ws is None:
+        ws = workspace(sv_workspace_size(SV_OP_NN_SDF, None, motions, cloud, mlp, precision))
+    _check(lib.sv_nn_sdf(mref, int(precision), ctypes.byref(md), ctypes.byref(cd), _ptr(sdf_hat), _ptr(ws),
+                         ws.numel(), _stream(stream)))
+    return ws
+
+
 def sv_check_motions(robot: sv_robot, motions: DeviceMotions, cloud: DeviceCloud, out: DeviceResults, eps: float,
-                     mlp=None, screen: int = 0, tau: float = 0.0, ws=None, stream=None):
-    """Per-motion min distance, argmin and verdict (exact check)."""
+                     mlp: DeviceMLP = None, screen: int = SV_SCREEN_NONE, tau: float = 0.0, ws=None, stream=None):
+    """Per-motion min distance, argmin, verdict (and fallback counts when screening)."""
     md, cd, rd = motions.desc(), cloud.desc(), out.desc()
+    keep, mref = _mlp_ref(mlp)
     if ws is None:
         ws = workspace(sv_workspace_size(SV_OP_CHECK, robot, motions, cloud, mlp))
-    _check(lib.sv_check_motions(ctypes.byref(robot), mlp, int(screen), float(eps), float(tau), ctypes.byref(md),
+    _check(lib.sv_check_motions(ctypes.byref(robot), mref, int(screen), float(eps), float(tau), ctypes.byref(md),
                                 ctypes.byref(cd), ctypes.byref(rd), _ptr(ws), ws.numel(), _stream(stream)))
     return ws
 

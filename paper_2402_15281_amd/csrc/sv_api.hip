@@ -129,34 +129,75 @@ MotionArgs to_args(const sv_motions& m) {
 }
 CloudArgs to_args(const sv_cloud& c) { return CloudArgs{(int)c.n, c.x, c.y, c.z}; }
 
-// Workspace layout of the exact check.
+int check_mlp(const sv_mlp* n, int precision, int dof) {
+  if (!n) return fail(SV_ERR_ARG, "mlp is NULL");
+  if (!n->params) return fail(SV_ERR_ARG, "mlp params is NULL");
+  if (n->in_dim < 5 || (n->in_dim - 3) % 2 != 0 || (n->in_dim - 3) / 2 > SV_MAX_DOF)
+    return fail(SV_ERR_ARG, "mlp in_dim %d is not 3 + 2*dof", n->in_dim);
+  if (dof > 0 && n->in_dim != 3 + 2 * dof)
+    return fail(SV_ERR_SHAPE, "mlp in_dim %d does not match robot dof %d", n->in_dim, dof);
+  if (n->n_hidden < 1) return fail(SV_ERR_ARG, "mlp n_hidden %d < 1", n->n_hidden);
+  if (precision == SV_FP32) {
+    if (n->width < 64 || n->width > 1024 || n->width % 64)
+      return fail(SV_ERR_UNSUPPORTED, "FP32 network width %d: need a multiple of 64 up to 1024", n->width);
+  } else if (precision == SV_BF16) {
+    if (!mlp_bf16_supported(n->width))
+      return fail(SV_ERR_UNSUPPORTED, "BF16 network width %d: need 128, 256 or 512", n->width);
+  } else {
+    return fail(SV_ERR_ARG, "unknown precision %d", precision);
+  }
+  return SV_OK;
+}
+
+MlpArgs to_args(const sv_mlp& n) { return MlpArgs{n.in_dim, n.width, n.n_hidden, (n.in_dim - 3) / 2, n.params}; }
+
+// Workspace layout of sv_check_motions.  The screening arrays are empty without a network.
 struct CheckWs {
   CapEntry* table;
   unsigned long long* keys;
-  int* list;
-  int* count;
+  int* band;          // motions in the certified band (FP64 recheck)
+  int* band_count;
   CapEntry64* table64;
   unsigned long long* keys64;
+  __bf16* packed;     // BF16 hidden-layer weights
+  int* plist;         // [M][N] points sent to the exact check
+  int* pcount;        // [M]
+  int* full;          // motions without a witness (certified mode)
+  int* full_count;
   size_t bytes;
 };
 
-CheckWs carve_check(void* ws, const sv_robot& r, const sv_motions& m) {
-  Carver c(ws);
-  CheckWs w;
+CheckWs carve_check(void* ws, const sv_robot& r, const sv_motions& m, const sv_cloud& c, const sv_mlp* mlp) {
+  Carver cv(ws);
+  CheckWs w{};
   const size_t entries = (size_t)m.n * r.n_caps * m.T;
-  w.table = c.take<CapEntry>(entries);
-  w.keys = c.take<unsigned long long>(m.n);
-  w.list = c.take<int>(m.n);
-  w.count = c.take<int>(1);
-  w.table64 = c.take<CapEntry64>(entries);
-  w.keys64 = c.take<unsigned long long>(m.n);
-  w.bytes = c.off;
+  w.table = cv.take<CapEntry>(entries);
+  w.keys = cv.take<unsigned long long>(m.n);
+  w.band = cv.take<int>(m.n);
+  w.band_count = cv.take<int>(1);
+  w.table64 = cv.take<CapEntry64>(entries);
+  w.keys64 = cv.take<unsigned long long>(m.n);
+  if (mlp) {
+    w.packed = cv.take<__bf16>(mlp_packed_elems(to_args(*mlp)));
+    w.plist = cv.take<int>((size_t)m.n * c.n);
+    w.pcount = cv.take<int>(m.n);
+    w.full = cv.take<int>(m.n);
+    w.full_count = cv.take<int>(1);
+  }
+  w.bytes = cv.off;
   return w;
 }
 
 size_t exact_sdf_bytes(const sv_robot& r, const sv_motions& m) {
   Carver c(nullptr);
   c.take<CapEntry>((size_t)m.n * r.n_caps * m.T);
+  return c.off;
+}
+
+size_t nn_sdf_bytes(const sv_mlp& n, int precision) {
+  if (precision == SV_FP32) return 0;
+  Carver c(nullptr);
+  c.take<__bf16>(mlp_packed_elems(to_args(n)));
   return c.off;
 }
 
@@ -206,15 +247,22 @@ int sv_profile_read(const char* kernel, double* total_ms, int64_t* launches) {
   return SV_OK;
 }
 
-int sv_workspace_size(int op, const sv_robot* robot, const void* mlp, const sv_motions* motions,
+int sv_workspace_size(int op, const sv_robot* robot, const sv_mlp* mlp, int precision, const sv_motions* motions,
                       const sv_cloud* cloud, size_t* bytes) {
-  (void)mlp;
   if (!bytes) return fail(SV_ERR_ARG, "bytes is NULL");
   int s;
+  if (op == SV_OP_NN_SDF) {
+    if ((s = check_mlp(mlp, precision, 0)) || (s = check_motions(motions, 0)) || (s = check_cloud(cloud))) return s;
+    *bytes = nn_sdf_bytes(*mlp, precision);
+    return SV_OK;
+  }
   if ((s = check_robot(robot)) || (s = check_motions(motions, robot->dof)) || (s = check_cloud(cloud))) return s;
   switch (op) {
     case SV_OP_EXACT_SDF: *bytes = exact_sdf_bytes(*robot, *motions); return SV_OK;
-    case SV_OP_CHECK: *bytes = carve_check(nullptr, *robot, *motions).bytes; return SV_OK;
+    case SV_OP_CHECK:
+      if (mlp && (s = check_mlp(mlp, SV_BF16, robot->dof))) return s;
+      *bytes = carve_check(nullptr, *robot, *motions, *cloud, mlp).bytes;
+      return SV_OK;
     default: return fail(SV_ERR_ARG, "unknown workspace op %d", op);
   }
 }
@@ -246,54 +294,112 @@ int sv_exact_sdf(const sv_robot* robot, const sv_motions* motions, const sv_clou
   }
   if (e != hipSuccess) return hip_fail(e, "motion table");
   ProfScope ps("exact_sdf", st);
-  e = launch_exact(*robot, table, ma, to_args(*cloud), nullptr, nullptr, motions->n, sdf, nullptr,
+  e = launch_exact(*robot, table, ma, to_args(*cloud), nullptr, nullptr, motions->n, nullptr, nullptr, sdf, nullptr,
                    default_exact_shape(), st);
   return e == hipSuccess ? SV_OK : hip_fail(e, "exact kernel");
 }
 
-int sv_check_motions(const sv_robot* robot, const void* mlp, int screen, float eps, float tau,
+int sv_nn_sdf(const sv_mlp* mlp, int precision, const sv_motions* motions, const sv_cloud* cloud, float* sdf_hat,
+              void* ws, size_t ws_bytes, void* stream) {
+  int s;
+  if ((s = check_mlp(mlp, precision, 0)) || (s = check_motions(motions, 0)) || (s = check_cloud(cloud))) return s;
+  if (motions->kind != SV_LINEAR) return fail(SV_ERR_UNSUPPORTED, "the network applies to linear motions only");
+  if (motions->n == 0 || cloud->n == 0) return SV_OK;
+  if (!sdf_hat) return fail(SV_ERR_ARG, "sdf_hat is NULL");
+  const size_t need = nn_sdf_bytes(*mlp, precision);
+  if (need && (!ws || ws_bytes < need))
+    return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", need, ws_bytes);
+  hipStream_t st = (hipStream_t)stream;
+  const MlpArgs na = to_args(*mlp);
+  hipError_t e;
+  if (precision == SV_FP32) {
+    ProfScope ps("mlp_f32", st);
+    e = launch_mlp_f32(na, to_args(*motions), to_args(*cloud), sdf_hat, st);
+    return e == hipSuccess ? SV_OK : hip_fail(e, "FP32 network");
+  }
+  __bf16* packed = static_cast<__bf16*>(ws);
+  {
+    ProfScope ps("pack_bf16", st);
+    e = launch_pack_bf16(na, packed, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "pack weights");
+  ProfScope ps("mlp_bf16", st);
+  e = launch_mlp_bf16(na, to_args(*motions), to_args(*cloud), packed, sdf_hat, 0.f, nullptr, nullptr, st);
+  return e == hipSuccess ? SV_OK : hip_fail(e, "BF16 network");
+}
+
+int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float eps, float tau,
                      const sv_motions* motions, const sv_cloud* cloud, sv_results* out, void* ws, size_t ws_bytes,
                      void* stream) {
-  (void)tau;
   int s;
   if ((s = check_robot(robot)) || (s = check_motions(motions, robot->dof)) || (s = check_cloud(cloud))) return s;
   if (!out) return fail(SV_ERR_ARG, "results is NULL");
   if (!isfinite(eps)) return fail(SV_ERR_ARG, "eps must be finite");
-  if (mlp || screen) return fail(SV_ERR_UNSUPPORTED, "network screening is not available in this call");
+  const bool screened = screen != SV_SCREEN_NONE;
+  if (screen < SV_SCREEN_NONE || screen > SV_SCREEN_CERTIFIED) return fail(SV_ERR_ARG, "unknown screen mode %d", screen);
+  if (screened != (mlp != nullptr)) return fail(SV_ERR_ARG, "a screen mode needs a network and a network a screen mode");
+  if (screened) {
+    if ((s = check_mlp(mlp, SV_BF16, robot->dof))) return s;
+    if (motions->kind != SV_LINEAR) return fail(SV_ERR_UNSUPPORTED, "the network applies to linear motions only");
+    if (isnan(tau)) return fail(SV_ERR_ARG, "tau is NaN");
+  }
   if (motions->n == 0) return SV_OK;
-  const CheckWs w0 = carve_check(nullptr, *robot, *motions);
+  const CheckWs w0 = carve_check(nullptr, *robot, *motions, *cloud, mlp);
   if (!ws || ws_bytes < w0.bytes)
     return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", w0.bytes, ws_bytes);
-  const CheckWs w = carve_check(ws, *robot, *motions);
+  const CheckWs w = carve_check(ws, *robot, *motions, *cloud, mlp);
   hipStream_t st = (hipStream_t)stream;
   const MotionArgs ma = to_args(*motions);
   const CloudArgs ca = to_args(*cloud);
+  const int64_t M = motions->n;
+  const ExactShape shape = default_exact_shape();
   hipError_t e;
-  if ((e = launch_fill_u64(w.keys, motions->n, ~0ull, st)) != hipSuccess) return hip_fail(e, "init keys");
-  if ((e = launch_fill_i32(w.count, 1, 0, st)) != hipSuccess) return hip_fail(e, "init count");
+#define SV_TRY(name, call)        \
+  do {                            \
+    ProfScope ps_(name, st);      \
+    e = (call);                   \
+  } while (0);                    \
+  if (e != hipSuccess) return hip_fail(e, name)
+
+  SV_TRY("init", launch_fill_u64(w.keys, M, ~0ull, st));
+  SV_TRY("init", launch_fill_i32(w.band_count, 1, 0, st));
+  const int* mlist = nullptr;
+  const int* mcount = nullptr;
   if (cloud->n > 0) {
-    {
-      ProfScope ps("motion_table", st);
-      e = launch_motion_table(*robot, ma, w.table, st);
+    SV_TRY("motion_table", launch_motion_table(*robot, ma, w.table, st));
+    if (!screened) {
+      SV_TRY("exact", launch_exact(*robot, w.table, ma, ca, nullptr, nullptr, M, nullptr, nullptr, nullptr, w.keys,
+                                   shape, st));
+    } else {
+      const MlpArgs na = to_args(*mlp);
+      SV_TRY("init", launch_fill_i32(w.pcount, M, 0, st));
+      SV_TRY("init", launch_fill_i32(w.full_count, 1, 0, st));
+      SV_TRY("pack_bf16", launch_pack_bf16(na, w.packed, st));
+      SV_TRY("screen", launch_mlp_bf16(na, ma, ca, w.packed, nullptr, tau, w.plist, w.pcount, st));
+      SV_TRY("fallback", launch_exact(*robot, w.table, ma, ca, nullptr, nullptr, M, w.plist, w.pcount, nullptr, w.keys,
+                                      shape, st));
+      SV_TRY("decide", launch_screen_decide(w.keys, M, w.pcount, eps, kCertBand, screen == SV_SCREEN_CERTIFIED, *out,
+                                            w.full, w.full_count, st));
+      if (screen == SV_SCREEN_CERTIFIED) {
+        SV_TRY("confirm", launch_exact(*robot, w.table, ma, ca, w.full, w.full_count, M, nullptr, nullptr, nullptr,
+                                       w.keys, shape, st));
+        mlist = w.full;
+        mcount = w.full_count;
+      }
     }
-    if (e != hipSuccess) return hip_fail(e, "motion table");
-    {
-      ProfScope ps("exact", st);
-      e = launch_exact(*robot, w.table, ma, ca, nullptr, nullptr, motions->n, nullptr, w.keys, default_exact_shape(),
-                       st);
+  } else if (screened) {
+    SV_TRY("init", launch_fill_i32(w.pcount, M, 0, st));
+    SV_TRY("init", launch_fill_i32(w.full_count, 1, 0, st));
+    SV_TRY("decide", launch_screen_decide(w.keys, M, w.pcount, eps, kCertBand, screen == SV_SCREEN_CERTIFIED, *out,
+                                          w.full, w.full_count, st));
+    if (screen == SV_SCREEN_CERTIFIED) {
+      mlist = w.full;
+      mcount = w.full_count;
     }
-    if (e != hipSuccess) return hip_fail(e, "exact kernel");
   }
-  {
-    ProfScope ps("finalize", st);
-    e = launch_finalize(w.keys, motions->n, eps, kCertBand, *out, w.list, w.count, st);
-  }
-  if (e != hipSuccess) return hip_fail(e, "finalize");
-  {
-    ProfScope ps("recheck64", st);
-    e = launch_recheck64(*robot, ma, ca, w.list, w.count, w.table64, w.keys64, eps, *out, st);
-  }
-  if (e != hipSuccess) return hip_fail(e, "fp64 recheck");
+  SV_TRY("finalize", launch_finalize(w.keys, M, mlist, mcount, eps, kCertBand, *out, w.band, w.band_count, st));
+  SV_TRY("recheck64", launch_recheck64(*robot, ma, ca, w.band, w.band_count, w.table64, w.keys64, eps, *out, st));
+#undef SV_TRY
   return SV_OK;
 }
 

@@ -205,23 +205,31 @@ __device__ __forceinline__ float seg_d2(const CapEntry& e, float x, float y, flo
 // grid: one block per (motion slot, tile of NT*P points), tile fastest.
 // Lanes own points base + p*NT + tid.  For every capsule k: running min over t of
 // the squared distance, then sqrt - r; the point's distance is the min over k.
+// With a point list, lane slot j of motion m stands for point plist[m * N + j],
+// j < pcount[m], and tiles beyond the list exit at once.
 template <int P, int NT>
 __global__ __launch_bounds__(NT) void k_exact(const CapEntry* __restrict__ table, int T, int K,
                                               const float* __restrict__ px, const float* __restrict__ py,
                                               const float* __restrict__ pz, int N, int tiles,
                                               const int* __restrict__ mlist, const int* __restrict__ mcount,
+                                              const int* __restrict__ plist, const int* __restrict__ pcount,
                                               float* __restrict__ sdf, unsigned long long* __restrict__ keys) {
   const int slot = blockIdx.x / tiles;
   const int tile = blockIdx.x - slot * tiles;
   if (mcount && slot >= *mcount) return;
   const int m = mlist ? mlist[slot] : slot;
+  const int n_here = pcount ? pcount[m] : N;
+  if (tile * (NT * P) >= n_here) return;
   const int base = tile * (NT * P) + threadIdx.x;
 
   float x[P], y[P], z[P], best[P];
+  int idx[P];
 #pragma unroll
   for (int p = 0; p < P; ++p) {
-    const int i = base + p * NT;
-    const bool ok = i < N;
+    const int j = base + p * NT;
+    const bool ok = j < n_here;
+    const int i = ok ? (plist ? plist[(size_t)m * N + j] : j) : -1;
+    idx[p] = i;
     x[p] = ok ? px[i] : 0.f;
     y[p] = ok ? py[i] : 0.f;
     z[p] = ok ? pz[i] : 0.f;
@@ -257,16 +265,16 @@ __global__ __launch_bounds__(NT) void k_exact(const CapEntry* __restrict__ table
   if (sdf) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      const int i = base + p * NT;
-      if (i < N) sdf[(size_t)m * N + i] = best[p];
+      const int i = idx[p];
+      if (i >= 0) sdf[(size_t)m * N + i] = best[p];
     }
   }
   if (keys) {
     unsigned long long key = kKeyEmpty;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      const int i = base + p * NT;
-      if (i < N) {
+      const int i = idx[p];
+      if (i >= 0) {
         const unsigned long long kk = ((unsigned long long)ord_f32(best[p]) << 32) | (uint32_t)i;
         key = kk < key ? kk : key;
       }
@@ -298,24 +306,53 @@ __global__ void k_fill_i32(int* __restrict__ p, int64_t n, int v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_finalize(const unsigned long long* __restrict__ keys, int64_t M, float eps, float band,
-                           sv_results out, int* __restrict__ list, int* __restrict__ count) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
-  const unsigned long long key = keys[m];
-  float d;
-  int arg;
+__device__ __forceinline__ void decode_key(unsigned long long key, float* d, int* arg) {
   if (key == kKeyEmpty) {
-    d = INFINITY;
-    arg = -1;
+    *d = INFINITY;
+    *arg = -1;
   } else {
-    d = unord_f32((uint32_t)(key >> 32));
-    arg = (int)(uint32_t)(key & 0xffffffffu);
+    *d = unord_f32((uint32_t)(key >> 32));
+    *arg = (int)(uint32_t)(key & 0xffffffffu);
   }
+}
+
+__device__ __forceinline__ void write_result(const sv_results& out, int64_t m, float d, int arg, float eps) {
   if (out.min_dist) out.min_dist[m] = d;
   if (out.argmin) out.argmin[m] = arg;
   if (out.verdict) out.verdict[m] = (uint8_t)(d <= eps);
-  if (list && fabsf(d - eps) <= band) list[atomicAdd(count, 1)] = (int)m;
+}
+
+// Grid-stride over the motions of (mlist, mcount), or all M.
+__global__ void k_finalize(const unsigned long long* __restrict__ keys, int64_t M, const int* __restrict__ mlist,
+                           const int* __restrict__ mcount, float eps, float band, sv_results out,
+                           int* __restrict__ list, int* __restrict__ count) {
+  const int64_t n = mcount ? (int64_t)*mcount : M;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = mlist ? mlist[s] : s;
+    float d;
+    int arg;
+    decode_key(keys[m], &d, &arg);
+    write_result(out, m, d, arg, eps);
+    if (list && fabsf(d - eps) <= band) list[atomicAdd(count, 1)] = (int)m;
+  }
+}
+
+__global__ void k_screen_decide(unsigned long long* __restrict__ keys, int64_t M, const int* __restrict__ pcount,
+                                float eps, float band, int certified, sv_results out, int* __restrict__ full,
+                                int* __restrict__ full_count) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  if (out.n_fallback) out.n_fallback[m] = pcount[m];
+  if (!certified) return;   // trust mode: the keys of the sent points are final
+  float d;
+  int arg;
+  decode_key(keys[m], &d, &arg);
+  if (d <= eps - band) {
+    write_result(out, m, d, arg, eps);
+  } else {
+    keys[m] = kKeyEmpty;
+    full[atomicAdd(full_count, 1)] = (int)m;
+  }
 }
 
 // --------------------------------------------------------- FP64 recheck
@@ -408,14 +445,14 @@ inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + thread
 
 template <int P, int NT>
 hipError_t launch_exact_t(const CapEntry* table, const MotionArgs& m, const CloudArgs& c, int K, const int* mlist,
-                          const int* mcount, int64_t n_slots, float* sdf, unsigned long long* keys,
-                          hipStream_t st) {
+                          const int* mcount, int64_t n_slots, const int* plist, const int* pcount, float* sdf,
+                          unsigned long long* keys, hipStream_t st) {
   const int tiles = (c.n + NT * P - 1) / (NT * P);
   const int64_t blocks = n_slots * tiles;
   if (blocks == 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((k_exact<P, NT>), dim3((unsigned)blocks), dim3(NT), 0, st, table, m.T, K, c.x, c.y, c.z, c.n,
-                     tiles, mlist, mcount, sdf, keys);
+                     tiles, mlist, mcount, plist, pcount, sdf, keys);
   return hipGetLastError();
 }
 
@@ -443,11 +480,12 @@ hipError_t launch_motion_table(const sv_robot& rb, const MotionArgs& m, CapEntry
 }
 
 hipError_t launch_exact(const sv_robot& rb, const CapEntry* table, const MotionArgs& m, const CloudArgs& c,
-                        const int* mlist, const int* mcount, int64_t n_slots, float* sdf, unsigned long long* keys,
-                        ExactShape s, hipStream_t st) {
+                        const int* mlist, const int* mcount, int64_t n_slots, const int* plist, const int* pcount,
+                        float* sdf, unsigned long long* keys, ExactShape s, hipStream_t st) {
   const int K = rb.n_caps;
-#define SV_EXACT_CASE(P, NT) \
-  if (s.ppl == P && s.threads == NT) return launch_exact_t<P, NT>(table, m, c, K, mlist, mcount, n_slots, sdf, keys, st);
+#define SV_EXACT_CASE(P, NT)            \
+  if (s.ppl == P && s.threads == NT)    \
+    return launch_exact_t<P, NT>(table, m, c, K, mlist, mcount, n_slots, plist, pcount, sdf, keys, st);
   SV_EXACT_CASE(1, 64) SV_EXACT_CASE(1, 128) SV_EXACT_CASE(1, 256)
   SV_EXACT_CASE(2, 64) SV_EXACT_CASE(2, 128) SV_EXACT_CASE(2, 256)
   SV_EXACT_CASE(4, 64) SV_EXACT_CASE(4, 128) SV_EXACT_CASE(4, 256)
@@ -467,10 +505,19 @@ hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const unsigned long long* keys, int64_t M, float eps, float band, sv_results out,
-                           int* list, int* count, hipStream_t st) {
+hipError_t launch_finalize(const unsigned long long* keys, int64_t M, const int* mlist, const int* mcount, float eps,
+                           float band, sv_results out, int* list, int* count, hipStream_t st) {
   if (M == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3(grid_for(M, 256)), dim3(256), 0, st, keys, M, eps, band, out, list, count);
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)std::min<int64_t>(grid_for(M, 256), 1024)), dim3(256), 0, st, keys, M,
+                     mlist, mcount, eps, band, out, list, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_screen_decide(unsigned long long* keys, int64_t M, const int* pcount, float eps, float band,
+                                int certified, sv_results out, int* full, int* full_count, hipStream_t st) {
+  if (M == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_screen_decide, dim3(grid_for(M, 256)), dim3(256), 0, st, keys, M, pcount, eps, band, certified,
+                     out, full, full_count);
   return hipGetLastError();
 }
 

@@ -49,6 +49,12 @@ struct MotionArgs {
   const float* via;
 };
 
+// Network description for kernels: flat FP32 parameters (see sv_mlp in sv.h).
+struct MlpArgs {
+  int in_dim, width, n_hidden, dof;
+  const float* params;
+};
+
 struct CloudArgs {
   int n;
   const float* x;
@@ -78,19 +84,38 @@ struct ExactShape {
 hipError_t launch_fk_configs(const sv_robot& rb, const float* q, int64_t n, float* caps, int fp64,
                              hipStream_t st);
 hipError_t launch_motion_table(const sv_robot& rb, const MotionArgs& m, CapEntry* table, hipStream_t st);
+// Exact kernel.  Motion slots: mlist/mcount (device) select motions, else slot = motion.
+// Points: plist/pcount (device, per motion: plist[m * N + j], j < pcount[m]) select
+// points, else all N points.
 hipError_t launch_exact(const sv_robot& rb, const CapEntry* table, const MotionArgs& m, const CloudArgs& c,
-                        const int* mlist, const int* mcount, int64_t n_slots, float* sdf,
-                        unsigned long long* keys, ExactShape shape, hipStream_t st);
+                        const int* mlist, const int* mcount, int64_t n_slots, const int* plist, const int* pcount,
+                        float* sdf, unsigned long long* keys, ExactShape shape, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
-// Decode FP32 keys into results; motions within `band` of eps are appended to
-// (list, count) for the FP64 recheck.
-hipError_t launch_finalize(const unsigned long long* keys, int64_t M, float eps, float band, sv_results out,
-                           int* list, int* count, hipStream_t st);
+// Decode FP32 keys into results for the motions in (mlist, mcount) (all M if mlist is
+// NULL); motions within `band` of eps are appended to (list, count) for the FP64 recheck.
+hipError_t launch_finalize(const unsigned long long* keys, int64_t M, const int* mlist, const int* mcount, float eps,
+                           float band, sv_results out, int* list, int* count, hipStream_t st);
+// Screening decision after the fallback check of the listed points: motions with a
+// witness below eps - band are final collisions; in certified mode every other motion
+// is appended to (full, full_count) with its key reset, for a check over all points;
+// in trust mode every motion is final.
+hipError_t launch_screen_decide(unsigned long long* keys, int64_t M, const int* pcount, float eps, float band,
+                                int certified, sv_results out, int* full, int* full_count, hipStream_t st);
 hipError_t launch_recheck64(const sv_robot& rb, const MotionArgs& m, const CloudArgs& c, const int* list,
                             const int* count, CapEntry64* table64, unsigned long long* keys64, float eps,
                             sv_results out, hipStream_t st);
 
 ExactShape default_exact_shape();
+
+// ---- network (sv_mlp.hip) --------------------------------------------------------
+bool mlp_bf16_supported(int width);
+size_t mlp_packed_elems(const MlpArgs& net);
+hipError_t launch_mlp_f32(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, float* out, hipStream_t st);
+hipError_t launch_pack_bf16(const MlpArgs& net, __bf16* packed, hipStream_t st);
+// out (optional): [M][N] predictions.  lists/counts (optional): per motion, the points
+// with prediction < tau are appended to lists[m * N ...] and counted in counts[m].
+hipError_t launch_mlp_bf16(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, const __bf16* packed,
+                           float* out, float tau, int* lists, int* counts, hipStream_t st);
 
 }  // namespace sv

@@ -47,11 +47,11 @@ def test_host_side_validation(b):
     m = b.sv_motions(0, 0, 4, None, None, None)                        # T = 0
     c = b.sv_cloud(0, None, None, None)
     n = ctypes.c_size_t(0)
-    assert b.lib.sv_workspace_size(1, ctypes.byref(r), None, ctypes.byref(m), ctypes.byref(c), ctypes.byref(n)) == -1
+    assert b.lib.sv_workspace_size(1, ctypes.byref(r), None, 0, ctypes.byref(m), ctypes.byref(c), ctypes.byref(n)) == -1
     m = b.sv_motions(1, 16, 4, None, None, None)                       # spline without pointers
-    assert b.lib.sv_workspace_size(1, ctypes.byref(r), None, ctypes.byref(m), ctypes.byref(c), ctypes.byref(n)) == -1
+    assert b.lib.sv_workspace_size(1, ctypes.byref(r), None, 0, ctypes.byref(m), ctypes.byref(c), ctypes.byref(n)) == -1
     m = b.sv_motions(0, 16, 4, 1, 1, None)
-    assert b.lib.sv_workspace_size(1, ctypes.byref(r), None, ctypes.byref(m), ctypes.byref(c), ctypes.byref(n)) == 0
+    assert b.lib.sv_workspace_size(1, ctypes.byref(r), None, 0, ctypes.byref(m), ctypes.byref(c), ctypes.byref(n)) == 0
     assert n.value >= 4 * 7 * 16 * (32 + 64)
 
 
@@ -65,3 +65,31 @@ def test_oracle_and_library_share_no_code():
         if src.endswith((".c", ".py", ".h")):
             t = open(src).read()
             assert "paper_2402_15281_amd" not in t and "sv_internal" not in t, src
+
+
+def test_network_validation_on_host(b):
+    arm = svgen.make_arm(1)
+    r = b.make_robot(arm)
+    m = b.sv_motions(0, 16, 4, 1, 1, None)
+    c = b.sv_cloud(100, 1, 1, 1)
+    n = ctypes.c_size_t(0)
+    net = b.sv_mlp(15, 512, 8, 1)
+    assert b.lib.sv_workspace_size(2, None, ctypes.byref(net), 1, ctypes.byref(m), ctypes.byref(c), ctypes.byref(n)) == 0
+    assert n.value == 7 * 512 * 512 * 2
+    assert b.lib.sv_workspace_size(2, None, ctypes.byref(net), 0, ctypes.byref(m), ctypes.byref(c), ctypes.byref(n)) == 0
+    assert n.value == 0
+    assert b.lib.sv_workspace_size(1, ctypes.byref(r), ctypes.byref(net), 1, ctypes.byref(m), ctypes.byref(c),
+                                   ctypes.byref(n)) == 0
+    assert n.value >= 4 * 100 * 4 + 7 * 512 * 512 * 2
+    bad = b.sv_mlp(15, 96, 8, 1)                     # BF16 needs 128/256/512
+    assert b.lib.sv_workspace_size(2, None, ctypes.byref(bad), 1, ctypes.byref(m), ctypes.byref(c),
+                                   ctypes.byref(n)) == -4
+    bad = b.sv_mlp(17, 512, 8, 1)                    # in_dim does not match dof 6
+    assert b.lib.sv_workspace_size(1, ctypes.byref(r), ctypes.byref(bad), 1, ctypes.byref(m), ctypes.byref(c),
+                                   ctypes.byref(n)) == -2
+    spline = b.sv_motions(1, 16, 4, 1, 1, 1)
+    res = b.sv_results(None, None, None, None)
+    assert b.lib.sv_check_motions(ctypes.byref(r), ctypes.byref(net), 2, 0.01, 0.03, ctypes.byref(spline),
+                                  ctypes.byref(c), ctypes.byref(res), None, 0, None) == -4
+    assert b.lib.sv_check_motions(ctypes.byref(r), None, 2, 0.01, 0.03, ctypes.byref(m),
+                                  ctypes.byref(c), ctypes.byref(res), None, 0, None) == -1

@@ -142,3 +142,35 @@ def test_screened_verdict_special_cases():
     np.testing.assert_array_equal(v_c, exact)            # certified mode is exact by construction
     v_t, _ = om.screened_verdicts(dhat, delta, 0.01, -1.0, certified=False)
     np.testing.assert_array_equal(v_t, 0)                # nothing sent: trust mode says free
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(13)
+    x = np.concatenate([rng.normal(size=5000) * 10 ** rng.uniform(-6, 3, 5000),
+                        [0.0, -0.0, 1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -9, 3.4e38]]).astype(np.float32)
+    ref = torch.tensor(x).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(om.round_bf16(x), ref)
+    # ties go to even: 1 + 2^-8 lies halfway between 1 and 1 + 2^-7
+    assert om.round_bf16(np.float32(1.0 + 2 ** -8)) == 1.0
+
+
+@pytest.mark.parametrize("n_hidden", [1, 2, 4])
+def test_bf16_emulation_matches_torch_rounding(n_hidden):
+    """The BF16-rounding forward pass against the same rounding points written with
+    torch's bfloat16 casts and FP64 torch modules."""
+    shape = (15, 64, n_hidden)
+    flat = svgen.mlp_init(svgen.MLPSpec(*shape), 14).astype(np.float64)
+    X = np.random.default_rng(15).uniform(-1, 1, (40, 15))
+    net = torch_net(flat, *shape)
+    lin = [m for m in net if isinstance(m, torch.nn.Linear)]
+    bf = lambda t: t.float().to(torch.bfloat16).to(torch.float64)
+    h = torch.tensor(X)
+    for l, mod in enumerate(lin[:-1]):
+        W = mod.weight if l == 0 else bf(mod.weight)
+        h = torch.nn.functional.softplus(h @ W.T + mod.bias, beta=1.0, threshold=1e9)
+        if l + 1 < n_hidden or n_hidden == 1:
+            h = bf(h)
+    ref = (h @ lin[-1].weight.T + lin[-1].bias)[:, 0].detach().numpy()
+    np.testing.assert_allclose(om.forward_bf16(flat, *shape, X), ref, rtol=1e-12, atol=1e-14)
+    y64, _ = om.forward(flat, *shape, X)
+    assert np.max(np.abs(om.forward_bf16(flat, *shape, X) - y64)) < 0.05   # rounding changes values a little

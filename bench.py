@@ -1,14 +1,20 @@
 #!/usr/bin/env python3
-"""Benchmark of the swept-volume collision check on one MI355X.
+"""Benchmark of swept-volume collision checking on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
 Workload "bin20k": 512 linear candidate motions of a synthetic 6-DOF arm (7
 capsules), each checked against one 20,000-point bin-picking cloud, T = 256
-samples per motion, safety margin 1 cm.  One step = one sv_check_motions call
-over the whole batch (motion sampling + FK, exact swept distances, per-motion
-reduction, verdicts, FP64 recheck of the certified band).  Inputs are resident
-in HBM before timing starts.
+samples per motion, safety margin eps = 1 cm, screening threshold tau = 3 cm,
+network 15 -> 8 x 512 softplus -> 1.
+
+One step = one sv_check_motions call over the whole batch with certified network
+screening: motion sampling + FK, the BF16 network on all 10.24M (motion, point)
+pairs, compaction of the points with prediction < tau, the exact check of those
+points, the exact check of every motion left without a witness, verdicts, and
+the FP64 recheck of the 1e-5 m band.  The plain exact checker (no network) and
+trust-mode screening are timed beside it on the same inputs.  Inputs are
+resident in HBM before timing starts.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -25,12 +31,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "motions checked/sec @20k-pt cloud: NN+fallback vs exact GPU; verdict agreement"
-PEAK_FP32_TFLOPS = 157.3          # MI355X vector FP32 (256 CUs x 2.4 GHz x 256 flop/clk, packed FMA)
+PEAK_FP32_TFLOPS = 157.3          # MI355X vector FP32: 256 CUs x 2.4 GHz x 256 flop/clk
+PEAK_BF16_TFLOPS = 2516.6         # MI355X dense BF16 MFMA: 256 CUs x 2.4 GHz x 4096 flop/clk
 FLOP_PER_SEGMENT_TEST = 21        # per (point, sample, capsule): sub 3, dot 5, scale 1, residual 6, norm 5, min 1
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def mlp_flops_per_query(in_dim, width, n_hidden):
+    return 2 * (in_dim * width + (n_hidden - 1) * width * width + width)
 
 
 def cpu_baseline(arm, motions, pts, eps, target_s, gpu_verdicts, gpu_min):
@@ -55,16 +66,36 @@ def cpu_baseline(arm, motions, pts, eps, target_s, gpu_verdicts, gpu_min):
     log(f"cpu oracle: {n} motions in {dt:.2f} s on {cores} threads; verdict agreement {agree:.4f}; "
         f"max |d_gpu - d_oracle| {err:.2e} m")
     return {"value": n / dt, "unit": "motions/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n} of the {motions.n} motions x all {pts.shape[0]} points, T={motions.T}, FP64 C "
-                      f"(gcc -O2, OpenMP over motions)",
+            "sample": f"first {n} of the {motions.n} motions x all {pts.shape[0]} points, T={motions.T}, exact "
+                      f"check in FP64 C (gcc -O2, OpenMP over motions)",
             "verdict_agreement_on_sample": agree, "max_abs_dist_err_m": err}
+
+
+def timed(sv, torch, fn, steps, warmup, kernels):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    sv.sv_profile_enable(True)
+    sv.sv_profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = {}
+    for k in kernels:
+        ms, n = sv.sv_profile_read(k)
+        per[k] = ms / max(n, 1)
+    sv.sv_profile_enable(False)
+    return (t1 - t0) * 1e3 / steps, per
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -84,53 +115,71 @@ def main():
     arm = svgen.make_arm(w["arm_seed"])
     motions = svgen.make_motions(arm, w["n_motions"], w["T"], w["motion_seed"])
     pts = svgen.bin_cloud(w["n_points"], w["cloud_seed"])
-    eps = w["eps"]
+    eps, tau = w["eps"], w["tau"]
+    in_dim, width, n_hidden = w["mlp"]
     robot = sv.make_robot(arm)
     dm, dc = sv.DeviceMotions(motions), sv.DeviceCloud(pts)
-    out = sv.DeviceResults(dm.n)
-    ws = sv.workspace(sv.sv_workspace_size(sv.SV_OP_CHECK, robot, dm, dc))
+    params = svgen.mlp_init(svgen.MLPSpec(in_dim, width, n_hidden), w["mlp_seed"])
+    weights_note = "seeded random init (untrained)"
+    mlp = sv.DeviceMLP(params, in_dim, width, n_hidden)
+    out_x, out_c, out_t = sv.DeviceResults(dm.n), sv.DeviceResults(dm.n), sv.DeviceResults(dm.n)
+    ws_x = sv.workspace(sv.sv_workspace_size(sv.SV_OP_CHECK, robot, dm, dc))
+    ws_n = sv.workspace(sv.sv_workspace_size(sv.SV_OP_CHECK, robot, dm, dc, mlp))
     torch.cuda.synchronize()
 
-    def step():
-        sv.sv_check_motions(robot, dm, dc, out, eps, ws=ws)
+    exact = lambda: sv.sv_check_motions(robot, dm, dc, out_x, eps, ws=ws_x)
+    cert = lambda: sv.sv_check_motions(robot, dm, dc, out_c, eps, mlp=mlp, screen=sv.SV_SCREEN_CERTIFIED, tau=tau,
+                                       ws=ws_n)
+    trust = lambda: sv.sv_check_motions(robot, dm, dc, out_t, eps, mlp=mlp, screen=sv.SV_SCREEN_TRUST, tau=tau,
+                                        ws=ws_n)
+    ms_x, kx = timed(sv, torch, exact, args.steps, args.warmup, ["exact"])
+    ms_t, kt = timed(sv, torch, trust, max(args.steps // 2, 1), 1, ["screen", "fallback"])
+    ms_c, kc = timed(sv, torch, cert, args.steps, args.warmup, ["screen", "fallback", "confirm"])
+    M, N = dm.n, dc.n
+    value = M / (ms_c / 1e3)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    sv.sv_profile_enable(True)
-    sv.sv_profile_reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    exact_ms, launches = sv.sv_profile_read("exact")
-    sv.sv_profile_enable(False)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = dm.n / (ms_per_step / 1e3)
-    k_ms = exact_ms / max(launches, 1)
-    flops = FLOP_PER_SEGMENT_TEST * motions.T * arm.n_caps * dm.n * dc.n
-    achieved = flops / (k_ms / 1e3) / 1e12
-    log(f"exact check: {ms_per_step:.3f} ms/step, {value:.0f} motions/s; k_exact {k_ms:.3f} ms, "
-        f"{achieved:.1f} TFLOP/s ({achieved / PEAK_FP32_TFLOPS:.1%} of FP32 vector peak)")
+    v_x = out_x.verdict.cpu().numpy()
+    v_c = out_c.verdict.cpu().numpy()
+    v_t = out_t.verdict.cpu().numpy()
+    nfb = out_c.n_fallback.cpu().numpy()
+    mind = out_x.min_dist.cpu().numpy().astype(np.float64)
 
-    verdicts = out.verdict.cpu().numpy()
-    mind = out.min_dist.cpu().numpy().astype(np.float64)
+    flop_exact = FLOP_PER_SEGMENT_TEST * motions.T * arm.n_caps * M * N
+    fx = flop_exact / (kx["exact"] / 1e3) / 1e12
+    flop_mlp = mlp_flops_per_query(in_dim, width, n_hidden) * M * N
+    fm = flop_mlp / (kc["screen"] / 1e3) / 1e12
+    log(f"exact:     {ms_x:.3f} ms/step = {M / ms_x * 1e3:.0f} motions/s; k_exact {kx['exact']:.3f} ms = "
+        f"{fx:.1f} TFLOP/s ({fx / PEAK_FP32_TFLOPS:.1%} of FP32 peak)")
+    log(f"certified: {ms_c:.3f} ms/step = {value:.0f} motions/s; network {kc['screen']:.3f} ms = {fm:.1f} TFLOP/s "
+        f"({fm / PEAK_BF16_TFLOPS:.1%} of BF16 peak); fallback {kc['fallback']:.3f} ms; confirm {kc['confirm']:.3f} ms")
+    log(f"trust:     {ms_t:.3f} ms/step; verdict agreement trust {np.mean(v_t == v_x):.4f}, "
+        f"certified {np.mean(v_c == v_x):.4f}; fallback fraction {nfb.sum() / (M * N):.4f}")
+
     result = {
         "metric": METRIC, "value": value, "unit": "motions/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "warmup": args.warmup, "ms_per_step": ms_c, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "bin20k: 512 linear motions x one 20,000-point bin cloud, T=256, 6-DOF arm with "
-                               "7 capsules, eps=0.01 m", "motions": dm.n, "points": dc.n, "T": motions.T,
-                   "capsules": arm.n_caps, "path": "exact (FP32, FP64 recheck of the 1e-5 m band)"},
-        "roofline": {"kernel": "k_exact", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel_ms": k_ms, "flop_per_launch": flops},
-        "collision_fraction": float(verdicts.mean()),
+                               "7 capsules, eps=0.01 m, tau=0.03 m, network 15->8x512 softplus->1 (BF16 MFMA, FP32 "
+                               "accumulate), certified screening with exact FP32 fallback",
+                   "motions": M, "points": N, "T": motions.T, "capsules": arm.n_caps, "network": [in_dim, width,
+                                                                                                 n_hidden],
+                   "weights": weights_note},
+        "roofline": {"kernel": "k_mlp_bf16", "bound": "mfma", "achieved": fm, "peak": PEAK_BF16_TFLOPS,
+                     "unit": "TFLOP/s", "frac": fm / PEAK_BF16_TFLOPS, "traffic": None,
+                     "kernel_ms": kc["screen"], "flop_per_launch": flop_mlp},
+        "exact_gpu": {"value": M / (ms_x / 1e3), "unit": "motions/s", "ms_per_step": ms_x, "dtype": "f32",
+                      "roofline": {"kernel": "k_exact", "bound": "alu", "achieved": fx, "peak": PEAK_FP32_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": fx / PEAK_FP32_TFLOPS, "kernel_ms": kx["exact"],
+                                   "flop_per_launch": flop_exact}},
+        "trust_screening": {"value": M / (ms_t / 1e3), "unit": "motions/s", "ms_per_step": ms_t,
+                            "verdict_agreement_vs_exact": float(np.mean(v_t == v_x))},
+        "verdict_agreement_certified_vs_exact": float(np.mean(v_c == v_x)),
+        "fallback_fraction": float(nfb.sum() / (M * N)),
+        "collision_fraction": float(v_x.mean()),
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(arm, motions, pts, eps, args.cpu_seconds, verdicts, mind)
+        result["cpu_baseline"] = cpu_baseline(arm, motions, pts, eps, args.cpu_seconds, v_x, mind)
     print(json.dumps(result), flush=True)
 
 

@@ -179,6 +179,62 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
                      const sv_motions* motions, const sv_cloud* cloud, sv_results* out, void* ws,
                      size_t ws_bytes, void* stream);
 
+/* ---- learning the network from the exact check (Sec. IV-C, Sec. V) ---------------- */
+
+/* Training rows: samples[s] = (x[3], q0[dof], q1[dof], delta), i.e. in_dim + 1 floats per
+ * row, the tuples (x, q0, q1, delta) of Sec. IV-C with delta in metres. */
+
+/* Training data generated by the exact check (Sec. IV-C: uniform coverage of the task
+ * space plus points close to the swept surface).  For every linear motion m of
+ * `motions` it writes n_uniform + n_near rows to out (dev [M * (n_uniform + n_near)]
+ * [in_dim + 1], motion-major, uniform rows first):
+ *   - uniform rows: x = cube_half * (2 u - 1) per coordinate;
+ *   - near rows: candidates are placed around the capsules of the motion's sampled
+ *     configurations (sample t, capsule k, axis position, direction on the unit sphere
+ *     and a radial offset in [-band, band] from the capsule surface, all from rnd);
+ *     each motion keeps, in candidate order, the first n_near candidates whose exact
+ *     distance satisfies |delta| <= band; if fewer qualify, the remaining slots take the
+ *     first non-qualifying candidates and *n_short (dev int, accumulated, may be NULL)
+ *     counts them.
+ * delta is the exact FP32 swept distance at motions->T samples (as sv_exact_sdf).
+ * rnd: dev [M][3 n_uniform + 6 n_cand] numbers in [0, 1) from the caller's generator.
+ * Workspace: sv_make_samples_workspace_size. */
+int sv_make_samples(const sv_robot* robot, const sv_motions* motions, float cube_half, int32_t n_uniform,
+                    int32_t n_near, int32_t n_cand, float band, const float* rnd, float* out, int32_t* n_short,
+                    void* ws, size_t ws_bytes, void* stream);
+int sv_make_samples_workspace_size(const sv_robot* robot, const sv_motions* motions, int32_t n_uniform,
+                                   int32_t n_cand, size_t* bytes);
+
+/* Network prediction for arbitrary rows (x, q0, q1, ...): out[s] = f_theta(rows[s][0:in_dim]),
+ * rows dev with row_stride floats per row (>= in_dim).  Workspace: SV_OP_NN_SDF sizes
+ * (motions and cloud unused: pass any valid ones) -- 0 bytes for SV_FP32. */
+int sv_nn_predict(const sv_mlp* mlp, int precision, const float* rows, int64_t row_stride, int64_t n, float* out,
+                  void* ws, size_t ws_bytes, void* stream);
+
+typedef struct {
+  float lr;            /* Adam step size (PyTorch default 1e-3, as used in Sec. V) */
+  float beta1, beta2;  /* Adam moment decays (0.9, 0.999) */
+  float adam_eps;      /* 1e-8 */
+  int64_t step;        /* 1-based index of this update, for Adam's bias correction */
+  float clamp_sigma;   /* loss = mean |y - clamp(delta, -s, s)|: an L1 on distances clamped to s
+                          (the prediction itself is not clamped, so it always has a gradient) */
+} sv_train_hparams;
+
+/* One training step of the BF16 network (mlp->width 128, 256 or 512): forward pass of
+ * the batch rows samples[batch_idx[i]], i < batch, clamped-L1 loss, backward pass,
+ * Adam update.  mlp->params holds the FP32 master weights and is updated in place
+ * (it must point to writable device memory); adam_m, adam_v: dev [n_params] FP32
+ * Adam moments (zero before the first step).  Hidden layers run in BF16 on MFMA
+ * with FP32 accumulation; gradient reductions are in fixed order, so a step is
+ * bitwise reproducible.
+ * loss_out: dev [1], the batch loss before the update (may be NULL).
+ * grad_out: dev [n_params], the batch gradient (may be NULL).
+ * Workspace: sv_train_workspace_size. */
+int sv_train_step(const sv_mlp* mlp, float* adam_m, float* adam_v, const sv_train_hparams* hp,
+                  const float* samples, int64_t n_samples, const int32_t* batch_idx, int64_t batch,
+                  float* loss_out, float* grad_out, void* ws, size_t ws_bytes, void* stream);
+int sv_train_workspace_size(const sv_mlp* mlp, int64_t batch, size_t* bytes);
+
 /* ---- measurement support (not part of the method) --------------------------------
  * When enabled, every later call records a HIP event pair on its stream around each
  * of its kernel groups ("motion_table", "exact", "exact_sdf", "finalize",

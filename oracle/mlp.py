@@ -82,24 +82,36 @@ def forward(flat, in_dim, width, n_hidden, H0):
 
 
 def clamped_l1(pred, target, sigma):
-    """L = mean |clamp(pred, -s, s) - clamp(target, -s, s)|."""
-    return float(np.mean(np.abs(np.clip(pred, -sigma, sigma) - np.clip(target, -sigma, sigma))))
+    """L = mean |pred - clamp(target, -s, s)|: an L1 loss on distances clamped to s.
+
+    Only the target is clamped.  Clamping the prediction as well would give every
+    prediction outside [-s, s] a zero gradient; Adam's first updates move the output
+    of a wide network by more than s, after which such a network stops learning.
+    """
+    return float(np.mean(np.abs(pred - np.clip(target, -sigma, sigma))))
 
 
-def loss_and_grad(flat, in_dim, width, n_hidden, H0, target, sigma):
-    """Clamped-L1 loss and its gradient w.r.t. the flat parameter vector (backprop).
+def loss_and_grad(flat, in_dim, width, n_hidden, H0, target, sigma, decide=None):
+    """Clamped-L1 loss (see clamped_l1) and its gradient w.r.t. the flat parameter
+    vector, by backpropagation.
 
-    dL/dpred = sign(clamp(pred) - clamp(target)) * [|pred| < sigma] / B, sign(0) = 0.
+    dL/dpred = sign(pred - clamp(target)) / B, sign(0) = 0.
     Through a softplus layer: dz = dh * sigmoid(z); dW = dz^T h_prev; db = sum dz;
     dh_prev = dz W.
+
+    The loss is not smooth: the sign is a decision taken on the prediction.
+    `decide` (optional, [B]) supplies the predictions it is taken on -- e.g. those
+    of the BF16 rounding points, to compare with a BF16 implementation in its own
+    precision; by default it is taken on y itself.
     """
     layers = unpack(flat, in_dim, width, n_hidden)
     y, (zs, hs) = forward(flat, in_dim, width, n_hidden, H0)
     B = y.shape[0]
     target = np.asarray(target, np.float64)
-    r = np.clip(y, -sigma, sigma) - np.clip(target, -sigma, sigma)
-    loss = float(np.mean(np.abs(r)))
-    dy = np.sign(r) * (np.abs(y) < sigma) / B
+    tc = np.clip(target, -sigma, sigma)
+    loss = float(np.mean(np.abs(y - tc)))
+    yd = y if decide is None else np.asarray(decide, np.float64)
+    dy = np.sign(yd - tc) / B
     grads = [None] * len(layers)
     W, b = layers[-1]
     grads[-1] = (dy[None, :] @ hs[-1], np.array([dy.sum()]))

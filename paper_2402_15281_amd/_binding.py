@@ -56,6 +56,11 @@ class sv_mlp(ctypes.Structure):
                 ("params", ctypes.c_void_p)]
 
 
+class sv_train_hparams(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("adam_eps", ctypes.c_float), ("step", ctypes.c_int64), ("clamp_sigma", ctypes.c_float)]
+
+
 class sv_results(ctypes.Structure):
     _fields_ = [("min_dist", ctypes.c_void_p), ("argmin", ctypes.c_void_p), ("verdict", ctypes.c_void_p),
                 ("n_fallback", ctypes.c_void_p)]
@@ -85,8 +90,18 @@ def _load():
     lib.sv_profile_reset.argtypes = []
     lib.sv_profile_reset.restype = None
     lib.sv_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    I32, I64, F32, SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.POINTER(ctypes.c_size_t)
+    lib.sv_make_samples.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_motions), F32, I32, I32, I32, F32, P,
+                                    P, P, P, ctypes.c_size_t, P]
+    lib.sv_make_samples_workspace_size.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_motions), I32, I32,
+                                                   SZ]
+    lib.sv_nn_predict.argtypes = [ctypes.POINTER(sv_mlp), ctypes.c_int, P, I64, I64, P, P, ctypes.c_size_t, P]
+    lib.sv_train_step.argtypes = [ctypes.POINTER(sv_mlp), P, P, ctypes.POINTER(sv_train_hparams), P, I64, P, I64, P,
+                                  P, P, ctypes.c_size_t, P]
+    lib.sv_train_workspace_size.argtypes = [ctypes.POINTER(sv_mlp), I64, SZ]
     for fn in ("sv_workspace_size", "sv_fk", "sv_exact_sdf", "sv_nn_sdf", "sv_check_motions", "sv_profile_enable",
-               "sv_profile_read"):
+               "sv_profile_read", "sv_make_samples", "sv_make_samples_workspace_size", "sv_nn_predict",
+               "sv_train_step", "sv_train_workspace_size"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -268,3 +283,53 @@ def sv_profile_read(kernel: str):
     ms, n = ctypes.c_double(0), ctypes.c_int64(0)
     _check(lib.sv_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
     return float(ms.value), int(n.value)
+
+
+def sv_make_samples(robot: sv_robot, motions: DeviceMotions, cube_half: float, n_uniform: int, n_near: int,
+                    n_cand: int, band: float, rnd: torch.Tensor, out: torch.Tensor, n_short: torch.Tensor = None,
+                    ws=None, stream=None):
+    """out[M*(n_uniform+n_near)][in_dim+1] <- training rows (x, q0, q1, delta) labelled by the exact check."""
+    md = motions.desc()
+    if ws is None:
+        n = ctypes.c_size_t(0)
+        _check(lib.sv_make_samples_workspace_size(ctypes.byref(robot), ctypes.byref(md), int(n_uniform), int(n_cand),
+                                                  ctypes.byref(n)))
+        ws = workspace(n.value)
+    _check(lib.sv_make_samples(ctypes.byref(robot), ctypes.byref(md), float(cube_half), int(n_uniform), int(n_near),
+                               int(n_cand), float(band), _ptr(rnd), _ptr(out), _ptr(n_short), _ptr(ws), ws.numel(),
+                               _stream(stream)))
+    return ws
+
+
+def sv_nn_predict(mlp: DeviceMLP, precision: int, rows: torch.Tensor, out: torch.Tensor, ws=None, stream=None):
+    """out[n] <- network prediction for rows[n][stride] (first in_dim columns)."""
+    d = mlp.desc()
+    n, stride = int(rows.shape[0]), int(rows.shape[1])
+    if ws is None:
+        ws = workspace(0 if precision == SV_FP32 else 2 * mlp.width * mlp.width * (mlp.n_hidden - 1))
+    _check(lib.sv_nn_predict(ctypes.byref(d), int(precision), _ptr(rows), stride, n, _ptr(out), _ptr(ws), ws.numel(),
+                             _stream(stream)))
+    return ws
+
+
+def sv_train_workspace_size(mlp: DeviceMLP, batch: int) -> int:
+    d = mlp.desc()
+    n = ctypes.c_size_t(0)
+    _check(lib.sv_train_workspace_size(ctypes.byref(d), int(batch), ctypes.byref(n)))
+    return int(n.value)
+
+
+def sv_train_step(mlp: DeviceMLP, adam_m: torch.Tensor, adam_v: torch.Tensor, step: int, samples: torch.Tensor,
+                  batch_idx: torch.Tensor, lr: float = 1e-3, betas=(0.9, 0.999), adam_eps: float = 1e-8,
+                  clamp_sigma: float = 0.1, loss_out: torch.Tensor = None, grad_out: torch.Tensor = None, ws=None,
+                  stream=None):
+    """One Adam step of the BF16 network on samples[batch_idx]; mlp.params is updated in place."""
+    d = mlp.desc()
+    hp = sv_train_hparams(float(lr), float(betas[0]), float(betas[1]), float(adam_eps), int(step), float(clamp_sigma))
+    B = int(batch_idx.shape[0])
+    if ws is None:
+        ws = workspace(sv_train_workspace_size(mlp, B))
+    _check(lib.sv_train_step(ctypes.byref(d), _ptr(adam_m), _ptr(adam_v), ctypes.byref(hp), _ptr(samples),
+                             int(samples.shape[0]), _ptr(batch_idx), B, _ptr(loss_out), _ptr(grad_out), _ptr(ws),
+                             ws.numel(), _stream(stream)))
+    return ws

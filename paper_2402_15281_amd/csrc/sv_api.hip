@@ -320,7 +320,7 @@ int sv_nn_sdf(const sv_mlp* mlp, int precision, const sv_motions* motions, const
   __bf16* packed = static_cast<__bf16*>(ws);
   {
     ProfScope ps("pack_bf16", st);
-    e = launch_pack_bf16(na, packed, st);
+    e = launch_pack_bf16(na, 0, packed, st);
   }
   if (e != hipSuccess) return hip_fail(e, "pack weights");
   ProfScope ps("mlp_bf16", st);
@@ -374,7 +374,7 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
       const MlpArgs na = to_args(*mlp);
       SV_TRY("init", launch_fill_i32(w.pcount, M, 0, st));
       SV_TRY("init", launch_fill_i32(w.full_count, 1, 0, st));
-      SV_TRY("pack_bf16", launch_pack_bf16(na, w.packed, st));
+      SV_TRY("pack_bf16", launch_pack_bf16(na, 0, w.packed, st));
       SV_TRY("screen", launch_mlp_bf16(na, ma, ca, w.packed, nullptr, tau, w.plist, w.pcount, st));
       SV_TRY("fallback", launch_exact(*robot, w.table, ma, ca, nullptr, nullptr, M, w.plist, w.pcount, nullptr, w.keys,
                                       shape, st));
@@ -401,6 +401,174 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
   SV_TRY("recheck64", launch_recheck64(*robot, ma, ca, w.band, w.band_count, w.table64, w.keys64, eps, *out, st));
 #undef SV_TRY
   return SV_OK;
+}
+
+// ---- training data, row prediction, training step --------------------------------
+
+namespace {
+struct SamplesWs {
+  CapEntry* table;
+  float *ux, *uy, *uz, *ud, *cx, *cy, *cz, *cd;
+  size_t bytes;
+};
+SamplesWs carve_samples(void* ws, const sv_robot& r, const sv_motions& m, int nu, int nc) {
+  Carver cv(ws);
+  SamplesWs w{};
+  w.table = cv.take<CapEntry>((size_t)m.n * r.n_caps * m.T);
+  const size_t U = (size_t)m.n * nu, C = (size_t)m.n * nc;
+  w.ux = cv.take<float>(U);
+  w.uy = cv.take<float>(U);
+  w.uz = cv.take<float>(U);
+  w.ud = cv.take<float>(U);
+  w.cx = cv.take<float>(C);
+  w.cy = cv.take<float>(C);
+  w.cz = cv.take<float>(C);
+  w.cd = cv.take<float>(C);
+  w.bytes = cv.off;
+  return w;
+}
+
+struct TrainWs {
+  __bf16 *packed, *packedT, *aT, *dzT;
+  float *h0T, *y, *dy, *grad, *part_w, *part_w1;
+  size_t bytes;
+};
+size_t n_params(const sv_mlp& n) {
+  const size_t W = n.width;
+  return W * n.in_dim + W + (size_t)(n.n_hidden - 1) * (W * W + W) + W + 1;
+}
+TrainWs carve_train(void* ws, const sv_mlp& mlp, int64_t B) {
+  const MlpArgs na = to_args(mlp);
+  const int64_t Bp = train_rows_padded(B);
+  const size_t W = mlp.width, L = mlp.n_hidden;
+  Carver cv(ws);
+  TrainWs w{};
+  w.packed = cv.take<__bf16>(mlp_packed_elems(na));
+  w.packedT = cv.take<__bf16>(mlp_packed_elems(na));
+  w.aT = cv.take<__bf16>(L * W * Bp);
+  w.dzT = cv.take<__bf16>(L * W * Bp);
+  w.h0T = cv.take<float>((size_t)mlp.in_dim * Bp);
+  w.y = cv.take<float>(Bp);
+  w.dy = cv.take<float>(Bp);
+  w.grad = cv.take<float>(n_params(mlp));
+  w.part_w = cv.take<float>(train_part_w_elems(na));
+  w.part_w1 = cv.take<float>(train_part_w1_elems(na, Bp));
+  w.bytes = cv.off;
+  return w;
+}
+}  // namespace
+
+int sv_make_samples_workspace_size(const sv_robot* robot, const sv_motions* motions, int32_t n_uniform,
+                                   int32_t n_cand, size_t* bytes) {
+  int s;
+  if (!bytes) return fail(SV_ERR_ARG, "bytes is NULL");
+  if ((s = check_robot(robot)) || (s = check_motions(motions, robot->dof))) return s;
+  if (n_uniform < 0 || n_cand < 0) return fail(SV_ERR_ARG, "negative sample counts");
+  *bytes = carve_samples(nullptr, *robot, *motions, n_uniform, n_cand).bytes;
+  return SV_OK;
+}
+
+int sv_make_samples(const sv_robot* robot, const sv_motions* motions, float cube_half, int32_t n_uniform,
+                    int32_t n_near, int32_t n_cand, float band, const float* rnd, float* out, int32_t* n_short,
+                    void* ws, size_t ws_bytes, void* stream) {
+  int s;
+  if ((s = check_robot(robot)) || (s = check_motions(motions, robot->dof))) return s;
+  if (motions->kind != SV_LINEAR) return fail(SV_ERR_UNSUPPORTED, "training samples are drawn for linear motions");
+  if (n_uniform < 0 || n_near < 0 || n_cand < n_near)
+    return fail(SV_ERR_ARG, "need n_uniform >= 0, n_near >= 0 and n_cand >= n_near");
+  if (!(cube_half > 0.f) || !(band >= 0.f)) return fail(SV_ERR_ARG, "cube_half must be > 0 and band >= 0");
+  if (motions->n * (int64_t)std::max(n_uniform, n_cand) > 0x7fffffffLL)
+    return fail(SV_ERR_SHAPE, "too many points for one call; split the motions");
+  if (motions->n == 0 || (n_uniform == 0 && n_near == 0)) return SV_OK;
+  if (!rnd || !out) return fail(SV_ERR_ARG, "rnd or out is NULL");
+  const SamplesWs w0 = carve_samples(nullptr, *robot, *motions, n_uniform, n_cand);
+  if (!ws || ws_bytes < w0.bytes) return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", w0.bytes, ws_bytes);
+  const SamplesWs w = carve_samples(ws, *robot, *motions, n_uniform, n_cand);
+  hipStream_t st = (hipStream_t)stream;
+  const MotionArgs ma = to_args(*motions);
+  hipError_t e;
+  {
+    ProfScope ps("motion_table", st);
+    e = launch_motion_table(*robot, ma, w.table, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "motion table");
+  ProfScope ps("make_samples", st);
+  e = launch_make_samples(*robot, ma, w.table, cube_half, n_uniform, n_near, n_cand, band, rnd, w.ux, w.uy, w.uz, w.ud,
+                          w.cx, w.cy, w.cz, w.cd, out, n_short, st);
+  return e == hipSuccess ? SV_OK : hip_fail(e, "make samples");
+}
+
+int sv_nn_predict(const sv_mlp* mlp, int precision, const float* rows, int64_t row_stride, int64_t n, float* out,
+                  void* ws, size_t ws_bytes, void* stream) {
+  int s;
+  if ((s = check_mlp(mlp, precision, 0))) return s;
+  if (n < 0 || n > 0x7fffffffLL) return fail(SV_ERR_SHAPE, "row count %lld outside 0..2^31-1", (long long)n);
+  if (row_stride < mlp->in_dim) return fail(SV_ERR_ARG, "row_stride %lld < in_dim", (long long)row_stride);
+  if (n == 0) return SV_OK;
+  if (!rows || !out) return fail(SV_ERR_ARG, "rows or out is NULL");
+  const size_t need = nn_sdf_bytes(*mlp, precision);
+  if (need && (!ws || ws_bytes < need))
+    return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", need, ws_bytes);
+  hipStream_t st = (hipStream_t)stream;
+  const MlpArgs na = to_args(*mlp);
+  hipError_t e = hipSuccess;
+  __bf16* packed = static_cast<__bf16*>(ws);
+  if (precision == SV_BF16) {
+    ProfScope ps("pack_bf16", st);
+    e = launch_pack_bf16(na, 0, packed, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "pack weights");
+  ProfScope ps("mlp_rows", st);
+  e = launch_mlp_rows(na, precision == SV_BF16, packed, rows, row_stride, n, out, st);
+  return e == hipSuccess ? SV_OK : hip_fail(e, "network rows");
+}
+
+int sv_train_workspace_size(const sv_mlp* mlp, int64_t batch, size_t* bytes) {
+  int s;
+  if (!bytes) return fail(SV_ERR_ARG, "bytes is NULL");
+  if ((s = check_mlp(mlp, SV_BF16, 0))) return s;
+  if (batch < 1 || batch > (1 << 24)) return fail(SV_ERR_SHAPE, "batch %lld outside 1..2^24", (long long)batch);
+  *bytes = carve_train(nullptr, *mlp, batch).bytes;
+  return SV_OK;
+}
+
+int sv_train_step(const sv_mlp* mlp, float* adam_m, float* adam_v, const sv_train_hparams* hp, const float* samples,
+                  int64_t n_samples, const int32_t* batch_idx, int64_t batch, float* loss_out, float* grad_out,
+                  void* ws, size_t ws_bytes, void* stream) {
+  int s;
+  if ((s = check_mlp(mlp, SV_BF16, 0))) return s;
+  if (!hp) return fail(SV_ERR_ARG, "hparams is NULL");
+  if (hp->step < 1) return fail(SV_ERR_ARG, "Adam step must be >= 1");
+  if (!(hp->clamp_sigma > 0.f) || !(hp->lr >= 0.f) || !(hp->beta1 >= 0.f && hp->beta1 < 1.f) ||
+      !(hp->beta2 >= 0.f && hp->beta2 < 1.f) || !(hp->adam_eps > 0.f))
+    return fail(SV_ERR_ARG, "hyper-parameter out of range");
+  if (batch < 1 || batch > (1 << 24)) return fail(SV_ERR_SHAPE, "batch %lld outside 1..2^24", (long long)batch);
+  if (n_samples < 1) return fail(SV_ERR_SHAPE, "no samples");
+  if (!adam_m || !adam_v || !samples || !batch_idx) return fail(SV_ERR_ARG, "NULL device pointer");
+  const TrainWs w0 = carve_train(nullptr, *mlp, batch);
+  if (!ws || ws_bytes < w0.bytes) return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", w0.bytes, ws_bytes);
+  const TrainWs w = carve_train(ws, *mlp, batch);
+  hipStream_t st = (hipStream_t)stream;
+  const MlpArgs na = to_args(*mlp);
+  float* grad = grad_out ? grad_out : w.grad;
+  const int64_t Bp = train_rows_padded(batch);
+  hipError_t e;
+  {
+    ProfScope ps("pack_bf16", st);
+    e = launch_pack_bf16(na, 0, w.packed, st);
+    if (e == hipSuccess) e = launch_pack_bf16(na, 1, w.packedT, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "pack weights");
+  {
+    ProfScope ps("train_grad", st);
+    e = launch_train_step(na, samples, batch_idx, (int)batch, (int)Bp, w.aT, w.dzT, w.h0T, w.y, w.dy, w.packed,
+                          w.packedT, grad, w.part_w, w.part_w1, hp->clamp_sigma, loss_out, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "train step");
+  ProfScope ps("adam", st);
+  e = launch_adam(const_cast<float*>(mlp->params), adam_m, adam_v, grad, (int64_t)n_params(*mlp), hp->lr, hp->beta1,
+                  hp->beta2, hp->adam_eps, hp->step, st);
+  return e == hipSuccess ? SV_OK : hip_fail(e, "adam");
 }
 
 }  // extern "C"

@@ -206,19 +206,20 @@ __device__ __forceinline__ float seg_d2(const CapEntry& e, float x, float y, flo
 // Lanes own points base + p*NT + tid.  For every capsule k: running min over t of
 // the squared distance, then sqrt - r; the point's distance is the min over k.
 // With a point list, lane slot j of motion m stands for point plist[m * N + j],
-// j < pcount[m], and tiles beyond the list exit at once.
+// j < pcount[m], and tiles beyond the list exit at once.  With seg > 0 motion m owns
+// the points m * seg .. m * seg + seg - 1 (and sdf is indexed by point).
 template <int P, int NT>
 __global__ __launch_bounds__(NT) void k_exact(const CapEntry* __restrict__ table, int T, int K,
                                               const float* __restrict__ px, const float* __restrict__ py,
                                               const float* __restrict__ pz, int N, int tiles,
                                               const int* __restrict__ mlist, const int* __restrict__ mcount,
-                                              const int* __restrict__ plist, const int* __restrict__ pcount,
+                                              const int* __restrict__ plist, const int* __restrict__ pcount, int seg,
                                               float* __restrict__ sdf, unsigned long long* __restrict__ keys) {
   const int slot = blockIdx.x / tiles;
   const int tile = blockIdx.x - slot * tiles;
   if (mcount && slot >= *mcount) return;
   const int m = mlist ? mlist[slot] : slot;
-  const int n_here = pcount ? pcount[m] : N;
+  const int n_here = pcount ? pcount[m] : (seg ? seg : N);
   if (tile * (NT * P) >= n_here) return;
   const int base = tile * (NT * P) + threadIdx.x;
 
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(NT) void k_exact(const CapEntry* __restrict__ table
   for (int p = 0; p < P; ++p) {
     const int j = base + p * NT;
     const bool ok = j < n_here;
-    const int i = ok ? (plist ? plist[(size_t)m * N + j] : j) : -1;
+    const int i = ok ? (plist ? plist[(size_t)m * N + j] : (seg ? m * seg + j : j)) : -1;
     idx[p] = i;
     x[p] = ok ? px[i] : 0.f;
     y[p] = ok ? py[i] : 0.f;
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(NT) void k_exact(const CapEntry* __restrict__ table
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const int i = idx[p];
-      if (i >= 0) sdf[(size_t)m * N + i] = best[p];
+      if (i >= 0) sdf[seg ? (size_t)i : (size_t)m * N + i] = best[p];
     }
   }
   if (keys) {
@@ -445,15 +446,121 @@ inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + thread
 
 template <int P, int NT>
 hipError_t launch_exact_t(const CapEntry* table, const MotionArgs& m, const CloudArgs& c, int K, const int* mlist,
-                          const int* mcount, int64_t n_slots, const int* plist, const int* pcount, float* sdf,
-                          unsigned long long* keys, hipStream_t st) {
-  const int tiles = (c.n + NT * P - 1) / (NT * P);
+                          const int* mcount, int64_t n_slots, const int* plist, const int* pcount, int seg,
+                          float* sdf, unsigned long long* keys, hipStream_t st) {
+  const int per_motion = seg ? seg : c.n;
+  const int tiles = (per_motion + NT * P - 1) / (NT * P);
   const int64_t blocks = n_slots * tiles;
   if (blocks == 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((k_exact<P, NT>), dim3((unsigned)blocks), dim3(NT), 0, st, table, m.T, K, c.x, c.y, c.z, c.n,
-                     tiles, mlist, mcount, plist, pcount, sdf, keys);
+                     tiles, mlist, mcount, plist, pcount, seg, sdf, keys);
   return hipGetLastError();
+}
+
+hipError_t launch_exact_any(const sv_robot& rb, const CapEntry* table, const MotionArgs& m, const CloudArgs& c,
+                            const int* mlist, const int* mcount, int64_t n_slots, const int* plist, const int* pcount,
+                            int seg, float* sdf, unsigned long long* keys, ExactShape s, hipStream_t st) {
+  const int K = rb.n_caps;
+#define SV_EXACT_CASE(P, NT)            \
+  if (s.ppl == P && s.threads == NT)    \
+    return launch_exact_t<P, NT>(table, m, c, K, mlist, mcount, n_slots, plist, pcount, seg, sdf, keys, st);
+  SV_EXACT_CASE(1, 64) SV_EXACT_CASE(1, 128) SV_EXACT_CASE(1, 256)
+  SV_EXACT_CASE(2, 64) SV_EXACT_CASE(2, 128) SV_EXACT_CASE(2, 256)
+  SV_EXACT_CASE(4, 64) SV_EXACT_CASE(4, 128) SV_EXACT_CASE(4, 256)
+#undef SV_EXACT_CASE
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------ training data
+// rnd per motion: [3 n_uniform] then [6 n_cand] numbers in [0, 1).
+__global__ void k_uniform_points(int64_t M, int nu, int stride, const float* __restrict__ rnd, float half,
+                                 float* __restrict__ x, float* __restrict__ y, float* __restrict__ z) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= M * nu) return;
+  const int64_t m = g / nu;
+  const int u = (int)(g - m * nu);
+  const float* r = rnd + m * stride + 3 * u;
+  x[g] = half * (2.f * r[0] - 1.f);
+  y[g] = half * (2.f * r[1] - 1.f);
+  z[g] = half * (2.f * r[2] - 1.f);
+}
+
+// Candidate c of motion m: sample t, capsule k, axis point A + u AB, unit direction d
+// (uniform on the sphere), position at radius r_k + o from the axis point, o in
+// [-band, band].
+__global__ void k_near_candidates(const CapEntry* __restrict__ table, int64_t M, int T, int K, int nu, int nc,
+                                  int stride, const float* __restrict__ rnd, float band, float* __restrict__ x,
+                                  float* __restrict__ y, float* __restrict__ z) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= M * nc) return;
+  const int64_t m = g / nc;
+  const int c = (int)(g - m * nc);
+  const float* r = rnd + m * stride + 3 * nu + 6 * c;
+  const int t = min((int)(r[0] * T), T - 1);
+  const int k = min((int)(r[1] * K), K - 1);
+  const CapEntry e = table[(m * K + k) * T + t];
+  const float cz = 2.f * r[3] - 1.f;
+  const float sz = sqrtf(fmaxf(0.f, 1.f - cz * cz));
+  float sphi, cphi;
+  sincosf(6.28318530717958648f * r[4], &sphi, &cphi);
+  const float rad = e.r + band * (2.f * r[5] - 1.f);
+  x[g] = e.ax + r[2] * e.bx + rad * sz * cphi;
+  y[g] = e.ay + r[2] * e.by + rad * sz * sphi;
+  z[g] = e.az + r[2] * e.bz + rad * cz;
+}
+
+__device__ __forceinline__ void write_row(float* __restrict__ row, int dof, const float* q0, const float* q1, float x,
+                                          float y, float z, float d) {
+  row[0] = x;
+  row[1] = y;
+  row[2] = z;
+  for (int j = 0; j < dof; ++j) {
+    row[3 + j] = q0[j];
+    row[3 + dof + j] = q1[j];
+  }
+  row[3 + 2 * dof] = d;
+}
+
+// One wave per motion: uniform rows, then the first n_near in-band candidates in
+// candidate order (then, if short, the first out-of-band ones).
+__global__ __launch_bounds__(256) void k_assemble_samples(int64_t M, int dof, int nu, int nn, int nc, float band,
+                                                          const float* __restrict__ q0, const float* __restrict__ q1,
+                                                          const float* __restrict__ ux, const float* __restrict__ uy,
+                                                          const float* __restrict__ uz, const float* __restrict__ ud,
+                                                          const float* __restrict__ cx, const float* __restrict__ cy,
+                                                          const float* __restrict__ cz, const float* __restrict__ cd,
+                                                          float* __restrict__ out, int* __restrict__ n_short) {
+  const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (m >= M) return;
+  const int width = 3 + 2 * dof + 1;
+  const float* mq0 = q0 + m * dof;
+  const float* mq1 = q1 + m * dof;
+  float* rows = out + (size_t)m * (nu + nn) * width;
+  for (int u = lane; u < nu; u += 64) {
+    const int64_t g = m * nu + u;
+    write_row(rows + (size_t)u * width, dof, mq0, mq1, ux[g], uy[g], uz[g], ud[g]);
+  }
+  float* near = rows + (size_t)nu * width;
+  int taken = 0;
+  for (int pass = 0; pass < 2 && taken < nn; ++pass) {
+    for (int c0 = 0; c0 < nc && taken < nn; c0 += 64) {
+      const int c = c0 + lane;
+      const int64_t g = m * nc + c;
+      bool ok = false;
+      if (c < nc) {
+        const bool in_band = fabsf(cd[g]) <= band;
+        ok = pass == 0 ? in_band : !in_band;
+      }
+      const unsigned long long mask = __ballot(ok);
+      const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+      if (ok && taken + rank < nn)
+        write_row(near + (size_t)(taken + rank) * width, dof, mq0, mq1, cx[g], cy[g], cz[g], cd[g]);
+      taken += __popcll(mask);
+    }
+    if (pass == 0 && taken < nn && lane == 0 && n_short) atomicAdd(n_short, nn - taken);
+  }
 }
 
 }  // namespace
@@ -482,15 +589,37 @@ hipError_t launch_motion_table(const sv_robot& rb, const MotionArgs& m, CapEntry
 hipError_t launch_exact(const sv_robot& rb, const CapEntry* table, const MotionArgs& m, const CloudArgs& c,
                         const int* mlist, const int* mcount, int64_t n_slots, const int* plist, const int* pcount,
                         float* sdf, unsigned long long* keys, ExactShape s, hipStream_t st) {
-  const int K = rb.n_caps;
-#define SV_EXACT_CASE(P, NT)            \
-  if (s.ppl == P && s.threads == NT)    \
-    return launch_exact_t<P, NT>(table, m, c, K, mlist, mcount, n_slots, plist, pcount, sdf, keys, st);
-  SV_EXACT_CASE(1, 64) SV_EXACT_CASE(1, 128) SV_EXACT_CASE(1, 256)
-  SV_EXACT_CASE(2, 64) SV_EXACT_CASE(2, 128) SV_EXACT_CASE(2, 256)
-  SV_EXACT_CASE(4, 64) SV_EXACT_CASE(4, 128) SV_EXACT_CASE(4, 256)
-#undef SV_EXACT_CASE
-  return hipErrorInvalidValue;
+  return launch_exact_any(rb, table, m, c, mlist, mcount, n_slots, plist, pcount, 0, sdf, keys, s, st);
+}
+
+hipError_t launch_make_samples(const sv_robot& rb, const MotionArgs& m, const CapEntry* table, float half, int nu,
+                               int nn, int nc, float band, const float* rnd, float* ux, float* uy, float* uz,
+                               float* ud, float* cx, float* cy, float* cz, float* cd, float* out, int* n_short,
+                               hipStream_t st) {
+  const int stride = 3 * nu + 6 * nc;
+  const ExactShape shape = default_exact_shape();
+  hipError_t e;
+  if (nu > 0) {
+    hipLaunchKernelGGL(k_uniform_points, dim3(grid_for(m.n * nu, 256)), dim3(256), 0, st, m.n, nu, stride, rnd, half,
+                       ux, uy, uz);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const CloudArgs cu{(int)(m.n * nu), ux, uy, uz};
+    if ((e = launch_exact_any(rb, table, m, cu, nullptr, nullptr, m.n, nullptr, nullptr, nu, ud, nullptr, shape,
+                              st)) != hipSuccess)
+      return e;
+  }
+  if (nc > 0) {
+    hipLaunchKernelGGL(k_near_candidates, dim3(grid_for(m.n * nc, 256)), dim3(256), 0, st, table, m.n, m.T, rb.n_caps,
+                       nu, nc, stride, rnd, band, cx, cy, cz);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const CloudArgs cc{(int)(m.n * nc), cx, cy, cz};
+    if ((e = launch_exact_any(rb, table, m, cc, nullptr, nullptr, m.n, nullptr, nullptr, nc, cd, nullptr, shape,
+                              st)) != hipSuccess)
+      return e;
+  }
+  hipLaunchKernelGGL(k_assemble_samples, dim3(grid_for(m.n, 4)), dim3(256), 0, st, m.n, rb.dof, nu, nn, nc, band, m.q0,
+                     m.q1, ux, uy, uz, ud, cx, cy, cz, cd, out, n_short);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st) {

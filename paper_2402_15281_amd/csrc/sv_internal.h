@@ -90,6 +90,12 @@ hipError_t launch_motion_table(const sv_robot& rb, const MotionArgs& m, CapEntry
 hipError_t launch_exact(const sv_robot& rb, const CapEntry* table, const MotionArgs& m, const CloudArgs& c,
                         const int* mlist, const int* mcount, int64_t n_slots, const int* plist, const int* pcount,
                         float* sdf, unsigned long long* keys, ExactShape shape, hipStream_t st);
+// Training rows (x, q0, q1, delta) for every motion: uniform points and near-surface
+// candidates (SoA scratch u*, c*), labelled by the exact kernel, assembled into out.
+hipError_t launch_make_samples(const sv_robot& rb, const MotionArgs& m, const CapEntry* table, float half, int nu,
+                               int nn, int nc, float band, const float* rnd, float* ux, float* uy, float* uz,
+                               float* ud, float* cx, float* cy, float* cz, float* cd, float* out, int* n_short,
+                               hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
 // Decode FP32 keys into results for the motions in (mlist, mcount) (all M if mlist is
@@ -112,7 +118,27 @@ ExactShape default_exact_shape();
 bool mlp_bf16_supported(int width);
 size_t mlp_packed_elems(const MlpArgs& net);
 hipError_t launch_mlp_f32(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, float* out, hipStream_t st);
-hipError_t launch_pack_bf16(const MlpArgs& net, __bf16* packed, hipStream_t st);
+// Hidden-layer weights (layers 2..L) to BF16 in MFMA A-operand order; transpose = 1
+// packs W_l^T (the backward pass's operand).
+hipError_t launch_pack_bf16(const MlpArgs& net, int transpose, __bf16* packed, hipStream_t st);
+// Network on n independent rows rows[i][0:in_dim] (row_stride floats apart); bf16
+// selects the BF16 kernel (packed weights required) over the FP32 one.
+hipError_t launch_mlp_rows(const MlpArgs& net, int bf16, const __bf16* packed, const float* rows, int64_t row_stride,
+                           int64_t n, float* out, hipStream_t st);
+
+// ---- training (sv_train.hip) -----------------------------------------------------
+int64_t train_rows_padded(int64_t B);
+size_t train_part_w_elems(const MlpArgs& n);
+size_t train_part_w1_elems(const MlpArgs& n, int64_t Bp);
+// Forward, loss, backward and gradient of one batch (rows idx[0..B) of samples);
+// writes the flat FP32 gradient to grad and the batch loss to loss_out (optional).
+hipError_t launch_train_step(const MlpArgs& net, const float* samples, const int* idx, int B, int Bp, __bf16* aT,
+                             __bf16* dzT, float* h0T, float* y, float* dy, const __bf16* packed,
+                             const __bf16* packedT, float* grad, float* part_w, float* part_w1, float sigma,
+                             float* loss_out, hipStream_t st);
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
+                       float eps, int64_t step, hipStream_t st);
+
 // out (optional): [M][N] predictions.  lists/counts (optional): per motion, the points
 // with prediction < tau are appended to lists[m * N ...] and counted in counts[m].
 hipError_t launch_mlp_bf16(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, const __bf16* packed,

@@ -16,23 +16,13 @@
 #include <math.h>
 
 #include "sv_internal.h"
+#include "sv_mlp_common.h"
 
 namespace sv {
 namespace {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
 // Accurate softplus for the FP32 path: max(z, 0) + log1p(exp(-|z|)).
 __device__ __forceinline__ float softplus_precise(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
-
-// Softplus for the BF16 path, whose result is rounded to BF16 (8 significant bits):
-// max(z, 0) + ln2 * log2(1 + 2^(-|z| log2 e)) with the hardware exp2/log2.
-__device__ __forceinline__ float softplus_fast(float z) {
-  const float e = __builtin_amdgcn_exp2f(-fabsf(z) * 1.44269504088896341f);
-  return fmaf(0.693147180559945309f, __builtin_amdgcn_logf(1.0f + e), fmaxf(z, 0.f));
-}
 
 // ----------------------------------------------------------------- FP32
 // Block: 256 threads, R rows (queries) of one motion.  LDS holds the current layer's
@@ -40,7 +30,10 @@ __device__ __forceinline__ float softplus_fast(float z) {
 constexpr int kF32Rows = 16;
 constexpr int kF32MaxChunks = 4;   // W <= 1024
 
+// Inputs: every (motion, point) pair of (mo, c), or with `rows` the c.n rows
+// rows[i][0:in_dim] (one motion slot, m = 0).
 __global__ __launch_bounds__(256) void k_mlp_f32(MlpArgs net, MotionArgs mo, CloudArgs c, int tiles,
+                                                 const float* __restrict__ rows, int64_t row_stride,
                                                  float* __restrict__ out) {
   extern __shared__ float hs[];    // [kF32Rows][W]
   const int W = net.width, in_dim = net.in_dim, dof = net.dof;
@@ -53,7 +46,8 @@ __global__ __launch_bounds__(256) void k_mlp_f32(MlpArgs net, MotionArgs mo, Clo
     const int r = e / in_dim, j = e - r * in_dim;
     const int i = min(r0 + r, c.n - 1);
     float v;
-    if (j < 3) v = (j == 0 ? c.x : (j == 1 ? c.y : c.z))[i];
+    if (rows) v = rows[(size_t)i * row_stride + j];
+    else if (j < 3) v = (j == 0 ? c.x : (j == 1 ? c.y : c.z))[i];
     else if (j < 3 + dof) v = mo.q0[(size_t)m * dof + (j - 3)];
     else v = mo.q1[(size_t)m * dof + (j - 3 - dof)];
     h0[r][j] = v;
@@ -126,22 +120,17 @@ __global__ __launch_bounds__(256) void k_mlp_f32(MlpArgs net, MotionArgs mo, Clo
 // Packed hidden-layer weights: for layer l (1..L-1), feature block fb (32 rows of W_l),
 // k-step ks (16 inputs): 64 lanes x 8 BF16 = the A operand of one MFMA, where lane ln
 // holds W_l[fb*32 + ln%32][ks*16 + 8*(ln/32) + e], e = 0..7.
-__global__ void k_pack_bf16(MlpArgs net, __bf16* __restrict__ packed) {
+// With `transpose`, W_l^T is packed instead (the operand of the backward pass).
+__global__ void k_pack_bf16(MlpArgs net, int transpose, __bf16* __restrict__ packed) {
   const int W = net.width;
   const int64_t per_layer = (int64_t)W * W;
   const int64_t total = per_layer * (net.n_hidden - 1);
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-    const int l = (int)(g / per_layer);               // 0-based hidden-layer index (layer l+1)
-    int64_t o = g - (int64_t)l * per_layer;
-    const int e = (int)(o & 7);
-    const int ln = (int)((o >> 3) & 63);
-    const int64_t blk = o >> 9;                        // (fb, ks) with ks fastest
-    const int ks = (int)(blk % (W / 16));
-    const int fb = (int)(blk / (W / 16));
-    const int f = fb * 32 + (ln & 31);
-    const int k = ks * 16 + 8 * (ln >> 5) + e;
+    const int l = (int)(g / per_layer);               // 0-based hidden-layer index (layer l+2 of 1..L)
+    int row, colk;
+    packed_coords(g - (int64_t)l * per_layer, W, transpose != 0, &row, &colk);
     const float* Wl = net.params + (size_t)W * net.in_dim + W + (size_t)l * (per_layer + W);
-    packed[g] = (__bf16)Wl[(size_t)f * W + k];
+    packed[g] = (__bf16)Wl[(size_t)row * W + colk];
   }
 }
 
@@ -149,35 +138,61 @@ __global__ void k_pack_bf16(MlpArgs net, __bf16* __restrict__ packed) {
 // activation buffers [64][W + 8] BF16 (the pad spreads rows over the LDS banks).
 // Wave w owns output features [64w, 64w + 64) = 2 feature blocks x 2 row blocks of
 // 32x32 MFMA tiles.
-constexpr int kBRows = 64;
-constexpr int kPad = 8;
+constexpr int kBRows = kTileRows;
+constexpr int kPad = kLdsPad;
 
+// Inputs: every (motion, point) pair of (mo, c), or with `rows` the c.n rows
+// rows[i][0:in_dim] (one motion slot, m = 0; layer 0 then runs unsplit per row).
 template <int W>
 __global__ __launch_bounds__(W) void k_mlp_bf16(MlpArgs net, MotionArgs mo, CloudArgs c, int tiles,
+                                                const float* __restrict__ rows, int64_t row_stride,
                                                 const __bf16* __restrict__ packed, float* __restrict__ out,
                                                 float tau, int* __restrict__ lists, int* __restrict__ counts) {
   constexpr int NW = W / 64;          // waves
-  constexpr int KS = W / 16;          // MFMA k-steps per layer
   constexpr int LD = W + kPad;        // LDS row stride (elements)
+  constexpr int kMaxIn = 3 + 2 * SV_MAX_DOF;
   extern __shared__ __align__(16) unsigned char smem[];
   __bf16* H0 = reinterpret_cast<__bf16*>(smem);
   __bf16* H1 = H0 + kBRows * LD;
   __shared__ float part[NW][kBRows];
   __shared__ float xyz[3][kBRows];
+  __shared__ float h0s[kBRows][kMaxIn];
 
   const int m = blockIdx.x / tiles;
   const int tile = blockIdx.x - m * tiles;
   const int r0 = tile * kBRows;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int dof = net.dof;
-  if (tid < kBRows) {
+  if (rows) {
+    // Layer 0 per row in FP32: z[f] = W0[f] . h0 + b0[f]; thread f.
+    for (int e = tid; e < kBRows * net.in_dim; e += W) {
+      const int r = e / net.in_dim, j = e - r * net.in_dim;
+      h0s[r][j] = rows[(size_t)min(r0 + r, c.n - 1) * row_stride + j];
+    }
+    const int f = tid;
+    float w[kMaxIn];
+#pragma unroll
+    for (int j = 0; j < kMaxIn; ++j) {
+      w[j] = 0.f;
+      if (j < net.in_dim) w[j] = net.params[(size_t)f * net.in_dim + j];
+    }
+    const float b0 = net.params[(size_t)W * net.in_dim + f];
+    __syncthreads();
+    for (int r = 0; r < kBRows; ++r) {
+      float z = b0;
+#pragma unroll
+      for (int j = 0; j < kMaxIn; ++j)
+        if (j < net.in_dim) z = fmaf(w[j], h0s[r][j], z);
+      H0[r * LD + f] = (__bf16)softplus_fast(z);
+    }
+  } else if (tid < kBRows) {
     const int i = min(r0 + tid, c.n - 1);
     xyz[0][tid] = c.x[i];
     xyz[1][tid] = c.y[i];
     xyz[2][tid] = c.z[i];
   }
   // Layer 0 in FP32: z[f] = W0[f][0:3] . x + (W0[f][3:] . [q0; q1] + b0[f]); thread f.
-  {
+  if (!rows) {
     const int f = tid;
     const float* w0 = net.params + (size_t)f * net.in_dim;
     float u = net.params[(size_t)W * net.in_dim + f];
@@ -203,25 +218,8 @@ __global__ __launch_bounds__(W) void k_mlp_bf16(MlpArgs net, MotionArgs mo, Clou
   for (int l = 1; l < net.n_hidden; ++l) {
     const __bf16* Wp = packed + (size_t)(l - 1) * W * W;
     const float* bl = bias_base + (size_t)(l - 1) * ((size_t)W * W + W) + (size_t)W * W;
-    f32x16 acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
-    const bf16x8* A0 = reinterpret_cast<const bf16x8*>(Wp) + ((size_t)(2 * wid) * KS) * 64 + lane;
-    const bf16x8* A1 = reinterpret_cast<const bf16x8*>(Wp) + ((size_t)(2 * wid + 1) * KS) * 64 + lane;
-    const __bf16* B0 = Hin + col * LD + 8 * half;
-    const __bf16* B1 = Hin + (32 + col) * LD + 8 * half;
-    bf16x8 a0 = A0[0], a1 = A1[0];
-#pragma unroll 2
-    for (int ks = 0; ks < KS; ++ks) {
-      const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(B0 + ks * 16);
-      const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(B1 + ks * 16);
-      const int kn = ks + 1 < KS ? ks + 1 : ks;
-      const bf16x8 na0 = A0[(size_t)kn * 64], na1 = A1[(size_t)kn * 64];
-      acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc00, 0, 0, 0);
-      acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc01, 0, 0, 0);
-      acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc10, 0, 0, 0);
-      acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc11, 0, 0, 0);
-      a0 = na0;
-      a1 = na1;
-    }
+    f32x16 acc00, acc01, acc10, acc11;
+    layer_mfma<W>(Wp, Hin, wid, lane, acc00, acc01, acc10, acc11);
     // Epilogue.  acc index 4j+i of tile (fb, rb) is feature 64 wid + 32 fb + 8j + 4 half + i
     // of row 32 rb + col.
     const bool last = l + 1 == net.n_hidden;
@@ -302,10 +300,11 @@ __global__ __launch_bounds__(W) void k_mlp_bf16(MlpArgs net, MotionArgs mo, Clou
 inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 template <int W>
-hipError_t launch_bf16_t(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, const __bf16* packed,
-                         float* out, float tau, int* lists, int* counts, hipStream_t st) {
+hipError_t launch_bf16_t(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, const float* rows,
+                         int64_t row_stride, const __bf16* packed, float* out, float tau, int* lists, int* counts,
+                         hipStream_t st) {
   const int tiles = (c.n + kBRows - 1) / kBRows;
-  const int64_t blocks = mo.n * tiles;
+  const int64_t blocks = (rows ? 1 : mo.n) * tiles;
   if (blocks == 0) return hipSuccess;
   const size_t lds = 2 * (size_t)kBRows * (W + kPad) * sizeof(__bf16);
   static bool attr_set = false;
@@ -315,8 +314,25 @@ hipError_t launch_bf16_t(const MlpArgs& net, const MotionArgs& mo, const CloudAr
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_mlp_bf16<W>), dim3((unsigned)blocks), dim3(W), lds, st, net, mo, c, tiles, packed, out, tau,
-                     lists, counts);
+  hipLaunchKernelGGL((k_mlp_bf16<W>), dim3((unsigned)blocks), dim3(W), lds, st, net, mo, c, tiles, rows, row_stride,
+                     packed, out, tau, lists, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_f32(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, const float* rows,
+                      int64_t row_stride, float* out, hipStream_t st) {
+  const int tiles = (c.n + kF32Rows - 1) / kF32Rows;
+  const int64_t blocks = (rows ? 1 : mo.n) * tiles;
+  if (blocks == 0) return hipSuccess;
+  const size_t lds = (size_t)kF32Rows * net.width * sizeof(float);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_f32),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_mlp_f32, dim3((unsigned)blocks), dim3(256), lds, st, net, mo, c, tiles, rows, row_stride, out);
   return hipGetLastError();
 }
 
@@ -327,35 +343,36 @@ bool mlp_bf16_supported(int width) { return width == 128 || width == 256 || widt
 size_t mlp_packed_elems(const MlpArgs& net) { return (size_t)net.width * net.width * (net.n_hidden - 1); }
 
 hipError_t launch_mlp_f32(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, float* out, hipStream_t st) {
-  const int tiles = (c.n + kF32Rows - 1) / kF32Rows;
-  const int64_t blocks = mo.n * tiles;
-  if (blocks == 0) return hipSuccess;
-  const size_t lds = (size_t)kF32Rows * net.width * sizeof(float);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_f32),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(k_mlp_f32, dim3((unsigned)blocks), dim3(256), lds, st, net, mo, c, tiles, out);
-  return hipGetLastError();
+  return launch_f32(net, mo, c, nullptr, 0, out, st);
 }
 
-hipError_t launch_pack_bf16(const MlpArgs& net, __bf16* packed, hipStream_t st) {
+hipError_t launch_mlp_rows(const MlpArgs& net, int bf16, const __bf16* packed, const float* rows, int64_t row_stride,
+                           int64_t n, float* out, hipStream_t st) {
+  const MotionArgs none{SV_LINEAR, 1, 1, nullptr, nullptr, nullptr};
+  const CloudArgs c{(int)n, nullptr, nullptr, nullptr};
+  if (!bf16) return launch_f32(net, none, c, rows, row_stride, out, st);
+  switch (net.width) {
+    case 128: return launch_bf16_t<128>(net, none, c, rows, row_stride, packed, out, 0.f, nullptr, nullptr, st);
+    case 256: return launch_bf16_t<256>(net, none, c, rows, row_stride, packed, out, 0.f, nullptr, nullptr, st);
+    case 512: return launch_bf16_t<512>(net, none, c, rows, row_stride, packed, out, 0.f, nullptr, nullptr, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pack_bf16(const MlpArgs& net, int transpose, __bf16* packed, hipStream_t st) {
   const int64_t total = (int64_t)mlp_packed_elems(net);
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)std::min<int64_t>(grid_for(total, 256), 4096)), dim3(256), 0, st, net,
-                     packed);
+                     transpose, packed);
   return hipGetLastError();
 }
 
 hipError_t launch_mlp_bf16(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, const __bf16* packed,
                            float* out, float tau, int* lists, int* counts, hipStream_t st) {
   switch (net.width) {
-    case 128: return launch_bf16_t<128>(net, mo, c, packed, out, tau, lists, counts, st);
-    case 256: return launch_bf16_t<256>(net, mo, c, packed, out, tau, lists, counts, st);
-    case 512: return launch_bf16_t<512>(net, mo, c, packed, out, tau, lists, counts, st);
+    case 128: return launch_bf16_t<128>(net, mo, c, nullptr, 0, packed, out, tau, lists, counts, st);
+    case 256: return launch_bf16_t<256>(net, mo, c, nullptr, 0, packed, out, tau, lists, counts, st);
+    case 512: return launch_bf16_t<512>(net, mo, c, nullptr, 0, packed, out, tau, lists, counts, st);
     default: return hipErrorInvalidValue;
   }
 }

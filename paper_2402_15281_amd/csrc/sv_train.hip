@@ -1,0 +1,512 @@
+// Training step of the swept-volume network on samples (x, q0, q1, delta) produced by
+// the exact check (paper Sec. IV-C: training tuples; Sec. V: Adam with PyTorch's
+// default constants).  Loss: mean over the batch of |y - clamp(delta)|, clamp to
+// [-sigma, sigma] (targets only: a clamped prediction would have no gradient beyond
+// sigma, where Adam's first updates leave a wide network).  BF16 hidden layers on
+// MFMA with FP32 accumulation, FP32 first and output layers, FP32 master weights,
+// FP32 Adam state.
+//
+// Workspace layouts (Bp = batch rounded up to 256 rows; rows >= batch carry zero
+// gradient):
+//   aT[l][f][b]   BF16 activation of hidden layer l+1, feature-major
+//   dzT[l][f][b]  BF16 gradient w.r.t. the pre-activation of hidden layer l+1
+//   h0T[j][b]     FP32 network input, feature-major
+//   y[b], dy[b]   FP32 prediction and d loss / d y
+// Kernels, in launch order:
+//   k_pack_bf16 (x2)  W_l and W_l^T in MFMA operand order (sv_mlp.hip)
+//   k_train_fwd       per 64-row tile: all layers, activations to aT, y
+//   k_train_loss      loss and dy (single block, fixed-order reduction)
+//   k_train_bwd       per 64-row tile: dz of every layer via W_l^T MFMA, to dzT
+//   k_grad_w          dW_l = dz_l^T a_{l-1} for l >= 2 (MFMA, split over the batch)
+//   k_grad_reduce     fixed-order sum of the splits
+//   k_grad_rows       db_l, w_out and b_out gradients (one wave per output)
+//   k_grad_w1         dW_1 = dz_1^T h0 in FP32 (split over the batch) + fixed-order sum
+//   k_adam            Adam update of the FP32 masters
+#include <math.h>
+
+#include "sv_internal.h"
+#include "sv_mlp_common.h"
+
+namespace sv {
+namespace {
+
+constexpr int kRows = kTileRows;
+constexpr int kSplitW = 8;        // batch splits of the dW GEMM
+constexpr int kW1Chunk = 256;     // batch rows per block of the dW_1 kernel
+
+struct TrainArgs {
+  MlpArgs net;
+  const float* samples;   // [n][in_dim + 1]
+  const int* idx;         // [B]
+  int B, Bp;
+  __bf16* aT;             // [L][W][Bp]
+  __bf16* dzT;            // [L][W][Bp]
+  float* h0T;             // [in_dim][Bp]
+  float* y;               // [Bp]
+  float* dy;              // [Bp]
+  const __bf16* packed;   // forward operands, layers 2..L
+  const __bf16* packedT;  // backward operands, layers 2..L
+  float* grad;            // [n_params]
+};
+
+// Parameter offsets of the flat vector (see sv_mlp in sv.h), 1-based layer l.
+__host__ __device__ inline size_t off_w(const MlpArgs& n, int l) {
+  const size_t W = n.width;
+  return l == 1 ? 0 : W * n.in_dim + W + (size_t)(l - 2) * (W * W + W);
+}
+__host__ __device__ inline size_t off_b(const MlpArgs& n, int l) {
+  const size_t W = n.width;
+  return off_w(n, l) + (l == 1 ? W * n.in_dim : W * W);
+}
+__host__ __device__ inline size_t off_out(const MlpArgs& n) {
+  const size_t W = n.width;
+  return W * n.in_dim + W + (size_t)(n.n_hidden - 1) * (W * W + W);
+}
+
+// Copy an LDS tile H[64][W + pad] to outT[f][r0 .. r0 + 63] (feature-major); thread f.
+template <int W>
+__device__ __forceinline__ void store_tile_T(const __bf16* H, __bf16* outT, int Bp, int r0) {
+  constexpr int LD = W + kLdsPad;
+  const int f = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < kRows / 8; ++c) {
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = H[(8 * c + e) * LD + f];
+    *reinterpret_cast<bf16x8*>(outT + (size_t)f * Bp + r0 + 8 * c) = v;
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(W) void k_train_fwd(TrainArgs a) {
+  constexpr int NW = W / 64;
+  constexpr int LD = W + kLdsPad;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __bf16* H0 = reinterpret_cast<__bf16*>(smem);
+  __bf16* H1 = H0 + kRows * LD;
+  __shared__ float h0s[kRows][3 + 2 * SV_MAX_DOF];
+  __shared__ float part[NW][kRows];
+  const MlpArgs& n = a.net;
+  const int in_dim = n.in_dim, L = n.n_hidden;
+  const int r0 = blockIdx.x * kRows;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  for (int e = tid; e < kRows * in_dim; e += W) {
+    const int r = e / in_dim, j = e - r * in_dim;
+    const int b = min(r0 + r, a.B - 1);
+    const float v = a.samples[(size_t)a.idx[b] * (in_dim + 1) + j];
+    h0s[r][j] = v;
+    a.h0T[(size_t)j * a.Bp + r0 + r] = v;
+  }
+  __syncthreads();
+  {  // layer 1 in FP32, thread f
+    const int f = tid;
+    const float* w1 = n.params + (size_t)f * in_dim;
+    const float b1 = n.params[off_b(n, 1) + f];
+    constexpr int kMaxIn = 3 + 2 * SV_MAX_DOF;
+    float w[kMaxIn];
+#pragma unroll
+    for (int j = 0; j < kMaxIn; ++j) {
+      w[j] = 0.f;
+      if (j < in_dim) w[j] = w1[j];
+    }
+    for (int r = 0; r < kRows; ++r) {
+      float z = b1;
+#pragma unroll
+      for (int j = 0; j < kMaxIn; ++j)
+        if (j < in_dim) z = fmaf(w[j], h0s[r][j], z);
+      H0[r * LD + f] = (__bf16)softplus_fast(z);
+    }
+  }
+  __syncthreads();
+  store_tile_T<W>(H0, a.aT, a.Bp, r0);
+  __bf16* Hin = H0;
+  __bf16* Hout = H1;
+  float p0 = 0.f, p1 = 0.f;
+  const float* wout = n.params + off_out(n);
+  for (int l = 2; l <= L; ++l) {
+    f32x16 acc00, acc01, acc10, acc11;
+    layer_mfma<W>(a.packed + (size_t)(l - 2) * W * W, Hin, wid, lane, acc00, acc01, acc10, acc11);
+    const float* bl = n.params + off_b(n, l);
+    const bool last = l == L;
+#pragma unroll
+    for (int fb = 0; fb < 2; ++fb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int f = 64 * wid + 32 * fb + 8 * j + 4 * half;
+        const float4 bb = *reinterpret_cast<const float4*>(bl + f);
+        const f32x16& t0 = fb == 0 ? acc00 : acc10;
+        const f32x16& t1 = fb == 0 ? acc01 : acc11;
+        const float s00 = softplus_fast(t0[4 * j + 0] + bb.x), s01 = softplus_fast(t0[4 * j + 1] + bb.y);
+        const float s02 = softplus_fast(t0[4 * j + 2] + bb.z), s03 = softplus_fast(t0[4 * j + 3] + bb.w);
+        const float s10 = softplus_fast(t1[4 * j + 0] + bb.x), s11 = softplus_fast(t1[4 * j + 1] + bb.y);
+        const float s12 = softplus_fast(t1[4 * j + 2] + bb.z), s13 = softplus_fast(t1[4 * j + 3] + bb.w);
+        if (last) {
+          const float4 wo = *reinterpret_cast<const float4*>(wout + f);
+          p0 = fmaf(wo.x, s00, fmaf(wo.y, s01, fmaf(wo.z, s02, fmaf(wo.w, s03, p0))));
+          p1 = fmaf(wo.x, s10, fmaf(wo.y, s11, fmaf(wo.z, s12, fmaf(wo.w, s13, p1))));
+        }
+        bf16x4 v0 = {(__bf16)s00, (__bf16)s01, (__bf16)s02, (__bf16)s03};
+        bf16x4 v1 = {(__bf16)s10, (__bf16)s11, (__bf16)s12, (__bf16)s13};
+        *reinterpret_cast<bf16x4*>(Hout + col * LD + f) = v0;
+        *reinterpret_cast<bf16x4*>(Hout + (32 + col) * LD + f) = v1;
+      }
+    __syncthreads();
+    store_tile_T<W>(Hout, a.aT + (size_t)(l - 1) * W * a.Bp, a.Bp, r0);
+    __bf16* t = Hin;
+    Hin = Hout;
+    Hout = t;
+  }
+  if (L == 1) {
+    for (int r = wid; r < kRows; r += NW) {
+      float s = 0.f;
+      for (int f = lane; f < W; f += 64) s = fmaf(wout[f], (float)Hin[r * LD + f], s);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (lane == 0) part[0][r] = s;
+    }
+    __syncthreads();
+    for (int w = 1; w < NW; ++w)
+      if (tid < kRows) part[w][tid] = 0.f;
+  } else {
+    p0 += __shfl_xor(p0, 32, 64);
+    p1 += __shfl_xor(p1, 32, 64);
+    if (half == 0) {
+      part[wid][col] = p0;
+      part[wid][32 + col] = p1;
+    }
+  }
+  __syncthreads();
+  if (tid < kRows) {
+    float yv = wout[W];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) yv += part[w][tid];
+    a.y[r0 + tid] = yv;
+  }
+}
+
+// One block of 1024 threads: dy and the mean clamped-L1 loss with a fixed-order tree.
+__global__ __launch_bounds__(1024) void k_train_loss(TrainArgs a, float sigma, float* __restrict__ loss_out) {
+  __shared__ float red[1024];
+  const int in_dim = a.net.in_dim;
+  float s = 0.f;
+  for (int b = threadIdx.x; b < a.Bp; b += 1024) {
+    float g = 0.f;
+    if (b < a.B) {
+      const float yv = a.y[b];
+      const float d = a.samples[(size_t)a.idx[b] * (in_dim + 1) + in_dim];
+      const float r = yv - fminf(fmaxf(d, -sigma), sigma);
+      s += fabsf(r);
+      g = (r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f)) / (float)a.B;
+    }
+    a.dy[b] = g;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss_out) *loss_out = red[0] / (float)a.B;
+}
+
+template <int W>
+__global__ __launch_bounds__(W) void k_train_bwd(TrainArgs a) {
+  constexpr int LD = W + kLdsPad;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __bf16* H0 = reinterpret_cast<__bf16*>(smem);
+  __bf16* H1 = H0 + kRows * LD;
+  const MlpArgs& n = a.net;
+  const int L = n.n_hidden;
+  const int r0 = blockIdx.x * kRows;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  {  // dz_L = dy * w_out * sigma(z_L), thread f
+    const int f = tid;
+    const float wo = n.params[off_out(n) + f];
+    const __bf16* aL = a.aT + ((size_t)(L - 1) * W + f) * a.Bp + r0;
+    __bf16* dzL = a.dzT + ((size_t)(L - 1) * W + f) * a.Bp + r0;
+#pragma unroll
+    for (int c = 0; c < kRows / 8; ++c) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(aL + 8 * c);
+      bf16x8 out;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int r = 8 * c + e;
+        const float g = a.dy[r0 + r] * wo * softplus_grad_from_out((float)av[e]);
+        out[e] = (__bf16)g;
+        H0[r * LD + f] = out[e];
+      }
+      *reinterpret_cast<bf16x8*>(dzL + 8 * c) = out;
+    }
+  }
+  __syncthreads();
+  __bf16* Hin = H0;
+  __bf16* Hout = H1;
+  for (int l = L; l >= 2; --l) {
+    // dh_{l-1}[r][k] = sum_f dz_l[r][f] W_l[f][k]: A operand = W_l^T packed
+    f32x16 acc00, acc01, acc10, acc11;
+    layer_mfma<W>(a.packedT + (size_t)(l - 2) * W * W, Hin, wid, lane, acc00, acc01, acc10, acc11);
+    const __bf16* aprev = a.aT + (size_t)(l - 2) * W * a.Bp;
+#pragma unroll
+    for (int fb = 0; fb < 2; ++fb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 64 * wid + 32 * fb + 8 * j + 4 * half;
+        const f32x16& t0 = fb == 0 ? acc00 : acc10;
+        const f32x16& t1 = fb == 0 ? acc01 : acc11;
+        bf16x4 v0, v1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float a0 = (float)aprev[(size_t)(k + i) * a.Bp + r0 + col];
+          const float a1 = (float)aprev[(size_t)(k + i) * a.Bp + r0 + 32 + col];
+          v0[i] = (__bf16)(t0[4 * j + i] * softplus_grad_from_out(a0));
+          v1[i] = (__bf16)(t1[4 * j + i] * softplus_grad_from_out(a1));
+        }
+        *reinterpret_cast<bf16x4*>(Hout + col * LD + k) = v0;
+        *reinterpret_cast<bf16x4*>(Hout + (32 + col) * LD + k) = v1;
+      }
+    __syncthreads();
+    store_tile_T<W>(Hout, a.dzT + (size_t)(l - 2) * W * a.Bp, a.Bp, r0);
+    __bf16* t = Hin;
+    Hin = Hout;
+    Hout = t;
+  }
+}
+
+// Partial dW_l[f][k] over one batch split: block = 4 waves, 128 x 128 output tile,
+// wave w owns rows 64 (w >> 1).. and columns 64 (w & 1).. as 2 x 2 MFMA tiles.
+// A operand: dz_l^T (rows f, k-dim = batch); B operand: a_{l-1}^T (k-dim = batch).
+template <int W>
+__global__ __launch_bounds__(256) void k_grad_w(TrainArgs a, float* __restrict__ part) {
+  constexpr int TB = W / 128;                       // tiles per dimension
+  const int L = a.net.n_hidden;
+  int g = blockIdx.x;
+  const int tk = g % TB; g /= TB;
+  const int tf = g % TB; g /= TB;
+  const int s = g % kSplitW; g /= kSplitW;
+  const int l = g + 2;                              // layer 2..L
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  const int f0 = tf * 128 + 64 * (wid >> 1), k0 = tk * 128 + 64 * (wid & 1);
+  const int chunk = a.Bp / kSplitW;                 // multiple of 16 (Bp is a multiple of 128)
+  const int b0 = s * chunk;
+  const __bf16* dz = a.dzT + (size_t)(l - 1) * W * a.Bp;
+  const __bf16* ap = a.aT + (size_t)(l - 2) * W * a.Bp;
+  const bf16x8* A0 = reinterpret_cast<const bf16x8*>(dz + (size_t)(f0 + col) * a.Bp + b0 + 8 * half);
+  const bf16x8* A1 = reinterpret_cast<const bf16x8*>(dz + (size_t)(f0 + 32 + col) * a.Bp + b0 + 8 * half);
+  const bf16x8* B0 = reinterpret_cast<const bf16x8*>(ap + (size_t)(k0 + col) * a.Bp + b0 + 8 * half);
+  const bf16x8* B1 = reinterpret_cast<const bf16x8*>(ap + (size_t)(k0 + 32 + col) * a.Bp + b0 + 8 * half);
+  f32x16 c00 = {}, c01 = {}, c10 = {}, c11 = {};
+  for (int kk = 0; kk < chunk / 16; ++kk) {
+    const bf16x8 x0 = A0[2 * kk], x1 = A1[2 * kk], y0 = B0[2 * kk], y1 = B1[2 * kk];
+    c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, y0, c00, 0, 0, 0);
+    c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, y1, c01, 0, 0, 0);
+    c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, y0, c10, 0, 0, 0);
+    c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, y1, c11, 0, 0, 0);
+  }
+  (void)L;
+  float* P = part + ((size_t)(l - 2) * kSplitW + s) * W * W;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int fr = 8 * j + 4 * half + i;
+      P[(size_t)(f0 + fr) * W + k0 + col] = c00[4 * j + i];
+      P[(size_t)(f0 + fr) * W + k0 + 32 + col] = c01[4 * j + i];
+      P[(size_t)(f0 + 32 + fr) * W + k0 + col] = c10[4 * j + i];
+      P[(size_t)(f0 + 32 + fr) * W + k0 + 32 + col] = c11[4 * j + i];
+    }
+}
+
+__global__ void k_grad_reduce(TrainArgs a, const float* __restrict__ part) {
+  const int W = a.net.width;
+  const int64_t per = (int64_t)W * W;
+  const int64_t total = per * (a.net.n_hidden - 1);
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(g / per) + 2;
+    const int64_t o = g - (int64_t)(l - 2) * per;
+    float s = 0.f;
+    for (int sp = 0; sp < kSplitW; ++sp) s += part[((size_t)(l - 2) * kSplitW + sp) * per + o];
+    a.grad[off_w(a.net, l) + o] = s;
+  }
+}
+
+// One wave per output: rows 0 .. L*W-1 are db_l[f]; then W rows of w_out; then b_out.
+__global__ __launch_bounds__(256) void k_grad_rows(TrainArgs a) {
+  const MlpArgs& n = a.net;
+  const int W = n.width, L = n.n_hidden;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int n_rows = L * W + W + 1;
+  if (row >= n_rows) return;
+  float s = 0.f;
+  if (row < L * W) {
+    const __bf16* v = a.dzT + (size_t)row * a.Bp;
+    for (int b = 8 * lane; b < a.Bp; b += 512) {
+      const bf16x8 x = *reinterpret_cast<const bf16x8*>(v + b);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) s += (float)x[e];
+    }
+  } else if (row < L * W + W) {
+    const int f = row - L * W;
+    const __bf16* v = a.aT + ((size_t)(L - 1) * W + f) * a.Bp;
+    for (int b = 8 * lane; b < a.Bp; b += 512) {
+      const bf16x8 x = *reinterpret_cast<const bf16x8*>(v + b);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) s = fmaf((float)x[e], a.dy[b + e], s);
+    }
+  } else {
+    for (int b = lane; b < a.Bp; b += 64) s += a.dy[b];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane != 0) return;
+  if (row < L * W) {
+    const int l = row / W + 1, f = row - (l - 1) * W;
+    a.grad[off_b(n, l) + f] = s;
+  } else if (row < L * W + W) {
+    a.grad[off_out(n) + (row - L * W)] = s;
+  } else {
+    a.grad[off_out(n) + W] = s;
+  }
+}
+
+// dW_1[f][j] over one chunk of kW1Chunk batch rows; thread f; FP32.
+__global__ __launch_bounds__(512) void k_grad_w1(TrainArgs a, float* __restrict__ part) {
+  __shared__ float hs[3 + 2 * SV_MAX_DOF][kW1Chunk];
+  const int W = a.net.width, in_dim = a.net.in_dim;
+  const int b0 = blockIdx.x * kW1Chunk;
+  for (int e = threadIdx.x; e < in_dim * kW1Chunk; e += blockDim.x) {
+    const int j = e / kW1Chunk, b = e - j * kW1Chunk;
+    hs[j][b] = a.h0T[(size_t)j * a.Bp + b0 + b];
+  }
+  __syncthreads();
+  constexpr int kMaxIn = 3 + 2 * SV_MAX_DOF;
+  for (int f = threadIdx.x; f < W; f += blockDim.x) {
+    float acc[kMaxIn];
+#pragma unroll
+    for (int j = 0; j < kMaxIn; ++j) acc[j] = 0.f;
+    const __bf16* dz = a.dzT + (size_t)f * a.Bp + b0;
+    for (int b = 0; b < kW1Chunk; b += 8) {
+      const bf16x8 x = *reinterpret_cast<const bf16x8*>(dz + b);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float g = (float)x[e];
+#pragma unroll
+        for (int j = 0; j < kMaxIn; ++j)
+          if (j < in_dim) acc[j] = fmaf(g, hs[j][b + e], acc[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxIn; ++j)
+      if (j < in_dim) part[((size_t)blockIdx.x * W + f) * in_dim + j] = acc[j];
+  }
+}
+
+__global__ void k_grad_w1_reduce(TrainArgs a, const float* __restrict__ part, int chunks) {
+  const int n = a.net.width * a.net.in_dim;
+  for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < n; o += gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n + o];
+    a.grad[o] = s;
+  }
+}
+
+// Adam, PyTorch's form: p -= (lr / (1 - b1^t)) * m / (sqrt(v) / sqrt(1 - b2^t) + eps).
+__global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, int64_t n, float lr, float b1, float b2, float eps,
+                       float step_size, float inv_sqrt_bc2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
+    const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= step_size * mi / (sqrtf(vi) * inv_sqrt_bc2 + eps);
+  }
+  (void)lr;
+}
+
+template <int W>
+hipError_t set_lds_attr(const void* fn) {
+  static bool done = false;
+  if (done) return hipSuccess;
+  const int lds = 2 * kRows * (W + kLdsPad) * (int)sizeof(__bf16);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+template <int W>
+hipError_t launch_train_t(TrainArgs a, float* part_w, float* part_w1, float sigma, float* loss_out, hipStream_t st) {
+  const size_t lds = 2 * (size_t)kRows * (W + kLdsPad) * sizeof(__bf16);
+  const unsigned tiles = (unsigned)(a.Bp / kRows);
+  hipError_t e;
+  if ((e = set_lds_attr<W>(reinterpret_cast<const void*>(&k_train_fwd<W>))) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_train_fwd<W>), dim3(tiles), dim3(W), lds, st, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_train_loss, dim3(1), dim3(1024), 0, st, a, sigma, loss_out);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  static bool bwd_attr = false;
+  if (!bwd_attr) {
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_train_bwd<W>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+      return e;
+    bwd_attr = true;
+  }
+  hipLaunchKernelGGL((k_train_bwd<W>), dim3(tiles), dim3(W), lds, st, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int L = a.net.n_hidden;
+  if (L >= 2) {
+    const unsigned blocks = (unsigned)((W / 128) * (W / 128) * kSplitW * (L - 1));
+    hipLaunchKernelGGL((k_grad_w<W>), dim3(blocks), dim3(256), 0, st, a, part_w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grad_reduce, dim3(2048), dim3(256), 0, st, a, part_w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const int rows = L * W + W + 1;
+  hipLaunchKernelGGL(k_grad_rows, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int chunks = a.Bp / kW1Chunk;
+  hipLaunchKernelGGL(k_grad_w1, dim3((unsigned)chunks), dim3(512), 0, st, a, part_w1);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grad_w1_reduce, dim3(64), dim3(256), 0, st, a, part_w1, chunks);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t train_rows_padded(int64_t B) { return (B + 255) / 256 * 256; }
+
+size_t train_part_w_elems(const MlpArgs& n) {
+  return n.n_hidden >= 2 ? (size_t)kSplitW * (n.n_hidden - 1) * n.width * n.width : 0;
+}
+size_t train_part_w1_elems(const MlpArgs& n, int64_t Bp) { return (size_t)(Bp / kW1Chunk) * n.width * n.in_dim; }
+
+hipError_t launch_train_step(const MlpArgs& net, const float* samples, const int* idx, int B, int Bp, __bf16* aT,
+                             __bf16* dzT, float* h0T, float* y, float* dy, const __bf16* packed,
+                             const __bf16* packedT, float* grad, float* part_w, float* part_w1, float sigma,
+                             float* loss_out, hipStream_t st) {
+  TrainArgs a{net, samples, idx, B, Bp, aT, dzT, h0T, y, dy, packed, packedT, grad};
+  switch (net.width) {
+    case 128: return launch_train_t<128>(a, part_w, part_w1, sigma, loss_out, st);
+    case 256: return launch_train_t<256>(a, part_w, part_w1, sigma, loss_out, st);
+    case 512: return launch_train_t<512>(a, part_w, part_w1, sigma, loss_out, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
+                       float eps, int64_t step, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const double bc1 = 1.0 - pow((double)b1, (double)step);
+  const double bc2 = 1.0 - pow((double)b2, (double)step);
+  const float step_size = (float)(lr / bc1);
+  const float inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, st, p, m, v, g,
+                     n, lr, b1, b2, eps, step_size, inv_sqrt_bc2);
+  return hipGetLastError();
+}
+
+}  // namespace sv

@@ -219,6 +219,17 @@ def mlp_init(spec: MLPSpec, seed: int) -> np.ndarray:
     return flat
 
 
+def uniforms(seed: int, rows: int, cols: int) -> np.ndarray:
+    """[rows][cols] float32 numbers uniform in [0, 1) (strictly below 1 after rounding)."""
+    u = _rng(seed).random((rows, cols), dtype=np.float32)
+    return np.minimum(u, np.float32(1.0) - np.float32(2.0 ** -24))
+
+
+def permutation(seed: int, n: int) -> np.ndarray:
+    """A seeded permutation of range(n) as int32 (e.g. the sample order of one epoch)."""
+    return _rng(seed).permutation(n).astype(np.int32)
+
+
 def log_uniform_int(g: np.random.Generator, lo: int, hi: int) -> int:
     """round(exp(U(ln lo, ln hi))) clipped to [lo, hi]."""
     v = int(round(math.exp(g.uniform(math.log(lo), math.log(hi)))))

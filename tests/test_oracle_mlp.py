@@ -75,7 +75,7 @@ def test_gradient_matches_autograd():
     net = torch_net(flat, *shape)
     pred = net(torch.tensor(X))[:, 0]
     tt = torch.tensor(t)
-    L = torch.mean(torch.abs(torch.clamp(pred, -sigma, sigma) - torch.clamp(tt, -sigma, sigma)))
+    L = torch.mean(torch.abs(pred - torch.clamp(tt, -sigma, sigma)))
     L.backward()
     ref = torch.cat([torch.cat([m.weight.grad.reshape(-1), m.bias.grad]) for m in net
                      if isinstance(m, torch.nn.Linear)]).numpy()
@@ -106,14 +106,39 @@ def test_gradient_matches_central_differences():
         assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-9)
 
 
-def test_clamp_blocks_gradient_outside_sigma():
+def test_decisions_default_to_own_prediction():
+    shape = (15, 32, 2)
+    flat = svgen.mlp_init(svgen.MLPSpec(*shape), 16).astype(np.float64)
+    X, t = _batch(17, B=32)
+    y, _ = om.forward(flat, *shape, X)
+    l1, g1 = om.loss_and_grad(flat, *shape, X, t, 0.1)
+    l2, g2 = om.loss_and_grad(flat, *shape, X, t, 0.1, decide=y)
+    assert l1 == l2
+    np.testing.assert_array_equal(g1, g2)
+    # flipping every decision flips the gradient
+    _, g3 = om.loss_and_grad(flat, *shape, X, t, 10.0, decide=2 * t - y)
+    _, g4 = om.loss_and_grad(flat, *shape, X, t, 10.0)
+    np.testing.assert_allclose(g3, -g4, rtol=1e-12, atol=1e-15)
+
+
+def test_clamp_acts_on_targets_only():
+    """Targets beyond sigma count as sigma; predictions are never clamped, so a
+    prediction beyond sigma is still pulled back (its gradient is the full sign)."""
     shape = (15, 16, 2)
     flat = svgen.mlp_init(svgen.MLPSpec(*shape), 9).astype(np.float64)
     X, _ = _batch(10, B=16)
     y, _ = om.forward(flat, *shape, X)
-    sigma = float(np.min(np.abs(y))) * 0.5           # every prediction lies outside [-s, s]
-    _, g = om.loss_and_grad(flat, *shape, X, np.zeros(16), sigma)
-    np.testing.assert_array_equal(g, 0.0)
+    sigma = 0.05
+    far = np.full(16, 3.0)
+    l_far, g_far = om.loss_and_grad(flat, *shape, X, far, sigma)
+    l_sig, g_sig = om.loss_and_grad(flat, *shape, X, np.full(16, sigma), sigma)
+    assert l_far == l_sig == pytest.approx(np.mean(np.abs(y - sigma)), rel=1e-14)
+    np.testing.assert_array_equal(g_far, g_sig)
+    assert np.linalg.norm(g_far) > 0
+    # d loss / d b_out = mean sign(y - clamp(t)) over every sample, also those with |y| > sigma
+    _, g_lo = om.loss_and_grad(flat, *shape, X, np.full(16, -3.0), 0.01)
+    assert np.any(np.abs(y) > 0.01)
+    assert g_lo[-1] == pytest.approx(np.mean(np.sign(y + 0.01)), abs=1e-15)
 
 
 def test_adam_matches_torch():

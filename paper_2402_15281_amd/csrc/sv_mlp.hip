@@ -134,154 +134,183 @@ __global__ void k_pack_bf16(MlpArgs net, int transpose, __bf16* __restrict__ pac
   }
 }
 
-// Block: W/64 waves x 64 threads, R = 64 rows (queries) of one motion.  LDS holds two
-// activation buffers [64][W + 8] BF16 (the pad spreads rows over the LDS banks).
-// Wave w owns output features [64w, 64w + 64) = 2 feature blocks x 2 row blocks of
-// 32x32 MFMA tiles.
-constexpr int kBRows = kTileRows;
+// Block: W / (32 FB) waves, each owning FB feature blocks (32 FB output features) of
+// all R = 32 RB rows (queries) of one motion, i.e. FB x RB MFMA tiles of 32 x 32.
+// LDS holds one activation tile [R][W + 8] BF16 (the pad spreads rows over the LDS
+// banks), updated in place: every wave reads the whole tile in a layer's MFMA loop,
+// a barrier, then every wave writes its outputs, a barrier.
+// The weight tiles stream from L2 through the vector L1, whose data path bounds the
+// MFMA loop (RB rows per weight tile set that traffic: 1/RB KB per MFMA).  FB = 4,
+// RB = 2 keeps the block at 64 rows and 66.5 KB of LDS, so two blocks share a CU and
+// one block's softplus epilogue overlaps the other's MFMA loop; FB = 2, RB = 4 halves
+// the weight traffic but needs 133 KB of LDS (one block per CU) and measures slower.
 constexpr int kPad = kLdsPad;
+constexpr int kRing = 2;               // weight-load ring depth (k-steps)
+constexpr int kFB = 4;                 // feature blocks per wave
+constexpr int kRB = 8 / kFB;           // row blocks per wave (FB x RB = 8 tiles, 128 accumulators)
+constexpr int kBRows = 32 * kRB;       // rows per block
+
+template <int W>
+constexpr int mlp_threads() { return 64 * (W / (32 * kFB)); }
 
 // Inputs: every (motion, point) pair of (mo, c), or with `rows` the c.n rows
 // rows[i][0:in_dim] (one motion slot, m = 0; layer 0 then runs unsplit per row).
 template <int W>
-__global__ __launch_bounds__(W) void k_mlp_bf16(MlpArgs net, MotionArgs mo, CloudArgs c, int tiles,
-                                                const float* __restrict__ rows, int64_t row_stride,
-                                                const __bf16* __restrict__ packed, float* __restrict__ out,
-                                                float tau, int* __restrict__ lists, int* __restrict__ counts) {
-  constexpr int NW = W / 64;          // waves
-  constexpr int LD = W + kPad;        // LDS row stride (elements)
+__global__ __launch_bounds__(mlp_threads<W>(), 2) void k_mlp_bf16(MlpArgs net, MotionArgs mo, CloudArgs c, int tiles,
+                                                               const float* __restrict__ rows, int64_t row_stride,
+                                                               const __bf16* __restrict__ packed,
+                                                               float* __restrict__ out, float tau,
+                                                               int* __restrict__ lists, int* __restrict__ counts) {
+  constexpr int NT = mlp_threads<W>();   // threads
+  constexpr int NW = NT / 64;            // waves
+  constexpr int R = kBRows;              // rows
+  constexpr int LD = W + kPad;           // LDS row stride (elements)
+  constexpr int P = W / 2;               // feature pairs of layer 0
+  constexpr int RG = NT / P;             // row groups of layer 0 (rows R / RG each)
   constexpr int kMaxIn = 3 + 2 * SV_MAX_DOF;
+  static_assert(NT % P == 0 || P % NT == 0, "layer-0 mapping");
   extern __shared__ __align__(16) unsigned char smem[];
-  __bf16* H0 = reinterpret_cast<__bf16*>(smem);
-  __bf16* H1 = H0 + kBRows * LD;
-  __shared__ float part[NW][kBRows];
-  __shared__ float xyz[3][kBRows];
-  __shared__ float h0s[kBRows][kMaxIn];
+  __bf16* H = reinterpret_cast<__bf16*>(smem);
+  __shared__ float part[NW][R];
+  __shared__ float4 xyz[R];
+  __shared__ float h0s[R][kMaxIn];
 
   const int m = blockIdx.x / tiles;
   const int tile = blockIdx.x - m * tiles;
-  const int r0 = tile * kBRows;
+  const int r0 = tile * R;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int dof = net.dof;
+  const int dof = net.dof, in_dim = net.in_dim;
+  // Layer 0 in FP32; thread t owns the adjacent features 2p, 2p + 1 (p = t mod P) of
+  // the rows of its row group, and writes them as one 32-bit LDS store per row.
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const int pr = tid % P, rg = tid / P;
+  const int ra = rg * (R / (RG > 0 ? RG : 1)), rz = ra + R / (RG > 0 ? RG : 1);
   if (rows) {
-    // Layer 0 per row in FP32: z[f] = W0[f] . h0 + b0[f]; thread f.
-    for (int e = tid; e < kBRows * net.in_dim; e += W) {
-      const int r = e / net.in_dim, j = e - r * net.in_dim;
+    // z[f] = W0[f] . h0 + b0[f] per row
+    for (int e = tid; e < R * in_dim; e += NT) {
+      const int r = e / in_dim, j = e - r * in_dim;
       h0s[r][j] = rows[(size_t)min(r0 + r, c.n - 1) * row_stride + j];
     }
-    const int f = tid;
-    float w[kMaxIn];
-#pragma unroll
-    for (int j = 0; j < kMaxIn; ++j) {
-      w[j] = 0.f;
-      if (j < net.in_dim) w[j] = net.params[(size_t)f * net.in_dim + j];
-    }
-    const float b0 = net.params[(size_t)W * net.in_dim + f];
     __syncthreads();
-    for (int r = 0; r < kBRows; ++r) {
-      float z = b0;
+    float w[2][kMaxIn], b0[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int f = 2 * pr + h;
+#pragma unroll
+      for (int j = 0; j < kMaxIn; ++j) {
+        w[h][j] = 0.f;
+        if (j < in_dim) w[h][j] = net.params[(size_t)f * in_dim + j];
+      }
+      b0[h] = net.params[(size_t)W * in_dim + f];
+    }
+    for (int r = ra; r < rz; ++r) {
+      float z0 = b0[0], z1 = b0[1];
 #pragma unroll
       for (int j = 0; j < kMaxIn; ++j)
-        if (j < net.in_dim) z = fmaf(w[j], h0s[r][j], z);
-      H0[r * LD + f] = (__bf16)softplus_fast(z);
+        if (j < in_dim) {
+          z0 = fmaf(w[0][j], h0s[r][j], z0);
+          z1 = fmaf(w[1][j], h0s[r][j], z1);
+        }
+      const bf16x2 v = {(__bf16)softplus_fast(z0), (__bf16)softplus_fast(z1)};
+      *reinterpret_cast<bf16x2*>(H + r * LD + 2 * pr) = v;
     }
-  } else if (tid < kBRows) {
-    const int i = min(r0 + tid, c.n - 1);
-    xyz[0][tid] = c.x[i];
-    xyz[1][tid] = c.y[i];
-    xyz[2][tid] = c.z[i];
-  }
-  // Layer 0 in FP32: z[f] = W0[f][0:3] . x + (W0[f][3:] . [q0; q1] + b0[f]); thread f.
-  if (!rows) {
-    const int f = tid;
-    const float* w0 = net.params + (size_t)f * net.in_dim;
-    float u = net.params[(size_t)W * net.in_dim + f];
-    for (int j = 0; j < dof; ++j) {
-      u = fmaf(w0[3 + j], mo.q0[(size_t)m * dof + j], u);
-      u = fmaf(w0[3 + dof + j], mo.q1[(size_t)m * dof + j], u);
+  } else {
+    // z[f] = W0[f][0:3] . x + u[f], u[f] = W0[f][3:] . [q0; q1] + b0[f] once per motion
+    if (tid < R) {
+      const int i = min(r0 + tid, c.n - 1);
+      xyz[tid] = make_float4(c.x[i], c.y[i], c.z[i], 0.f);
     }
-    const float wx = w0[0], wy = w0[1], wz = w0[2];
     __syncthreads();
+    float u[2], wx[2], wy[2], wz[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int f = 2 * pr + h;
+      const float* w0 = net.params + (size_t)f * in_dim;
+      float uu = net.params[(size_t)W * in_dim + f];
+      for (int j = 0; j < dof; ++j) {
+        uu = fmaf(w0[3 + j], mo.q0[(size_t)m * dof + j], uu);
+        uu = fmaf(w0[3 + dof + j], mo.q1[(size_t)m * dof + j], uu);
+      }
+      u[h] = uu;
+      wx[h] = w0[0];
+      wy[h] = w0[1];
+      wz[h] = w0[2];
+    }
 #pragma unroll 4
-    for (int r = 0; r < kBRows; ++r) {
-      const float z = fmaf(wx, xyz[0][r], fmaf(wy, xyz[1][r], fmaf(wz, xyz[2][r], u)));
-      H0[r * LD + f] = (__bf16)softplus_fast(z);
+    for (int r = ra; r < rz; ++r) {
+      const float4 p = xyz[r];
+      const float z0 = fmaf(wx[0], p.x, fmaf(wy[0], p.y, fmaf(wz[0], p.z, u[0])));
+      const float z1 = fmaf(wx[1], p.x, fmaf(wy[1], p.y, fmaf(wz[1], p.z, u[1])));
+      const bf16x2 v = {(__bf16)softplus_fast(z0), (__bf16)softplus_fast(z1)};
+      *reinterpret_cast<bf16x2*>(H + r * LD + 2 * pr) = v;
     }
   }
   __syncthreads();
 
-  const float* bias_base = net.params + (size_t)W * net.in_dim + W;   // start of layer 1
+  const float* bias_base = net.params + (size_t)W * in_dim + W;   // start of layer 2
+  const float* wout = bias_base + (size_t)(net.n_hidden - 1) * ((size_t)W * W + W);
   const int half = lane >> 5, col = lane & 31;
-  __bf16* Hin = H0;
-  __bf16* Hout = H1;
-  float p0 = 0.f, p1 = 0.f;   // output-layer partial sums for rows col and 32 + col
+  float p[kRB];   // output-layer partial sums for rows 32 rb + col
+#pragma unroll
+  for (int rb = 0; rb < kRB; ++rb) p[rb] = 0.f;
   for (int l = 1; l < net.n_hidden; ++l) {
     const __bf16* Wp = packed + (size_t)(l - 1) * W * W;
     const float* bl = bias_base + (size_t)(l - 1) * ((size_t)W * W + W) + (size_t)W * W;
-    f32x16 acc00, acc01, acc10, acc11;
-    layer_mfma<W>(Wp, Hin, wid, lane, acc00, acc01, acc10, acc11);
-    // Epilogue.  acc index 4j+i of tile (fb, rb) is feature 64 wid + 32 fb + 8j + 4 half + i
-    // of row 32 rb + col.
+    f32x16 acc[kFB][kRB];
+    layer_mfma_fb<W, kFB, kRB, kRing>(Wp, H, wid, 0, lane, bl, acc);
     const bool last = l + 1 == net.n_hidden;
-    const float* wout = bias_base + (size_t)(net.n_hidden - 1) * ((size_t)W * W + W);
+    if (!last) __syncthreads();   // every wave has read the tile
+    // Epilogue: acc[fb][rb][4j+i] is feature 32 (FB wid + fb) + 8j + 4 half + i of row
+    // 32 rb + col (the bias is already in the accumulators).
 #pragma unroll
-    for (int fb = 0; fb < 2; ++fb) {
+    for (int fb = 0; fb < kFB; ++fb) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int f = 64 * wid + 32 * fb + 8 * j + 4 * half;
-        const float4 bb = *reinterpret_cast<const float4*>(bl + f);
-        const f32x16& t0 = fb == 0 ? acc00 : acc10;
-        const f32x16& t1 = fb == 0 ? acc01 : acc11;
-        const float s00 = softplus_fast(t0[4 * j + 0] + bb.x), s01 = softplus_fast(t0[4 * j + 1] + bb.y);
-        const float s02 = softplus_fast(t0[4 * j + 2] + bb.z), s03 = softplus_fast(t0[4 * j + 3] + bb.w);
-        const float s10 = softplus_fast(t1[4 * j + 0] + bb.x), s11 = softplus_fast(t1[4 * j + 1] + bb.y);
-        const float s12 = softplus_fast(t1[4 * j + 2] + bb.z), s13 = softplus_fast(t1[4 * j + 3] + bb.w);
-        if (last) {
-          const float4 wo = *reinterpret_cast<const float4*>(wout + f);
-          p0 = fmaf(wo.x, s00, fmaf(wo.y, s01, fmaf(wo.z, s02, fmaf(wo.w, s03, p0))));
-          p1 = fmaf(wo.x, s10, fmaf(wo.y, s11, fmaf(wo.z, s12, fmaf(wo.w, s13, p1))));
-        } else {
-          bf16x4 v0 = {(__bf16)s00, (__bf16)s01, (__bf16)s02, (__bf16)s03};
-          bf16x4 v1 = {(__bf16)s10, (__bf16)s11, (__bf16)s12, (__bf16)s13};
-          *reinterpret_cast<bf16x4*>(Hout + col * LD + f) = v0;
-          *reinterpret_cast<bf16x4*>(Hout + (32 + col) * LD + f) = v1;
+        const int f = 32 * (kFB * wid + fb) + 8 * j + 4 * half;
+        float4 wo = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (last) wo = *reinterpret_cast<const float4*>(wout + f);
+#pragma unroll
+        for (int rb = 0; rb < kRB; ++rb) {
+          const float s0 = softplus_fast(acc[fb][rb][4 * j + 0]), s1 = softplus_fast(acc[fb][rb][4 * j + 1]);
+          const float s2 = softplus_fast(acc[fb][rb][4 * j + 2]), s3 = softplus_fast(acc[fb][rb][4 * j + 3]);
+          if (last) {
+            p[rb] = fmaf(wo.x, s0, fmaf(wo.y, s1, fmaf(wo.z, s2, fmaf(wo.w, s3, p[rb]))));
+          } else {
+            bf16x4 v = {(__bf16)s0, (__bf16)s1, (__bf16)s2, (__bf16)s3};
+            *reinterpret_cast<bf16x4*>(H + (32 * rb + col) * LD + f) = v;
+          }
         }
       }
     }
-    __syncthreads();
-    __bf16* t = Hin;
-    Hin = Hout;
-    Hout = t;
+    if (!last) __syncthreads();   // the new tile is complete
   }
   if (net.n_hidden == 1) {
     // no hidden MFMA layer: output layer straight from layer 0 (FP32 accumulate of BF16 h1)
-    const float* wout = bias_base;
-    for (int r = wid; r < kBRows; r += NW) {
+    for (int r = wid; r < R; r += NW) {
       float s = 0.f;
-      for (int f = lane; f < W; f += 64) s = fmaf(wout[f], (float)Hin[r * LD + f], s);
+      for (int f = lane; f < W; f += 64) s = fmaf(wout[f], (float)H[r * LD + f], s);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
       if (lane == 0) part[0][r] = s;
     }
     __syncthreads();
     for (int w = 1; w < NW; ++w)
-      if (tid < kBRows) part[w][tid] = 0.f;
+      for (int r = tid; r < R; r += NT) part[w][r] = 0.f;
   } else {
     // lanes col and col + 32 hold disjoint features of the same rows
-    p0 += __shfl_xor(p0, 32, 64);
-    p1 += __shfl_xor(p1, 32, 64);
-    if (half == 0) {
-      part[wid][col] = p0;
-      part[wid][32 + col] = p1;
+#pragma unroll
+    for (int rb = 0; rb < kRB; ++rb) {
+      const float q = p[rb] + __shfl_xor(p[rb], 32, 64);
+      if (half == 0) part[wid][32 * rb + col] = q;
     }
   }
   __syncthreads();
-  if (wid == 0) {
-    const float* wout = bias_base + (size_t)(net.n_hidden - 1) * ((size_t)W * W + W);
+  if (wid < R / 64) {
+    const int r = 64 * wid + lane;
     float y = wout[W];
 #pragma unroll
-    for (int w = 0; w < NW; ++w) y += part[w][lane];
-    const int i = r0 + lane;
+    for (int w = 0; w < NW; ++w) y += part[w][r];
+    const int i = r0 + r;
     const bool valid = i < c.n;
     if (out && valid) out[(size_t)m * c.n + i] = y;
     if (lists) {
@@ -306,7 +335,7 @@ hipError_t launch_bf16_t(const MlpArgs& net, const MotionArgs& mo, const CloudAr
   const int tiles = (c.n + kBRows - 1) / kBRows;
   const int64_t blocks = (rows ? 1 : mo.n) * tiles;
   if (blocks == 0) return hipSuccess;
-  const size_t lds = 2 * (size_t)kBRows * (W + kPad) * sizeof(__bf16);
+  const size_t lds = (size_t)kBRows * (W + kPad) * sizeof(__bf16);
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_bf16<W>),
@@ -314,8 +343,8 @@ hipError_t launch_bf16_t(const MlpArgs& net, const MotionArgs& mo, const CloudAr
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_mlp_bf16<W>), dim3((unsigned)blocks), dim3(W), lds, st, net, mo, c, tiles, rows, row_stride,
-                     packed, out, tau, lists, counts);
+  hipLaunchKernelGGL((k_mlp_bf16<W>), dim3((unsigned)blocks), dim3(mlp_threads<W>()), lds, st, net, mo, c, tiles,
+                     rows, row_stride, packed, out, tau, lists, counts);
   return hipGetLastError();
 }
 

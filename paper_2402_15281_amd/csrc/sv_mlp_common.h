@@ -36,11 +36,19 @@ __device__ __forceinline__ float softplus_grad_from_out(float a) {
 // One layer's MFMA loop for one wave: output features [64 wid, 64 wid + 64) of the
 // 64 tile rows, i.e. 2 feature blocks (fb) x 2 row blocks (rb) of 32 x 32.
 // Wp: packed weights of this layer; Hin: LDS tile [64][W + pad].
+// Weight tiles stream from L2 through a ring of kDepth k-steps held in registers,
+// so each load has kDepth - 1 k-steps of MFMA work to arrive; the LDS operands of
+// the next k-step are read while the current one computes.
+constexpr int kDepth = 4;
+
+// bias (optional): the accumulators start from the bias of their output feature.
 template <int W>
 __device__ __forceinline__ void layer_mfma(const __bf16* __restrict__ Wp, const __bf16* Hin, int wid, int lane,
-                                           f32x16& acc00, f32x16& acc01, f32x16& acc10, f32x16& acc11) {
+                                           const float* __restrict__ bias, f32x16& acc00, f32x16& acc01,
+                                           f32x16& acc10, f32x16& acc11) {
   constexpr int KS = W / 16;
   constexpr int LD = W + kLdsPad;
+  static_assert(KS % kDepth == 0, "k-steps must fill the load ring");
   const int half = lane >> 5, col = lane & 31;
   const bf16x8* A0 = reinterpret_cast<const bf16x8*>(Wp) + ((size_t)(2 * wid) * KS) * 64 + lane;
   const bf16x8* A1 = A0 + (size_t)KS * 64;
@@ -50,19 +58,115 @@ __device__ __forceinline__ void layer_mfma(const __bf16* __restrict__ Wp, const 
   acc01 = f32x16{};
   acc10 = f32x16{};
   acc11 = f32x16{};
-  bf16x8 a0 = A0[0], a1 = A1[0];
-#pragma unroll 2
-  for (int ks = 0; ks < KS; ++ks) {
-    const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(B0 + ks * 16);
-    const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(B1 + ks * 16);
-    const int kn = ks + 1 < KS ? ks + 1 : ks;
-    const bf16x8 na0 = A0[(size_t)kn * 64], na1 = A1[(size_t)kn * 64];
-    acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc00, 0, 0, 0);
-    acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc01, 0, 0, 0);
-    acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc10, 0, 0, 0);
-    acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc11, 0, 0, 0);
-    a0 = na0;
-    a1 = na1;
+  if (bias) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float4 c0 = *reinterpret_cast<const float4*>(bias + 64 * wid + 8 * j + 4 * half);
+      const float4 c1 = *reinterpret_cast<const float4*>(bias + 64 * wid + 32 + 8 * j + 4 * half);
+      acc00[4 * j + 0] = c0.x; acc00[4 * j + 1] = c0.y; acc00[4 * j + 2] = c0.z; acc00[4 * j + 3] = c0.w;
+      acc10[4 * j + 0] = c1.x; acc10[4 * j + 1] = c1.y; acc10[4 * j + 2] = c1.z; acc10[4 * j + 3] = c1.w;
+    }
+    acc01 = acc00;
+    acc11 = acc10;
+  }
+  bf16x8 a0[kDepth], a1[kDepth];
+#pragma unroll
+  for (int s = 0; s < kDepth; ++s) {
+    a0[s] = A0[(size_t)s * 64];
+    a1[s] = A1[(size_t)s * 64];
+  }
+  bf16x8 b0 = *reinterpret_cast<const bf16x8*>(B0);
+  bf16x8 b1 = *reinterpret_cast<const bf16x8*>(B1);
+  for (int ks = 0; ks < KS; ks += kDepth) {
+#pragma unroll
+    for (int s = 0; s < kDepth; ++s) {
+      const int kc = ks + s;
+      bf16x8 nb0 = b0, nb1 = b1;
+      if (kc + 1 < KS) {
+        nb0 = *reinterpret_cast<const bf16x8*>(B0 + (kc + 1) * 16);
+        nb1 = *reinterpret_cast<const bf16x8*>(B1 + (kc + 1) * 16);
+      }
+      acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[s], b0, acc00, 0, 0, 0);
+      acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[s], b1, acc01, 0, 0, 0);
+      acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[s], b0, acc10, 0, 0, 0);
+      acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[s], b1, acc11, 0, 0, 0);
+      if (ks + kDepth < KS) {
+        a0[s] = A0[(size_t)(kc + kDepth) * 64];
+        a1[s] = A1[(size_t)(kc + kDepth) * 64];
+      }
+      b0 = nb0;
+      b1 = nb1;
+      // keep each k-step's loads where they are issued (the scheduler would
+      // otherwise sink them next to their first use)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// The same loop for a wave owning FB feature blocks (32 FB features from feature
+// 32 FB wf) of RB row blocks (32 RB rows from row 32 RB wr): FB x RB MFMA tiles,
+// acc[fb][rb].  Each weight tile is used RB times and each activation tile FB times
+// per load, so weight traffic per MFMA is 1/RB KB and LDS traffic 1/FB KB.
+// Ring depth D for the weight tiles.
+template <int W, int FB, int RB, int D>
+__device__ __forceinline__ void layer_mfma_fb(const __bf16* __restrict__ Wp, const __bf16* Hin, int wf, int wr,
+                                              int lane, const float* __restrict__ bias, f32x16 (&acc)[FB][RB]) {
+  constexpr int KS = W / 16;
+  constexpr int LD = W + kLdsPad;
+  static_assert(KS % D == 0, "k-steps must fill the load ring");
+  const int half = lane >> 5, col = lane & 31;
+  const bf16x8* A = reinterpret_cast<const bf16x8*>(Wp) + ((size_t)(FB * wf) * KS) * 64 + lane;
+  const __bf16* B = Hin + (32 * RB * wr + col) * LD + 8 * half;
+#pragma unroll
+  for (int fb = 0; fb < FB; ++fb) {
+    acc[fb][0] = f32x16{};
+    if (bias) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float4 c = *reinterpret_cast<const float4*>(bias + 32 * (FB * wf + fb) + 8 * j + 4 * half);
+        acc[fb][0][4 * j + 0] = c.x;
+        acc[fb][0][4 * j + 1] = c.y;
+        acc[fb][0][4 * j + 2] = c.z;
+        acc[fb][0][4 * j + 3] = c.w;
+      }
+    }
+#pragma unroll
+    for (int rb = 1; rb < RB; ++rb) acc[fb][rb] = acc[fb][0];
+  }
+  bf16x8 a[D][FB];
+#pragma unroll
+  for (int s = 0; s < D; ++s)
+#pragma unroll
+    for (int fb = 0; fb < FB; ++fb) a[s][fb] = A[((size_t)fb * KS + s) * 64];
+  bf16x8 b[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) b[rb] = *reinterpret_cast<const bf16x8*>(B + 32 * rb * LD);
+  for (int ks = 0; ks < KS; ks += D) {
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      const int kc = ks + s;
+      bf16x8 nb[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        nb[rb] = b[rb];
+        if (kc + 1 < KS) nb[rb] = *reinterpret_cast<const bf16x8*>(B + 32 * rb * LD + (kc + 1) * 16);
+      }
+      // the next k-step's LDS reads go out before this step's MFMAs, whose in-order
+      // issue then covers their latency
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int fb = 0; fb < FB; ++fb)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          acc[fb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s][fb], b[rb], acc[fb][rb], 0, 0, 0);
+      if (ks + D < KS) {
+#pragma unroll
+        for (int fb = 0; fb < FB; ++fb) a[s][fb] = A[((size_t)fb * KS + kc + D) * 64];
+      }
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) b[rb] = nb[rb];
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 }
 

@@ -126,21 +126,20 @@ __global__ __launch_bounds__(W) void k_train_fwd(TrainArgs a) {
   const float* wout = n.params + off_out(n);
   for (int l = 2; l <= L; ++l) {
     f32x16 acc00, acc01, acc10, acc11;
-    layer_mfma<W>(a.packed + (size_t)(l - 2) * W * W, Hin, wid, lane, acc00, acc01, acc10, acc11);
-    const float* bl = n.params + off_b(n, l);
+    layer_mfma<W>(a.packed + (size_t)(l - 2) * W * W, Hin, wid, lane, n.params + off_b(n, l), acc00, acc01, acc10,
+                  acc11);
     const bool last = l == L;
 #pragma unroll
     for (int fb = 0; fb < 2; ++fb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int f = 64 * wid + 32 * fb + 8 * j + 4 * half;
-        const float4 bb = *reinterpret_cast<const float4*>(bl + f);
         const f32x16& t0 = fb == 0 ? acc00 : acc10;
         const f32x16& t1 = fb == 0 ? acc01 : acc11;
-        const float s00 = softplus_fast(t0[4 * j + 0] + bb.x), s01 = softplus_fast(t0[4 * j + 1] + bb.y);
-        const float s02 = softplus_fast(t0[4 * j + 2] + bb.z), s03 = softplus_fast(t0[4 * j + 3] + bb.w);
-        const float s10 = softplus_fast(t1[4 * j + 0] + bb.x), s11 = softplus_fast(t1[4 * j + 1] + bb.y);
-        const float s12 = softplus_fast(t1[4 * j + 2] + bb.z), s13 = softplus_fast(t1[4 * j + 3] + bb.w);
+        const float s00 = softplus_fast(t0[4 * j + 0]), s01 = softplus_fast(t0[4 * j + 1]);
+        const float s02 = softplus_fast(t0[4 * j + 2]), s03 = softplus_fast(t0[4 * j + 3]);
+        const float s10 = softplus_fast(t1[4 * j + 0]), s11 = softplus_fast(t1[4 * j + 1]);
+        const float s12 = softplus_fast(t1[4 * j + 2]), s13 = softplus_fast(t1[4 * j + 3]);
         if (last) {
           const float4 wo = *reinterpret_cast<const float4*>(wout + f);
           p0 = fmaf(wo.x, s00, fmaf(wo.y, s01, fmaf(wo.z, s02, fmaf(wo.w, s03, p0))));
@@ -246,7 +245,7 @@ __global__ __launch_bounds__(W) void k_train_bwd(TrainArgs a) {
   for (int l = L; l >= 2; --l) {
     // dh_{l-1}[r][k] = sum_f dz_l[r][f] W_l[f][k]: A operand = W_l^T packed
     f32x16 acc00, acc01, acc10, acc11;
-    layer_mfma<W>(a.packedT + (size_t)(l - 2) * W * W, Hin, wid, lane, acc00, acc01, acc10, acc11);
+    layer_mfma<W>(a.packedT + (size_t)(l - 2) * W * W, Hin, wid, lane, nullptr, acc00, acc01, acc10, acc11);
     const __bf16* aprev = a.aT + (size_t)(l - 2) * W * a.Bp;
 #pragma unroll
     for (int fb = 0; fb < 2; ++fb)

@@ -42,6 +42,37 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(doc, sources):
+    """HBM bytes per launch from a committed rocprofv3 counter summary under profiles/.
+
+    The summary records FETCH_SIZE + WRITE_SIZE per launch, scaled by a plain copy
+    kernel's reading, and the sha256 of the kernel's source files when the counters
+    were taken.  Returns None when the summary is missing or the source has changed
+    since (the figure would describe another kernel).
+    """
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, "profiles", doc)).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        for key in ("kernel_source_sha256_16", "traffic_bytes_per_launch"):
+            if line.startswith(key + ": "):
+                fields[key] = line.split(": ", 1)[1].split()[0]
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if "traffic_bytes_per_launch" not in fields or fields.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
+MLP_SOURCES = ["paper_2402_15281_amd/csrc/sv_mlp.hip", "paper_2402_15281_amd/csrc/sv_mlp_common.h"]
+GEOM_SOURCES = ["paper_2402_15281_amd/csrc/sv_geom.hip"]
+
+
 def mlp_flops_per_query(in_dim, width, n_hidden):
     return 2 * (in_dim * width + (n_hidden - 1) * width * width + width)
 
@@ -211,12 +242,15 @@ def main():
                    "weights": f"trained on the GPU before timing: {args.train_motions} motions x 500 exact-check "
                               f"samples, {args.train_epochs} epochs, batch 65536, Adam lr 1e-3"},
         "roofline": {"kernel": "k_mlp_bf16", "bound": "mfma", "achieved": fm, "peak": PEAK_BF16_TFLOPS,
-                     "unit": "TFLOP/s", "frac": fm / PEAK_BF16_TFLOPS, "traffic": None,
-                     "kernel_ms": kc["screen"], "flop_per_launch": flop_mlp},
+                     "unit": "TFLOP/s", "frac": fm / PEAK_BF16_TFLOPS,
+                     "traffic": profiled_traffic("k_mlp_bf16_bin20k_traffic.md", MLP_SOURCES),
+                     "kernel_ms": kc["screen"], "flop_per_launch": flop_mlp,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
         "exact_gpu": {"value": M / (ms_x / 1e3), "unit": "motions/s", "ms_per_step": ms_x, "dtype": "f32",
                       "roofline": {"kernel": "k_exact", "bound": "alu", "achieved": fx, "peak": PEAK_FP32_TFLOPS,
                                    "unit": "TFLOP/s", "frac": fx / PEAK_FP32_TFLOPS, "kernel_ms": kx["exact"],
-                                   "flop_per_launch": flop_exact}},
+                                   "flop_per_launch": flop_exact,
+                                   "traffic": profiled_traffic("k_exact_bin20k_traffic.md", GEOM_SOURCES)}},
         "trust_screening": {"value": M / (ms_t / 1e3), "unit": "motions/s", "ms_per_step": ms_t,
                             "verdict_agreement_vs_exact": float(np.mean(v_t == v_x))},
         "verdict_agreement_certified_vs_exact": float(np.mean(v_c == v_x)),

@@ -153,9 +153,15 @@ constexpr int kBRows = 32 * kRB;       // rows per block
 template <int W>
 constexpr int mlp_threads() { return 64 * (W / (32 * kFB)); }
 
-// Inputs: every (motion, point) pair of (mo, c), or with `rows` the c.n rows
-// rows[i][0:in_dim] (one motion slot, m = 0; layer 0 then runs unsplit per row).
-template <int W>
+// Output modes (one kernel instance each, so profiles tell the launches apart):
+//   kScreen: every (motion, point) pair of (mo, c); indices of the points with
+//            prediction < tau appended to lists[m][*], counts[m] advanced;
+//   kDense:  every pair; prediction written to out[m][point];
+//   kRows:   the c.n rows rows[i][0:in_dim] (one motion slot, m = 0; layer 0 then runs
+//            unsplit per row); prediction written to out[i].
+constexpr int kScreen = 0, kDense = 1, kRows = 2;
+
+template <int W, int kMode>
 __global__ __launch_bounds__(mlp_threads<W>(), 2) void k_mlp_bf16(MlpArgs net, MotionArgs mo, CloudArgs c, int tiles,
                                                                const float* __restrict__ rows, int64_t row_stride,
                                                                const __bf16* __restrict__ packed,
@@ -185,7 +191,7 @@ __global__ __launch_bounds__(mlp_threads<W>(), 2) void k_mlp_bf16(MlpArgs net, M
   typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
   const int pr = tid % P, rg = tid / P;
   const int ra = rg * (R / (RG > 0 ? RG : 1)), rz = ra + R / (RG > 0 ? RG : 1);
-  if (rows) {
+  if constexpr (kMode == kRows) {
     // z[f] = W0[f] . h0 + b0[f] per row
     for (int e = tid; e < R * in_dim; e += NT) {
       const int r = e / in_dim, j = e - r * in_dim;
@@ -312,8 +318,9 @@ __global__ __launch_bounds__(mlp_threads<W>(), 2) void k_mlp_bf16(MlpArgs net, M
     for (int w = 0; w < NW; ++w) y += part[w][r];
     const int i = r0 + r;
     const bool valid = i < c.n;
-    if (out && valid) out[(size_t)m * c.n + i] = y;
-    if (lists) {
+    if constexpr (kMode != kScreen) {
+      if (valid) out[(size_t)m * c.n + i] = y;
+    } else {
       const bool hit = valid && y < tau;
       const unsigned long long mask = __ballot(hit);
       const int n_hit = __popcll(mask);
@@ -328,24 +335,33 @@ __global__ __launch_bounds__(mlp_threads<W>(), 2) void k_mlp_bf16(MlpArgs net, M
 
 inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
-template <int W>
-hipError_t launch_bf16_t(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, const float* rows,
-                         int64_t row_stride, const __bf16* packed, float* out, float tau, int* lists, int* counts,
-                         hipStream_t st) {
+template <int W, int kMode>
+hipError_t launch_bf16_mode(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, const float* rows,
+                            int64_t row_stride, const __bf16* packed, float* out, float tau, int* lists, int* counts,
+                            hipStream_t st) {
   const int tiles = (c.n + kBRows - 1) / kBRows;
-  const int64_t blocks = (rows ? 1 : mo.n) * tiles;
+  const int64_t blocks = (kMode == kRows ? 1 : mo.n) * tiles;
   if (blocks == 0) return hipSuccess;
   const size_t lds = (size_t)kBRows * (W + kPad) * sizeof(__bf16);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_bf16<W>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_bf16<W, kMode>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_mlp_bf16<W>), dim3((unsigned)blocks), dim3(mlp_threads<W>()), lds, st, net, mo, c, tiles,
-                     rows, row_stride, packed, out, tau, lists, counts);
+  hipLaunchKernelGGL((k_mlp_bf16<W, kMode>), dim3((unsigned)blocks), dim3(mlp_threads<W>()), lds, st, net, mo, c,
+                     tiles, rows, row_stride, packed, out, tau, lists, counts);
   return hipGetLastError();
+}
+
+template <int W>
+hipError_t launch_bf16_t(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, const float* rows,
+                         int64_t row_stride, const __bf16* packed, float* out, float tau, int* lists, int* counts,
+                         hipStream_t st) {
+  if (rows) return launch_bf16_mode<W, kRows>(net, mo, c, rows, row_stride, packed, out, tau, lists, counts, st);
+  if (lists) return launch_bf16_mode<W, kScreen>(net, mo, c, rows, row_stride, packed, out, tau, lists, counts, st);
+  return launch_bf16_mode<W, kDense>(net, mo, c, rows, row_stride, packed, out, tau, lists, counts, st);
 }
 
 hipError_t launch_f32(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, const float* rows,

@@ -179,6 +179,82 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
                      const sv_motions* motions, const sv_cloud* cloud, sv_results* out, void* ws,
                      size_t ws_bytes, void* stream);
 
+/* ---- batches of uneven requests (Sec. IV-B's check, many callers at once) --------
+ * A request is one set of motions checked against one cloud: exactly the question of
+ * sv_check_motions without a network, answered with the same per-point arithmetic, so
+ * a request's results equal those of sv_check_motions on it bit for bit.
+ * sv_check_requests answers a whole batch with a fixed sequence of kernels whose
+ * launch shapes depend only on the capacities and the tile below, never on the
+ * request contents:
+ *   1. plan: validate every request, order them by estimated work (smallest first:
+ *      small requests then finish early), lay out per-request offsets;
+ *   2. capsule tables of every motion of every request;
+ *   3. one persistent exact-check kernel: its blocks take (request, motion, chunk of
+ *      point tiles) items from a device work queue; the block that finishes a
+ *      request's last item writes the request's results and stamps done_ticks;
+ *   4. FP64 recheck of the motions within 1e-5 m of eps (as sv_check_motions).
+ * The call can therefore be captured in a HIP graph once and replayed after the
+ * caller rewrites the request table (and the buffers it points to) within the same
+ * capacities. */
+typedef struct {
+  sv_motions motions;  /* LINEAR or SPLINE, any T in [1, caps.max_T] */
+  sv_cloud cloud;      /* cloud.n <= caps.max_points */
+  sv_results out;      /* dev [motions.n] each; n_fallback is not written */
+} sv_request;          /* the request table lives in device memory: dev [n_req] */
+
+typedef struct {
+  int32_t max_requests;  /* n_req <= max_requests <= 4096 */
+  int32_t max_T;         /* every request's T <= max_T */
+  int64_t max_motions;   /* sum of motions.n over the batch */
+  int64_t max_samples;   /* sum of motions.n * T over the batch */
+  int64_t max_points;    /* every request's cloud.n <= max_points < 2^31 */
+  int32_t max_band;      /* motions that can be rechecked in FP64 per call, >= 1 */
+} sv_batch_caps;
+
+/* Launch shape of the persistent exact-check kernel (chosen by an autotuner). */
+typedef struct {
+  int32_t ppl;            /* points per lane: 1, 2 or 4 */
+  int32_t threads;        /* threads per block: 64, 128 or 256 */
+  int32_t blocks_per_cu;  /* persistent blocks per compute unit: 1..32 */
+  int32_t tiles_per_item; /* point tiles (threads * ppl points each) per work item: 1..64 */
+} sv_tile;
+
+/* Bits of the device status word written by sv_check_requests. */
+enum {
+  SV_BATCH_BAD_REQUEST = 1,   /* a request is malformed (kind, T, sizes, NULL pointers): nothing computed */
+  SV_BATCH_OVER_CAPACITY = 2, /* the batch exceeds caps: nothing computed */
+  SV_BATCH_BAND_OVERFLOW = 4  /* more than max_band motions fell in the FP64 band: the excess keep
+                                 their FP32 verdicts */
+};
+
+/* Workspace bytes for batches within caps. */
+int sv_batch_workspace_size(const sv_robot* robot, const sv_batch_caps* caps, size_t* bytes);
+
+/* Exact check of every request of the batch.
+ * reqs: dev [n_req] request table (read by the kernels during the call).
+ * done_ticks: dev [n_req + 1] (may be NULL): done_ticks[r] = device wall-clock tick at
+ *   which request r's results became final (0 if nothing was computed);
+ *   done_ticks[n_req] = tick at which the batch started.  Ticks run at
+ *   sv_wall_clock_hz().
+ * status: dev [1] (may be NULL): 0, or an OR of SV_BATCH_* bits.  With
+ *   SV_BATCH_BAD_REQUEST or SV_BATCH_OVER_CAPACITY no result is written.
+ * tile: launch shape (NULL: the library's default).
+ * Host checks: robot, caps, tile, n_req <= caps->max_requests, workspace size.
+ * Concurrent calls must not share a workspace. */
+int sv_check_requests(const sv_robot* robot, const sv_request* reqs, int32_t n_req, const sv_batch_caps* caps,
+                      float eps, const sv_tile* tile, uint64_t* done_ticks, int32_t* status, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* The launch shapes sv_check_requests accepts, for an autotuner: writes up to
+ * `capacity` of them to tiles (may be NULL) and their total count to *n. */
+int sv_tile_candidates(sv_tile* tiles, int32_t capacity, int32_t* n);
+
+/* The default launch shape. */
+int sv_default_tile(sv_tile* tile);
+
+/* Frequency of the device wall clock that stamps done_ticks (current device). */
+int sv_wall_clock_hz(int64_t* hz);
+
 /* ---- learning the network from the exact check (Sec. IV-C, Sec. V) ---------------- */
 
 /* Training rows: samples[s] = (x[3], q0[dof], q1[dof], delta), i.e. in_dim + 1 floats per

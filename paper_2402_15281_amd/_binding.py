@@ -66,6 +66,29 @@ class sv_results(ctypes.Structure):
                 ("n_fallback", ctypes.c_void_p)]
 
 
+class sv_request(ctypes.Structure):
+    _fields_ = [("motions", sv_motions), ("cloud", sv_cloud), ("out", sv_results)]
+
+
+class sv_batch_caps(ctypes.Structure):
+    _fields_ = [("max_requests", ctypes.c_int32), ("max_T", ctypes.c_int32), ("max_motions", ctypes.c_int64),
+                ("max_samples", ctypes.c_int64), ("max_points", ctypes.c_int64), ("max_band", ctypes.c_int32)]
+
+
+class sv_tile(ctypes.Structure):
+    _fields_ = [("ppl", ctypes.c_int32), ("threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("tiles_per_item", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.ppl, self.threads, self.blocks_per_cu, self.tiles_per_item)
+
+    def __repr__(self):
+        return "sv_tile(ppl=%d, threads=%d, blocks_per_cu=%d, tiles_per_item=%d)" % self.as_tuple()
+
+
+SV_BATCH_BAD_REQUEST, SV_BATCH_OVER_CAPACITY, SV_BATCH_BAND_OVERFLOW = 1, 2, 4
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libsv.so not built at {LIB_PATH}; run `python -m paper_2402_15281_amd.build`")
@@ -99,9 +122,16 @@ def _load():
     lib.sv_train_step.argtypes = [ctypes.POINTER(sv_mlp), P, P, ctypes.POINTER(sv_train_hparams), P, I64, P, I64, P,
                                   P, P, ctypes.c_size_t, P]
     lib.sv_train_workspace_size.argtypes = [ctypes.POINTER(sv_mlp), I64, SZ]
+    lib.sv_batch_workspace_size.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_batch_caps), SZ]
+    lib.sv_check_requests.argtypes = [ctypes.POINTER(sv_robot), P, I32, ctypes.POINTER(sv_batch_caps), F32,
+                                      ctypes.POINTER(sv_tile), P, P, P, ctypes.c_size_t, P]
+    lib.sv_tile_candidates.argtypes = [ctypes.POINTER(sv_tile), I32, ctypes.POINTER(I32)]
+    lib.sv_default_tile.argtypes = [ctypes.POINTER(sv_tile)]
+    lib.sv_wall_clock_hz.argtypes = [ctypes.POINTER(I64)]
     for fn in ("sv_workspace_size", "sv_fk", "sv_exact_sdf", "sv_nn_sdf", "sv_check_motions", "sv_profile_enable",
                "sv_profile_read", "sv_make_samples", "sv_make_samples_workspace_size", "sv_nn_predict",
-               "sv_train_step", "sv_train_workspace_size"):
+               "sv_train_step", "sv_train_workspace_size", "sv_batch_workspace_size", "sv_check_requests",
+               "sv_tile_candidates", "sv_default_tile", "sv_wall_clock_hz"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -333,3 +363,82 @@ def sv_train_step(mlp: DeviceMLP, adam_m: torch.Tensor, adam_v: torch.Tensor, st
                              int(samples.shape[0]), _ptr(batch_idx), B, _ptr(loss_out), _ptr(grad_out), _ptr(ws),
                              ws.numel(), _stream(stream)))
     return ws
+
+
+# ------------------------------------------------------------- batched requests
+
+class DeviceRequests:
+    """A batch of requests (motions, cloud, results) and its request table in device memory.
+
+    requests: list of (DeviceMotions, DeviceCloud, DeviceResults).  The table is one
+    device tensor of sv_request records; rewrite() refreshes it in place (same
+    storage), so a captured graph that reads it sees the new contents.
+    """
+
+    def __init__(self, requests, device="cuda"):
+        self.requests = list(requests)
+        n = max(len(self.requests), 1)
+        self.table = torch.zeros(n * ctypes.sizeof(sv_request), dtype=torch.uint8, device=device)
+        self.rewrite()
+
+    @property
+    def n(self) -> int:
+        return len(self.requests)
+
+    def rewrite(self, requests=None):
+        if requests is not None:
+            if len(requests) > self.table.numel() // ctypes.sizeof(sv_request):
+                raise ValueError("more requests than the table holds")
+            self.requests = list(requests)
+        arr = (sv_request * max(self.n, 1))()
+        for i, (m, c, o) in enumerate(self.requests):
+            arr[i] = sv_request(m.desc(), c.desc(), o.desc())
+        host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+        self.table[:host.numel()].copy_(host)
+
+    def caps(self, max_band: int = 64, slack: float = 1.0) -> sv_batch_caps:
+        """Capacities that hold this batch (times slack)."""
+        ms = [m for m, _, _ in self.requests]
+        tot_m = sum(m.n for m in ms)
+        tot_s = sum(m.n * m.T for m in ms)
+        return sv_batch_caps(max(self.n, 1), max([m.T for m in ms] + [1]), max(int(tot_m * slack), 1),
+                             max(int(tot_s * slack), 1), max([c.n for _, c, _ in self.requests] + [0]), int(max_band))
+
+
+def sv_batch_workspace_size(robot: sv_robot, caps: sv_batch_caps) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib.sv_batch_workspace_size(ctypes.byref(robot), ctypes.byref(caps), ctypes.byref(n)))
+    return int(n.value)
+
+
+def sv_check_requests(robot: sv_robot, reqs: DeviceRequests, caps: sv_batch_caps, eps: float, tile: sv_tile = None,
+                      done_ticks: torch.Tensor = None, status: torch.Tensor = None, ws=None, n_req: int = None,
+                      stream=None):
+    """Exact check of every request of the batch (results into each request's DeviceResults)."""
+    if ws is None:
+        ws = workspace(sv_batch_workspace_size(robot, caps))
+    n = reqs.n if n_req is None else int(n_req)
+    _check(lib.sv_check_requests(ctypes.byref(robot), _ptr(reqs.table), n, ctypes.byref(caps), float(eps),
+                                 ctypes.byref(tile) if tile is not None else None, _ptr(done_ticks), _ptr(status),
+                                 _ptr(ws), ws.numel(), _stream(stream)))
+    return ws
+
+
+def sv_tile_candidates():
+    n = ctypes.c_int32(0)
+    _check(lib.sv_tile_candidates(None, 0, ctypes.byref(n)))
+    arr = (sv_tile * n.value)()
+    _check(lib.sv_tile_candidates(arr, n.value, ctypes.byref(n)))
+    return [sv_tile(*t.as_tuple()) for t in arr]
+
+
+def sv_default_tile() -> sv_tile:
+    t = sv_tile()
+    _check(lib.sv_default_tile(ctypes.byref(t)))
+    return t
+
+
+def sv_wall_clock_hz() -> int:
+    hz = ctypes.c_int64(0)
+    _check(lib.sv_wall_clock_hz(ctypes.byref(hz)))
+    return int(hz.value)

@@ -74,21 +74,6 @@ void prof_resolve() {
   g_prof_pending.clear();
 }
 
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-// Sequential carving of the caller's workspace.
-struct Carver {
-  char* base;
-  size_t off = 0;
-  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
-  template <typename T>
-  T* take(size_t count) {
-    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-    off = align_up(off + count * sizeof(T));
-    return p;
-  }
-};
 
 int check_robot(const sv_robot* r) {
   if (!r) return fail(SV_ERR_ARG, "robot is NULL");
@@ -203,6 +188,29 @@ size_t nn_sdf_bytes(const sv_mlp& n, int precision) {
 
 // Motions whose FP32 cloud distance lies within this band of eps are recomputed in FP64.
 constexpr float kCertBand = 1e-5f;
+
+int check_caps(const sv_batch_caps* c) {
+  if (!c) return fail(SV_ERR_ARG, "caps is NULL");
+  if (c->max_requests < 1 || c->max_requests > kMaxBatchRequests)
+    return fail(SV_ERR_ARG, "caps.max_requests %d outside 1..%d", c->max_requests, kMaxBatchRequests);
+  if (c->max_T < 1) return fail(SV_ERR_ARG, "caps.max_T must be >= 1");
+  if (c->max_motions < 1 || c->max_motions > 0x7fffffffLL)
+    return fail(SV_ERR_ARG, "caps.max_motions outside 1..2^31-1");
+  if (c->max_samples < 1) return fail(SV_ERR_ARG, "caps.max_samples must be >= 1");
+  if (c->max_points < 0 || c->max_points > 0x7fffffffLL) return fail(SV_ERR_ARG, "caps.max_points outside 0..2^31-1");
+  if (c->max_band < 1 || c->max_band > (1 << 20)) return fail(SV_ERR_ARG, "caps.max_band outside 1..2^20");
+  return SV_OK;
+}
+
+// The launch shapes offered to an autotuner (all accepted by sv_check_requests).
+std::vector<sv_tile> tile_candidates() {
+  std::vector<sv_tile> v;
+  for (int ppl : {1, 2, 4})
+    for (int threads : {64, 128, 256})
+      for (int bpc : {1, 2, 4, 8, 16, 32})
+        for (int tpi : {1, 2, 4, 8, 16, 32}) v.push_back(sv_tile{ppl, threads, bpc, tpi});
+  return v;
+}
 
 }  // namespace
 }  // namespace sv
@@ -569,6 +577,70 @@ int sv_train_step(const sv_mlp* mlp, float* adam_m, float* adam_v, const sv_trai
   e = launch_adam(const_cast<float*>(mlp->params), adam_m, adam_v, grad, (int64_t)n_params(*mlp), hp->lr, hp->beta1,
                   hp->beta2, hp->adam_eps, hp->step, st);
   return e == hipSuccess ? SV_OK : hip_fail(e, "adam");
+}
+
+int sv_batch_workspace_size(const sv_robot* robot, const sv_batch_caps* caps, size_t* bytes) {
+  int s;
+  if (!bytes) return fail(SV_ERR_ARG, "bytes is NULL");
+  if ((s = check_robot(robot)) || (s = check_caps(caps))) return s;
+  carve_batch(nullptr, *robot, *caps, bytes);
+  return SV_OK;
+}
+
+int sv_check_requests(const sv_robot* robot, const sv_request* reqs, int32_t n_req, const sv_batch_caps* caps,
+                      float eps, const sv_tile* tile, uint64_t* done_ticks, int32_t* status, void* ws,
+                      size_t ws_bytes, void* stream) {
+  int s;
+  if ((s = check_robot(robot)) || (s = check_caps(caps))) return s;
+  if (n_req < 0 || n_req > caps->max_requests)
+    return fail(SV_ERR_SHAPE, "n_req %d outside 0..caps.max_requests (%d)", n_req, caps->max_requests);
+  if (n_req > 0 && !reqs) return fail(SV_ERR_ARG, "request table is NULL");
+  if (isnan(eps)) return fail(SV_ERR_ARG, "eps is NaN");
+  sv_tile t{};
+  sv_default_tile(&t);
+  if (tile) t = *tile;
+  if (!batch_tile_supported(t))
+    return fail(SV_ERR_ARG, "unsupported tile (ppl %d, threads %d, blocks/CU %d, tiles/item %d)", t.ppl, t.threads,
+                t.blocks_per_cu, t.tiles_per_item);
+  size_t need = 0;
+  carve_batch(nullptr, *robot, *caps, &need);
+  if (!ws || ws_bytes < need) return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", need, ws_bytes);
+  if (n_req == 0) return SV_OK;
+  size_t unused = 0;
+  const BatchWs w = carve_batch(ws, *robot, *caps, &unused);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  {
+    ProfScope ps("batch", st);
+    e = launch_batch(*robot, reqs, n_req, *caps, eps, kCertBand, t, reinterpret_cast<unsigned long long*>(done_ticks),
+                     status, w, st);
+  }
+  return e == hipSuccess ? SV_OK : hip_fail(e, "batched check");
+}
+
+int sv_tile_candidates(sv_tile* tiles, int32_t capacity, int32_t* n) {
+  if (!n) return fail(SV_ERR_ARG, "n is NULL");
+  const std::vector<sv_tile> v = tile_candidates();
+  *n = (int32_t)v.size();
+  if (tiles)
+    for (int32_t i = 0; i < capacity && i < (int32_t)v.size(); ++i) tiles[i] = v[i];
+  return SV_OK;
+}
+
+int sv_default_tile(sv_tile* tile) {
+  if (!tile) return fail(SV_ERR_ARG, "tile is NULL");
+  *tile = sv_tile{2, 256, 8, 4};
+  return SV_OK;
+}
+
+int sv_wall_clock_hz(int64_t* hz) {
+  if (!hz) return fail(SV_ERR_ARG, "hz is NULL");
+  int dev = 0, khz = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess) return hip_fail(e, "wall clock rate");
+  *hz = (int64_t)khz * 1000;
+  return SV_OK;
 }
 
 }  // extern "C"

@@ -12,123 +12,10 @@
 //                  optional per-point output and per-motion (distance, index) min keys
 //   k_finalize     keys -> min distance, argmin, verdict; certified-band list
 //   k_fk64_table / k_exact64 / k_finalize64: FP64 recheck of the band list
-#include <math.h>
-
-#include "sv_internal.h"
+#include "sv_geom_common.h"
 
 namespace sv {
 namespace {
-
-constexpr unsigned long long kKeyEmpty = ~0ull;
-
-// Monotone map of a float onto uint32 so that unsigned order equals float order.
-__device__ __forceinline__ uint32_t ord_f32(float f) {
-  uint32_t u = __float_as_uint(f);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float unord_f32(uint32_t o) {
-  uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
-  return __uint_as_float(u);
-}
-__device__ __forceinline__ unsigned long long ord_f64(double f) {
-  unsigned long long u = (unsigned long long)__double_as_longlong(f);
-  return (u >> 63) ? ~u : (u | (1ull << 63));
-}
-__device__ __forceinline__ double unord_f64(unsigned long long o) {
-  unsigned long long u = (o >> 63) ? (o & ~(1ull << 63)) : ~o;
-  return __longlong_as_double((long long)u);
-}
-
-__device__ __forceinline__ void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
-
-// Path parameter of sample t of T.
-template <typename R>
-__device__ __forceinline__ R sample_s(int t, int T) {
-  return T > 1 ? (R)t / (R)(T - 1) : (R)0;
-}
-
-// Joint configuration q_s of one motion (eq. (2)).
-// Linear: q0 + s (q1 - q0).  Spline: per joint, the C2 cubic through (0, q0),
-// (1/3, v1), (2/3, v2), (1, q1) with zero end slopes.  With knot spacing 1/3 the
-// two interior slopes, already multiplied by the spacing, are
-//   h m1 = (4 (v2 - q0) - (q1 - v1)) / 5,   h m2 = (4 (q1 - v1) - (v2 - q0)) / 5,
-// and each segment is a cubic Hermite in u = 3 s - segment.
-template <typename R>
-__device__ __forceinline__ void motion_config(int kind, int dof, const float* q0, const float* q1,
-                                              const float* via, R s, R* q) {
-  if (kind == SV_LINEAR) {
-#pragma unroll
-    for (int j = 0; j < SV_MAX_DOF; ++j)
-      if (j < dof) {
-        R a = (R)q0[j], b = (R)q1[j];
-        q[j] = a + s * (b - a);
-      }
-    return;
-  }
-  R s3 = s * (R)3;
-  int seg = (int)s3;
-  seg = seg > 2 ? 2 : (seg < 0 ? 0 : seg);
-  R u = s3 - (R)seg;
-  R u2 = u * u, u3 = u2 * u;
-  R h00 = (R)2 * u3 - (R)3 * u2 + (R)1;
-  R h10 = u3 - (R)2 * u2 + u;
-  R h01 = (R)3 * u2 - (R)2 * u3;
-  R h11 = u3 - u2;
-#pragma unroll
-  for (int j = 0; j < SV_MAX_DOF; ++j)
-    if (j < dof) {
-      R y0 = (R)q0[j], y1 = (R)via[j], y2 = (R)via[dof + j], y3 = (R)q1[j];
-      R hm1 = ((R)4 * (y2 - y0) - (y3 - y1)) / (R)5;
-      R hm2 = ((R)4 * (y3 - y1) - (y2 - y0)) / (R)5;
-      R ya = seg == 0 ? y0 : (seg == 1 ? y1 : y2);
-      R yb = seg == 0 ? y1 : (seg == 1 ? y2 : y3);
-      R ma = seg == 0 ? (R)0 : (seg == 1 ? hm1 : hm2);
-      R mb = seg == 0 ? hm1 : (seg == 1 ? hm2 : (R)0);
-      q[j] = h00 * ya + h10 * ma + h01 * yb + h11 * mb;
-    }
-}
-
-// World endpoints of every capsule at configuration q (standard DH chain).
-// F holds the running frame [R | p] (3x4, row-major); after joint i it is frame i.
-template <typename R>
-__device__ __forceinline__ void fk_capsules(const RobotT<R>& rb, const R* q, R (&A)[SV_MAX_CAPS][3],
-                                            R (&B)[SV_MAX_CAPS][3]) {
-  R F[12] = {(R)1, (R)0, (R)0, (R)0, (R)0, (R)1, (R)0, (R)0, (R)0, (R)0, (R)1, (R)0};
-  for (int f = 0; f <= rb.dof; ++f) {
-    if (f > 0) {
-      const int i = f - 1;
-      R st, ct, sa, ca;
-      sincos_r(q[i] + rb.dh[i][3], &st, &ct);
-      sincos_r(rb.dh[i][1], &sa, &ca);
-      const R a = rb.dh[i][0], d = rb.dh[i][2];
-      // F <- F * [[ct, -st ca, st sa, a ct], [st, ct ca, -ct sa, a st], [0, sa, ca, d]]
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const R f0 = F[4 * r], f1 = F[4 * r + 1], f2 = F[4 * r + 2], f3 = F[4 * r + 3];
-        const R c0 = f0 * ct + f1 * st;
-        const R s0 = f1 * ct - f0 * st;   // row . (-st, ct, 0)
-        F[4 * r + 0] = c0;
-        F[4 * r + 1] = s0 * ca + f2 * sa;
-        F[4 * r + 2] = f2 * ca - s0 * sa;
-        F[4 * r + 3] = a * c0 + d * f2 + f3;
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < SV_MAX_CAPS; ++k) {
-      if (k < rb.n_caps) {
-        if (rb.fa[k] == f)
-#pragma unroll
-          for (int r = 0; r < 3; ++r)
-            A[k][r] = F[4 * r] * rb.pa[k][0] + F[4 * r + 1] * rb.pa[k][1] + F[4 * r + 2] * rb.pa[k][2] + F[4 * r + 3];
-        if (rb.fb[k] == f)
-#pragma unroll
-          for (int r = 0; r < 3; ++r)
-            B[k][r] = F[4 * r] * rb.pb[k][0] + F[4 * r + 1] * rb.pb[k][1] + F[4 * r + 2] * rb.pb[k][2] + F[4 * r + 3];
-      }
-    }
-  }
-}
 
 // ---------------------------------------------------------------- sv_fk
 template <typename R>
@@ -159,49 +46,11 @@ __global__ __launch_bounds__(256) void k_motion_table(Robot32 rb, MotionArgs mo,
   if (g >= mo.n * mo.T) return;
   const int64_t m = g / mo.T;
   const int t = (int)(g - m * mo.T);
-  float q[SV_MAX_DOF];
-  motion_config<float>(mo.kind, rb.dof, mo.q0 + m * rb.dof, mo.q1 + m * rb.dof,
-                       mo.via ? mo.via + m * 2 * rb.dof : nullptr, sample_s<float>(t, mo.T), q);
-  float A[SV_MAX_CAPS][3], B[SV_MAX_CAPS][3];
-  fk_capsules<float>(rb, q, A, B);
-#pragma unroll
-  for (int k = 0; k < SV_MAX_CAPS; ++k)
-    if (k < rb.n_caps) {
-      const float bx = B[k][0] - A[k][0], by = B[k][1] - A[k][1], bz = B[k][2] - A[k][2];
-      const float l2 = bx * bx + by * by + bz * bz;
-      CapEntry e;
-      e.ax = A[k][0]; e.ay = A[k][1]; e.az = A[k][2];
-      e.inv_l2 = l2 > 0.f ? 1.0f / l2 : 0.f;
-      e.bx = bx; e.by = by; e.bz = bz; e.r = rb.r[k];
-      table[(m * rb.n_caps + k) * mo.T + t] = e;
-    }
+  write_entries(rb, mo.kind, mo.q0 + m * rb.dof, mo.q1 + m * rb.dof, mo.via ? mo.via + m * 2 * rb.dof : nullptr, t,
+                mo.T, table + (size_t)m * rb.n_caps * mo.T + t, mo.T);
 }
 
 // ------------------------------------------------------------ exact check
-// Capsule entries are uniform across a wave: read them through the constant
-// address space so that they arrive in scalar registers (s_load).
-typedef float vf4 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(4))) const vf4* ConstF4Ptr;
-
-__device__ __forceinline__ CapEntry load_entry(ConstF4Ptr p, size_t idx) {
-  const vf4 lo = p[2 * idx], hi = p[2 * idx + 1];
-  CapEntry e;
-  e.ax = lo.x; e.ay = lo.y; e.az = lo.z; e.inv_l2 = lo.w;
-  e.bx = hi.x; e.by = hi.y; e.bz = hi.z; e.r = hi.w;
-  return e;
-}
-
-// Squared distance from (x, y, z) to the segment of entry e.  The closest-point
-// parameter is clamped to [0, 1]; the residual is formed explicitly (never as
-// |ap|^2 - dot^2 / |ab|^2, which cancels near the segment's axis).
-__device__ __forceinline__ float seg_d2(const CapEntry& e, float x, float y, float z) {
-  const float px = x - e.ax, py = y - e.ay, pz = z - e.az;
-  const float dot = px * e.bx + py * e.by + pz * e.bz;
-  const float u = __builtin_amdgcn_fmed3f(dot * e.inv_l2, 0.0f, 1.0f);
-  const float ex = px - u * e.bx, ey = py - u * e.by, ez = pz - u * e.bz;
-  return ex * ex + ey * ey + ez * ez;
-}
-
 // grid: one block per (motion slot, tile of NT*P points), tile fastest.
 // Lanes own points base + p*NT + tid.  For every capsule k: running min over t of
 // the squared distance, then sqrt - r; the point's distance is the min over k.
@@ -234,34 +83,8 @@ __global__ __launch_bounds__(NT) void k_exact(const CapEntry* __restrict__ table
     x[p] = ok ? px[i] : 0.f;
     y[p] = ok ? py[i] : 0.f;
     z[p] = ok ? pz[i] : 0.f;
-    best[p] = INFINITY;
   }
-  ConstF4Ptr tab = (ConstF4Ptr)table;
-  for (int k = 0; k < K; ++k) {
-    const size_t e = ((size_t)m * K + k) * T;
-    float m2[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) m2[p] = INFINITY;
-    int t = 0;
-    for (; t + 1 < T; t += 2) {
-      const CapEntry a = load_entry(tab, e + t);
-      const CapEntry b = load_entry(tab, e + t + 1);
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-        const float da = seg_d2(a, x[p], y[p], z[p]);
-        const float db = seg_d2(b, x[p], y[p], z[p]);
-        m2[p] = fminf(m2[p], fminf(da, db));
-      }
-    }
-    if (t < T) {
-      const CapEntry a = load_entry(tab, e + t);
-#pragma unroll
-      for (int p = 0; p < P; ++p) m2[p] = fminf(m2[p], seg_d2(a, x[p], y[p], z[p]));
-    }
-    const float r = load_entry(tab, e).r;
-#pragma unroll
-    for (int p = 0; p < P; ++p) best[p] = fminf(best[p], sqrtf(m2[p]) - r);
-  }
+  swept_min<P>((ConstF4Ptr)table, (size_t)m * K * T, T, K, x, y, z, best);
 
   if (sdf) {
 #pragma unroll
@@ -271,30 +94,9 @@ __global__ __launch_bounds__(NT) void k_exact(const CapEntry* __restrict__ table
     }
   }
   if (keys) {
-    unsigned long long key = kKeyEmpty;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int i = idx[p];
-      if (i >= 0) {
-        const unsigned long long kk = ((unsigned long long)ord_f32(best[p]) << 32) | (uint32_t)i;
-        key = kk < key ? kk : key;
-      }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const unsigned long long o = __shfl_xor(key, off, 64);
-      key = o < key ? o : key;
-    }
     __shared__ unsigned long long wmin[NT / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) wmin[wid] = key;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned long long k2 = wmin[0];
-#pragma unroll
-      for (int w = 1; w < NT / 64; ++w) k2 = wmin[w] < k2 ? wmin[w] : k2;
-      if (k2 != kKeyEmpty) atomicMin(keys + m, k2);
-    }
+    const unsigned long long k2 = block_min_key<NT>(lane_min_key<P>(best, idx), wmin);
+    if (threadIdx.x == 0 && k2 != kKeyEmpty) atomicMin(keys + m, k2);
   }
 }
 
@@ -305,22 +107,6 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n, unsign
 __global__ void k_fill_i32(int* __restrict__ p, int64_t n, int v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
-}
-
-__device__ __forceinline__ void decode_key(unsigned long long key, float* d, int* arg) {
-  if (key == kKeyEmpty) {
-    *d = INFINITY;
-    *arg = -1;
-  } else {
-    *d = unord_f32((uint32_t)(key >> 32));
-    *arg = (int)(uint32_t)(key & 0xffffffffu);
-  }
-}
-
-__device__ __forceinline__ void write_result(const sv_results& out, int64_t m, float d, int arg, float eps) {
-  if (out.min_dist) out.min_dist[m] = d;
-  if (out.argmin) out.argmin[m] = arg;
-  if (out.verdict) out.verdict[m] = (uint8_t)(d <= eps);
 }
 
 // Grid-stride over the motions of (mlist, mcount), or all M.
@@ -365,33 +151,9 @@ __global__ __launch_bounds__(256) void k_fk64_table(Robot64 rb, MotionArgs mo, c
     const int64_t slot = g / mo.T;
     const int t = (int)(g - slot * mo.T);
     const int64_t m = list[slot];
-    double q[SV_MAX_DOF];
-    motion_config<double>(mo.kind, rb.dof, mo.q0 + m * rb.dof, mo.q1 + m * rb.dof,
-                          mo.via ? mo.via + m * 2 * rb.dof : nullptr, sample_s<double>(t, mo.T), q);
-    double A[SV_MAX_CAPS][3], B[SV_MAX_CAPS][3];
-    fk_capsules<double>(rb, q, A, B);
-#pragma unroll
-    for (int k = 0; k < SV_MAX_CAPS; ++k)
-      if (k < rb.n_caps) {
-        CapEntry64 e;
-        e.ax = A[k][0]; e.ay = A[k][1]; e.az = A[k][2];
-        e.bx = B[k][0] - A[k][0]; e.by = B[k][1] - A[k][1]; e.bz = B[k][2] - A[k][2];
-        e.l2 = e.bx * e.bx + e.by * e.by + e.bz * e.bz;
-        e.r = rb.r[k];
-        table[(slot * rb.n_caps + k) * mo.T + t] = e;
-      }
+    write_entries64(rb, mo.kind, mo.q0 + m * rb.dof, mo.q1 + m * rb.dof, mo.via ? mo.via + m * 2 * rb.dof : nullptr,
+                    t, mo.T, table + (size_t)slot * rb.n_caps * mo.T + t, mo.T);
   }
-}
-
-__device__ __forceinline__ double seg_d2_64(const CapEntry64& e, double x, double y, double z) {
-  const double px = x - e.ax, py = y - e.ay, pz = z - e.az;
-  double u = 0.0;
-  if (e.l2 > 0.0) {
-    u = (px * e.bx + py * e.by + pz * e.bz) / e.l2;
-    u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
-  }
-  const double ex = px - u * e.bx, ey = py - u * e.by, ez = pz - u * e.bz;
-  return ex * ex + ey * ey + ez * ez;
 }
 
 // Grid-stride over (slot, tile of 256 points); per-slot min of the FP64 distance.
@@ -405,15 +167,7 @@ __global__ __launch_bounds__(256) void k_exact64(const CapEntry64* __restrict__ 
     const int tile = (int)(w - slot * tiles);
     const int i = tile * 256 + threadIdx.x;
     double best = INFINITY;
-    if (i < c.n) {
-      const double x = c.x[i], y = c.y[i], z = c.z[i];
-      const CapEntry64* e0 = table + (size_t)slot * K * T;
-      for (int k = 0; k < K; ++k) {
-        double m2 = INFINITY;
-        for (int t = 0; t < T; ++t) m2 = fmin(m2, seg_d2_64(e0[(size_t)k * T + t], x, y, z));
-        best = fmin(best, sqrt(m2) - e0[(size_t)k * T].r);
-      }
-    }
+    if (i < c.n) best = swept_min64(table + (size_t)slot * K * T, T, T, K, c.x[i], c.y[i], c.z[i]);
     unsigned long long key = i < c.n ? ord_f64(best) : kKeyEmpty;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {

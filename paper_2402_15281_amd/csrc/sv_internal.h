@@ -80,6 +80,55 @@ struct ExactShape {
   int threads;  // 64, 128, 256
 };
 
+// Sequential carving of the caller's workspace (256-byte aligned pieces); with a NULL
+// base it only counts bytes.
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+// ---- batched requests (sv_batch.hip) ----------------------------------------------
+constexpr int kMaxBatchRequests = 4096;
+
+// Device-side header of a batch call, written by the plan kernel.
+struct BatchPlan {
+  int status;                       // SV_BATCH_* bits
+  int band_count;                   // motions queued for the FP64 recheck (may exceed capacity)
+  int64_t total_items;              // work items of the batch (0 if nothing runs)
+  int64_t total_samples;            // (motion, sample) pairs of the batch
+  unsigned long long next_item;     // head of the work queue
+};
+
+// Workspace of a batch call: per-request arrays [max_requests] (offsets [+1]), keys
+// [max_motions], capsule table [max_samples * K], band arrays [max_band].
+struct BatchWs {
+  BatchPlan* plan;
+  int64_t *motion_off, *sample_off, *item_off;   // request order; item_off in work order
+  int64_t *n_motions, *n_samples, *n_items;
+  int *order, *tiles, *chunks, *remaining;        // order: work position -> request
+  unsigned long long* keys;
+  CapEntry* table;
+  int* band_list;                                 // global motion index
+  unsigned long long* keys64;
+  CapEntry64* table64;                            // [max_band][K][max_T]
+};
+
+bool batch_tile_supported(const sv_tile& t);
+// Carves ws (NULL: only sizes); *bytes = total.
+BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, size_t* bytes);
+hipError_t launch_batch(const sv_robot& rb, const sv_request* reqs, int n_req, const sv_batch_caps& caps, float eps,
+                        float band, const sv_tile& tile, unsigned long long* done_ticks, int* status,
+                        const BatchWs& w, hipStream_t st);
+
 // ---- launchers (sv_geom.hip) ------------------------------------------------------
 hipError_t launch_fk_configs(const sv_robot& rb, const float* q, int64_t n, float* caps, int fp64,
                              hipStream_t st);

@@ -124,6 +124,107 @@ def timed(sv, torch, fn, steps, warmup, kernels):
     return (t1 - t0) * 1e3 / steps, per
 
 
+def batched_requests(sv, torch, np, arm, reps=5):
+    """64 uneven SPLINE requests (1-2048 motions x 2k-200k bin points, log-uniform, T = 512):
+    one graph-captured sv_check_requests call vs one sv_check_motions call per request."""
+    import svgen
+    from paper_2402_15281_amd import autotune
+    t0 = time.perf_counter()
+    rq = svgen.make_requests(arm, 64, 4242)
+    dev = [(sv.DeviceMotions(r.motions), sv.DeviceCloud(r.cloud), sv.DeviceResults(r.motions.n)) for r in rq]
+    reqs = sv.DeviceRequests(dev)
+    robot = sv.make_robot(arm)
+    eps = 0.01
+    caps = reqs.caps(max_band=64)
+    ws = sv.workspace(sv.sv_batch_workspace_size(robot, caps))
+    M = sum(r.motions.n for r in rq)
+    pairs = sum(r.motions.n * r.cloud.shape[0] for r in rq)
+    T, K = rq[0].motions.T, arm.n_caps
+    log(f"requests: {len(rq)} requests, {M} motions, {pairs / 1e6:.1f}M pairs, built in {time.perf_counter() - t0:.1f} s")
+
+    # launch shape: tuned on every 4th request (same mix, a quarter of the work)
+    sub = sv.DeviceRequests(dev[::4])
+    sub_caps = sub.caps(max_band=64)
+    t1 = time.perf_counter()
+    tile, timings, _ = autotune.tune(robot, sub, sub_caps, eps, reps=2)
+    log(f"autotune: {len(timings)} shapes in {time.perf_counter() - t1:.1f} s -> {tile}")
+
+    hz = sv.sv_wall_clock_hz()
+    ticks = torch.zeros(len(rq) + 1, dtype=torch.int64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sv.sv_check_requests(robot, reqs, caps, eps, tile=tile, ws=ws, done_ticks=ticks, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            sv.sv_check_requests(robot, reqs, caps, eps, tile=tile, ws=ws, done_ticks=ticks, status=status, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    g.replay()
+    torch.cuda.synchronize()
+    b_ms, b_lat = [], []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        g.replay()
+        b.record()
+        b.synchronize()
+        b_ms.append(a.elapsed_time(b))
+        tk = ticks.cpu().numpy().astype(np.float64)
+        b_lat.append((tk[:-1] - tk[-1]) / hz * 1e3)
+    batched = [(o.min_dist.cpu().numpy(), o.argmin.cpu().numpy(), o.verdict.cpu().numpy()) for _, _, o in dev]
+
+    # per-request launches, in request order, on one stream
+    outs = [sv.DeviceResults(r.motions.n) for r in rq]
+    wss = [sv.workspace(sv.sv_workspace_size(sv.SV_OP_CHECK, robot, m, c)) for m, c, _ in dev]
+    def per_request():
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(rq) + 1)]
+        evs[0].record()
+        for i, (m, c, _) in enumerate(dev):
+            sv.sv_check_motions(robot, m, c, outs[i], eps, ws=wss[i])
+            evs[i + 1].record()
+        evs[-1].synchronize()
+        return evs[0].elapsed_time(evs[-1]), np.array([evs[0].elapsed_time(e) for e in evs[1:]])
+    per_request()
+    p_ms, p_lat = [], []
+    for _ in range(reps):
+        t_, l_ = per_request()
+        p_ms.append(t_)
+        p_lat.append(l_)
+    torch.cuda.synchronize()
+    same = all(np.array_equal(a[0].view(np.int32), o.min_dist.cpu().numpy().view(np.int32))
+               and np.array_equal(a[1], o.argmin.cpu().numpy()) and np.array_equal(a[2], o.verdict.cpu().numpy())
+               for a, o in zip(batched, outs))
+    bi, pi = int(np.argsort(b_ms)[len(b_ms) // 2]), int(np.argsort(p_ms)[len(p_ms) // 2])
+    bl, pl = b_lat[bi], p_lat[pi]
+    flop = FLOP_PER_SEGMENT_TEST * T * K * pairs
+    res = {
+        "workload": "64 requests, log-uniform 1-2048 spline motions x 2,000-200,000 bin points, T=512, eps=0.01 m",
+        "motions": M, "pairs": pairs, "tile": list(tile.as_tuple()),
+        "batched": {"ms": b_ms[bi], "motions_per_s": M / (b_ms[bi] / 1e3),
+                    "latency_ms_p50": float(np.percentile(bl, 50)), "latency_ms_p99": float(np.percentile(bl, 99)),
+                    "roofline": {"kernel": "sv_check_requests (whole call)", "bound": "alu",
+                                 "achieved": flop / (b_ms[bi] / 1e3) / 1e12, "peak": PEAK_FP32_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": flop / (b_ms[bi] / 1e3) / 1e12 / PEAK_FP32_TFLOPS},
+                    "launch": "one graph-captured call (plan, tables, persistent exact kernel, FP64 band recheck)"},
+        "per_request": {"ms": p_ms[pi], "motions_per_s": M / (p_ms[pi] / 1e3),
+                        "latency_ms_p50": float(np.percentile(pl, 50)),
+                        "latency_ms_p99": float(np.percentile(pl, 99)),
+                        "launch": "one sv_check_motions call per request, request order, one stream"},
+        "results_identical": bool(same),
+        "latency_definition": "all requests submitted at the batch start; latency = completion - start "
+                              "(device completion stamps for the batch, HIP events for per-request calls)",
+    }
+    log(f"requests: batched {b_ms[bi]:.1f} ms ({res['batched']['motions_per_s']:.0f} motions/s, p50 "
+        f"{res['batched']['latency_ms_p50']:.1f} ms, p99 {res['batched']['latency_ms_p99']:.1f} ms, "
+        f"{res['batched']['roofline']['achieved']:.1f} TFLOP/s); per-request {p_ms[pi]:.1f} ms (p50 "
+        f"{res['per_request']['latency_ms_p50']:.1f} ms, p99 {res['per_request']['latency_ms_p99']:.1f} ms); "
+        f"identical {same}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +234,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--train-motions", type=int, default=20000)
+    ap.add_argument("--no-batched", action="store_true", help="skip the uneven-request batch leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         log("this benchmark runs on exactly one GPU: the collision check is measured on one MI355X; "
@@ -268,6 +370,8 @@ def main():
                      "val_clamped_mae_m": {"untrained": ev0["mae_clamped"], "trained": ev1["mae_clamped"]},
                      "val_near_surface_mae_m": {"untrained": ev0["mae_near"], "trained": ev1["mae_near"]}},
     }
+    if not args.no_batched:
+        result["batched_requests"] = batched_requests(sv, torch, np, arm)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(arm, motions, pts, eps, args.cpu_seconds, v_x, mind)
     print(json.dumps(result), flush=True)

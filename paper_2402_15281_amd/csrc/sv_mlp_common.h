@@ -33,6 +33,19 @@ __device__ __forceinline__ float softplus_grad_from_out(float a) {
   return 1.0f - __builtin_amdgcn_exp2f(-a * 1.44269504088896341f);
 }
 
+// Weight tiles are read with buffer loads: the wave's slice of packed weights is one
+// buffer resource (a wave-uniform base and byte range in scalar registers), the lane's
+// 16-byte part of a tile is a 32-bit vector offset, and the tile index goes into the
+// scalar offset.  Unlike 64-bit per-lane pointers this needs no vector address
+// arithmetic in the MFMA loop, and a read past the range returns zeros instead of
+// touching other memory.  0x00020000 is the resource's format word for the gfx9 family.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t weight_rsrc(const __bf16* slice, int tiles) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)slice, (short)0, tiles * 1024, 0x00020000);
+}
+__device__ __forceinline__ bf16x8 load_tile(__amdgpu_buffer_rsrc_t rs, int lane_off, int tile) {
+  return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, lane_off, tile * 1024, 0));
+}
+
 // One layer's MFMA loop for one wave: output features [64 wid, 64 wid + 64) of the
 // 64 tile rows, i.e. 2 feature blocks (fb) x 2 row blocks (rb) of 32 x 32.
 // Wp: packed weights of this layer; Hin: LDS tile [64][W + pad].
@@ -50,8 +63,9 @@ __device__ __forceinline__ void layer_mfma(const __bf16* __restrict__ Wp, const 
   constexpr int LD = W + kLdsPad;
   static_assert(KS % kDepth == 0, "k-steps must fill the load ring");
   const int half = lane >> 5, col = lane & 31;
-  const bf16x8* A0 = reinterpret_cast<const bf16x8*>(Wp) + ((size_t)(2 * wid) * KS) * 64 + lane;
-  const bf16x8* A1 = A0 + (size_t)KS * 64;
+  const int wid_u = __builtin_amdgcn_readfirstlane(wid);
+  const __amdgpu_buffer_rsrc_t rs = weight_rsrc(Wp + (size_t)(2 * wid_u) * KS * 512, 2 * KS);
+  const int lo = lane * 16;
   const __bf16* B0 = Hin + col * LD + 8 * half;
   const __bf16* B1 = B0 + 32 * LD;
   acc00 = f32x16{};
@@ -72,8 +86,8 @@ __device__ __forceinline__ void layer_mfma(const __bf16* __restrict__ Wp, const 
   bf16x8 a0[kDepth], a1[kDepth];
 #pragma unroll
   for (int s = 0; s < kDepth; ++s) {
-    a0[s] = A0[(size_t)s * 64];
-    a1[s] = A1[(size_t)s * 64];
+    a0[s] = load_tile(rs, lo, s);
+    a1[s] = load_tile(rs, lo, KS + s);
   }
   bf16x8 b0 = *reinterpret_cast<const bf16x8*>(B0);
   bf16x8 b1 = *reinterpret_cast<const bf16x8*>(B1);
@@ -91,8 +105,8 @@ __device__ __forceinline__ void layer_mfma(const __bf16* __restrict__ Wp, const 
       acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[s], b0, acc10, 0, 0, 0);
       acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[s], b1, acc11, 0, 0, 0);
       if (ks + kDepth < KS) {
-        a0[s] = A0[(size_t)(kc + kDepth) * 64];
-        a1[s] = A1[(size_t)(kc + kDepth) * 64];
+        a0[s] = load_tile(rs, lo, kc + kDepth);
+        a1[s] = load_tile(rs, lo, KS + kc + kDepth);
       }
       b0 = nb0;
       b1 = nb1;
@@ -115,7 +129,9 @@ __device__ __forceinline__ void layer_mfma_fb(const __bf16* __restrict__ Wp, con
   constexpr int LD = W + kLdsPad;
   static_assert(KS % D == 0, "k-steps must fill the load ring");
   const int half = lane >> 5, col = lane & 31;
-  const bf16x8* A = reinterpret_cast<const bf16x8*>(Wp) + ((size_t)(FB * wf) * KS) * 64 + lane;
+  const int wf_u = __builtin_amdgcn_readfirstlane(wf);
+  const __amdgpu_buffer_rsrc_t rs = weight_rsrc(Wp + (size_t)(FB * wf_u) * KS * 512, FB * KS);
+  const int lo = lane * 16;
   const __bf16* B = Hin + (32 * RB * wr + col) * LD + 8 * half;
 #pragma unroll
   for (int fb = 0; fb < FB; ++fb) {
@@ -137,7 +153,7 @@ __device__ __forceinline__ void layer_mfma_fb(const __bf16* __restrict__ Wp, con
 #pragma unroll
   for (int s = 0; s < D; ++s)
 #pragma unroll
-    for (int fb = 0; fb < FB; ++fb) a[s][fb] = A[((size_t)fb * KS + s) * 64];
+    for (int fb = 0; fb < FB; ++fb) a[s][fb] = load_tile(rs, lo, fb * KS + s);
   bf16x8 b[RB];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) b[rb] = *reinterpret_cast<const bf16x8*>(B + 32 * rb * LD);
@@ -161,7 +177,7 @@ __device__ __forceinline__ void layer_mfma_fb(const __bf16* __restrict__ Wp, con
           acc[fb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s][fb], b[rb], acc[fb][rb], 0, 0, 0);
       if (ks + D < KS) {
 #pragma unroll
-        for (int fb = 0; fb < FB; ++fb) a[s][fb] = A[((size_t)fb * KS + kc + D) * 64];
+        for (int fb = 0; fb < FB; ++fb) a[s][fb] = load_tile(rs, lo, fb * KS + kc + D);
       }
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) b[rb] = nb[rb];

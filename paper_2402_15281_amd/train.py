@@ -121,8 +121,15 @@ def train(mlp, samples, recipe: TrainRecipe, val_rows=None, log=None, device="cu
     tl = TrainLog()
     step = 0
     t0 = time.perf_counter()
+
+    def epoch_order(ep):
+        # the seeded sample order of one epoch, staged in pinned memory so that its copy
+        # to the device is queued behind the running steps instead of waiting for them
+        return torch.from_numpy(svgen.permutation(recipe.seed * 7919 + ep, n)).pin_memory()
+
+    order = epoch_order(0)
     for ep in range(recipe.epochs):
-        perm = torch.as_tensor(svgen.permutation(recipe.seed * 7919 + ep, n), device=device)
+        perm = order.to(device, non_blocking=True)
         ep_loss = torch.zeros(1, dtype=torch.float32, device=device)
         for s in range(steps_per_epoch):
             idx = perm[s * recipe.batch:(s + 1) * recipe.batch]
@@ -130,6 +137,8 @@ def train(mlp, samples, recipe: TrainRecipe, val_rows=None, log=None, device="cu
             sv.sv_train_step(mlp, m, v, step, samples, idx, lr=recipe.lr, clamp_sigma=recipe.clamp_sigma,
                              loss_out=loss, ws=ws)
             ep_loss += loss * idx.shape[0]
+        if ep + 1 < recipe.epochs:
+            order = epoch_order(ep + 1)       # on the host while the GPU runs this epoch
         tl.epoch_loss.append(float(ep_loss.item()) / n)
         if val_rows is not None:
             tl.val_mae.append(val_mae(mlp, val_rows, recipe.clamp_sigma))

@@ -225,6 +225,83 @@ def batched_requests(sv, torch, np, arm, reps=5):
     return res
 
 
+def box_world_search(sv, torch, np, arm, train_epochs, reps=3):
+    """Alg. 1 on the box-world scenes: plain search (exact checks in the given order) vs
+    the network-guided search (proxy d_hat of every motion, then exact checks in Alg. 1's
+    order), per scene: time to the first free motion, exact checks, network evaluations."""
+    import svgen
+    from paper_2402_15281_amd import train as tr
+    w = svgen.WORKLOADS["boxworld"]
+    spec = svgen.MLPSpec(*w["mlp"])
+    t0 = time.perf_counter()
+    rec = tr.DataRecipe(cube_half=w["cube_half"], T=w["T"])
+    samples, _ = tr.make_dataset(arm, rec, seed=201)
+    val, _ = tr.make_dataset(arm, tr.DataRecipe(n_motions=2000, cube_half=w["cube_half"], T=w["T"]), seed=202)
+    mlp = sv.DeviceMLP(tr.init_params(spec, w["mlp_seed"]), *w["mlp"])
+    tlog = tr.train(mlp, samples, tr.TrainRecipe(epochs=train_epochs, batch=16384))
+    ev = tr.evaluate(mlp, val)
+    del samples
+    log(f"box world: network {w['mlp']} trained in {time.perf_counter() - t0:.1f} s, val clamped MAE "
+        f"{ev['mae_clamped'] * 1e3:.1f} mm")
+    robot = sv.make_robot(arm)
+    eps = w["eps"]
+    res = sv.search_result_tensor()
+    rows = []
+    for scene in range(w["scenes"]):
+        motions, pts = svgen.box_world_scene(arm, scene)
+        dm, dc = sv.DeviceMotions(motions), sv.DeviceCloud(pts)
+        d_hat = torch.empty(dm.n, device="cuda")
+        ws_s = sv.sv_first_free(robot, dm, dc, eps, res)
+        ws_n = sv.sv_nn_min(mlp, dm, dc, d_hat)
+        out = sv.DeviceResults(dm.n)
+        sv.sv_check_motions(robot, dm, dc, out, eps)
+        torch.cuda.synchronize()
+        free = float(1.0 - out.verdict.float().mean().item())
+
+        def plain():
+            sv.sv_first_free(robot, dm, dc, eps, res, ws=ws_s)
+
+        def guided():
+            sv.sv_nn_min(mlp, dm, dc, d_hat, ws=ws_n)
+            sv.sv_first_free(robot, dm, dc, eps, res, d_hat=d_hat, ws=ws_s)
+
+        rec_ = {"free_fraction": free}
+        for name, fn in (("plain", plain), ("guided", guided)):
+            fn()
+            torch.cuda.synchronize()
+            ms = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn()
+                b.record()
+                b.synchronize()
+                ms.append(a.elapsed_time(b))
+            r = sv.read_search_result(res)
+            ok = r["motion"] < 0 or bool(out.verdict[r["motion"]].item() == 0)
+            rec_[name] = {"ms": float(np.median(ms)), "n_exact": r["n_exact"], "n_nn": r["n_nn"],
+                          "n_exact_run": r["n_exact_run"], "found": r["motion"] >= 0, "answer_free": ok}
+        rows.append(rec_)
+    stat = lambda k1, k2: (float(np.mean([r[k1][k2] for r in rows])), float(np.std([r[k1][k2] for r in rows])))
+    out = {"workload": "box world: 100 scenes x (1 start, 100 goals), 50 boxes of 1-10 cm in a region scaled 1.2x "
+                       "to the arm, 0.1 points/cm^2, T=200, eps=5 mm, linear motions",
+           "scenes": len(rows),
+           "free_fraction_mean": float(np.mean([r["free_fraction"] for r in rows])),
+           "network": {"shape": list(w["mlp"]), "train_epochs": train_epochs, "train_batch": 16384,
+                       "train_rows": rec.n_motions * (rec.n_uniform + rec.n_near), "train_seconds": tlog.seconds,
+                       "val_clamped_mae_m": ev["mae_clamped"], "val_near_surface_mae_m": ev["mae_near"]},
+           "answers_free": all(r[k]["answer_free"] for r in rows for k in ("plain", "guided"))}
+    for k in ("plain", "guided"):
+        out[k] = {"ms_mean": stat(k, "ms")[0], "ms_std": stat(k, "ms")[1],
+                  "n_exact_mean": stat(k, "n_exact")[0], "n_exact_std": stat(k, "n_exact")[1],
+                  "n_nn_mean": stat(k, "n_nn")[0], "n_exact_run_mean": stat(k, "n_exact_run")[0],
+                  "found_fraction": float(np.mean([r[k]["found"] for r in rows]))}
+    log(f"box world: plain {out['plain']['ms_mean']:.3f} ms, {out['plain']['n_exact_mean']:.2f} exact checks; "
+        f"guided {out['guided']['ms_mean']:.3f} ms, {out['guided']['n_exact_mean']:.2f} exact checks, "
+        f"{out['guided']['n_nn_mean']:.2f} network checks; free fraction {out['free_fraction_mean']:.3f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +312,7 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--train-motions", type=int, default=20000)
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-request batch leg")
+    ap.add_argument("--no-boxworld", action="store_true", help="skip the box-world search leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         log("this benchmark runs on exactly one GPU: the collision check is measured on one MI355X; "
@@ -372,6 +450,8 @@ def main():
     }
     if not args.no_batched:
         result["batched_requests"] = batched_requests(sv, torch, np, arm)
+    if not args.no_boxworld:
+        result["alg1_box_world"] = box_world_search(sv, torch, np, arm, args.train_epochs)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(arm, motions, pts, eps, args.cpu_seconds, v_x, mind)
     print(json.dumps(result), flush=True)

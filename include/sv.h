@@ -255,6 +255,50 @@ int sv_default_tile(sv_tile* tile);
 /* Frequency of the device wall clock that stamps done_ticks (current device). */
 int sv_wall_clock_hz(int64_t* hz);
 
+/* ---- finding the first collision-free motion (Sec. IV-B, Alg. 1) ----------------- */
+
+/* Network proxy of the cloud distance, d_hat(X, m) = min over x in X of f_theta(x, q0_m,
+ * q1_m) (Sec. IV-B), for every motion: d_hat dev [M] (+inf when N = 0; NaN
+ * predictions are skipped).  BF16 network (mlp->width 128, 256 or 512), linear motions.
+ * Workspace: sv_nn_min_workspace_size. */
+int sv_nn_min(const sv_mlp* mlp, const sv_motions* motions, const sv_cloud* cloud, float* d_hat, void* ws,
+              size_t ws_bytes, void* stream);
+int sv_nn_min_workspace_size(const sv_mlp* mlp, const sv_motions* motions, size_t* bytes);
+
+/* Result of sv_first_free (written to device memory). */
+typedef struct {
+  int32_t motion;      /* index of the motion returned, -1 if no motion is free */
+  int32_t position;    /* its position in the visiting order (M if none) */
+  float dist;          /* its exact distance d(X, m) (+inf if none) */
+  int32_t n_exact;     /* exact checks made when the search runs one motion at a time: the
+                          visiting-order position of the answer + 1, or M */
+  int32_t n_exact_run; /* motions whose exact check this call completed (checks run in
+                          parallel, so motions past the answer may be checked too) */
+  int32_t n_first;     /* motions visited in the first loop (d_hat > eps); 0 without d_hat */
+  int32_t n_nn;        /* network evaluations of the one-at-a-time search: the original
+                          index of the answer + 1 if the first loop found it, else M; 0
+                          without d_hat */
+  int32_t status;      /* 0 */
+} sv_search_result;
+
+/* First collision-free motion of a set (Alg. 1).  The visiting order is:
+ *   d_hat == NULL: the given order (checking each motion in turn);
+ *   d_hat != NULL (dev [M], e.g. from sv_nn_min): first the motions with d_hat > eps in
+ *     the given order (the first loop), then the others by d_hat descending, equal
+ *     values in the given order (the second loop; NaN counts as -inf).
+ * The answer is the first motion in that order whose exact distance d(X, m) > eps,
+ * which is the motion Alg. 1 returns.  Exact checks run as one persistent launch over
+ * the visiting order; blocks stop taking motions that lie after an answer already
+ * found.  Distances are FP32; motions within 1e-5 m of eps are recomputed in FP64
+ * before they count as free.  1 <= M <= 4096 (M = 0 is a no-op that reports none).
+ * order: dev [M] (may be NULL) receives the visiting order.  result: dev, one record.
+ * Workspace: sv_first_free_workspace_size. */
+int sv_first_free(const sv_robot* robot, const sv_motions* motions, const sv_cloud* cloud, float eps,
+                  const float* d_hat, sv_search_result* result, int32_t* order, void* ws, size_t ws_bytes,
+                  void* stream);
+int sv_first_free_workspace_size(const sv_robot* robot, const sv_motions* motions, const sv_cloud* cloud,
+                                 size_t* bytes);
+
 /* ---- learning the network from the exact check (Sec. IV-C, Sec. V) ---------------- */
 
 /* Training rows: samples[s] = (x[3], q0[dof], q1[dof], delta), i.e. in_dim + 1 floats per

@@ -89,6 +89,12 @@ class sv_tile(ctypes.Structure):
 SV_BATCH_BAD_REQUEST, SV_BATCH_OVER_CAPACITY, SV_BATCH_BAND_OVERFLOW = 1, 2, 4
 
 
+class sv_search_result(ctypes.Structure):
+    _fields_ = [("motion", ctypes.c_int32), ("position", ctypes.c_int32), ("dist", ctypes.c_float),
+                ("n_exact", ctypes.c_int32), ("n_exact_run", ctypes.c_int32), ("n_first", ctypes.c_int32),
+                ("n_nn", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libsv.so not built at {LIB_PATH}; run `python -m paper_2402_15281_amd.build`")
@@ -128,10 +134,18 @@ def _load():
     lib.sv_tile_candidates.argtypes = [ctypes.POINTER(sv_tile), I32, ctypes.POINTER(I32)]
     lib.sv_default_tile.argtypes = [ctypes.POINTER(sv_tile)]
     lib.sv_wall_clock_hz.argtypes = [ctypes.POINTER(I64)]
+    lib.sv_nn_min.argtypes = [ctypes.POINTER(sv_mlp), ctypes.POINTER(sv_motions), ctypes.POINTER(sv_cloud), P, P,
+                              ctypes.c_size_t, P]
+    lib.sv_nn_min_workspace_size.argtypes = [ctypes.POINTER(sv_mlp), ctypes.POINTER(sv_motions), SZ]
+    lib.sv_first_free.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_motions), ctypes.POINTER(sv_cloud),
+                                  F32, P, P, P, P, ctypes.c_size_t, P]
+    lib.sv_first_free_workspace_size.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_motions),
+                                                 ctypes.POINTER(sv_cloud), SZ]
     for fn in ("sv_workspace_size", "sv_fk", "sv_exact_sdf", "sv_nn_sdf", "sv_check_motions", "sv_profile_enable",
                "sv_profile_read", "sv_make_samples", "sv_make_samples_workspace_size", "sv_nn_predict",
                "sv_train_step", "sv_train_workspace_size", "sv_batch_workspace_size", "sv_check_requests",
-               "sv_tile_candidates", "sv_default_tile", "sv_wall_clock_hz"):
+               "sv_tile_candidates", "sv_default_tile", "sv_wall_clock_hz", "sv_nn_min", "sv_nn_min_workspace_size",
+               "sv_first_free", "sv_first_free_workspace_size"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -442,3 +456,42 @@ def sv_wall_clock_hz() -> int:
     hz = ctypes.c_int64(0)
     _check(lib.sv_wall_clock_hz(ctypes.byref(hz)))
     return int(hz.value)
+
+
+# ------------------------------------------------------------- first free motion
+
+def sv_nn_min(mlp: DeviceMLP, motions: DeviceMotions, cloud: DeviceCloud, d_hat: torch.Tensor, ws=None,
+              stream=None):
+    """d_hat[m] <- min over the cloud of the BF16 network's prediction for motion m."""
+    md, cd, nd = motions.desc(), cloud.desc(), mlp.desc()
+    if ws is None:
+        n = ctypes.c_size_t(0)
+        _check(lib.sv_nn_min_workspace_size(ctypes.byref(nd), ctypes.byref(md), ctypes.byref(n)))
+        ws = workspace(n.value)
+    _check(lib.sv_nn_min(ctypes.byref(nd), ctypes.byref(md), ctypes.byref(cd), _ptr(d_hat), _ptr(ws), ws.numel(),
+                         _stream(stream)))
+    return ws
+
+
+def search_result_tensor(device="cuda"):
+    """Device buffer for one sv_search_result record."""
+    return torch.zeros(ctypes.sizeof(sv_search_result) // 4, dtype=torch.int32, device=device)
+
+
+def read_search_result(t: torch.Tensor) -> dict:
+    r = sv_search_result.from_buffer_copy(t.cpu().numpy().tobytes())
+    return {f: getattr(r, f) for f, _ in sv_search_result._fields_}
+
+
+def sv_first_free(robot: sv_robot, motions: DeviceMotions, cloud: DeviceCloud, eps: float, result: torch.Tensor,
+                  d_hat: torch.Tensor = None, order: torch.Tensor = None, ws=None, stream=None):
+    """First collision-free motion (Alg. 1); result is a search_result_tensor()."""
+    md, cd = motions.desc(), cloud.desc()
+    if ws is None:
+        n = ctypes.c_size_t(0)
+        _check(lib.sv_first_free_workspace_size(ctypes.byref(robot), ctypes.byref(md), ctypes.byref(cd),
+                                                ctypes.byref(n)))
+        ws = workspace(n.value)
+    _check(lib.sv_first_free(ctypes.byref(robot), ctypes.byref(md), ctypes.byref(cd), float(eps), _ptr(d_hat),
+                             _ptr(result), _ptr(order), _ptr(ws), ws.numel(), _stream(stream)))
+    return ws

@@ -618,6 +618,77 @@ int sv_check_requests(const sv_robot* robot, const sv_request* reqs, int32_t n_r
   return e == hipSuccess ? SV_OK : hip_fail(e, "batched check");
 }
 
+int sv_nn_min_workspace_size(const sv_mlp* mlp, const sv_motions* motions, size_t* bytes) {
+  int s;
+  if (!bytes) return fail(SV_ERR_ARG, "bytes is NULL");
+  if ((s = check_mlp(mlp, SV_BF16, 0)) || (s = check_motions(motions, 0))) return s;
+  Carver cv(nullptr);
+  cv.take<__bf16>(mlp_packed_elems(to_args(*mlp)));
+  cv.take<unsigned>((size_t)motions->n);
+  *bytes = cv.off;
+  return SV_OK;
+}
+
+int sv_nn_min(const sv_mlp* mlp, const sv_motions* motions, const sv_cloud* cloud, float* d_hat, void* ws,
+              size_t ws_bytes, void* stream) {
+  int s;
+  if ((s = check_mlp(mlp, SV_BF16, 0)) || (s = check_motions(motions, 0)) || (s = check_cloud(cloud))) return s;
+  if (motions->kind != SV_LINEAR) return fail(SV_ERR_UNSUPPORTED, "the network applies to linear motions only");
+  if (motions->n > 0 && !d_hat) return fail(SV_ERR_ARG, "d_hat is NULL");
+  size_t need = 0;
+  if ((s = sv_nn_min_workspace_size(mlp, motions, &need))) return s;
+  if (motions->n == 0) return SV_OK;
+  if (!ws || ws_bytes < need) return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", need, ws_bytes);
+  Carver cv(ws);
+  const MlpArgs na = to_args(*mlp);
+  __bf16* packed = cv.take<__bf16>(mlp_packed_elems(na));
+  unsigned* keys = cv.take<unsigned>((size_t)motions->n);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_fill_i32(reinterpret_cast<int*>(keys), motions->n, -1, st);
+  if (e == hipSuccess && cloud->n > 0) {
+    {
+      ProfScope ps("pack_bf16", st);
+      e = launch_pack_bf16(na, 0, packed, st);
+    }
+    if (e == hipSuccess) {
+      ProfScope ps("nn_min", st);
+      e = launch_mlp_min(na, to_args(*motions), to_args(*cloud), packed, keys, st);
+    }
+  }
+  if (e == hipSuccess) e = launch_decode_min(keys, motions->n, d_hat, st);
+  return e == hipSuccess ? SV_OK : hip_fail(e, "network minimum");
+}
+
+int sv_first_free_workspace_size(const sv_robot* robot, const sv_motions* motions, const sv_cloud* cloud,
+                                 size_t* bytes) {
+  int s;
+  if (!bytes) return fail(SV_ERR_ARG, "bytes is NULL");
+  if ((s = check_robot(robot)) || (s = check_motions(motions, robot->dof)) || (s = check_cloud(cloud))) return s;
+  if (motions->n > kMaxSearchMotions) return fail(SV_ERR_SHAPE, "more than %d motions", kMaxSearchMotions);
+  carve_search(nullptr, *robot, motions->n, motions->T, bytes);
+  return SV_OK;
+}
+
+int sv_first_free(const sv_robot* robot, const sv_motions* motions, const sv_cloud* cloud, float eps,
+                  const float* d_hat, sv_search_result* result, int32_t* order, void* ws, size_t ws_bytes,
+                  void* stream) {
+  int s;
+  size_t need = 0;
+  if ((s = sv_first_free_workspace_size(robot, motions, cloud, &need))) return s;
+  if (!result) return fail(SV_ERR_ARG, "result is NULL");
+  if (isnan(eps)) return fail(SV_ERR_ARG, "eps is NaN");
+  if (!ws || ws_bytes < need) return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", need, ws_bytes);
+  size_t unused = 0;
+  const SearchWs w = carve_search(ws, *robot, motions->n, motions->T, &unused);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  {
+    ProfScope ps("search", st);
+    e = launch_search(*robot, to_args(*motions), to_args(*cloud), eps, kCertBand, d_hat, result, order, w, st);
+  }
+  return e == hipSuccess ? SV_OK : hip_fail(e, "first free motion");
+}
+
 int sv_tile_candidates(sv_tile* tiles, int32_t capacity, int32_t* n) {
   if (!n) return fail(SV_ERR_ARG, "n is NULL");
   const std::vector<sv_tile> v = tile_candidates();

@@ -129,6 +129,39 @@ hipError_t launch_batch(const sv_robot& rb, const sv_request* reqs, int n_req, c
                         float band, const sv_tile& tile, unsigned long long* done_ticks, int* status,
                         const BatchWs& w, hipStream_t st);
 
+// ---- first collision-free motion (sv_search.hip) ----------------------------------
+constexpr int kMaxSearchMotions = 4096;
+
+struct SearchHdr {
+  int answer;                    // earliest position found free outside the band (M: none yet)
+  int n_run;                     // motions whose exact check completed
+  int band_count;                // motions queued for the FP64 recheck
+  int n_first;                   // first-loop motions (d_hat > eps)
+  unsigned long long next_item;  // head of the work queue
+};
+
+// Workspace of a search over M motions: per-position / per-motion arrays [M], the
+// capsule table [M][K][T] and its FP64 counterpart for the band recheck.
+struct SearchWs {
+  SearchHdr* hdr;
+  int *order, *remaining;
+  unsigned long long* keys;
+  float* dist_pos;
+  CapEntry* table;
+  int *band_list, *band_pos;
+  CapEntry64* table64;
+  unsigned long long* keys64;
+  float* d64;
+  uint8_t* v64;
+};
+
+SearchWs carve_search(void* ws, const sv_robot& rb, int64_t M, int T, size_t* bytes);
+hipError_t launch_search(const sv_robot& rb, const MotionArgs& mo, const CloudArgs& c, float eps, float band,
+                         const float* d_hat, sv_search_result* result, int* order_out, const SearchWs& w,
+                         hipStream_t st);
+// d_hat[m] <- the float of min key keys[m] (+inf for the empty key ~0u).
+hipError_t launch_decode_min(const unsigned* keys, int64_t M, float* d_hat, hipStream_t st);
+
 // ---- launchers (sv_geom.hip) ------------------------------------------------------
 hipError_t launch_fk_configs(const sv_robot& rb, const float* q, int64_t n, float* caps, int fp64,
                              hipStream_t st);
@@ -187,6 +220,11 @@ hipError_t launch_train_step(const MlpArgs& net, const float* samples, const int
                              float* loss_out, hipStream_t st);
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
                        float eps, int64_t step, hipStream_t st);
+
+// Per-motion minimum of the BF16 prediction over the cloud, folded into min_keys[m]
+// (order-preserving unsigned keys of the float; the caller fills them with ~0u first).
+hipError_t launch_mlp_min(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, const __bf16* packed,
+                          unsigned* min_keys, hipStream_t st);
 
 // out (optional): [M][N] predictions.  lists/counts (optional): per motion, the points
 // with prediction < tau are appended to lists[m * N ...] and counted in counts[m].

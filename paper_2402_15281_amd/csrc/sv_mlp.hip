@@ -15,6 +15,7 @@
 //                  per-motion list (screening).
 #include <math.h>
 
+#include "sv_geom_common.h"
 #include "sv_internal.h"
 #include "sv_mlp_common.h"
 
@@ -158,8 +159,11 @@ constexpr int mlp_threads() { return 64 * (W / (32 * kFB)); }
 //            prediction < tau appended to lists[m][*], counts[m] advanced;
 //   kDense:  every pair; prediction written to out[m][point];
 //   kRows:   the c.n rows rows[i][0:in_dim] (one motion slot, m = 0; layer 0 then runs
-//            unsplit per row); prediction written to out[i].
-constexpr int kScreen = 0, kDense = 1, kRows = 2;
+//            unsplit per row); prediction written to out[i];
+//   kMin:    every pair; the per-motion minimum over the cloud is folded into counts[m]
+//            read as an order-preserving unsigned key of the float (NaN predictions are
+//            skipped).
+constexpr int kScreen = 0, kDense = 1, kRows = 2, kMin = 3;
 
 template <int W, int kMode>
 __global__ __launch_bounds__(mlp_threads<W>(), 2) void k_mlp_bf16(MlpArgs net, MotionArgs mo, CloudArgs c, int tiles,
@@ -318,8 +322,13 @@ __global__ __launch_bounds__(mlp_threads<W>(), 2) void k_mlp_bf16(MlpArgs net, M
     for (int w = 0; w < NW; ++w) y += part[w][r];
     const int i = r0 + r;
     const bool valid = i < c.n;
-    if constexpr (kMode != kScreen) {
+    if constexpr (kMode == kDense || kMode == kRows) {
       if (valid) out[(size_t)m * c.n + i] = y;
+    } else if constexpr (kMode == kMin) {
+      float v = valid ? y : INFINITY;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+      if (lane == 0 && v < INFINITY) atomicMin(reinterpret_cast<unsigned*>(counts) + m, ord_f32(v));
     } else {
       const bool hit = valid && y < tau;
       const unsigned long long mask = __ballot(hit);
@@ -410,6 +419,17 @@ hipError_t launch_pack_bf16(const MlpArgs& net, int transpose, __bf16* packed, h
   hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)std::min<int64_t>(grid_for(total, 256), 4096)), dim3(256), 0, st, net,
                      transpose, packed);
   return hipGetLastError();
+}
+
+hipError_t launch_mlp_min(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, const __bf16* packed,
+                          unsigned* min_keys, hipStream_t st) {
+  int* k = reinterpret_cast<int*>(min_keys);
+  switch (net.width) {
+    case 128: return launch_bf16_mode<128, kMin>(net, mo, c, nullptr, 0, packed, nullptr, 0.f, nullptr, k, st);
+    case 256: return launch_bf16_mode<256, kMin>(net, mo, c, nullptr, 0, packed, nullptr, 0.f, nullptr, k, st);
+    case 512: return launch_bf16_mode<512, kMin>(net, mo, c, nullptr, 0, packed, nullptr, 0.f, nullptr, k, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_mlp_bf16(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, const __bf16* packed,

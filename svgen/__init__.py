@@ -255,6 +255,61 @@ def make_requests(arm: Arm, n_req: int, seed: int, m_range=(1, 2048), n_range=(2
     return reqs
 
 
+def _random_rotation(g: np.random.Generator) -> np.ndarray:
+    """Uniformly distributed rotation matrix (from a normalised Gaussian quaternion)."""
+    w, x, y, z = _unit4(g)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def _unit4(g: np.random.Generator):
+    q = g.normal(size=4)
+    return q / np.linalg.norm(q)
+
+
+def box_world(seed: int, n_boxes: int = 50, side=(0.01, 0.10), density: float = 1000.0,
+              region=((-1.0, 1.0), (-1.0, 1.0), (0.0, 1.5))) -> np.ndarray:
+    """Box-world cloud [n][3] (FP32-exact): points on the surfaces of n_boxes boxes.
+
+    Boxes: sides U[side]^3, a uniformly random orientation, centre uniform in the
+    region (the scenes of the paper's box-world experiment, Sec. V-B).  Points: density
+    per square metre of surface (0.1 per cm^2 = 1000 per m^2), spread over all faces in
+    proportion to area, uniform within a face.
+    """
+    g = _rng(seed)
+    faces = []
+    for _ in range(n_boxes):
+        s = g.uniform(side[0], side[1], size=3)
+        R = _random_rotation(g)
+        c = np.array([g.uniform(*region[0]), g.uniform(*region[1]), g.uniform(*region[2])])
+        e = [R[:, i] * s[i] for i in range(3)]                      # edge vectors
+        corner = c - 0.5 * (e[0] + e[1] + e[2])
+        for i, j, k in ((0, 1, 2), (1, 2, 0), (2, 0, 1)):
+            faces.append((corner, e[i], e[j]))
+            faces.append((corner + e[k], e[i], e[j]))
+    area = np.array([np.linalg.norm(np.cross(u, v)) for _, u, v in faces])
+    n = int(round(area.sum() * density))
+    counts = g.multinomial(n, area / area.sum())
+    pts = np.empty((n, 3))
+    i = 0
+    for (o, u, v), cnt in zip(faces, counts):
+        ab = g.uniform(0.0, 1.0, size=(cnt, 2))
+        pts[i:i + cnt] = o + ab[:, :1] * u + ab[:, 1:] * v
+        i += cnt
+    return _f32(pts[g.permutation(n)])
+
+
+def scene_motions(arm: Arm, n_goals: int, T: int, seed: int) -> Motions:
+    """One start configuration and n_goals goal configurations, uniform within the joint
+    limits: the linear motions start -> goal_j of one scene (Sec. V-B)."""
+    g = _rng(seed)
+    lo, hi = arm.qlim[:, 0], arm.qlim[:, 1]
+    q0 = _f32(g.uniform(lo, hi, size=(1, arm.dof)))
+    q1 = _f32(g.uniform(lo, hi, size=(n_goals, arm.dof)))
+    return Motions(q0=np.repeat(q0, n_goals, axis=0), q1=q1, T=int(T))
+
+
 # Named workloads (seeds explicit).  Sizes follow the workloads of the paper's
 # Sec. V as scaled up for a bin-picking batch on one GPU.
 WORKLOADS = {
@@ -262,4 +317,18 @@ WORKLOADS = {
                  cloud_seed=21, mlp=(15, 256, 4), mlp_seed=31),
     "bin20k": dict(arm_seed=1, motion_seed=12, n_motions=512, T=256, cloud="bin", n_points=20000,
                    cloud_seed=22, eps=0.01, tau=0.03, mlp=(15, 512, 8), mlp_seed=32),
+    # the box-world scenes of Sec. V-B (50 boxes of 1-10 cm, 0.1 points per cm^2, one start
+    # and 100 goals per scene, T = 200, eps = 5 mm) with the box region scaled by 1.2 to
+    # this arm's reach; a 5 x 512 network as in that experiment
+    "boxworld": dict(arm_seed=1, scenes=100, n_goals=100, T=200, eps=0.005, region_scale=1.2, scene_seed=300,
+                     mlp=(15, 512, 5), mlp_seed=33, cube_half=1.8),
 }
+
+
+def box_world_scene(arm: Arm, scene: int, w: dict = None):
+    """(motions, cloud) of box-world scene number `scene` of the named workload."""
+    w = w or WORKLOADS["boxworld"]
+    k = w["region_scale"]
+    region = ((-k, k), (-k, k), (0.0, 1.5 * k))
+    pts = box_world(w["scene_seed"] + 2 * scene, region=region)
+    return scene_motions(arm, w["n_goals"], w["T"], w["scene_seed"] + 2 * scene + 1), pts

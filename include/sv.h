@@ -174,7 +174,13 @@ int sv_nn_sdf(const sv_mlp* mlp, int precision, const sv_motions* motions, const
  *     +inf if none (TRUST).
  * Exact distances are FP32; every motion whose FP32 distance lies within 1e-5 m of eps
  * is recomputed in FP64 over all its points so that its verdict is the FP64 one
- * (min_dist then holds the FP64 value rounded to FP32).  Workspace: SV_OP_CHECK. */
+ * (min_dist then holds the FP64 value rounded to FP32).
+ * The exact passes over all points of a motion skip groups of (point, capsule, sample)
+ * tests that bounding spheres prove to lie above the motion's minimum (the cloud is
+ * put in Morton order internally; reported indices are the caller's).  Skipping never
+ * changes min_dist, argmin or verdict: they equal the unskipped computation bit for
+ * bit.  Workspace: SV_OP_CHECK; after a call its first 256 uint64 words sum to the
+ * number of segment tests those passes executed (a measurement aid). */
 int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float eps, float tau,
                      const sv_motions* motions, const sv_cloud* cloud, sv_results* out, void* ws,
                      size_t ws_bytes, void* stream);
@@ -362,6 +368,9 @@ int sv_train_workspace_size(const sv_mlp* mlp, int64_t batch, size_t* bytes);
  * summed elapsed milliseconds and the number of recorded launches of that group
  * since the last reset.  Do not enable while capturing a HIP graph. */
 int sv_profile_enable(int on);
+/* Switch the test skipping of sv_check_motions' exact passes off (0) or on (1, the
+ * default) for this process; results are identical either way.  Measurement aid. */
+int sv_set_exact_culling(int on);
 void sv_profile_reset(void);
 int sv_profile_read(const char* kernel, double* total_ms, int64_t* launches);
 

@@ -134,6 +134,7 @@ def _load():
     lib.sv_tile_candidates.argtypes = [ctypes.POINTER(sv_tile), I32, ctypes.POINTER(I32)]
     lib.sv_default_tile.argtypes = [ctypes.POINTER(sv_tile)]
     lib.sv_wall_clock_hz.argtypes = [ctypes.POINTER(I64)]
+    lib.sv_set_exact_culling.argtypes = [ctypes.c_int]
     lib.sv_nn_min.argtypes = [ctypes.POINTER(sv_mlp), ctypes.POINTER(sv_motions), ctypes.POINTER(sv_cloud), P, P,
                               ctypes.c_size_t, P]
     lib.sv_nn_min_workspace_size.argtypes = [ctypes.POINTER(sv_mlp), ctypes.POINTER(sv_motions), SZ]
@@ -145,7 +146,7 @@ def _load():
                "sv_profile_read", "sv_make_samples", "sv_make_samples_workspace_size", "sv_nn_predict",
                "sv_train_step", "sv_train_workspace_size", "sv_batch_workspace_size", "sv_check_requests",
                "sv_tile_candidates", "sv_default_tile", "sv_wall_clock_hz", "sv_nn_min", "sv_nn_min_workspace_size",
-               "sv_first_free", "sv_first_free_workspace_size"):
+               "sv_first_free", "sv_first_free_workspace_size", "sv_set_exact_culling"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -312,6 +313,15 @@ def sv_check_motions(robot: sv_robot, motions: DeviceMotions, cloud: DeviceCloud
     _check(lib.sv_check_motions(ctypes.byref(robot), mref, int(screen), float(eps), float(tau), ctypes.byref(md),
                                 ctypes.byref(cd), ctypes.byref(rd), _ptr(ws), ws.numel(), _stream(stream)))
     return ws
+
+
+def sv_set_exact_culling(on: bool = True):
+    _check(lib.sv_set_exact_culling(int(bool(on))))
+
+
+def executed_tests(ws: torch.Tensor) -> int:
+    """Segment tests the culled exact passes of the last sv_check_motions on ws ran."""
+    return int(ws[:8 * 256].cpu().numpy().view(np.uint64).sum())
 
 
 def sv_profile_enable(on: bool = True):

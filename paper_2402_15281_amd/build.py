@@ -21,7 +21,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsv.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["sv_api.hip", "sv_geom.hip", "sv_batch.hip", "sv_search.hip", "sv_mlp.hip", "sv_train.hip"]
+SOURCES = ["sv_api.hip", "sv_geom.hip", "sv_batch.hip", "sv_search.hip", "sv_cull.hip", "sv_mlp.hip", "sv_train.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -138,6 +138,8 @@ MlpArgs to_args(const sv_mlp& n) { return MlpArgs{n.in_dim, n.width, n.n_hidden,
 
 // Workspace layout of sv_check_motions.  The screening arrays are empty without a network.
 struct CheckWs {
+  unsigned long long* work;   // first 8 bytes: segment tests of the culled exact pass
+  CullWs cull;
   CapEntry* table;
   unsigned long long* keys;
   int* band;          // motions in the certified band (FP64 recheck)
@@ -156,6 +158,24 @@ CheckWs carve_check(void* ws, const sv_robot& r, const sv_motions& m, const sv_c
   Carver cv(ws);
   CheckWs w{};
   const size_t entries = (size_t)m.n * r.n_caps * m.T;
+  w.work = cv.take<unsigned long long>(kWorkSlots);
+  const size_t N = (size_t)c.n;
+  w.cull.bounds = cv.take<unsigned>(8);
+  w.cull.codes = cv.take<unsigned>(N);
+  w.cull.codes_sorted = cv.take<unsigned>(N);
+  w.cull.idx = cv.take<int>(N);
+  w.cull.perm = cv.take<int>(N);
+  w.cull.sx = cv.take<float>(N);
+  w.cull.sy = cv.take<float>(N);
+  w.cull.sz = cv.take<float>(N);
+  w.cull.sort_bytes = N > 0 ? cull_sort_bytes((int64_t)N) : 0;
+  w.cull.sort_tmp = cv.take<char>(w.cull.sort_bytes);
+  w.cull.spheres = cv.take<float4>((size_t)m.n * r.n_caps * cull_blocks(m.T));
+  w.cull.tile_spheres = cv.take<float4>((size_t)cull_tiles(c.n));
+  w.cull.list = cv.take<int>((size_t)m.n * cull_tiles(c.n) * r.n_caps);
+  w.cull.list_masks = cv.take<int>((size_t)m.n * cull_tiles(c.n) * r.n_caps);
+  w.cull.list_count = cv.take<int>(1);
+  w.cull.work = w.work;
   w.table = cv.take<CapEntry>(entries);
   w.keys = cv.take<unsigned long long>(m.n);
   w.band = cv.take<int>(m.n);
@@ -188,6 +208,9 @@ size_t nn_sdf_bytes(const sv_mlp& n, int precision) {
 
 // Motions whose FP32 cloud distance lies within this band of eps are recomputed in FP64.
 constexpr float kCertBand = 1e-5f;
+
+// Culled per-motion minimum in sv_check_motions (on unless switched off for measurement).
+bool g_cull = true;
 
 int check_caps(const sv_batch_caps* c) {
   if (!c) return fail(SV_ERR_ARG, "caps is NULL");
@@ -362,22 +385,29 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
   const int64_t M = motions->n;
   const ExactShape shape = default_exact_shape();
   hipError_t e;
-#define SV_TRY(name, call)        \
-  do {                            \
-    ProfScope ps_(name, st);      \
-    e = (call);                   \
-  } while (0);                    \
-  if (e != hipSuccess) return hip_fail(e, name)
+#define SV_TRY(name, call)                    \
+  do {                                        \
+    {                                         \
+      ProfScope ps_(name, st);                \
+      e = (call);                             \
+    }                                         \
+    if (e != hipSuccess) return hip_fail(e, name); \
+  } while (0)
 
   SV_TRY("init", launch_fill_u64(w.keys, M, ~0ull, st));
   SV_TRY("init", launch_fill_i32(w.band_count, 1, 0, st));
+  SV_TRY("init", launch_fill_u64(w.work, kWorkSlots, 0ull, st));
   const int* mlist = nullptr;
   const int* mcount = nullptr;
   if (cloud->n > 0) {
     SV_TRY("motion_table", launch_motion_table(*robot, ma, w.table, st));
     if (!screened) {
-      SV_TRY("exact", launch_exact(*robot, w.table, ma, ca, nullptr, nullptr, M, nullptr, nullptr, nullptr, w.keys,
-                                   shape, st));
+      if (g_cull) {
+        SV_TRY("exact", launch_exact_culled(*robot, w.table, ma, ca, nullptr, nullptr, M, w.keys, w.cull, st));
+      } else {
+        SV_TRY("exact", launch_exact(*robot, w.table, ma, ca, nullptr, nullptr, M, nullptr, nullptr, nullptr, w.keys,
+                                     shape, st));
+      }
     } else {
       const MlpArgs na = to_args(*mlp);
       SV_TRY("init", launch_fill_i32(w.pcount, M, 0, st));
@@ -389,8 +419,12 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
       SV_TRY("decide", launch_screen_decide(w.keys, M, w.pcount, eps, kCertBand, screen == SV_SCREEN_CERTIFIED, *out,
                                             w.full, w.full_count, st));
       if (screen == SV_SCREEN_CERTIFIED) {
-        SV_TRY("confirm", launch_exact(*robot, w.table, ma, ca, w.full, w.full_count, M, nullptr, nullptr, nullptr,
-                                       w.keys, shape, st));
+        if (g_cull) {
+          SV_TRY("confirm", launch_exact_culled(*robot, w.table, ma, ca, w.full, w.full_count, M, w.keys, w.cull, st));
+        } else {
+          SV_TRY("confirm", launch_exact(*robot, w.table, ma, ca, w.full, w.full_count, M, nullptr, nullptr, nullptr,
+                                         w.keys, shape, st));
+        }
         mlist = w.full;
         mcount = w.full_count;
       }
@@ -687,6 +721,11 @@ int sv_first_free(const sv_robot* robot, const sv_motions* motions, const sv_clo
     e = launch_search(*robot, to_args(*motions), to_args(*cloud), eps, kCertBand, d_hat, result, order, w, st);
   }
   return e == hipSuccess ? SV_OK : hip_fail(e, "first free motion");
+}
+
+int sv_set_exact_culling(int on) {
+  g_cull = on != 0;
+  return SV_OK;
 }
 
 int sv_tile_candidates(sv_tile* tiles, int32_t capacity, int32_t* n) {

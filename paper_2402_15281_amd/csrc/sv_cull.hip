@@ -1,0 +1,433 @@
+// Exact cloud distance per motion with culling (branch and bound), gfx950.
+//
+// sv_check_motions needs, per motion, only d(X, m) = min over the cloud of the swept
+// distance (Sec. IV-B) and the lowest index attaining it -- not every point's
+// distance.  Most (point, capsule, sample) tests of a motion are far above that
+// minimum, and whole groups of them can be proven so with two bounding spheres:
+//   - a wave's points: the cloud is put in Morton order first, so the 64 P points a
+//     wave holds are close together; their sphere is reduced across the wave;
+//   - a block of kCullB consecutive samples of one capsule: a sphere around all their
+//     segment endpoints, grown by the capsule radius (k_block_spheres).
+// If |c_wave - c_block| - R_wave - R_block exceeds an upper bound G of d(X, m) (plus
+// kCullMargin for FP32 rounding of the bound), every test of that group is larger than
+// the final minimum, so skipping it changes neither the minimum nor the lowest index
+// attaining it: per-motion results equal the unculled kernels' bit for bit.  G starts
+// from an exact check of a stride sample of the sorted cloud (k_exact_seed) and
+// tightens as waves finish capsules and as other blocks publish their minima.
+// Per-point distances are not produced here (skipped tests would leave them high).
+#include <hipcub/hipcub.hpp>
+
+#include "sv_geom_common.h"
+
+namespace sv {
+namespace {
+
+constexpr float kCullMargin = 1e-5f;   // m, above the FP32 rounding of the bounds
+constexpr int kCullB = 16;            // samples per bounding block
+constexpr int kSeedSampleStride = 4;  // the seed bound uses every 4th sample
+constexpr int kCullP = 2, kCullNT = 256;  // culled pass: points per lane, threads per block
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ float uniform_f(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ float key_dist(unsigned long long key) {
+  return key == kKeyEmpty ? INFINITY : unord_f32((uint32_t)(key >> 32));
+}
+
+// Axis-aligned bounds of the cloud as order-preserving keys: bounds[0..2] minima
+// (start ~0u), bounds[3..5] maxima (start 0).
+__global__ __launch_bounds__(256) void k_cloud_bounds(CloudArgs c, unsigned* __restrict__ bounds) {
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < c.n; i += gridDim.x * blockDim.x) {
+    const float v[3] = {c.x[i], c.y[i], c.z[i]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], v[a]);
+      hi[a] = fmaxf(hi[a], v[a]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = wave_min(lo[a]);
+    hi[a] = wave_max(hi[a]);
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (lo[a] < INFINITY) atomicMin(bounds + a, ord_f32(lo[a]));
+      if (hi[a] > -INFINITY) atomicMax(bounds + 3 + a, ord_f32(hi[a]));
+    }
+  }
+}
+
+// 10 bits per axis, interleaved: a 30-bit Morton code of each point within the bounds.
+__device__ __forceinline__ unsigned spread10(unsigned v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+__global__ __launch_bounds__(256) void k_morton(CloudArgs c, const unsigned* __restrict__ bounds,
+                                                unsigned* __restrict__ codes, int* __restrict__ idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n) return;
+  const float v[3] = {c.x[i], c.y[i], c.z[i]};
+  unsigned q[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float lo = unord_f32(bounds[a]), hi = unord_f32(bounds[3 + a]);
+    const float s = hi > lo ? 1023.0f / (hi - lo) : 0.f;
+    q[a] = (unsigned)fminf(fmaxf((v[a] - lo) * s, 0.f), 1023.f);
+  }
+  codes[i] = spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
+  idx[i] = i;
+}
+
+__global__ __launch_bounds__(256) void k_gather(CloudArgs c, const int* __restrict__ perm, float* __restrict__ sx,
+                                                float* __restrict__ sy, float* __restrict__ sz) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= c.n) return;
+  const int i = perm[j];
+  sx[j] = c.x[i];
+  sy[j] = c.y[i];
+  sz[j] = c.z[i];
+}
+
+// One thread per (motion, capsule, block of kCullB samples): centre of the endpoints'
+// bounding box and the largest endpoint distance from it plus the capsule radius.
+// The segment of every sample in the block lies in the convex hull of its endpoints,
+// hence inside that sphere.
+__global__ __launch_bounds__(256) void k_block_spheres(const CapEntry* __restrict__ table, int64_t M, int T, int K,
+                                                       int nb, float4* __restrict__ spheres) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= M * K * nb) return;
+  const int64_t mk = g / nb;
+  const int b = (int)(g - mk * nb);
+  const CapEntry* e = table + mk * T;
+  const int t0 = b * kCullB, t1 = min(t0 + kCullB, T);
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int t = t0; t < t1; ++t) {
+    const CapEntry q = e[t];
+    const float a[3] = {q.ax, q.ay, q.az}, d[3] = {q.ax + q.bx, q.ay + q.by, q.az + q.bz};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      lo[i] = fminf(lo[i], fminf(a[i], d[i]));
+      hi[i] = fmaxf(hi[i], fmaxf(a[i], d[i]));
+    }
+  }
+  const float cx = 0.5f * (lo[0] + hi[0]), cy = 0.5f * (lo[1] + hi[1]), cz = 0.5f * (lo[2] + hi[2]);
+  float r2 = 0.f;
+  for (int t = t0; t < t1; ++t) {
+    const CapEntry q = e[t];
+    const float ax = q.ax - cx, ay = q.ay - cy, az = q.az - cz;
+    const float bx = ax + q.bx, by = ay + q.by, bz = az + q.bz;
+    r2 = fmaxf(r2, fmaxf(ax * ax + ay * ay + az * az, bx * bx + by * by + bz * bz));
+  }
+  spheres[g] = make_float4(cx, cy, cz, sqrtf(r2) + e[t0].r);
+}
+
+// Upper bound of d(X, m) to start from: the smallest test distance over a stride
+// sample of the sorted cloud (thread i: sorted point i * stride) and every tstride-th
+// sample of the motion, folded into the motion's key.  Any subset of the tests gives a
+// value at or above the minimum, and each value is the distance of a real test, so it
+// cannot displace the true minimum or its index.
+__global__ __launch_bounds__(256) void k_exact_seed(const CapEntry* __restrict__ table, int T, int K,
+                                                    const float* __restrict__ sx, const float* __restrict__ sy,
+                                                    const float* __restrict__ sz, const int* __restrict__ perm, int N,
+                                                    int stride, int tstride, const int* __restrict__ mlist,
+                                                    const int* __restrict__ mcount,
+                                                    unsigned long long* __restrict__ keys) {
+  const int k = blockIdx.x % K;            // one capsule per block
+  const int slot = blockIdx.x / K;
+  if (mcount && slot >= *mcount) return;
+  const int m = mlist ? mlist[slot] : slot;
+  const int j = threadIdx.x * stride;
+  const bool ok = j < N;
+  const float x = ok ? sx[j] : 0.f, y = ok ? sy[j] : 0.f, z = ok ? sz[j] : 0.f;
+  int idx[1] = {ok ? perm[j] : -1};
+  const ConstF4Ptr tab = (ConstF4Ptr)table;
+  const size_t e = ((size_t)m * K + k) * T;
+  float m2 = INFINITY;
+  for (int t = 0; t < T; t += tstride) m2 = fminf(m2, seg_d2(load_entry(tab, e + t), x, y, z));
+  float best[1] = {sqrtf(m2) - load_entry(tab, e).r};
+  __shared__ unsigned long long wmin[4];
+  const unsigned long long k2 = block_min_key<256>(lane_min_key<1>(best, idx), wmin);
+  if (threadIdx.x == 0 && k2 != kKeyEmpty) atomicMin(keys + m, k2);
+}
+
+// Bounding sphere of each tile of kTilePts consecutive sorted points: centre of the
+// points' bounding box and the largest distance from it.  One block per tile.
+__global__ __launch_bounds__(256) void k_tile_spheres(const float* __restrict__ sx, const float* __restrict__ sy,
+                                                      const float* __restrict__ sz, int N, int tile_pts,
+                                                      float4* __restrict__ out) {
+  __shared__ float part[4][6];
+  __shared__ float pr[4];
+  const int j0 = blockIdx.x * tile_pts;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int j = j0 + threadIdx.x; j < min(j0 + tile_pts, N); j += blockDim.x) {
+    const float v[3] = {sx[j], sy[j], sz[j]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], v[a]);
+      hi[a] = fmaxf(hi[a], v[a]);
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = wave_min(lo[a]);
+    hi[a] = wave_max(hi[a]);
+  }
+  if (lane == 0)
+    for (int a = 0; a < 3; ++a) {
+      part[wid][a] = lo[a];
+      part[wid][3 + a] = hi[a];
+    }
+  __syncthreads();
+  float c[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float l = part[0][a], h = part[0][3 + a];
+    for (int q = 1; q < 4; ++q) {
+      l = fminf(l, part[q][a]);
+      h = fmaxf(h, part[q][3 + a]);
+    }
+    c[a] = 0.5f * (l + h);
+  }
+  float r2 = 0.f;
+  for (int j = j0 + threadIdx.x; j < min(j0 + tile_pts, N); j += blockDim.x) {
+    const float dx = sx[j] - c[0], dy = sy[j] - c[1], dz = sz[j] - c[2];
+    r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
+  }
+  r2 = wave_max(r2);
+  if (lane == 0) pr[wid] = r2;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = make_float4(c[0], c[1], c[2], sqrtf(fmaxf(fmaxf(pr[0], pr[1]), fmaxf(pr[2], pr[3]))));
+}
+
+// Coarse pass: one thread per (motion slot, tile, capsule); the capsule is kept for
+// the tile if any of its sample blocks may come within the motion's current bound of
+// the tile's sphere.  Kept (slot, tile) items are appended to (list, masks, count) --
+// one atomic per wave -- with a one-capsule mask: one capsule per item keeps the items
+// short, which balances the persistent blocks, since the surviving work concentrates
+// on the few tiles near the robot.
+__global__ __launch_bounds__(256) void k_cull_list(const float4* __restrict__ tile_sph,
+                                                   const float4* __restrict__ spheres, int K, int nb, int tiles,
+                                                   int64_t n_slots, const int* __restrict__ mlist,
+                                                   const int* __restrict__ mcount,
+                                                   const unsigned long long* __restrict__ keys,
+                                                   int* __restrict__ list, int* __restrict__ masks,
+                                                   int* __restrict__ count) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t slots = mcount ? (int64_t)*mcount : n_slots;
+  int mask = 0;
+  if (g < slots * tiles * K) {
+    const int k = (int)(g % K);
+    const int64_t st = g / K;
+    const int slot = (int)(st / tiles);
+    const int tile = (int)(st - (int64_t)slot * tiles);
+    const int m = mlist ? mlist[slot] : slot;
+    const float G = key_dist(keys[m]) + kCullMargin;
+    const float4 ts = tile_sph[tile];
+    const float4* sp = spheres + ((size_t)m * K + k) * nb;
+    bool keep = false;
+    for (int b = 0; b < nb && !keep; ++b) {
+      const float4 s = sp[b];
+      const float dx = s.x - ts.x, dy = s.y - ts.y, dz = s.z - ts.z;
+      keep = sqrtf(dx * dx + dy * dy + dz * dz) - ts.w - s.w <= G;
+    }
+    mask = keep ? 1 << k : 0;
+  }
+  const bool keep = mask != 0;
+  const unsigned long long ballot = __ballot(keep);
+  int base = 0;
+  if ((threadIdx.x & 63) == 0 && ballot) base = atomicAdd(count, __popcll(ballot));
+  base = __shfl(base, 0, 64);
+  const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0));
+  if (keep) {
+    list[base + rank] = (int)(g / K);
+    masks[base + rank] = mask;
+  }
+}
+
+// One listed item (motion slot, tile of NT P sorted points, mask of kept capsules) per
+// block iteration; each wave owns 64 P consecutive sorted points and decides per
+// (capsule, sample block) whether the group can come below its bound.  Persistent
+// blocks take items grid-stride.  work (optional) counts the executed segment tests.
+template <int P, int NT>
+__global__ __launch_bounds__(NT) void k_exact_cull(const CapEntry* __restrict__ table,
+                                                   const float4* __restrict__ spheres, int T, int K, int nb,
+                                                   const float* __restrict__ sx, const float* __restrict__ sy,
+                                                   const float* __restrict__ sz, const int* __restrict__ perm, int N,
+                                                   int tiles, const int* __restrict__ mlist,
+                                                   const int* __restrict__ list, const int* __restrict__ masks,
+                                                   const int* __restrict__ count,
+                                                   unsigned long long* __restrict__ keys,
+                                                   unsigned long long* __restrict__ work) {
+  __shared__ unsigned long long wexec[NT / 64];
+  __shared__ unsigned long long wmin[NT / 64];
+  const int n_items = *count;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  unsigned long long executed = 0;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int g = list[it];
+    const int cmask = masks[it];
+    const int slot = g / tiles;
+    const int tile = g - slot * tiles;
+    const int m = mlist ? mlist[slot] : slot;
+    const int base = tile * (NT * P) + wid * (64 * P) + lane;
+    float x[P], y[P], z[P], best[P];
+    int idx[P];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int j = base + p * 64;
+      const bool ok = j < N;
+      idx[p] = ok ? perm[j] : -1;
+      x[p] = ok ? sx[j] : 0.f;
+      y[p] = ok ? sy[j] : 0.f;
+      z[p] = ok ? sz[j] : 0.f;
+      best[p] = INFINITY;
+      if (ok) {
+        lo[0] = fminf(lo[0], x[p]); hi[0] = fmaxf(hi[0], x[p]);
+        lo[1] = fminf(lo[1], y[p]); hi[1] = fmaxf(hi[1], y[p]);
+        lo[2] = fminf(lo[2], z[p]); hi[2] = fmaxf(hi[2], z[p]);
+      }
+    }
+    const bool any = base < N;   // lane 0 holds the wave's first point
+    if (__builtin_amdgcn_readfirstlane((int)any)) {
+      // the wave's sphere
+      const float cx = uniform_f(0.5f * (wave_min(lo[0]) + wave_max(hi[0])));
+      const float cy = uniform_f(0.5f * (wave_min(lo[1]) + wave_max(hi[1])));
+      const float cz = uniform_f(0.5f * (wave_min(lo[2]) + wave_max(hi[2])));
+      float r2 = 0.f;
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        if (idx[p] >= 0) {
+          const float dx = x[p] - cx, dy = y[p] - cy, dz = z[p] - cz;
+          r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
+        }
+      const float rw = uniform_f(sqrtf(wave_max(r2)));
+      float G = uniform_f(key_dist(__hip_atomic_load(keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+      const ConstF4Ptr tab = (ConstF4Ptr)table;
+      for (int k = 0; k < K; ++k) {
+        if (!((cmask >> k) & 1)) continue;
+        const size_t e = ((size_t)m * K + k) * T;
+        const ConstF4Ptr sph = (ConstF4Ptr)(spheres + ((size_t)m * K + k) * nb);
+        const float r = load_entry(tab, e).r;
+        float m2[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) m2[p] = INFINITY;
+        for (int b = 0; b < nb; ++b) {
+          const vf4 sb = sph[b];
+          const float dx = sb.x - cx, dy = sb.y - cy, dz = sb.z - cz;
+          const float lb = sqrtf(dx * dx + dy * dy + dz * dz) - rw - sb.w;
+          if (lb > G + kCullMargin) continue;   // every test of the group exceeds the final minimum
+          const int t0 = b * kCullB, t1 = min(t0 + kCullB, T);
+          swept_range<P>(tab, e, t0, t1, x, y, z, m2);
+          executed += (unsigned long long)(t1 - t0) * (64 * P);
+          // tighten the bound with this wave's points
+          float wb = INFINITY;
+#pragma unroll
+          for (int p = 0; p < P; ++p)
+            if (idx[p] >= 0) wb = fminf(wb, sqrtf(m2[p]) - r);
+          G = uniform_f(fminf(G, wave_min(wb)));
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) best[p] = fminf(best[p], sqrtf(m2[p]) - r);
+      }
+    }
+    const unsigned long long k2 = block_min_key<NT>(lane_min_key<P>(best, idx), wmin);
+    // publish only a new minimum: most items end above the motion's current key
+    if (threadIdx.x == 0 && k2 < __hip_atomic_load(keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMin(keys + m, k2);
+    __syncthreads();
+  }
+  // executed tests: one add per block, spread over kWorkSlots counters (same-address
+  // atomics from every wave would serialise)
+  if (lane == 0) wexec[wid] = executed;
+  __syncthreads();
+  if (threadIdx.x == 0 && work) {
+    unsigned long long ex = 0;
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) ex += wexec[q];
+    if (ex) atomicAdd(work + blockIdx.x % kWorkSlots, ex);
+  }
+}
+
+inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+int device_cus_cull() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cus[dev] = v;
+  }
+  return cus[dev];
+}
+
+}  // namespace
+
+size_t cull_sort_bytes(int64_t N) {
+  size_t b = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const unsigned*)nullptr, (unsigned*)nullptr,
+                                           (const int*)nullptr, (int*)nullptr, (int)N, 0, 30, (hipStream_t)0);
+  return b;
+}
+
+int cull_blocks(int T) { return (T + kCullB - 1) / kCullB; }
+int cull_tiles(int64_t N) { return (int)((N + kCullNT * kCullP - 1) / (kCullNT * kCullP)); }
+
+hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const MotionArgs& mo, const CloudArgs& c,
+                               const int* mlist, const int* mcount, int64_t n_slots, unsigned long long* keys,
+                               const CullWs& w, hipStream_t st) {
+  if (n_slots == 0 || c.n == 0) return hipSuccess;
+  const int K = rb.n_caps, T = mo.T, nb = cull_blocks(T);
+  hipError_t e;
+  if ((e = launch_fill_i32(reinterpret_cast<int*>(w.bounds), 3, -1, st)) != hipSuccess) return e;
+  if ((e = launch_fill_i32(reinterpret_cast<int*>(w.bounds) + 3, 3, 0, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cloud_bounds, dim3(std::min<unsigned>(grid_for(c.n, 256), 1024)), dim3(256), 0, st, c,
+                     w.bounds);
+  hipLaunchKernelGGL(k_morton, dim3(grid_for(c.n, 256)), dim3(256), 0, st, c, w.bounds, w.codes, w.idx);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  size_t tb = w.sort_bytes;
+  if ((e = hipcub::DeviceRadixSort::SortPairs(w.sort_tmp, tb, w.codes, w.codes_sorted, w.idx, w.perm, c.n, 0, 30,
+                                              st)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(c.n, 256)), dim3(256), 0, st, c, w.perm, w.sx, w.sy, w.sz);
+  hipLaunchKernelGGL(k_block_spheres, dim3(grid_for(mo.n * K * nb, 256)), dim3(256), 0, st, table, mo.n, T, K, nb,
+                     w.spheres);
+  const int stride = std::max(1, c.n / 256);
+  hipLaunchKernelGGL(k_exact_seed, dim3((unsigned)(n_slots * K)), dim3(256), 0, st, table, T, K, w.sx, w.sy, w.sz, w.perm,
+                     c.n, stride, kSeedSampleStride, mlist, mcount, keys);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int tiles = (c.n + kCullNT * kCullP - 1) / (kCullNT * kCullP);
+  const int64_t items = n_slots * tiles;
+  if (items * K > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_tile_spheres, dim3((unsigned)tiles), dim3(256), 0, st, w.sx, w.sy, w.sz, c.n,
+                     kCullNT * kCullP, w.tile_spheres);
+  if ((e = launch_fill_i32(w.list_count, 1, 0, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cull_list, dim3(grid_for(items * K, 256)), dim3(256), 0, st, w.tile_spheres, w.spheres, K, nb,
+                     tiles, n_slots, mlist, mcount, keys, w.list, w.list_masks, w.list_count);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int blocks = (int)std::min<int64_t>(items * K, (int64_t)device_cus_cull() * 8);
+  hipLaunchKernelGGL((k_exact_cull<kCullP, kCullNT>), dim3(blocks), dim3(kCullNT), 0, st, table, w.spheres, T, K, nb,
+                     w.sx, w.sy, w.sz, w.perm, c.n, tiles, mlist, w.list, w.list_masks, w.list_count, keys, w.work);
+  return hipGetLastError();
+}
+
+}  // namespace sv

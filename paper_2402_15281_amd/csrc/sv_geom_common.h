@@ -229,10 +229,34 @@ __device__ __forceinline__ double swept_min64(const CapEntry64* __restrict__ e0,
   return best;
 }
 
+// Per lane: m2[p] <- min(m2[p], squared distance from point p to the segments of entries
+// e + t, t0 <= t < t1).  Samples are taken two at a time (the compiler merges the pair
+// into one three-way min); the minimum is exact, so how a range is split does not
+// change the result.
+template <int P>
+__device__ __forceinline__ void swept_range(ConstF4Ptr tab, size_t e, int t0, int t1, const float (&x)[P],
+                                            const float (&y)[P], const float (&z)[P], float (&m2)[P]) {
+  int t = t0;
+  for (; t + 1 < t1; t += 2) {
+    const CapEntry a = load_entry(tab, e + t);
+    const CapEntry b = load_entry(tab, e + t + 1);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const float da = seg_d2(a, x[p], y[p], z[p]);
+      const float db = seg_d2(b, x[p], y[p], z[p]);
+      m2[p] = fminf(m2[p], fminf(da, db));
+    }
+  }
+  if (t < t1) {
+    const CapEntry a = load_entry(tab, e + t);
+#pragma unroll
+    for (int p = 0; p < P; ++p) m2[p] = fminf(m2[p], seg_d2(a, x[p], y[p], z[p]));
+  }
+}
+
 // Per lane: best[p] = min over capsules k of (sqrt(min over samples t of the squared
 // distance from point p to segment k at t) - r_k), for the motion whose table entries
-// start at entry e0 and run [K][T].  Samples are taken two at a time (the compiler
-// merges the pair into one three-way min).
+// start at entry e0 and run [K][T].
 template <int P>
 __device__ __forceinline__ void swept_min(ConstF4Ptr tab, size_t e0, int T, int K, const float (&x)[P],
                                           const float (&y)[P], const float (&z)[P], float (&best)[P]) {
@@ -243,22 +267,7 @@ __device__ __forceinline__ void swept_min(ConstF4Ptr tab, size_t e0, int T, int 
     float m2[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) m2[p] = INFINITY;
-    int t = 0;
-    for (; t + 1 < T; t += 2) {
-      const CapEntry a = load_entry(tab, e + t);
-      const CapEntry b = load_entry(tab, e + t + 1);
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-        const float da = seg_d2(a, x[p], y[p], z[p]);
-        const float db = seg_d2(b, x[p], y[p], z[p]);
-        m2[p] = fminf(m2[p], fminf(da, db));
-      }
-    }
-    if (t < T) {
-      const CapEntry a = load_entry(tab, e + t);
-#pragma unroll
-      for (int p = 0; p < P; ++p) m2[p] = fminf(m2[p], seg_d2(a, x[p], y[p], z[p]));
-    }
+    swept_range<P>(tab, e, 0, T, x, y, z, m2);
     const float r = load_entry(tab, e).r;
 #pragma unroll
     for (int p = 0; p < P; ++p) best[p] = fminf(best[p], sqrtf(m2[p]) - r);

@@ -162,6 +162,35 @@ hipError_t launch_search(const sv_robot& rb, const MotionArgs& mo, const CloudAr
 // d_hat[m] <- the float of min key keys[m] (+inf for the empty key ~0u).
 hipError_t launch_decode_min(const unsigned* keys, int64_t M, float* d_hat, hipStream_t st);
 
+// ---- culled per-motion minimum (sv_cull.hip) ----------------------------------------
+// Workspace of the culled exact pass: cloud bounds and Morton sort, the sorted cloud
+// (SoA) with its permutation to the caller's indices, radix-sort scratch, and one
+// bounding sphere per (motion, capsule, block of samples).
+struct CullWs {
+  unsigned* bounds;                 // [6]
+  unsigned *codes, *codes_sorted;   // [N]
+  int *idx, *perm;                  // [N]
+  float *sx, *sy, *sz;              // [N]
+  void* sort_tmp;
+  size_t sort_bytes;
+  float4* spheres;                  // [M][K][cull_blocks(T)]
+  float4* tile_spheres;             // [cull_tiles(N)]
+  int* list;                        // [M * cull_tiles(N) * K] surviving (motion slot, tile) items
+  int* list_masks;                  // [M * cull_tiles(N) * K] the capsule(s) each item checks
+  int* list_count;                  // [1]
+  unsigned long long* work;         // [kWorkSlots] executed segment tests, summed (may be NULL)
+};
+constexpr int kWorkSlots = 256;
+size_t cull_sort_bytes(int64_t N);
+int cull_blocks(int T);
+int cull_tiles(int64_t N);
+// Per-motion (distance, index) keys of the motion slots (mlist/mcount as launch_exact)
+// over all points, with groups of tests that provably exceed the minimum skipped.
+// keys must hold kKeyEmpty or a valid upper bound on entry.
+hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const MotionArgs& mo, const CloudArgs& c,
+                               const int* mlist, const int* mcount, int64_t n_slots, unsigned long long* keys,
+                               const CullWs& w, hipStream_t st);
+
 // ---- launchers (sv_geom.hip) ------------------------------------------------------
 hipError_t launch_fk_configs(const sv_robot& rb, const float* q, int64_t n, float* caps, int fp64,
                              hipStream_t st);

@@ -126,7 +126,8 @@ def timed(sv, torch, fn, steps, warmup, kernels):
 
 def batched_requests(sv, torch, np, arm, reps=5):
     """64 uneven SPLINE requests (1-2048 motions x 2k-200k bin points, log-uniform, T = 512):
-    one graph-captured sv_check_requests call vs one sv_check_motions call per request."""
+    one graph-captured sv_check_requests call (culled pass) vs one sv_check_motions call
+    per request, and the unculled batched kernel under its autotuned launch shape."""
     import svgen
     from paper_2402_15281_amd import autotune
     t0 = time.perf_counter()
@@ -142,39 +143,53 @@ def batched_requests(sv, torch, np, arm, reps=5):
     T, K = rq[0].motions.T, arm.n_caps
     log(f"requests: {len(rq)} requests, {M} motions, {pairs / 1e6:.1f}M pairs, built in {time.perf_counter() - t0:.1f} s")
 
-    # launch shape: tuned on every 4th request (same mix, a quarter of the work)
-    sub = sv.DeviceRequests(dev[::4])
-    sub_caps = sub.caps(max_band=64)
-    t1 = time.perf_counter()
-    tile, timings, _ = autotune.tune(robot, sub, sub_caps, eps, reps=2)
-    log(f"autotune: {len(timings)} shapes in {time.perf_counter() - t1:.1f} s -> {tile}")
-
     hz = sv.sv_wall_clock_hz()
     ticks = torch.zeros(len(rq) + 1, dtype=torch.int64, device="cuda")
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
-    sv.sv_check_requests(robot, reqs, caps, eps, tile=tile, ws=ws, done_ticks=ticks, status=status)
-    torch.cuda.synchronize()
-    assert int(status.item()) == 0
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(s):
-        with torch.cuda.graph(g, stream=s):
-            sv.sv_check_requests(robot, reqs, caps, eps, tile=tile, ws=ws, done_ticks=ticks, status=status, stream=s)
-    torch.cuda.current_stream().wait_stream(s)
-    g.replay()
-    torch.cuda.synchronize()
-    b_ms, b_lat = [], []
-    for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
+
+    def graph_timing(tile, n):
+        sv.sv_check_requests(robot, reqs, caps, eps, tile=tile, ws=ws, done_ticks=ticks, status=status)
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                sv.sv_check_requests(robot, reqs, caps, eps, tile=tile, ws=ws, done_ticks=ticks, status=status,
+                                     stream=s)
+        torch.cuda.current_stream().wait_stream(s)
         g.replay()
-        b.record()
-        b.synchronize()
-        b_ms.append(a.elapsed_time(b))
-        tk = ticks.cpu().numpy().astype(np.float64)
-        b_lat.append((tk[:-1] - tk[-1]) / hz * 1e3)
-    batched = [(o.min_dist.cpu().numpy(), o.argmin.cpu().numpy(), o.verdict.cpu().numpy()) for _, _, o in dev]
+        torch.cuda.synchronize()
+        ms, lat = [], []
+        for _ in range(n):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            g.replay()
+            b.record()
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+            tk = ticks.cpu().numpy().astype(np.float64)
+            lat.append((tk[:-1] - tk[-1]) / hz * 1e3)
+        assert int(status.item()) == 0
+        outs_ = [(o.min_dist.cpu().numpy(), o.argmin.cpu().numpy(), o.verdict.cpu().numpy()) for _, _, o in dev]
+        return ms, lat, outs_
+
+    b_ms, b_lat, batched = graph_timing(None, reps)
+    b_exec = sv.executed_tests(ws)
+
+    # the unculled persistent kernel, launch shape tuned on every 4th request (same mix,
+    # a quarter of the work)
+    sv.sv_set_exact_culling(False)
+    try:
+        sub = sv.DeviceRequests(dev[::4])
+        sub_caps = sub.caps(max_band=64)
+        t1 = time.perf_counter()
+        tile, timings, _ = autotune.tune(robot, sub, sub_caps, eps, reps=2)
+        log(f"autotune (unculled kernel): {len(timings)} shapes in {time.perf_counter() - t1:.1f} s -> {tile}")
+        u_ms, _, unculled = graph_timing(tile, 2)
+    finally:
+        sv.sv_set_exact_culling(True)
 
     # per-request launches, in request order, on one stream
     outs = [sv.DeviceResults(r.motions.n) for r in rq]
@@ -188,28 +203,36 @@ def batched_requests(sv, torch, np, arm, reps=5):
         evs[-1].synchronize()
         return evs[0].elapsed_time(evs[-1]), np.array([evs[0].elapsed_time(e) for e in evs[1:]])
     per_request()
+    p_exec = sum(sv.executed_tests(w_) for w_ in wss)
     p_ms, p_lat = [], []
     for _ in range(reps):
         t_, l_ = per_request()
         p_ms.append(t_)
         p_lat.append(l_)
     torch.cuda.synchronize()
-    same = all(np.array_equal(a[0].view(np.int32), o.min_dist.cpu().numpy().view(np.int32))
-               and np.array_equal(a[1], o.argmin.cpu().numpy()) and np.array_equal(a[2], o.verdict.cpu().numpy())
-               for a, o in zip(batched, outs))
+    def same_as(x):
+        return all(np.array_equal(a[0].view(np.int32), b[0].view(np.int32)) and np.array_equal(a[1], b[1])
+                   and np.array_equal(a[2], b[2]) for a, b in zip(batched, x))
+    per = [(o.min_dist.cpu().numpy(), o.argmin.cpu().numpy(), o.verdict.cpu().numpy()) for o in outs]
+    same = same_as(per) and same_as(unculled)
     bi, pi = int(np.argsort(b_ms)[len(b_ms) // 2]), int(np.argsort(p_ms)[len(p_ms) // 2])
     bl, pl = b_lat[bi], p_lat[pi]
+    u = min(u_ms)
     flop = FLOP_PER_SEGMENT_TEST * T * K * pairs
     res = {
         "workload": "64 requests, log-uniform 1-2048 spline motions x 2,000-200,000 bin points, T=512, eps=0.01 m",
-        "motions": M, "pairs": pairs, "tile": list(tile.as_tuple()),
+        "motions": M, "pairs": pairs, "segment_tests_dense": T * K * pairs,
         "batched": {"ms": b_ms[bi], "motions_per_s": M / (b_ms[bi] / 1e3),
                     "latency_ms_p50": float(np.percentile(bl, 50)), "latency_ms_p99": float(np.percentile(bl, 99)),
-                    "roofline": {"kernel": "sv_check_requests (whole call)", "bound": "alu",
-                                 "achieved": flop / (b_ms[bi] / 1e3) / 1e12, "peak": PEAK_FP32_TFLOPS,
-                                 "unit": "TFLOP/s", "frac": flop / (b_ms[bi] / 1e3) / 1e12 / PEAK_FP32_TFLOPS},
-                    "launch": "one graph-captured call (plan, tables, persistent exact kernel, FP64 band recheck)"},
+                    "executed_tests": b_exec, "executed_fraction": b_exec / (T * K * pairs),
+                    "launch": "one graph-captured call: plan, tables, counting sort of all clouds by (request, "
+                              "Morton cell), bounds, culled item list, persistent culled kernel, FP64 band recheck"},
+        "batched_unculled": {"ms": u, "motions_per_s": M / (u / 1e3), "tile": list(tile.as_tuple()),
+                             "roofline": {"kernel": "sv_check_requests, culling off (whole call)", "bound": "alu",
+                                          "achieved": flop / (u / 1e3) / 1e12, "peak": PEAK_FP32_TFLOPS,
+                                          "unit": "TFLOP/s", "frac": flop / (u / 1e3) / 1e12 / PEAK_FP32_TFLOPS}},
         "per_request": {"ms": p_ms[pi], "motions_per_s": M / (p_ms[pi] / 1e3),
+                        "executed_tests": p_exec, "executed_fraction": p_exec / (T * K * pairs),
                         "latency_ms_p50": float(np.percentile(pl, 50)),
                         "latency_ms_p99": float(np.percentile(pl, 99)),
                         "launch": "one sv_check_motions call per request, request order, one stream"},
@@ -218,8 +241,10 @@ def batched_requests(sv, torch, np, arm, reps=5):
                               "(device completion stamps for the batch, HIP events for per-request calls)",
     }
     log(f"requests: batched {b_ms[bi]:.1f} ms ({res['batched']['motions_per_s']:.0f} motions/s, p50 "
-        f"{res['batched']['latency_ms_p50']:.1f} ms, p99 {res['batched']['latency_ms_p99']:.1f} ms, "
-        f"{res['batched']['roofline']['achieved']:.1f} TFLOP/s); per-request {p_ms[pi]:.1f} ms (p50 "
+        f"{res['batched']['latency_ms_p50']:.1f} ms, p99 {res['batched']['latency_ms_p99']:.1f} ms, executed "
+        f"{res['batched']['executed_fraction']:.4f}); unculled "
+        f"{u:.1f} ms ({res['batched_unculled']['roofline']['achieved']:.1f} TFLOP/s); per-request {p_ms[pi]:.1f} ms "
+        f"(executed {res['per_request']['executed_fraction']:.4f}, p50 "
         f"{res['per_request']['latency_ms_p50']:.1f} ms, p99 {res['per_request']['latency_ms_p99']:.1f} ms); "
         f"identical {same}")
     return res
@@ -366,6 +391,14 @@ def main():
                                            ws=ws_x if net is None else ws_n)
 
     ms_x, kx = timed(sv, torch, check(out_x), args.steps, args.warmup, ["exact"])
+    executed = sv.executed_tests(ws_x)            # segment tests the culled pass ran (last call)
+    # the dense kernel (every test, no culling): the roofline of the exact arithmetic
+    out_d = sv.DeviceResults(dm.n)
+    sv.sv_set_exact_culling(False)
+    ms_d, kd = timed(sv, torch, check(out_d), max(args.steps // 2, 1), 1, ["exact"])
+    sv.sv_set_exact_culling(True)
+    dense_same = bool(torch.equal(out_d.min_dist.view(torch.int32), out_x.min_dist.view(torch.int32))
+                      and torch.equal(out_d.argmin, out_x.argmin) and torch.equal(out_d.verdict, out_x.verdict))
     ms_t, kt = timed(sv, torch, check(out_t, mlp, sv.SV_SCREEN_TRUST), max(args.steps // 2, 1), 1,
                      ["screen", "fallback"])
     ms_u, ku = timed(sv, torch, check(out_u, untrained, sv.SV_SCREEN_CERTIFIED), max(args.steps // 2, 1), 1,
@@ -398,11 +431,15 @@ def main():
               "sample": "32 of the 512 motions x all 20,000 points, BF16 network vs exact distances"}
 
     flop_exact = FLOP_PER_SEGMENT_TEST * motions.T * arm.n_caps * M * N
-    fx = flop_exact / (kx["exact"] / 1e3) / 1e12
+    fd = flop_exact / (kd["exact"] / 1e3) / 1e12                       # dense kernel, all tests
+    fx = FLOP_PER_SEGMENT_TEST * executed / (kx["exact"] / 1e3) / 1e12  # culled pass, executed tests
+    fx_eff = flop_exact / (kx["exact"] / 1e3) / 1e12                   # culled pass, all tests' worth
     flop_mlp = mlp_flops_per_query(in_dim, width, n_hidden) * M * N
     fm = flop_mlp / (kc["screen"] / 1e3) / 1e12
-    log(f"exact:     {ms_x:.3f} ms/step = {M / ms_x * 1e3:.0f} motions/s; k_exact {kx['exact']:.3f} ms = "
-        f"{fx:.1f} TFLOP/s ({fx / PEAK_FP32_TFLOPS:.1%} of FP32 peak)")
+    log(f"exact:     {ms_x:.3f} ms/step = {M / ms_x * 1e3:.0f} motions/s; culled pass {kx['exact']:.3f} ms, "
+        f"{executed / (M * N * motions.T * arm.n_caps):.4f} of the tests executed at {fx:.1f} TFLOP/s "
+        f"({fx / PEAK_FP32_TFLOPS:.1%} of FP32 peak); dense kernel {kd['exact']:.3f} ms = {fd:.1f} TFLOP/s "
+        f"({fd / PEAK_FP32_TFLOPS:.1%}), results identical {dense_same}")
     log(f"certified: {ms_c:.3f} ms/step = {value:.0f} motions/s; network {kc['screen']:.3f} ms = {fm:.1f} TFLOP/s "
         f"({fm / PEAK_BF16_TFLOPS:.1%} of BF16 peak); fallback {kc['fallback']:.3f} ms; confirm {kc['confirm']:.3f} ms")
     log(f"trust:     {ms_t:.3f} ms/step; verdict agreement trust {np.mean(v_t == v_x):.4f}, "
@@ -427,10 +464,19 @@ def main():
                      "kernel_ms": kc["screen"], "flop_per_launch": flop_mlp,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
         "exact_gpu": {"value": M / (ms_x / 1e3), "unit": "motions/s", "ms_per_step": ms_x, "dtype": "f32",
-                      "roofline": {"kernel": "k_exact", "bound": "alu", "achieved": fx, "peak": PEAK_FP32_TFLOPS,
-                                   "unit": "TFLOP/s", "frac": fx / PEAK_FP32_TFLOPS, "kernel_ms": kx["exact"],
-                                   "flop_per_launch": flop_exact,
-                                   "traffic": profiled_traffic("k_exact_bin20k_traffic.md", GEOM_SOURCES)}},
+                      "culling": {"pass_ms": kx["exact"], "executed_tests": executed,
+                                  "executed_fraction": executed / (M * N * motions.T * arm.n_caps),
+                                  "executed_tflops": fx, "executed_frac_of_fp32_peak": fx / PEAK_FP32_TFLOPS,
+                                  "all_tests_equivalent_tflops": fx_eff,
+                                  "note": "culling skips groups of tests proven above the motion's minimum; "
+                                          "results equal the dense kernel's bit for bit"},
+                      "dense_kernel": {"value": M / (ms_d / 1e3), "ms_per_step": ms_d, "results_identical": dense_same,
+                                       "roofline": {"kernel": "k_exact", "bound": "alu", "achieved": fd,
+                                                    "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                                                    "frac": fd / PEAK_FP32_TFLOPS, "kernel_ms": kd["exact"],
+                                                    "flop_per_launch": flop_exact,
+                                                    "traffic": profiled_traffic("k_exact_bin20k_traffic.md",
+                                                                                GEOM_SOURCES)}}},
         "trust_screening": {"value": M / (ms_t / 1e3), "unit": "motions/s", "ms_per_step": ms_t,
                             "verdict_agreement_vs_exact": float(np.mean(v_t == v_x))},
         "verdict_agreement_certified_vs_exact": float(np.mean(v_c == v_x)),

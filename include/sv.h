@@ -195,9 +195,15 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
  *   1. plan: validate every request, order them by estimated work (smallest first:
  *      small requests then finish early), lay out per-request offsets;
  *   2. capsule tables of every motion of every request;
- *   3. one persistent exact-check kernel: its blocks take (request, motion, chunk of
- *      point tiles) items from a device work queue; the block that finishes a
- *      request's last item writes the request's results and stamps done_ticks;
+ *   3. the exact check, skipping (as sv_check_motions does) the (motion, 512-point
+ *      tile, capsule) items and the sample blocks that provably cannot lower a
+ *      motion's minimum: all clouds are sorted together by (request, Morton code), a
+ *      seed bound and bounding spheres are computed for every request, the surviving
+ *      items are listed in work order, and one persistent kernel takes them in that
+ *      order; the block that retires a request's last item writes the request's
+ *      results and stamps done_ticks.  With culling switched off
+ *      (sv_set_exact_culling(0)) a persistent kernel of the given tile shape takes
+ *      (request, motion, chunk of point tiles) items from a device work queue;
  *   4. FP64 recheck of the motions within 1e-5 m of eps (as sv_check_motions).
  * The call can therefore be captured in a HIP graph once and replayed after the
  * caller rewrites the request table (and the buffers it points to) within the same
@@ -215,9 +221,12 @@ typedef struct {
   int64_t max_samples;   /* sum of motions.n * T over the batch */
   int64_t max_points;    /* every request's cloud.n <= max_points < 2^31 */
   int32_t max_band;      /* motions that can be rechecked in FP64 per call, >= 1 */
-} sv_batch_caps;
+  int64_t max_total_points; /* sum of cloud.n over the batch (< 2^30); 0: max_requests * max_points,
+                               which must then be < 2^30 */
+} sv_batch_caps;          /* also max_motions * ceil(max_points / 512) * 16 < 2^31 */
 
-/* Launch shape of the persistent exact-check kernel (chosen by an autotuner). */
+/* Launch shape of the persistent exact-check kernel without culling (chosen by an
+ * autotuner); the culled pass has a fixed shape and only validates it. */
 typedef struct {
   int32_t ppl;            /* points per lane: 1, 2 or 4 */
   int32_t threads;        /* threads per block: 64, 128 or 256 */
@@ -245,6 +254,8 @@ int sv_batch_workspace_size(const sv_robot* robot, const sv_batch_caps* caps, si
  * status: dev [1] (may be NULL): 0, or an OR of SV_BATCH_* bits.  With
  *   SV_BATCH_BAD_REQUEST or SV_BATCH_OVER_CAPACITY no result is written.
  * tile: launch shape (NULL: the library's default).
+ * ws: after a call, its first 256 uint64 words sum to the number of segment tests the
+ *   culled pass executed (a measurement aid; 0 with culling off).
  * Host checks: robot, caps, tile, n_req <= caps->max_requests, workspace size.
  * Concurrent calls must not share a workspace. */
 int sv_check_requests(const sv_robot* robot, const sv_request* reqs, int32_t n_req, const sv_batch_caps* caps,

@@ -72,7 +72,8 @@ class sv_request(ctypes.Structure):
 
 class sv_batch_caps(ctypes.Structure):
     _fields_ = [("max_requests", ctypes.c_int32), ("max_T", ctypes.c_int32), ("max_motions", ctypes.c_int64),
-                ("max_samples", ctypes.c_int64), ("max_points", ctypes.c_int64), ("max_band", ctypes.c_int32)]
+                ("max_samples", ctypes.c_int64), ("max_points", ctypes.c_int64), ("max_band", ctypes.c_int32),
+                ("max_total_points", ctypes.c_int64)]
 
 
 class sv_tile(ctypes.Structure):
@@ -320,7 +321,8 @@ def sv_set_exact_culling(on: bool = True):
 
 
 def executed_tests(ws: torch.Tensor) -> int:
-    """Segment tests the culled exact passes of the last sv_check_motions on ws ran."""
+    """Segment tests the culled exact passes of the last sv_check_motions or
+    sv_check_requests call on ws ran."""
     return int(ws[:8 * 256].cpu().numpy().view(np.uint64).sum())
 
 
@@ -425,8 +427,10 @@ class DeviceRequests:
         ms = [m for m, _, _ in self.requests]
         tot_m = sum(m.n for m in ms)
         tot_s = sum(m.n * m.T for m in ms)
+        tot_p = sum(c.n for _, c, _ in self.requests)
         return sv_batch_caps(max(self.n, 1), max([m.T for m in ms] + [1]), max(int(tot_m * slack), 1),
-                             max(int(tot_s * slack), 1), max([c.n for _, c, _ in self.requests] + [0]), int(max_band))
+                             max(int(tot_s * slack), 1), max([c.n for _, c, _ in self.requests] + [0]), int(max_band),
+                             max(int(tot_p * slack), 1))
 
 
 def sv_batch_workspace_size(robot: sv_robot, caps: sv_batch_caps) -> int:

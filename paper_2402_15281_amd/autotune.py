@@ -1,6 +1,8 @@
 """Autotuner for the launch shape of the batched exact check (sv_tile).
 
-The persistent kernel of sv_check_requests has four shape parameters:
+The unculled persistent kernel of sv_check_requests (the one that runs when exact-check
+culling is switched off with sv_set_exact_culling(0); the culled pass has a fixed
+shape) has four shape parameters:
 - points per lane;
 - threads per block;
 - resident blocks per compute unit;

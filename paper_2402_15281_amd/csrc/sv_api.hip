@@ -173,7 +173,7 @@ CheckWs carve_check(void* ws, const sv_robot& r, const sv_motions& m, const sv_c
   w.cull.spheres = cv.take<float4>((size_t)m.n * r.n_caps * cull_blocks(m.T));
   w.cull.tile_spheres = cv.take<float4>((size_t)cull_tiles(c.n));
   w.cull.list = cv.take<int>((size_t)m.n * cull_tiles(c.n) * r.n_caps);
-  w.cull.list_masks = cv.take<int>((size_t)m.n * cull_tiles(c.n) * r.n_caps);
+  w.cull.list_caps = cv.take<int>((size_t)m.n * cull_tiles(c.n) * r.n_caps);
   w.cull.list_count = cv.take<int>(1);
   w.cull.work = w.work;
   w.table = cv.take<CapEntry>(entries);
@@ -222,6 +222,13 @@ int check_caps(const sv_batch_caps* c) {
   if (c->max_samples < 1) return fail(SV_ERR_ARG, "caps.max_samples must be >= 1");
   if (c->max_points < 0 || c->max_points > 0x7fffffffLL) return fail(SV_ERR_ARG, "caps.max_points outside 0..2^31-1");
   if (c->max_band < 1 || c->max_band > (1 << 20)) return fail(SV_ERR_ARG, "caps.max_band outside 1..2^20");
+  if (c->max_total_points < 0) return fail(SV_ERR_ARG, "caps.max_total_points is negative");
+  const int64_t pts = c->max_total_points > 0 ? c->max_total_points : (int64_t)c->max_requests * c->max_points;
+  if (pts >= (1LL << 30))
+    return fail(SV_ERR_ARG, "total points (caps.max_total_points, or max_requests * max_points when 0) must be "
+                            "below 2^30");
+  if (c->max_motions * ((c->max_points + 511) / 512) * SV_MAX_CAPS > 0x7fffffffLL)
+    return fail(SV_ERR_ARG, "caps.max_motions * ceil(caps.max_points / 512) * 16 exceeds 2^31-1");
   return SV_OK;
 }
 
@@ -725,6 +732,7 @@ int sv_first_free(const sv_robot* robot, const sv_motions* motions, const sv_clo
 
 int sv_set_exact_culling(int on) {
   g_cull = on != 0;
+  g_batch_cull = on != 0;
   return SV_OK;
 }
 

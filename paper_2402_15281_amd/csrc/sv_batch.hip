@@ -19,7 +19,7 @@
 //                    within the certified band of eps, then their requests' stamps.
 // No kernel waits on another block: the queue only hands out items, so every block
 // exits once the queue is empty, whatever the residency.
-#include "sv_geom_common.h"
+#include "sv_cull_common.h"
 
 namespace sv {
 namespace {
@@ -36,10 +36,13 @@ struct BatchArgs {
   float eps, band;
   int tile_pts;  // points per tile (threads * ppl)
   int tpi;       // tiles per work item
+  int culled;    // culled pass (1) or the persistent dense kernel (0)
   BatchWs w;
   unsigned long long* done_ticks;
   int* status_out;
 };
+
+constexpr int kCullTilePts = kCullNT * kCullP;   // sorted points per tile of the culled pass
 
 // Last index r in [0, n) with off[r] <= g (off[0] = 0 <= g; requests with no entries
 // share their offset with the next one, so r is the request that holds g).
@@ -108,11 +111,18 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchArgs a) {
     w.n_items[r] = items;
     w.tiles[r] = (int)tiles;
     w.chunks[r] = (int)chunks;
-    w.remaining[r] = (int)items;
+    w.remaining[r] = a.culled ? 1 : (int)items;   // culled: a token the list pass releases
+    w.n_points[r] = N;
+    int L = 0;   // cells per axis 2^L: up to kBinCellsPerPoint cells per point
+    while (L < kBinMaxLevel && (int64_t)1 << (3 * (L + 1)) <= N * kBinCellsPerPoint) ++L;
+    w.level[r] = L;
+    const int64_t ctiles = (N + kCullTilePts - 1) / kCullTilePts;
+    w.n_cands[r] = M * ctiles * a.K;
     cost[r] = M * N * T;
     if (a.done_ticks) a.done_ticks[r] = 0;
   }
   for (int s = tid; s < a.max_band; s += kPlanThreads) w.keys64[s] = kKeyEmpty;
+  for (int s = tid; s < kWorkSlots; s += kPlanThreads) w.work[s] = 0;
   __syncthreads();
   const int64_t tm = plan_scan(n, [&](int i) { return w.n_motions[i]; }, w.motion_off, lds);
   const int64_t ts = plan_scan(n, [&](int i) { return w.n_samples[i]; }, w.sample_off, lds);
@@ -125,15 +135,29 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchArgs a) {
   }
   __syncthreads();
   const int64_t ti = plan_scan(n, [&](int p) { return w.n_items[w.order[p]]; }, w.item_off, lds);
+  const int64_t tp = plan_scan(n, [&](int i) { return w.n_points[i]; }, w.point_off, lds);
+  const int64_t tt = plan_scan(n, [&](int i) { return (w.n_points[i] + kCullTilePts - 1) / kCullTilePts; },
+                               w.tile_off, lds);
+  const int64_t tc = plan_scan(n, [&](int p) { return w.n_cands[w.order[p]]; }, w.cand_off, lds);
+  const int64_t tb = plan_scan(n, [&](int i) { return (int64_t)1 << (3 * w.level[i]); }, w.bin_off, lds);
+  for (int r = tid; r < n * 6; r += kPlanThreads) w.bounds[r] = (r % 6) < 3 ? 0xffffffffu : 0u;
   if (tid == 0) {
     int st = s_status;
     if (tm > a.max_motions || ts > a.max_samples || tm > 0x7fffffffLL) st |= SV_BATCH_OVER_CAPACITY;
+    if (a.culled && (tp > w.point_cap || tt > w.tile_cap || tc > w.cand_cap || tb > w.bin_cap))
+      st |= SV_BATCH_OVER_CAPACITY;
     const bool run = (st & (SV_BATCH_BAD_REQUEST | SV_BATCH_OVER_CAPACITY)) == 0;
     w.plan->status = st;
     w.plan->band_count = 0;
     w.plan->total_items = run ? ti : 0;
     w.plan->total_samples = run ? ts : 0;
     w.plan->next_item = 0;
+    w.plan->total_motions = run ? tm : 0;
+    w.plan->total_points = run ? tp : 0;
+    w.plan->total_tiles = run ? tt : 0;
+    w.plan->total_cands = run ? tc : 0;
+    w.plan->total_bins = run ? tb : 0;
+    w.plan->list_count = 0;
   }
 }
 
@@ -186,6 +210,24 @@ __device__ void finalize_request(const BatchArgs& a, int r, int* s_band) {
   }
 }
 
+// Retires n items of request r (all threads of the block): one release fence and one
+// counter update for the run, and the block that retires the request's last item
+// finalizes it after an acquire fence.  (A fence per item would write back and
+// invalidate the compute unit's L2 once per item.)
+template <int NT>
+__device__ void retire_run(const BatchArgs& a, int r, int n, int* s_last, int* s_band) {
+  if (threadIdx.x == 0) {
+    *s_band = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const int old = __hip_atomic_fetch_add(a.w.remaining + r, -n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *s_last = old == n;
+    if (old == n) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  if (*s_last) finalize_request<NT>(a, r, s_band);
+  __syncthreads();
+}
+
 template <int P, int NT>
 __global__ __launch_bounds__(NT) void k_batch_exact(BatchArgs a) {
   __shared__ unsigned long long wmin[NT / 64];
@@ -195,16 +237,19 @@ __global__ __launch_bounds__(NT) void k_batch_exact(BatchArgs a) {
   const int tid = threadIdx.x;
   const int64_t total = w.plan->total_items;
   const ConstF4Ptr tab = (ConstF4Ptr)w.table;
+  int cur = -1, pending = 0;   // request of the current run, items retired in it (block-uniform)
   for (;;) {
-    if (tid == 0) {
-      s_item = (int64_t)atomicAdd(&w.plan->next_item, 1ull);
-      s_band = 0;
-    }
+    if (tid == 0) s_item = (int64_t)atomicAdd(&w.plan->next_item, 1ull);
     __syncthreads();
     const int64_t item = s_item;
     if (item >= total) break;
     const int pos = find_seg(w.item_off, a.n_req, item);
     const int r = w.order[pos];
+    if (r != cur) {
+      if (pending) retire_run<NT>(a, cur, pending, &s_last, &s_band);
+      cur = r;
+      pending = 0;
+    }
     const int64_t local = item - w.item_off[pos];
     const int chunks = w.chunks[r];
     if (w.n_motions[r] > 0 && chunks > 0) {
@@ -236,16 +281,456 @@ __global__ __launch_bounds__(NT) void k_batch_exact(BatchArgs a) {
       const unsigned long long k2 = block_min_key<NT>(key, wmin);
       if (tid == 0 && k2 != kKeyEmpty) atomicMin(w.keys + w.motion_off[r] + m, k2);
     }
-    if (tid == 0) {
-      __threadfence();
-      s_last = atomicSub(w.remaining + r, 1) == 1;
+    ++pending;
+    __syncthreads();   // s_item and wmin reused by the next item
+  }
+  if (pending) retire_run<NT>(a, cur, pending, &s_last, &s_band);
+}
+
+// ---- culled pass -----------------------------------------------------------------
+// All requests' clouds are sorted together by (request, Morton cell within the
+// request's bounds), so request r's sorted points occupy [point_off[r], point_off[r] +
+// N_r).  Candidates (motion, tile of kCullTilePts sorted points, capsule) are listed in
+// work order (smallest request first) when a sample block of the capsule may come
+// within the motion's bound of the tile; the persistent kernel then takes the list in
+// order, so small requests complete first.  Every request carries a token in
+// remaining[] besides its listed items; the last of them to retire finalizes it.
+
+// Grid-stride over the points of all requests: per-request bounds (order-preserving
+// keys), one atomic per wave and axis when the wave's points share a request.
+__global__ __launch_bounds__(256) void k_batch_bounds(BatchArgs a) {
+  const BatchWs& w = a.w;
+  const int64_t total = w.plan->total_points;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    const bool ok = i < total;
+    const int r = ok ? find_seg(w.point_off, a.n_req, i) : -1;
+    float v[3] = {0.f, 0.f, 0.f};
+    if (ok) {
+      const sv_cloud cl = a.reqs[r].cloud;
+      const int64_t j = i - w.point_off[r];
+      v[0] = cl.x[j]; v[1] = cl.y[j]; v[2] = cl.z[j];
     }
-    __syncthreads();
-    if (s_last) {
-      __threadfence();
-      finalize_request<NT>(a, r, &s_band);
+    const int r0 = __builtin_amdgcn_readfirstlane(r);
+    const bool same = __ballot(ok && r != r0) == 0 && r0 >= 0;
+    if (same) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const float lo = wave_min(ok ? v[q] : INFINITY), hi = wave_max(ok ? v[q] : -INFINITY);
+        if ((threadIdx.x & 63) == 0) {
+          atomicMin(w.bounds + 6 * r0 + q, ord_f32(lo));
+          atomicMax(w.bounds + 6 * r0 + 3 + q, ord_f32(hi));
+        }
+      }
+    } else if (ok) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        atomicMin(w.bounds + 6 * r + q, ord_f32(v[q]));
+        atomicMax(w.bounds + 6 * r + 3 + q, ord_f32(v[q]));
+      }
     }
-    __syncthreads();
+  }
+}
+
+// Counting sort of all requests' points by (request, Morton cell of the request's
+// bounds): request r's 8^L_r cells are bins [bin_off[r], bin_off[r+1]).  Points of
+// one bin land in the order their atomics were served; nothing downstream depends
+// on the order within a bin (every result is a minimum over all points, keyed by the
+// caller's point index).
+
+// Grid-stride zero fill of the bin counters in use.
+__global__ __launch_bounds__(256) void k_batch_clear_bins(BatchArgs a) {
+  const BatchWs& w = a.w;
+  const int64_t total = w.plan->total_bins;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    w.bin_count[i] = 0;
+}
+
+// Grid-stride over the points: bin of each point and its slot within the bin.
+__global__ __launch_bounds__(256) void k_batch_bin(BatchArgs a) {
+  const BatchWs& w = a.w;
+  const int64_t total = w.plan->total_points;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int r = find_seg(w.point_off, a.n_req, i);
+    const sv_cloud cl = a.reqs[r].cloud;
+    const int64_t j = i - w.point_off[r];
+    const float v[3] = {cl.x[j], cl.y[j], cl.z[j]};
+    const unsigned* bd = w.bounds + 6 * r;
+    const int L = w.level[r];
+    const float cells = (float)(1 << L);
+    unsigned q[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float lo = unord_f32(bd[c]), hi = unord_f32(bd[3 + c]);
+      const float sc = hi > lo ? cells / (hi - lo) : 0.f;
+      q[c] = (unsigned)fminf(fmaxf((v[c] - lo) * sc, 0.f), cells - 1.f);
+    }
+    const int64_t bin = w.bin_off[r] + (spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2));
+    w.pbin[i] = (int)bin;
+    w.pslot[i] = atomicAdd(w.bin_count + bin, 1);
+  }
+}
+
+// Exclusive scan of v over a 256-thread block; lds: 4 words.  Returns the block total.
+__device__ __forceinline__ int block_excl_scan256(int& v, int* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) lds[wid] = x;
+  __syncthreads();
+  int before = 0, total = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    before += u < wid ? lds[u] : 0;
+    total += lds[u];
+  }
+  v = before + x - v;
+  __syncthreads();   // lds free again
+  return total;
+}
+
+// Bins are scanned in groups of kScanGroup (256 threads x 8 bins).
+constexpr int kScanGroup = 2048;
+
+// Block-stride over the groups: the count of each group.
+__global__ __launch_bounds__(256) void k_batch_scan_up(BatchArgs a) {
+  __shared__ int lds[4];
+  const BatchWs& w = a.w;
+  const int64_t nb = w.plan->total_bins;
+  const int64_t groups = (nb + kScanGroup - 1) / kScanGroup;
+  for (int64_t gi = blockIdx.x; gi < groups; gi += gridDim.x) {
+    const int64_t b0 = gi * kScanGroup + threadIdx.x * 8;
+    int v = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += b0 + u < nb ? w.bin_count[b0 + u] : 0;
+    const int tot = block_excl_scan256(v, lds);
+    if (threadIdx.x == 0) w.group_sum[gi] = tot;
+  }
+}
+
+// One block: exclusive scan of the group counts.
+__global__ __launch_bounds__(kPlanThreads) void k_batch_scan_top(BatchArgs a) {
+  __shared__ int64_t lds[kPlanThreads];
+  const BatchWs& w = a.w;
+  const int64_t groups = (w.plan->total_bins + kScanGroup - 1) / kScanGroup;
+  plan_scan((int)groups, [&](int i) { return (int64_t)w.group_sum[i]; }, w.group_off, lds);
+}
+
+// Block-stride over the groups: the first sorted position of every bin.
+__global__ __launch_bounds__(256) void k_batch_scan_down(BatchArgs a) {
+  __shared__ int lds[4];
+  const BatchWs& w = a.w;
+  const int64_t nb = w.plan->total_bins;
+  const int64_t groups = (nb + kScanGroup - 1) / kScanGroup;
+  for (int64_t gi = blockIdx.x; gi < groups; gi += gridDim.x) {
+    const int64_t b0 = gi * kScanGroup + threadIdx.x * 8;
+    int c[8], v = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      c[u] = b0 + u < nb ? w.bin_count[b0 + u] : 0;
+      v += c[u];
+    }
+    block_excl_scan256(v, lds);
+    int pos = (int)w.group_off[gi] + v;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b0 + u < nb) {
+        w.bin_start[b0 + u] = pos;
+        pos += c[u];
+      }
+  }
+}
+
+// Grid-stride over the points: sorted points (SoA) and their index in their
+// request's cloud.  Request r's points land in [point_off[r], point_off[r] + N_r).
+__global__ __launch_bounds__(256) void k_batch_scatter(BatchArgs a) {
+  const BatchWs& w = a.w;
+  const int64_t total = w.plan->total_points;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int r = find_seg(w.point_off, a.n_req, i);
+    const sv_cloud cl = a.reqs[r].cloud;
+    const int64_t local = i - w.point_off[r];
+    const int j = w.bin_start[w.pbin[i]] + w.pslot[i];
+    w.sx[j] = cl.x[local];
+    w.sy[j] = cl.y[local];
+    w.sz[j] = cl.z[local];
+    w.sidx[j] = (int)local;
+  }
+}
+
+// The sphere of tile t's sorted points (all threads of a 256-thread block).
+__device__ void tile_sphere(const BatchArgs& a, int64_t t, float (*part)[6], float* pr) {
+  const BatchWs& w = a.w;
+  const int r = find_seg(w.tile_off, a.n_req, t);
+  const int64_t j0 = w.point_off[r] + (t - w.tile_off[r]) * kCullTilePts;
+  const int64_t j1 = min(j0 + kCullTilePts, w.point_off[r] + w.n_points[r]);
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    const float v[3] = {w.sx[j], w.sy[j], w.sz[j]};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      lo[q] = fminf(lo[q], v[q]);
+      hi[q] = fmaxf(hi[q], v[q]);
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    lo[q] = wave_min(lo[q]);
+    hi[q] = wave_max(hi[q]);
+  }
+  if (lane == 0)
+    for (int q = 0; q < 3; ++q) {
+      part[wid][q] = lo[q];
+      part[wid][3 + q] = hi[q];
+    }
+  __syncthreads();
+  float c[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    float l = part[0][q], h = part[0][3 + q];
+    for (int u = 1; u < 4; ++u) {
+      l = fminf(l, part[u][q]);
+      h = fmaxf(h, part[u][3 + q]);
+    }
+    c[q] = 0.5f * (l + h);
+  }
+  float r2 = 0.f;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    const float dx = w.sx[j] - c[0], dy = w.sy[j] - c[1], dz = w.sz[j] - c[2];
+    r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
+  }
+  r2 = wave_max(r2);
+  if (lane == 0) pr[wid] = r2;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    w.tile_sph[t] = make_float4(c[0], c[1], c[2], sqrtf(fmaxf(fmaxf(pr[0], pr[1]), fmaxf(pr[2], pr[3]))));
+}
+
+// Block-stride over the tiles of all requests: the sphere of each tile's sorted points.
+__global__ __launch_bounds__(256) void k_batch_tile_spheres(BatchArgs a) {
+  const BatchWs& w = a.w;
+  __shared__ float part[4][6];
+  __shared__ float pr[4];
+  const int64_t total = w.plan->total_tiles;
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    tile_sphere(a, t, part, pr);
+    __syncthreads();   // part, pr reused by the next tile
+  }
+}
+
+// The sphere of sample block b of capsule k of global motion g (q = (g K + k) nb_max
+// + b), at spheres[q]: centred on the block's segment end points, radius to the
+// farthest end point plus the capsule radius.
+__device__ __forceinline__ void block_sphere(const BatchArgs& a, int64_t q) {
+  const BatchWs& w = a.w;
+  const int64_t gk = q / w.nb_max;
+  const int b = (int)(q - gk * w.nb_max);
+  const int64_t g = gk / a.K;
+  const int k = (int)(gk - g * a.K);
+  const int r = find_seg(w.motion_off, a.n_req, g);
+  const int T = a.reqs[r].motions.T;
+  const int nb = (T + kCullB - 1) / kCullB;
+  if (b >= nb || w.n_points[r] == 0) return;
+  const int64_t m = g - w.motion_off[r];
+  const CapEntry* e = w.table + (size_t)(w.sample_off[r] + m * T) * a.K + (size_t)k * T;
+  const int t0 = b * kCullB, t1 = min(t0 + kCullB, T);
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int t = t0; t < t1; ++t) {
+    const CapEntry c = e[t];
+    const float p0[3] = {c.ax, c.ay, c.az}, p1[3] = {c.ax + c.bx, c.ay + c.by, c.az + c.bz};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      lo[i] = fminf(lo[i], fminf(p0[i], p1[i]));
+      hi[i] = fmaxf(hi[i], fmaxf(p0[i], p1[i]));
+    }
+  }
+  const float cx = 0.5f * (lo[0] + hi[0]), cy = 0.5f * (lo[1] + hi[1]), cz = 0.5f * (lo[2] + hi[2]);
+  float r2 = 0.f;
+  for (int t = t0; t < t1; ++t) {
+    const CapEntry c = e[t];
+    const float ax = c.ax - cx, ay = c.ay - cy, az = c.az - cz;
+    const float bx = ax + c.bx, by = ay + c.by, bz = az + c.bz;
+    r2 = fmaxf(r2, fmaxf(ax * ax + ay * ay + az * az, bx * bx + by * by + bz * bz));
+  }
+  w.spheres[(size_t)gk * w.nb_max + b] = make_float4(cx, cy, cz, sqrtf(r2) + e[t0].r);
+}
+
+// Grid-stride over (motion, capsule, sample block) of the batch.
+__global__ __launch_bounds__(256) void k_batch_block_spheres(BatchArgs a) {
+  const BatchWs& w = a.w;
+  const int64_t total = w.plan->total_motions * a.K * w.nb_max;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x)
+    block_sphere(a, q);
+}
+
+// The seed bound of (motion g, capsule k) from a stride sample of 256 points of the
+// request's sorted cloud and every kSeedSampleStride-th sample (a 256-thread block).
+__device__ void seed_bound(const BatchArgs& a, int64_t g, int k, unsigned long long* wmin) {
+  const BatchWs& w = a.w;
+  const int r = find_seg(w.motion_off, a.n_req, g);
+  const int64_t N = w.n_points[r];
+  if (N == 0) return;   // block-uniform
+  const int T = a.reqs[r].motions.T;
+  const int64_t m = g - w.motion_off[r];
+  const int64_t stride = max((int64_t)1, N / 256);
+  const int64_t j = (int64_t)threadIdx.x * stride;
+  const bool ok = j < N;
+  const int64_t js = w.point_off[r] + (ok ? j : 0);
+  const float x = ok ? w.sx[js] : 0.f, y = ok ? w.sy[js] : 0.f, z = ok ? w.sz[js] : 0.f;
+  int idx[1] = {ok ? w.sidx[js] : -1};
+  const ConstF4Ptr tab = (ConstF4Ptr)w.table;
+  const size_t e = (size_t)(w.sample_off[r] + m * T) * a.K + (size_t)k * T;
+  float m2 = INFINITY;
+  for (int t = 0; t < T; t += kSeedSampleStride) m2 = fminf(m2, seg_d2(load_entry(tab, e + t), x, y, z));
+  float best[1] = {sqrtf(m2) - load_entry(tab, e).r};
+  const unsigned long long k2 = block_min_key<256>(lane_min_key<1>(best, idx), wmin);
+  if (threadIdx.x == 0 && k2 != kKeyEmpty) atomicMin(w.keys + g, k2);
+}
+
+// Block-stride over (motion, capsule) of the batch.
+__global__ __launch_bounds__(256) void k_batch_seed(BatchArgs a) {
+  __shared__ unsigned long long wmin[4];
+  const BatchWs& w = a.w;
+  const int64_t total = w.plan->total_motions * a.K;
+  for (int64_t gk = blockIdx.x; gk < total; gk += gridDim.x) {
+    const int64_t g = gk / a.K;
+    seed_bound(a, g, (int)(gk - g * a.K), wmin);
+    __syncthreads();   // wmin reused by the next pair
+  }
+}
+
+// One thread per candidate (in work order) up to the capacity: keep the item if any
+// of its capsule's sample blocks may come within the motion's bound of the tile.
+// Kept items are appended in work order (one atomic per wave); each request's count
+// goes to remaining[r], one atomic per wave when its kept items share a request.
+__device__ __forceinline__ void cull_list_step(const BatchArgs& a, int64_t c, int64_t total) {
+  const BatchWs& w = a.w;
+  bool keep = false;
+  int r = -1, g32 = 0, tk = 0;
+  if (c < total) {
+    const int p = find_seg(w.cand_off, a.n_req, c);
+    r = w.order[p];
+    const int64_t tiles = w.tile_off[r + 1] - w.tile_off[r];
+    const int64_t local = c - w.cand_off[p];
+    const int64_t m = local / (tiles * a.K);
+    const int64_t rem = local - m * tiles * a.K;
+    const int t = (int)(rem / a.K);
+    const int k = (int)(rem - (int64_t)t * a.K);
+    const int64_t g = w.motion_off[r] + m;
+    const float G = key_dist(w.keys[g]) + kCullMargin;
+    const float4 ts = w.tile_sph[w.tile_off[r] + t];
+    const float4* sp = w.spheres + ((size_t)g * a.K + k) * w.nb_max;
+    const int nb = (a.reqs[r].motions.T + kCullB - 1) / kCullB;
+    for (int b = 0; b < nb && !keep; ++b) {
+      const float4 sb = sp[b];
+      const float dx = sb.x - ts.x, dy = sb.y - ts.y, dz = sb.z - ts.z;
+      keep = sqrtf(dx * dx + dy * dy + dz * dz) - ts.w - sb.w <= G;
+    }
+    g32 = (int)g;
+    tk = (t << 4) | k;
+  }
+  const unsigned long long ballot = __ballot(keep);
+  if (!ballot) return;
+  int base = 0;
+  if ((threadIdx.x & 63) == 0) base = atomicAdd(&w.plan->list_count, __popcll(ballot));
+  base = __shfl(base, 0, 64);
+  const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0));
+  if (keep) {
+    w.list_g[base + rank] = g32;
+    w.list_tk[base + rank] = tk;
+  }
+  // per-request counts
+  const int first = __ffsll((long long)ballot) - 1;
+  const int r0 = __shfl(r, first, 64);
+  if (__ballot(keep && r != r0) == 0) {
+    if ((threadIdx.x & 63) == 0) atomicAdd(w.remaining + r0, __popcll(ballot));
+  } else if (keep) {
+    atomicAdd(w.remaining + r, 1);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_batch_cull_list(BatchArgs a) {
+  const int64_t total = a.w.plan->total_cands;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += (int64_t)gridDim.x * blockDim.x)
+    cull_list_step(a, base + threadIdx.x, total);   // whole waves: the step appends per wave
+}
+
+// One block per request: release the request's token; a request with no listed item
+// (no motion or no point) is finalized here.
+__global__ __launch_bounds__(256) void k_batch_token(BatchArgs a) {
+  __shared__ int s_last, s_band;
+  const int r = blockIdx.x;
+  if (a.w.plan->status & (SV_BATCH_BAD_REQUEST | SV_BATCH_OVER_CAPACITY)) return;   // nothing runs
+  if (threadIdx.x == 0) {
+    s_band = 0;
+    __threadfence();
+    s_last = atomicSub(a.w.remaining + r, 1) == 1;
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    finalize_request<256>(a, r, &s_band);
+  }
+}
+
+// Persistent blocks take listed items in work order from a queue (the next index is
+// requested while the current item runs), so the blocks stay together in the list and
+// work on the same requests' data.  A block counts the items it retires per request
+// and publishes the count when it moves to another request (the list holds each
+// request's items together) or runs out of items.
+template <int P, int NT>
+__global__ __launch_bounds__(NT) void k_batch_cull(BatchArgs a) {
+  __shared__ unsigned long long wmin[NT / 64];
+  __shared__ unsigned long long wexec[NT / 64];
+  __shared__ int s_last, s_band, s_next;
+  const BatchWs& w = a.w;
+  const int n_items = w.plan->list_count;
+  unsigned long long executed = 0;
+  int cur = -1, pending = 0;   // request of the current run, items retired in it (block-uniform)
+  if (threadIdx.x == 0) s_next = (int)atomicAdd(&w.plan->next_item, 1ull);
+  __syncthreads();
+  for (int it = s_next; it < n_items; it = s_next) {
+    unsigned long long nxt = 0;
+    if (threadIdx.x == 0) nxt = atomicAdd(&w.plan->next_item, 1ull);
+    const int g = w.list_g[it];
+    const int tk = w.list_tk[it];
+    const int t = tk >> 4, k = tk & 15;
+    const int r = find_seg(w.motion_off, a.n_req, g);
+    if (r != cur) {
+      if (pending) retire_run<NT>(a, cur, pending, &s_last, &s_band);
+      cur = r;
+      pending = 0;
+    }
+    const int T = a.reqs[r].motions.T;
+    const int nb = (T + kCullB - 1) / kCullB;
+    const int64_t m = g - w.motion_off[r];
+    const int64_t po = w.point_off[r];
+    const float G = key_dist(__hip_atomic_load(w.keys + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const unsigned long long k2 = cull_item<P, NT>(
+        (ConstF4Ptr)w.table, (size_t)(w.sample_off[r] + m * T) * a.K + (size_t)k * T, T,
+        (ConstF4Ptr)(w.spheres + ((size_t)g * a.K + k) * w.nb_max), nb, w.sx + po, w.sy + po, w.sz + po,
+        w.sidx + po, (int)w.n_points[r], t, G, wmin, executed);
+    if (threadIdx.x == 0) {
+      if (k2 < __hip_atomic_load(w.keys + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(w.keys + g, k2);
+      s_next = (int)min(nxt, (unsigned long long)n_items);
+    }
+    ++pending;
+    __syncthreads();   // s_next written; wmin reused by the next item
+  }
+  if (pending) retire_run<NT>(a, cur, pending, &s_last, &s_band);
+  // executed tests: one add per block, spread over kWorkSlots counters
+  if ((threadIdx.x & 63) == 0) wexec[threadIdx.x >> 6] = executed;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long ex = 0;
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) ex += wexec[q];
+    if (ex) atomicAdd(w.work + blockIdx.x % kWorkSlots, ex);
   }
 }
 
@@ -336,6 +821,21 @@ int device_cus() {
   return cus[dev];
 }
 
+// Blocks of kernel f (threads per block nt) that the device holds at once: the grid of
+// a persistent kernel (more would wait for a slot and run as a tail).
+template <auto F>
+unsigned resident_blocks(int nt) {
+  static int per_cu[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (per_cu[dev] == 0) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, F, nt, 0) != hipSuccess || b < 1) b = 1;
+    per_cu[dev] = b;
+  }
+  return (unsigned)(device_cus() * per_cu[dev]);
+}
+
 template <int P, int NT>
 hipError_t launch_exact_batch(const BatchArgs& a, int blocks, hipStream_t st) {
   hipLaunchKernelGGL((k_batch_exact<P, NT>), dim3(blocks), dim3(NT), 0, st, a);
@@ -343,6 +843,8 @@ hipError_t launch_exact_batch(const BatchArgs& a, int blocks, hipStream_t st) {
 }
 
 }  // namespace
+
+bool g_batch_cull = true;
 
 bool batch_tile_supported(const sv_tile& t) {
   const bool ppl = t.ppl == 1 || t.ppl == 2 || t.ppl == 4;
@@ -355,6 +857,7 @@ BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, siz
   Carver cv(ws);
   BatchWs w{};
   const size_t R = (size_t)caps.max_requests;
+  w.work = cv.take<unsigned long long>(kWorkSlots);   // first: callers read it at offset 0
   w.plan = cv.take<BatchPlan>(1);
   w.motion_off = cv.take<int64_t>(R + 1);
   w.sample_off = cv.take<int64_t>(R + 1);
@@ -371,6 +874,36 @@ BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, siz
   w.band_list = cv.take<int>((size_t)caps.max_band);
   w.keys64 = cv.take<unsigned long long>((size_t)caps.max_band);
   w.table64 = cv.take<CapEntry64>((size_t)caps.max_band * rb.n_caps * caps.max_T);
+  // culled pass
+  w.point_cap = caps.max_total_points > 0 ? caps.max_total_points : (int64_t)caps.max_requests * caps.max_points;
+  w.tile_cap = w.point_cap / kCullTilePts + caps.max_requests;
+  w.nb_max = (caps.max_T + kCullB - 1) / kCullB;
+  w.cand_cap = caps.max_motions * ((caps.max_points + kCullTilePts - 1) / kCullTilePts) * rb.n_caps;
+  w.n_points = cv.take<int64_t>(R);
+  w.point_off = cv.take<int64_t>(R + 1);
+  w.tile_off = cv.take<int64_t>(R + 1);
+  w.n_cands = cv.take<int64_t>(R);
+  w.cand_off = cv.take<int64_t>(R + 1);
+  w.bounds = cv.take<unsigned>(R * 6);
+  w.level = cv.take<int>(R);
+  w.bin_off = cv.take<int64_t>(R + 1);
+  w.bin_cap = w.point_cap * kBinCellsPerPoint + caps.max_requests;
+  const size_t P = (size_t)w.point_cap, B = (size_t)w.bin_cap;
+  w.pbin = cv.take<int>(P);
+  w.pslot = cv.take<int>(P);
+  w.bin_count = cv.take<int>(B);
+  w.bin_start = cv.take<int>(B);
+  const size_t G = (B + kScanGroup - 1) / kScanGroup;
+  w.group_sum = cv.take<int>(G);
+  w.group_off = cv.take<int64_t>(G + 1);
+  w.sx = cv.take<float>(P);
+  w.sy = cv.take<float>(P);
+  w.sz = cv.take<float>(P);
+  w.sidx = cv.take<int>(P);
+  w.tile_sph = cv.take<float4>((size_t)w.tile_cap);
+  w.spheres = cv.take<float4>((size_t)caps.max_motions * rb.n_caps * w.nb_max);
+  w.list_g = cv.take<int>((size_t)w.cand_cap);
+  w.list_tk = cv.take<int>((size_t)w.cand_cap);
   *bytes = cv.off;
   return w;
 }
@@ -391,6 +924,7 @@ hipError_t launch_batch(const sv_robot& rb, const sv_request* reqs, int n_req, c
   a.band = band;
   a.tile_pts = tile.ppl * tile.threads;
   a.tpi = tile.tiles_per_item;
+  a.culled = g_batch_cull ? 1 : 0;
   a.w = w;
   a.done_ticks = done_ticks;
   a.status_out = status;
@@ -401,16 +935,40 @@ hipError_t launch_batch(const sv_robot& rb, const sv_request* reqs, int n_req, c
   hipLaunchKernelGGL(k_batch_tables, dim3(tgrid), dim3(256), 0, st, robot_to_dev<float>(rb), a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int blocks = device_cus() * tile.blocks_per_cu;
+  if (a.culled) {
+    const int64_t P = w.point_cap;
+    const unsigned pg = std::min<unsigned>(grid_for(std::max<int64_t>(P, 1), 256), 8192);
+    hipLaunchKernelGGL(k_batch_bounds, dim3(std::min<unsigned>(pg, 2048)), dim3(256), 0, st, a);
+    auto capped = [](int64_t n) { return (unsigned)std::min<int64_t>(std::max<int64_t>(n, 1), 16384); };
+    const unsigned groups = capped((w.bin_cap + kScanGroup - 1) / kScanGroup);
+    hipLaunchKernelGGL(k_batch_clear_bins, dim3(capped(grid_for(w.bin_cap, 256))), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_batch_bin, dim3(pg), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_batch_scan_up, dim3(groups), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_batch_scan_top, dim3(1), dim3(kPlanThreads), 0, st, a);
+    hipLaunchKernelGGL(k_batch_scan_down, dim3(groups), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_batch_scatter, dim3(pg), dim3(256), 0, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_tile_spheres, dim3(capped(w.tile_cap)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_batch_block_spheres, dim3(capped(grid_for(caps.max_motions * rb.n_caps * w.nb_max, 256))),
+                       dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_batch_seed, dim3(capped(caps.max_motions * rb.n_caps)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_batch_cull_list, dim3(capped(grid_for(w.cand_cap, 256))), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_batch_token, dim3(n_req), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_batch_cull<kCullP, kCullNT>), dim3(resident_blocks<k_batch_cull<kCullP, kCullNT>>(kCullNT)),
+                       dim3(kCullNT), 0, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else {
 #define SV_BATCH_CASE(P, NT) \
   else if (tile.ppl == P && tile.threads == NT) e = launch_exact_batch<P, NT>(a, blocks, st);
-  if (false) {
-  }
-  SV_BATCH_CASE(1, 64) SV_BATCH_CASE(1, 128) SV_BATCH_CASE(1, 256)
-  SV_BATCH_CASE(2, 64) SV_BATCH_CASE(2, 128) SV_BATCH_CASE(2, 256)
-  SV_BATCH_CASE(4, 64) SV_BATCH_CASE(4, 128) SV_BATCH_CASE(4, 256)
-  else e = hipErrorInvalidValue;
+    if (false) {
+    }
+    SV_BATCH_CASE(1, 64) SV_BATCH_CASE(1, 128) SV_BATCH_CASE(1, 256)
+    SV_BATCH_CASE(2, 64) SV_BATCH_CASE(2, 128) SV_BATCH_CASE(2, 256)
+    SV_BATCH_CASE(4, 64) SV_BATCH_CASE(4, 128) SV_BATCH_CASE(4, 256)
+    else e = hipErrorInvalidValue;
 #undef SV_BATCH_CASE
-  if (e != hipSuccess) return e;
+    if (e != hipSuccess) return e;
+  }
   const unsigned fgrid = (unsigned)std::min<int64_t>(
       std::max<int64_t>(grid_for((int64_t)caps.max_band * caps.max_T, 256), 1), 1024);
   hipLaunchKernelGGL(k_batch_fk64, dim3(fgrid), dim3(256), 0, st, robot_to_dev<double>(rb), a);

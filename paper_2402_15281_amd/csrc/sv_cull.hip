@@ -17,32 +17,10 @@
 // Per-point distances are not produced here (skipped tests would leave them high).
 #include <hipcub/hipcub.hpp>
 
-#include "sv_geom_common.h"
+#include "sv_cull_common.h"
 
 namespace sv {
 namespace {
-
-constexpr float kCullMargin = 1e-5f;   // m, above the FP32 rounding of the bounds
-constexpr int kCullB = 16;            // samples per bounding block
-constexpr int kSeedSampleStride = 4;  // the seed bound uses every 4th sample
-constexpr int kCullP = 2, kCullNT = 256;  // culled pass: points per lane, threads per block
-
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
-  return v;
-}
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  return v;
-}
-__device__ __forceinline__ float uniform_f(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-__device__ __forceinline__ float key_dist(unsigned long long key) {
-  return key == kKeyEmpty ? INFINITY : unord_f32((uint32_t)(key >> 32));
-}
 
 // Axis-aligned bounds of the cloud as order-preserving keys: bounds[0..2] minima
 // (start ~0u), bounds[3..5] maxima (start 0).
@@ -70,15 +48,6 @@ __global__ __launch_bounds__(256) void k_cloud_bounds(CloudArgs c, unsigned* __r
   }
 }
 
-// 10 bits per axis, interleaved: a 30-bit Morton code of each point within the bounds.
-__device__ __forceinline__ unsigned spread10(unsigned v) {
-  v &= 0x3ffu;
-  v = (v | (v << 16)) & 0x030000ffu;
-  v = (v | (v << 8)) & 0x0300f00fu;
-  v = (v | (v << 4)) & 0x030c30c3u;
-  v = (v | (v << 2)) & 0x09249249u;
-  return v;
-}
 __global__ __launch_bounds__(256) void k_morton(CloudArgs c, const unsigned* __restrict__ bounds,
                                                 unsigned* __restrict__ codes, int* __restrict__ idx) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -219,16 +188,16 @@ __global__ __launch_bounds__(256) void k_tile_spheres(const float* __restrict__ 
 
 // Coarse pass: one thread per (motion slot, tile, capsule); the capsule is kept for
 // the tile if any of its sample blocks may come within the motion's current bound of
-// the tile's sphere.  Kept (slot, tile) items are appended to (list, masks, count) --
-// one atomic per wave -- with a one-capsule mask: one capsule per item keeps the items
-// short, which balances the persistent blocks, since the surviving work concentrates
-// on the few tiles near the robot.
+// the tile's sphere.  Kept items are appended to (list: slot * tiles + tile, caps:
+// capsule, count) -- one atomic per wave.  One capsule per item keeps the items short,
+// which balances the persistent blocks, since the surviving work concentrates on the
+// few tiles near the robot.
 __global__ __launch_bounds__(256) void k_cull_list(const float4* __restrict__ tile_sph,
                                                    const float4* __restrict__ spheres, int K, int nb, int tiles,
                                                    int64_t n_slots, const int* __restrict__ mlist,
                                                    const int* __restrict__ mcount,
                                                    const unsigned long long* __restrict__ keys,
-                                                   int* __restrict__ list, int* __restrict__ masks,
+                                                   int* __restrict__ list, int* __restrict__ caps,
                                                    int* __restrict__ count) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t slots = mcount ? (int64_t)*mcount : n_slots;
@@ -248,7 +217,7 @@ __global__ __launch_bounds__(256) void k_cull_list(const float4* __restrict__ ti
       const float dx = s.x - ts.x, dy = s.y - ts.y, dz = s.z - ts.z;
       keep = sqrtf(dx * dx + dy * dy + dz * dz) - ts.w - s.w <= G;
     }
-    mask = keep ? 1 << k : 0;
+    mask = keep ? 1 : 0;
   }
   const bool keep = mask != 0;
   const unsigned long long ballot = __ballot(keep);
@@ -258,7 +227,7 @@ __global__ __launch_bounds__(256) void k_cull_list(const float4* __restrict__ ti
   const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0));
   if (keep) {
     list[base + rank] = (int)(g / K);
-    masks[base + rank] = mask;
+    caps[base + rank] = (int)(g % K);
   }
 }
 
@@ -272,7 +241,7 @@ __global__ __launch_bounds__(NT) void k_exact_cull(const CapEntry* __restrict__ 
                                                    const float* __restrict__ sx, const float* __restrict__ sy,
                                                    const float* __restrict__ sz, const int* __restrict__ perm, int N,
                                                    int tiles, const int* __restrict__ mlist,
-                                                   const int* __restrict__ list, const int* __restrict__ masks,
+                                                   const int* __restrict__ list, const int* __restrict__ caps,
                                                    const int* __restrict__ count,
                                                    unsigned long long* __restrict__ keys,
                                                    unsigned long long* __restrict__ work) {
@@ -283,73 +252,14 @@ __global__ __launch_bounds__(NT) void k_exact_cull(const CapEntry* __restrict__ 
   unsigned long long executed = 0;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int g = list[it];
-    const int cmask = masks[it];
+    const int k = caps[it];
     const int slot = g / tiles;
     const int tile = g - slot * tiles;
     const int m = mlist ? mlist[slot] : slot;
-    const int base = tile * (NT * P) + wid * (64 * P) + lane;
-    float x[P], y[P], z[P], best[P];
-    int idx[P];
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int j = base + p * 64;
-      const bool ok = j < N;
-      idx[p] = ok ? perm[j] : -1;
-      x[p] = ok ? sx[j] : 0.f;
-      y[p] = ok ? sy[j] : 0.f;
-      z[p] = ok ? sz[j] : 0.f;
-      best[p] = INFINITY;
-      if (ok) {
-        lo[0] = fminf(lo[0], x[p]); hi[0] = fmaxf(hi[0], x[p]);
-        lo[1] = fminf(lo[1], y[p]); hi[1] = fmaxf(hi[1], y[p]);
-        lo[2] = fminf(lo[2], z[p]); hi[2] = fmaxf(hi[2], z[p]);
-      }
-    }
-    const bool any = base < N;   // lane 0 holds the wave's first point
-    if (__builtin_amdgcn_readfirstlane((int)any)) {
-      // the wave's sphere
-      const float cx = uniform_f(0.5f * (wave_min(lo[0]) + wave_max(hi[0])));
-      const float cy = uniform_f(0.5f * (wave_min(lo[1]) + wave_max(hi[1])));
-      const float cz = uniform_f(0.5f * (wave_min(lo[2]) + wave_max(hi[2])));
-      float r2 = 0.f;
-#pragma unroll
-      for (int p = 0; p < P; ++p)
-        if (idx[p] >= 0) {
-          const float dx = x[p] - cx, dy = y[p] - cy, dz = z[p] - cz;
-          r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
-        }
-      const float rw = uniform_f(sqrtf(wave_max(r2)));
-      float G = uniform_f(key_dist(__hip_atomic_load(keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-      const ConstF4Ptr tab = (ConstF4Ptr)table;
-      for (int k = 0; k < K; ++k) {
-        if (!((cmask >> k) & 1)) continue;
-        const size_t e = ((size_t)m * K + k) * T;
-        const ConstF4Ptr sph = (ConstF4Ptr)(spheres + ((size_t)m * K + k) * nb);
-        const float r = load_entry(tab, e).r;
-        float m2[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) m2[p] = INFINITY;
-        for (int b = 0; b < nb; ++b) {
-          const vf4 sb = sph[b];
-          const float dx = sb.x - cx, dy = sb.y - cy, dz = sb.z - cz;
-          const float lb = sqrtf(dx * dx + dy * dy + dz * dz) - rw - sb.w;
-          if (lb > G + kCullMargin) continue;   // every test of the group exceeds the final minimum
-          const int t0 = b * kCullB, t1 = min(t0 + kCullB, T);
-          swept_range<P>(tab, e, t0, t1, x, y, z, m2);
-          executed += (unsigned long long)(t1 - t0) * (64 * P);
-          // tighten the bound with this wave's points
-          float wb = INFINITY;
-#pragma unroll
-          for (int p = 0; p < P; ++p)
-            if (idx[p] >= 0) wb = fminf(wb, sqrtf(m2[p]) - r);
-          G = uniform_f(fminf(G, wave_min(wb)));
-        }
-#pragma unroll
-        for (int p = 0; p < P; ++p) best[p] = fminf(best[p], sqrtf(m2[p]) - r);
-      }
-    }
-    const unsigned long long k2 = block_min_key<NT>(lane_min_key<P>(best, idx), wmin);
+    const float G = key_dist(__hip_atomic_load(keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const unsigned long long k2 =
+        cull_item<P, NT>((ConstF4Ptr)table, ((size_t)m * K + k) * T, T, (ConstF4Ptr)(spheres + ((size_t)m * K + k) * nb),
+                         nb, sx, sy, sz, perm, N, tile, G, wmin, executed);
     // publish only a new minimum: most items end above the motion's current key
     if (threadIdx.x == 0 && k2 < __hip_atomic_load(keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       atomicMin(keys + m, k2);
@@ -422,11 +332,11 @@ hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const 
                      kCullNT * kCullP, w.tile_spheres);
   if ((e = launch_fill_i32(w.list_count, 1, 0, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_cull_list, dim3(grid_for(items * K, 256)), dim3(256), 0, st, w.tile_spheres, w.spheres, K, nb,
-                     tiles, n_slots, mlist, mcount, keys, w.list, w.list_masks, w.list_count);
+                     tiles, n_slots, mlist, mcount, keys, w.list, w.list_caps, w.list_count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int blocks = (int)std::min<int64_t>(items * K, (int64_t)device_cus_cull() * 8);
   hipLaunchKernelGGL((k_exact_cull<kCullP, kCullNT>), dim3(blocks), dim3(kCullNT), 0, st, table, w.spheres, T, K, nb,
-                     w.sx, w.sy, w.sz, w.perm, c.n, tiles, mlist, w.list, w.list_masks, w.list_count, keys, w.work);
+                     w.sx, w.sy, w.sz, w.perm, c.n, tiles, mlist, w.list, w.list_caps, w.list_count, keys, w.work);
   return hipGetLastError();
 }
 

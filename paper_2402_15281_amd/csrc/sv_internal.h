@@ -106,11 +106,15 @@ struct BatchPlan {
   int64_t total_items;              // work items of the batch (0 if nothing runs)
   int64_t total_samples;            // (motion, sample) pairs of the batch
   unsigned long long next_item;     // head of the work queue
+  // culled pass
+  int64_t total_motions, total_points, total_tiles, total_cands, total_bins;
+  int list_count;                   // surviving (motion, tile, capsule) items
 };
 
 // Workspace of a batch call: per-request arrays [max_requests] (offsets [+1]), keys
 // [max_motions], capsule table [max_samples * K], band arrays [max_band].
 struct BatchWs {
+  unsigned long long* work;                       // [kWorkSlots] segment tests of the culled pass
   BatchPlan* plan;
   int64_t *motion_off, *sample_off, *item_off;   // request order; item_off in work order
   int64_t *n_motions, *n_samples, *n_items;
@@ -120,9 +124,29 @@ struct BatchWs {
   int* band_list;                                 // global motion index
   unsigned long long* keys64;
   CapEntry64* table64;                            // [max_band][K][max_T]
+  // culled pass (all requests' clouds sorted together by (request, Morton code))
+  int64_t *n_points, *point_off, *tile_off, *n_cands, *cand_off;   // cand_off in work order
+  unsigned* bounds;                               // [max_requests][6] per-request cloud bounds
+  int* level;                                     // [max_requests] Morton cells per axis 2^level
+  int64_t* bin_off;                               // [max_requests + 1] first bin of each request
+  int *pbin, *pslot;                              // [point_cap] bin of each point, slot within it
+  int *bin_count, *bin_start;                     // [bin_cap]
+  int* group_sum;                                 // [bin_cap / 2048] counts of groups of bins
+  int64_t* group_off;                             // their exclusive scan
+  float *sx, *sy, *sz;                            // [point_cap] sorted points
+  int* sidx;                                      // [point_cap] their index in the request's cloud
+  float4* tile_sph;                               // [tile_cap]
+  float4* spheres;                                // [max_motions][K][nb_max]
+  int *list_g, *list_tk;                          // [cand_cap] motion, tile << 4 | capsule
+  int64_t point_cap, tile_cap, cand_cap, bin_cap;
+  int nb_max;
 };
 
 bool batch_tile_supported(const sv_tile& t);
+// The culled batched pass, on unless switched off for measurement (sv_set_exact_culling).
+extern bool g_batch_cull;
+constexpr int kBinCellsPerPoint = 2;   // Morton cells per point of a request, at most
+constexpr int kBinMaxLevel = 7;        // at most 128 cells per axis
 // Carves ws (NULL: only sizes); *bytes = total.
 BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, size_t* bytes);
 hipError_t launch_batch(const sv_robot& rb, const sv_request* reqs, int n_req, const sv_batch_caps& caps, float eps,
@@ -176,7 +200,7 @@ struct CullWs {
   float4* spheres;                  // [M][K][cull_blocks(T)]
   float4* tile_spheres;             // [cull_tiles(N)]
   int* list;                        // [M * cull_tiles(N) * K] surviving (motion slot, tile) items
-  int* list_masks;                  // [M * cull_tiles(N) * K] the capsule(s) each item checks
+  int* list_caps;                  // [M * cull_tiles(N) * K] the capsule each item checks
   int* list_count;                  // [1]
   unsigned long long* work;         // [kWorkSlots] executed segment tests, summed (may be NULL)
 };

@@ -120,10 +120,12 @@ __global__ __launch_bounds__(NT) void k_search_exact(SearchArgs a) {
         if (tid == 0 && k2 != kKeyEmpty) atomicMin(w.keys + m, k2);
       }
       if (tid == 0) {
-        __threadfence();
-        s_last = atomicSub(w.remaining + p, 1) == 1;
+        // release this item's key; only the block that completes the motion acquires
+        // (an acquire fence invalidates the compute unit's L2)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        s_last = __hip_atomic_fetch_add(w.remaining + p, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1;
         if (s_last) {
-          __threadfence();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           float d;
           int arg;
           decode_key(__hip_atomic_load(w.keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), &d, &arg);

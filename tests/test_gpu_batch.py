@@ -3,7 +3,9 @@
 Bars:
 - every request's results equal sv_check_motions on that request bit for bit
   (the same per-point arithmetic, only scheduled differently), for every launch
-  shape;
+  shape of the unculled kernel;
+- the culled pass (branch and bound over sorted clouds) equals the unculled one
+  bit for bit: skipped tests provably exceed the final minimum;
 - against the FP64 oracle: distances within 1e-5 m, verdicts exact, argmin valid;
 - a captured HIP graph replays to the eager results, also after the request
   contents change;
@@ -28,6 +30,19 @@ def sv():
     from paper_2402_15281_amd import _binding
     assert torch.cuda.is_available()
     return _binding
+
+
+class culling:
+    """Context: exact-check culling on or off (both the per-call and the batched pass)."""
+
+    def __init__(self, sv, on):
+        self.sv, self.on = sv, on
+
+    def __enter__(self):
+        self.sv.sv_set_exact_culling(self.on)
+
+    def __exit__(self, *exc):
+        self.sv.sv_set_exact_culling(True)
 
 
 def make_batch(sv, arm, specs, seed):
@@ -115,20 +130,85 @@ def test_batch_against_oracle(sv, orc):
 
 @pytest.mark.parametrize("ppl", [1, 2, 4])
 def test_every_launch_shape_bitwise(sv, ppl):
+    """The unculled persistent kernel under every tile shape."""
     arm = svgen.make_arm(1)
     robot = sv.make_robot(arm)
     _, reqs = make_batch(sv, arm, MIXED, 700)
     caps = reqs.caps(max_band=8)
     ref = per_request(sv, robot, reqs)
     ws = sv.workspace(sv.sv_batch_workspace_size(robot, caps))
-    for threads in (64, 128, 256):
-        for bpc, tpi in ((1, 1), (3, 2), (8, 64), (32, 5)):
-            poison(reqs)
-            sv.sv_check_requests(robot, reqs, caps, EPS, tile=sv.sv_tile(ppl, threads, bpc, tpi), ws=ws)
-            assert_bitwise(results(reqs), ref)
+    with culling(sv, False):
+        for threads in (64, 128, 256):
+            for bpc, tpi in ((1, 1), (3, 2), (8, 64), (32, 5)):
+                poison(reqs)
+                sv.sv_check_requests(robot, reqs, caps, EPS, tile=sv.sv_tile(ppl, threads, bpc, tpi), ws=ws)
+                assert_bitwise(results(reqs), ref)
 
 
-def test_graph_capture_and_replay_with_new_contents(sv):
+CULL_MIX = [(40, 20000, 64, "spline"), (3, 9000, 17, "linear"), (0, 3000, 64, "spline"), (25, 0, 48, "linear"),
+            (1, 1, 1, "linear"), (60, 5000, 100, "spline"), (8, 513, 16, "linear"), (12, 40000, 33, "spline"),
+            (2, 511, 2, "linear"), (30, 12345, 64, "linear")]
+
+
+@pytest.mark.parametrize("specs", [MIXED, CULL_MIX], ids=["mixed", "multi_tile"])
+def test_culled_batch_equals_unculled(sv, specs):
+    """Culled and unculled batched passes bit for bit, and both equal per-request calls
+    with and without culling (ragged tiles and sample blocks, empty requests and clouds,
+    single points, T = 1)."""
+    arm = svgen.make_arm(2)
+    robot = sv.make_robot(arm)
+    _, reqs = make_batch(sv, arm, specs, 1300)
+    caps = reqs.caps(max_band=16)
+    ws = sv.workspace(sv.sv_batch_workspace_size(robot, caps))
+    status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    with culling(sv, False):
+        poison(reqs)
+        sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, status=status)
+        dense = results(reqs)
+        assert int(status.item()) == 0
+        assert_bitwise(dense, per_request(sv, robot, reqs))
+    for rep in range(2):
+        poison(reqs)
+        sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, status=status)
+        assert_bitwise(results(reqs), dense)
+        assert int(status.item()) == 0
+    assert_bitwise(per_request(sv, robot, reqs), dense)
+
+
+def test_total_points_capacity(sv):
+    """caps.max_total_points bounds the sum of cloud sizes: a batch over it is flagged,
+    nothing written; the host rejects capacities the pass cannot index."""
+    arm = svgen.make_arm(1)
+    robot = sv.make_robot(arm)
+    _, reqs = make_batch(sv, arm, [(3, 900, 32, "linear"), (2, 700, 40, "spline")], 1400)
+    caps = reqs.caps()
+    ws = sv.workspace(sv.sv_batch_workspace_size(robot, caps))
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    tight = sv.sv_batch_caps(caps.max_requests, caps.max_T, caps.max_motions, caps.max_samples, caps.max_points,
+                             caps.max_band, 1599)
+    poison(reqs)
+    sv.sv_check_requests(robot, reqs, tight, EPS, ws=ws, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == sv.SV_BATCH_OVER_CAPACITY
+    assert all((o.verdict.cpu() == 7).all() for _, _, o in reqs.requests)
+    exact = sv.sv_batch_caps(caps.max_requests, caps.max_T, caps.max_motions, caps.max_samples, caps.max_points,
+                             caps.max_band, 1600)
+    sv.sv_check_requests(robot, reqs, exact, EPS, ws=ws, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    huge = sv.sv_batch_caps(4096, 64, 1000, 64000, 1 << 30, 8, 0)
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_batch_workspace_size(robot, huge)
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("culled", [True, False], ids=["culled", "unculled"])
+def test_graph_capture_and_replay_with_new_contents(sv, culled):
+    with culling(sv, culled):
+        graph_replay_case(sv)
+
+
+def graph_replay_case(sv):
     arm = svgen.make_arm(1)
     robot = sv.make_robot(arm)
     specs = [(5, 800, 48, "spline"), (1, 3000, 48, "linear"), (9, 150, 48, "spline")]
@@ -180,7 +260,8 @@ def test_status_word_and_host_checks(sv):
     ticks = torch.full((reqs.n + 1,), 5, dtype=torch.int64, device="cuda")
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
     # a request beyond the capacities: flagged on the device, nothing written
-    small = sv.sv_batch_caps(caps.max_requests, 32, caps.max_motions, caps.max_samples, caps.max_points, 4)
+    small = sv.sv_batch_caps(caps.max_requests, 32, caps.max_motions, caps.max_samples, caps.max_points, 4,
+                             caps.max_total_points)
     poison(reqs)
     sv.sv_check_requests(robot, reqs, small, EPS, ws=ws, done_ticks=ticks, status=status)
     torch.cuda.synchronize()
@@ -244,8 +325,8 @@ def test_band_recheck_in_batch(sv, orc):
 
 def test_requests_workload_full_size(sv, orc):
     """64 uneven SPLINE requests, T = 512 (1-2048 motions x 2k-200k points, log-uniform):
-    bitwise equal to per-request calls; sampled motions of small requests against
-    the oracle."""
+    culled batch bitwise equal to per-request calls and to the unculled batch; sampled
+    motions of small requests against the oracle."""
     arm = svgen.make_arm(1)
     robot = sv.make_robot(arm)
     rq = svgen.make_requests(arm, 64, 4242)
@@ -254,10 +335,15 @@ def test_requests_workload_full_size(sv, orc):
     caps = reqs.caps(max_band=64)
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
     print(f"{sum(r.motions.n for r in rq)} motions, {sum(r.motions.n * r.cloud.shape[0] for r in rq) / 1e6:.1f}M pairs")
-    sv.sv_check_requests(robot, reqs, caps, EPS, status=status)
+    ws = sv.workspace(sv.sv_batch_workspace_size(robot, caps))
+    sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, status=status)
     got = results(reqs)
     assert int(status.item()) == 0
     assert_bitwise(got, per_request(sv, robot, reqs))
+    with culling(sv, False):
+        poison(reqs)
+        sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, status=status)
+        assert_bitwise(results(reqs), got)
     order = np.argsort([r.motions.n * r.cloud.shape[0] for r in rq])
     for ri in order[:3]:
         r = rq[ri]

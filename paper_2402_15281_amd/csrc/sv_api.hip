@@ -161,20 +161,23 @@ CheckWs carve_check(void* ws, const sv_robot& r, const sv_motions& m, const sv_c
   w.work = cv.take<unsigned long long>(kWorkSlots);
   const size_t N = (size_t)c.n;
   w.cull.bounds = cv.take<unsigned>(8);
-  w.cull.codes = cv.take<unsigned>(N);
-  w.cull.codes_sorted = cv.take<unsigned>(N);
-  w.cull.idx = cv.take<int>(N);
+  w.cull.level = morton_level(N);
+  const size_t bins = (size_t)1 << (3 * w.cull.level);
+  w.cull.pbin = cv.take<int>(N);
+  w.cull.pslot = cv.take<int>(N);
+  w.cull.bin_count = cv.take<int>(bins);
+  w.cull.bin_start = cv.take<int>(bins);
+  w.cull.group_sum = cv.take<int>((size_t)bin_scan_groups((int64_t)bins));
+  w.cull.group_off = cv.take<int64_t>((size_t)bin_scan_groups((int64_t)bins) + 1);
   w.cull.perm = cv.take<int>(N);
   w.cull.sx = cv.take<float>(N);
   w.cull.sy = cv.take<float>(N);
   w.cull.sz = cv.take<float>(N);
-  w.cull.sort_bytes = N > 0 ? cull_sort_bytes((int64_t)N) : 0;
-  w.cull.sort_tmp = cv.take<char>(w.cull.sort_bytes);
   w.cull.spheres = cv.take<float4>((size_t)m.n * r.n_caps * cull_blocks(m.T));
   w.cull.tile_spheres = cv.take<float4>((size_t)cull_tiles(c.n));
   w.cull.list = cv.take<int>((size_t)m.n * cull_tiles(c.n) * r.n_caps);
   w.cull.list_caps = cv.take<int>((size_t)m.n * cull_tiles(c.n) * r.n_caps);
-  w.cull.list_count = cv.take<int>(1);
+  w.cull.list_count = cv.take<int>(2);
   w.cull.work = w.work;
   w.table = cv.take<CapEntry>(entries);
   w.keys = cv.take<unsigned long long>(m.n);

@@ -28,7 +28,7 @@ constexpr int kPlanThreads = 1024;
 
 struct BatchArgs {
   const sv_request* reqs;
-  int n_req;
+  int n_req, max_requests;
   int K;
   int max_T;
   int max_band;
@@ -113,9 +113,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchArgs a) {
     w.chunks[r] = (int)chunks;
     w.remaining[r] = a.culled ? 1 : (int)items;   // culled: a token the list pass releases
     w.n_points[r] = N;
-    int L = 0;   // cells per axis 2^L: up to kBinCellsPerPoint cells per point
-    while (L < kBinMaxLevel && (int64_t)1 << (3 * (L + 1)) <= N * kBinCellsPerPoint) ++L;
-    w.level[r] = L;
+    w.level[r] = morton_level(N);
     const int64_t ctiles = (N + kCullTilePts - 1) / kCullTilePts;
     w.n_cands[r] = M * ctiles * a.K;
     cost[r] = M * N * T;
@@ -141,6 +139,19 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchArgs a) {
   const int64_t tc = plan_scan(n, [&](int p) { return w.n_cands[w.order[p]]; }, w.cand_off, lds);
   const int64_t tb = plan_scan(n, [&](int i) { return (int64_t)1 << (3 * w.level[i]); }, w.bin_off, lds);
   for (int r = tid; r < n * 6; r += kPlanThreads) w.bounds[r] = (r % 6) < 3 ? 0xffffffffu : 0u;
+  for (int p = tid; p < n; p += kPlanThreads) {   // offsets from the scans above (same block)
+    const int r = w.order[p];
+    BatchReq q;
+    q.sample_off = w.sample_off[r];
+    q.point_off = (int)w.point_off[r];
+    q.motion_off = (int)w.motion_off[r];
+    q.n_points = (int)w.n_points[r];
+    q.T = a.reqs[r].motions.T;
+    q.nb = (q.T + kCullB - 1) / kCullB;
+    q.list_off = (int)w.cand_off[p];
+    w.req[r] = q;
+    w.fill[r] = 0;
+  }
   if (tid == 0) {
     int st = s_status;
     if (tm > a.max_motions || ts > a.max_samples || tm > 0x7fffffffLL) st |= SV_BATCH_OVER_CAPACITY;
@@ -157,7 +168,6 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchArgs a) {
     w.plan->total_tiles = run ? tt : 0;
     w.plan->total_cands = run ? tc : 0;
     w.plan->total_bins = run ? tb : 0;
-    w.plan->list_count = 0;
   }
 }
 
@@ -355,93 +365,9 @@ __global__ __launch_bounds__(256) void k_batch_bin(BatchArgs a) {
     const sv_cloud cl = a.reqs[r].cloud;
     const int64_t j = i - w.point_off[r];
     const float v[3] = {cl.x[j], cl.y[j], cl.z[j]};
-    const unsigned* bd = w.bounds + 6 * r;
-    const int L = w.level[r];
-    const float cells = (float)(1 << L);
-    unsigned q[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float lo = unord_f32(bd[c]), hi = unord_f32(bd[3 + c]);
-      const float sc = hi > lo ? cells / (hi - lo) : 0.f;
-      q[c] = (unsigned)fminf(fmaxf((v[c] - lo) * sc, 0.f), cells - 1.f);
-    }
-    const int64_t bin = w.bin_off[r] + (spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2));
+    const int64_t bin = w.bin_off[r] + morton_cell(v, w.bounds + 6 * r, w.level[r]);
     w.pbin[i] = (int)bin;
     w.pslot[i] = atomicAdd(w.bin_count + bin, 1);
-  }
-}
-
-// Exclusive scan of v over a 256-thread block; lds: 4 words.  Returns the block total.
-__device__ __forceinline__ int block_excl_scan256(int& v, int* lds) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int x = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  if (lane == 63) lds[wid] = x;
-  __syncthreads();
-  int before = 0, total = 0;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    before += u < wid ? lds[u] : 0;
-    total += lds[u];
-  }
-  v = before + x - v;
-  __syncthreads();   // lds free again
-  return total;
-}
-
-// Bins are scanned in groups of kScanGroup (256 threads x 8 bins).
-constexpr int kScanGroup = 2048;
-
-// Block-stride over the groups: the count of each group.
-__global__ __launch_bounds__(256) void k_batch_scan_up(BatchArgs a) {
-  __shared__ int lds[4];
-  const BatchWs& w = a.w;
-  const int64_t nb = w.plan->total_bins;
-  const int64_t groups = (nb + kScanGroup - 1) / kScanGroup;
-  for (int64_t gi = blockIdx.x; gi < groups; gi += gridDim.x) {
-    const int64_t b0 = gi * kScanGroup + threadIdx.x * 8;
-    int v = 0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v += b0 + u < nb ? w.bin_count[b0 + u] : 0;
-    const int tot = block_excl_scan256(v, lds);
-    if (threadIdx.x == 0) w.group_sum[gi] = tot;
-  }
-}
-
-// One block: exclusive scan of the group counts.
-__global__ __launch_bounds__(kPlanThreads) void k_batch_scan_top(BatchArgs a) {
-  __shared__ int64_t lds[kPlanThreads];
-  const BatchWs& w = a.w;
-  const int64_t groups = (w.plan->total_bins + kScanGroup - 1) / kScanGroup;
-  plan_scan((int)groups, [&](int i) { return (int64_t)w.group_sum[i]; }, w.group_off, lds);
-}
-
-// Block-stride over the groups: the first sorted position of every bin.
-__global__ __launch_bounds__(256) void k_batch_scan_down(BatchArgs a) {
-  __shared__ int lds[4];
-  const BatchWs& w = a.w;
-  const int64_t nb = w.plan->total_bins;
-  const int64_t groups = (nb + kScanGroup - 1) / kScanGroup;
-  for (int64_t gi = blockIdx.x; gi < groups; gi += gridDim.x) {
-    const int64_t b0 = gi * kScanGroup + threadIdx.x * 8;
-    int c[8], v = 0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      c[u] = b0 + u < nb ? w.bin_count[b0 + u] : 0;
-      v += c[u];
-    }
-    block_excl_scan256(v, lds);
-    int pos = (int)w.group_off[gi] + v;
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (b0 + u < nb) {
-        w.bin_start[b0 + u] = pos;
-        pos += c[u];
-      }
   }
 }
 
@@ -636,21 +562,23 @@ __device__ __forceinline__ void cull_list_step(const BatchArgs& a, int64_t c, in
   }
   const unsigned long long ballot = __ballot(keep);
   if (!ballot) return;
-  int base = 0;
-  if ((threadIdx.x & 63) == 0) base = atomicAdd(&w.plan->list_count, __popcll(ballot));
-  base = __shfl(base, 0, 64);
-  const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0));
-  if (keep) {
-    w.list_g[base + rank] = g32;
-    w.list_tk[base + rank] = tk;
-  }
-  // per-request counts
+  // kept items go to their request's segment of the list, in any order within it;
+  // one atomic per wave when the wave's kept items share a request
   const int first = __ffsll((long long)ballot) - 1;
   const int r0 = __shfl(r, first, 64);
+  int slot;
   if (__ballot(keep && r != r0) == 0) {
-    if ((threadIdx.x & 63) == 0) atomicAdd(w.remaining + r0, __popcll(ballot));
-  } else if (keep) {
-    atomicAdd(w.remaining + r, 1);
+    int base = 0;
+    if ((threadIdx.x & 63) == 0) base = atomicAdd(w.fill + r0, __popcll(ballot));
+    base = __shfl(base, 0, 64);
+    slot = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0));
+  } else {
+    slot = keep ? atomicAdd(w.fill + r, 1) : 0;
+  }
+  if (keep) {
+    const int at = w.req[r].list_off + slot;
+    w.list_g[at] = g32;
+    w.list_tk[at] = tk;
   }
 }
 
@@ -660,67 +588,124 @@ __global__ __launch_bounds__(256) void k_batch_cull_list(BatchArgs a) {
     cull_list_step(a, base + threadIdx.x, total);   // whole waves: the step appends per wave
 }
 
-// One block per request: release the request's token; a request with no listed item
-// (no motion or no point) is finalized here.
-__global__ __launch_bounds__(256) void k_batch_token(BatchArgs a) {
-  __shared__ int s_last, s_band;
+// One block per request: its listed items become its remaining count; a request with
+// no listed item (no motion or no point) is finalized here.
+__global__ __launch_bounds__(256) void k_batch_counts(BatchArgs a) {
+  __shared__ int s_band;
   const int r = blockIdx.x;
-  if (a.w.plan->status & (SV_BATCH_BAD_REQUEST | SV_BATCH_OVER_CAPACITY)) return;   // nothing runs
+  if (r >= a.n_req || (a.w.plan->status & (SV_BATCH_BAD_REQUEST | SV_BATCH_OVER_CAPACITY))) return;   // nothing runs
+  const int items = a.w.fill[r];
   if (threadIdx.x == 0) {
     s_band = 0;
-    __threadfence();
-    s_last = atomicSub(a.w.remaining + r, 1) == 1;
+    a.w.remaining[r] = items;
   }
   __syncthreads();
-  if (s_last) {
-    __threadfence();
-    finalize_request<256>(a, r, &s_band);
+  if (items == 0) finalize_request<256>(a, r, &s_band);
+}
+
+// One thread: requests are dealt to the gangs in work order (smallest estimated work
+// first), each to the gang with the fewest items so far.
+__global__ void k_batch_gangs(BatchArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const BatchWs& w = a.w;
+  int load[kGangs], cnt[kGangs];
+  for (int g = 0; g < kGangs; ++g) {
+    load[g] = 0;
+    cnt[g] = 0;
+    w.gang_head[g] = 0;
+  }
+  const bool run = (w.plan->status & (SV_BATCH_BAD_REQUEST | SV_BATCH_OVER_CAPACITY)) == 0;
+  const int R = a.max_requests;
+  for (int p = 0; run && p < a.n_req; ++p) {
+    const int r = w.order[p];
+    const int items = w.fill[r];
+    if (items == 0) continue;
+    int best = 0;
+    for (int g = 1; g < kGangs; ++g) best = load[g] < load[best] ? g : best;
+    w.gang_req[best * R + cnt[best]] = r;
+    w.gang_off[best * (R + 1) + cnt[best]] = load[best];
+    load[best] += items;
+    ++cnt[best];
+  }
+  for (int g = 0; g < kGangs; ++g) {
+    w.gang_off[g * (R + 1) + cnt[g]] = load[g];
+    w.gang_n[g] = cnt[g];
+    w.gang_total[g] = load[g];
   }
 }
 
-// Persistent blocks take listed items in work order from a queue (the next index is
-// requested while the current item runs), so the blocks stay together in the list and
-// work on the same requests' data.  A block counts the items it retires per request
-// and publishes the count when it moves to another request (the list holds each
-// request's items together) or runs out of items.
+// Thread 0: the next item for a block of gang *gang (moving to the next gang when its
+// queue is empty): *r its request (-1: none left), *slot its list slot.
+__device__ void claim_item(const BatchArgs& a, int* gang, int g0, int* r, int* slot) {
+  const BatchWs& w = a.w;
+  for (;;) {
+    const int g = *gang;
+    const unsigned idx = atomicAdd(w.gang_head + g, 1u);
+    if ((int)idx < w.gang_total[g]) {
+      const int* off = w.gang_off + g * (a.max_requests + 1);
+      int lo = 0, hi = w.gang_n[g];   // last j with off[j] <= idx
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= (int)idx) lo = mid; else hi = mid;
+      }
+      *r = w.gang_req[g * a.max_requests + lo];
+      *slot = w.req[*r].list_off + ((int)idx - off[lo]);
+      return;
+    }
+    *gang = (g + 1) % kGangs;
+    if (*gang == g0) {
+      *r = -1;
+      return;
+    }
+  }
+}
+
+// Persistent blocks take listed items from their gang's queue (the next item is
+// claimed while the current one runs).  A gang works through its requests in order, so
+// a block touches only a few requests; it counts the items it retires per request and
+// publishes the count (one release fence) when it moves to another request or runs
+// out of items.
 template <int P, int NT>
-__global__ __launch_bounds__(NT) void k_batch_cull(BatchArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_cull(BatchArgs a) {
   __shared__ unsigned long long wmin[NT / 64];
   __shared__ unsigned long long wexec[NT / 64];
-  __shared__ int s_last, s_band, s_next;
+  __shared__ int s_last, s_band, s_r, s_slot;
   const BatchWs& w = a.w;
-  const int n_items = w.plan->list_count;
+  const int g0 = blockIdx.x % kGangs;
+  int gang = g0;   // thread 0's current queue
   unsigned long long executed = 0;
   int cur = -1, pending = 0;   // request of the current run, items retired in it (block-uniform)
-  if (threadIdx.x == 0) s_next = (int)atomicAdd(&w.plan->next_item, 1ull);
+  if (threadIdx.x == 0) claim_item(a, &gang, g0, &s_r, &s_slot);
   __syncthreads();
-  for (int it = s_next; it < n_items; it = s_next) {
-    unsigned long long nxt = 0;
-    if (threadIdx.x == 0) nxt = atomicAdd(&w.plan->next_item, 1ull);
-    const int g = w.list_g[it];
-    const int tk = w.list_tk[it];
-    const int t = tk >> 4, k = tk & 15;
-    const int r = find_seg(w.motion_off, a.n_req, g);
+  for (;;) {
+    const int r = s_r, slot = s_slot;
+    if (r < 0) break;
+    int nr = -1, nslot = 0;
+    if (threadIdx.x == 0) claim_item(a, &gang, g0, &nr, &nslot);
     if (r != cur) {
       if (pending) retire_run<NT>(a, cur, pending, &s_last, &s_band);
       cur = r;
       pending = 0;
     }
-    const int T = a.reqs[r].motions.T;
-    const int nb = (T + kCullB - 1) / kCullB;
-    const int64_t m = g - w.motion_off[r];
-    const int64_t po = w.point_off[r];
+    const int su = __builtin_amdgcn_readfirstlane(slot);   // scalar loads of the item's header
+    const int g = w.list_g[su];
+    const int tk = w.list_tk[su];
+    const int t = tk >> 4, k = tk & 15;
+    const BatchReq q = w.req[r];
+    const int64_t m = g - q.motion_off;
+    const int64_t po = q.point_off;
     const float G = key_dist(__hip_atomic_load(w.keys + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const unsigned long long k2 = cull_item<P, NT>(
-        (ConstF4Ptr)w.table, (size_t)(w.sample_off[r] + m * T) * a.K + (size_t)k * T, T,
-        (ConstF4Ptr)(w.spheres + ((size_t)g * a.K + k) * w.nb_max), nb, w.sx + po, w.sy + po, w.sz + po,
-        w.sidx + po, (int)w.n_points[r], t, G, wmin, executed);
+        (ConstF4Ptr)w.table, (size_t)(q.sample_off + m * q.T) * a.K + (size_t)k * q.T, q.T,
+        (ConstF4Ptr)(w.spheres + ((size_t)g * a.K + k) * w.nb_max), q.nb, w.sx + po, w.sy + po, w.sz + po,
+        w.sidx + po, q.n_points, t, G, wmin, executed);
     if (threadIdx.x == 0) {
       if (k2 < __hip_atomic_load(w.keys + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(w.keys + g, k2);
-      s_next = (int)min(nxt, (unsigned long long)n_items);
+      s_r = nr;
+      s_slot = nslot;
     }
     ++pending;
-    __syncthreads();   // s_next written; wmin reused by the next item
+    __syncthreads();   // s_r, s_slot written; wmin reused by the next item
   }
   if (pending) retire_run<NT>(a, cur, pending, &s_last, &s_band);
   // executed tests: one add per block, spread over kWorkSlots counters
@@ -893,7 +878,7 @@ BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, siz
   w.pslot = cv.take<int>(P);
   w.bin_count = cv.take<int>(B);
   w.bin_start = cv.take<int>(B);
-  const size_t G = (B + kScanGroup - 1) / kScanGroup;
+  const size_t G = (size_t)bin_scan_groups(w.bin_cap);
   w.group_sum = cv.take<int>(G);
   w.group_off = cv.take<int64_t>(G + 1);
   w.sx = cv.take<float>(P);
@@ -904,6 +889,13 @@ BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, siz
   w.spheres = cv.take<float4>((size_t)caps.max_motions * rb.n_caps * w.nb_max);
   w.list_g = cv.take<int>((size_t)w.cand_cap);
   w.list_tk = cv.take<int>((size_t)w.cand_cap);
+  w.req = cv.take<BatchReq>(R);
+  w.fill = cv.take<int>(R);
+  w.gang_n = cv.take<int>(kGangs);
+  w.gang_total = cv.take<int>(kGangs);
+  w.gang_head = cv.take<unsigned>(kGangs);
+  w.gang_req = cv.take<int>(kGangs * R);
+  w.gang_off = cv.take<int>(kGangs * (R + 1));
   *bytes = cv.off;
   return w;
 }
@@ -914,6 +906,7 @@ hipError_t launch_batch(const sv_robot& rb, const sv_request* reqs, int n_req, c
   BatchArgs a{};
   a.reqs = reqs;
   a.n_req = n_req;
+  a.max_requests = caps.max_requests;
   a.K = rb.n_caps;
   a.max_T = caps.max_T;
   a.max_band = caps.max_band;
@@ -940,12 +933,12 @@ hipError_t launch_batch(const sv_robot& rb, const sv_request* reqs, int n_req, c
     const unsigned pg = std::min<unsigned>(grid_for(std::max<int64_t>(P, 1), 256), 8192);
     hipLaunchKernelGGL(k_batch_bounds, dim3(std::min<unsigned>(pg, 2048)), dim3(256), 0, st, a);
     auto capped = [](int64_t n) { return (unsigned)std::min<int64_t>(std::max<int64_t>(n, 1), 16384); };
-    const unsigned groups = capped((w.bin_cap + kScanGroup - 1) / kScanGroup);
     hipLaunchKernelGGL(k_batch_clear_bins, dim3(capped(grid_for(w.bin_cap, 256))), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_batch_bin, dim3(pg), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_batch_scan_up, dim3(groups), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_batch_scan_top, dim3(1), dim3(kPlanThreads), 0, st, a);
-    hipLaunchKernelGGL(k_batch_scan_down, dim3(groups), dim3(256), 0, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_bin_scan(w.bin_count, 0, &w.plan->total_bins, w.bin_cap, w.group_sum, w.group_off, w.bin_start,
+                             st)) != hipSuccess)
+      return e;
     hipLaunchKernelGGL(k_batch_scatter, dim3(pg), dim3(256), 0, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_tile_spheres, dim3(capped(w.tile_cap)), dim3(256), 0, st, a);
@@ -953,7 +946,8 @@ hipError_t launch_batch(const sv_robot& rb, const sv_request* reqs, int n_req, c
                        dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_batch_seed, dim3(capped(caps.max_motions * rb.n_caps)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_batch_cull_list, dim3(capped(grid_for(w.cand_cap, 256))), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_batch_token, dim3(n_req), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_batch_counts, dim3(std::max(n_req, 1)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_batch_gangs, dim3(1), dim3(64), 0, st, a);
     hipLaunchKernelGGL((k_batch_cull<kCullP, kCullNT>), dim3(resident_blocks<k_batch_cull<kCullP, kCullNT>>(kCullNT)),
                        dim3(kCullNT), 0, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;

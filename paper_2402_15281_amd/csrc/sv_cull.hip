@@ -4,8 +4,9 @@
 // distance (Sec. IV-B) and the lowest index attaining it -- not every point's
 // distance.  Most (point, capsule, sample) tests of a motion are far above that
 // minimum, and whole groups of them can be proven so with two bounding spheres:
-//   - a wave's points: the cloud is put in Morton order first, so the 64 P points a
-//     wave holds are close together; their sphere is reduced across the wave;
+//   - a wave's points: the cloud is sorted by Morton cell first (a counting sort), so
+//     the 64 P points a wave holds are close together; their sphere is reduced across
+//     the wave;
 //   - a block of kCullB consecutive samples of one capsule: a sphere around all their
 //     segment endpoints, grown by the capsule radius (k_block_spheres).
 // If |c_wave - c_block| - R_wave - R_block exceeds an upper bound G of d(X, m) (plus
@@ -15,8 +16,6 @@
 // from an exact check of a stride sample of the sorted cloud (k_exact_seed) and
 // tightens as waves finish capsules and as other blocks publish their minima.
 // Per-point distances are not produced here (skipped tests would leave them high).
-#include <hipcub/hipcub.hpp>
-
 #include "sv_cull_common.h"
 
 namespace sv {
@@ -48,30 +47,130 @@ __global__ __launch_bounds__(256) void k_cloud_bounds(CloudArgs c, unsigned* __r
   }
 }
 
-__global__ __launch_bounds__(256) void k_morton(CloudArgs c, const unsigned* __restrict__ bounds,
-                                                unsigned* __restrict__ codes, int* __restrict__ idx) {
+// One thread per point: its Morton cell and its slot among the cell's points.
+__global__ __launch_bounds__(256) void k_cell_bin(CloudArgs c, const unsigned* __restrict__ bounds, int L,
+                                                  int* __restrict__ pbin, int* __restrict__ pslot,
+                                                  int* __restrict__ bin_count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= c.n) return;
   const float v[3] = {c.x[i], c.y[i], c.z[i]};
-  unsigned q[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float lo = unord_f32(bounds[a]), hi = unord_f32(bounds[3 + a]);
-    const float s = hi > lo ? 1023.0f / (hi - lo) : 0.f;
-    q[a] = (unsigned)fminf(fmaxf((v[a] - lo) * s, 0.f), 1023.f);
-  }
-  codes[i] = spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
-  idx[i] = i;
+  const int b = (int)morton_cell(v, bounds, L);
+  pbin[i] = b;
+  pslot[i] = atomicAdd(bin_count + b, 1);
 }
 
-__global__ __launch_bounds__(256) void k_gather(CloudArgs c, const int* __restrict__ perm, float* __restrict__ sx,
-                                                float* __restrict__ sy, float* __restrict__ sz) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= c.n) return;
-  const int i = perm[j];
+// One thread per point: the sorted cloud (SoA) and each sorted point's caller index.
+__global__ __launch_bounds__(256) void k_cell_scatter(CloudArgs c, const int* __restrict__ pbin,
+                                                      const int* __restrict__ pslot,
+                                                      const int* __restrict__ bin_start, float* __restrict__ sx,
+                                                      float* __restrict__ sy, float* __restrict__ sz,
+                                                      int* __restrict__ perm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n) return;
+  const int j = bin_start[pbin[i]] + pslot[i];
   sx[j] = c.x[i];
   sy[j] = c.y[i];
   sz[j] = c.z[i];
+  perm[j] = i;
+}
+
+// ---- exclusive scan of bin counts (three passes over groups of kScanGroup bins) ------
+constexpr int kScanGroup = 2048;   // 256 threads x 8 bins
+constexpr int kScanTop = 1024;     // threads of the one-block pass over the group sums
+
+// Exclusive scan of v over a 256-thread block; lds: 4 words.  Returns the block total.
+__device__ __forceinline__ int block_excl_scan256(int& v, int* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) lds[wid] = x;
+  __syncthreads();
+  int before = 0, total = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    before += u < wid ? lds[u] : 0;
+    total += lds[u];
+  }
+  v = before + x - v;
+  __syncthreads();   // lds free again
+  return total;
+}
+
+__device__ __forceinline__ int64_t scan_n(int64_t n_host, const int64_t* n_dev) { return n_dev ? *n_dev : n_host; }
+
+// Block-stride over the groups: the count of each group.
+__global__ __launch_bounds__(256) void k_scan_up(const int* __restrict__ count, int64_t n_host,
+                                                 const int64_t* __restrict__ n_dev, int* __restrict__ group_sum) {
+  __shared__ int lds[4];
+  const int64_t n = scan_n(n_host, n_dev);
+  const int64_t groups = (n + kScanGroup - 1) / kScanGroup;
+  for (int64_t gi = blockIdx.x; gi < groups; gi += gridDim.x) {
+    const int64_t b0 = gi * kScanGroup + threadIdx.x * 8;
+    int v = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += b0 + u < n ? count[b0 + u] : 0;
+    const int tot = block_excl_scan256(v, lds);
+    if (threadIdx.x == 0) group_sum[gi] = tot;
+  }
+}
+
+// One block: exclusive scan of the group counts into group_off (group_off[groups] =
+// total); each thread sums a contiguous run of groups.
+__global__ __launch_bounds__(kScanTop) void k_scan_top(const int* __restrict__ group_sum, int64_t n_host,
+                                                       const int64_t* __restrict__ n_dev,
+                                                       int64_t* __restrict__ group_off) {
+  __shared__ int64_t lds[kScanTop];
+  const int64_t n = scan_n(n_host, n_dev);
+  const int64_t groups = (n + kScanGroup - 1) / kScanGroup;
+  const int tid = threadIdx.x;
+  const int64_t S = (groups + kScanTop - 1) / kScanTop;
+  const int64_t b = min((int64_t)tid * S, groups), e = min(b + S, groups);
+  int64_t sum = 0;
+  for (int64_t i = b; i < e; ++i) sum += group_sum[i];
+  lds[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < kScanTop; off <<= 1) {   // Hillis-Steele inclusive scan
+    const int64_t y = tid >= off ? lds[tid - off] : 0;
+    __syncthreads();
+    lds[tid] += y;
+    __syncthreads();
+  }
+  int64_t run = lds[tid] - sum;
+  for (int64_t i = b; i < e; ++i) {
+    group_off[i] = run;
+    run += group_sum[i];
+  }
+  if (tid == kScanTop - 1) group_off[groups] = lds[tid];
+}
+
+// Block-stride over the groups: the first sorted position of every bin.
+__global__ __launch_bounds__(256) void k_scan_down(const int* __restrict__ count, int64_t n_host,
+                                                   const int64_t* __restrict__ n_dev,
+                                                   const int64_t* __restrict__ group_off, int* __restrict__ start) {
+  __shared__ int lds[4];
+  const int64_t n = scan_n(n_host, n_dev);
+  const int64_t groups = (n + kScanGroup - 1) / kScanGroup;
+  for (int64_t gi = blockIdx.x; gi < groups; gi += gridDim.x) {
+    const int64_t b0 = gi * kScanGroup + threadIdx.x * 8;
+    int c[8], v = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      c[u] = b0 + u < n ? count[b0 + u] : 0;
+      v += c[u];
+    }
+    block_excl_scan256(v, lds);
+    int pos = (int)group_off[gi] + v;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b0 + u < n) {
+        start[b0 + u] = pos;
+        pos += c[u];
+      }
+  }
 }
 
 // One thread per (motion, capsule, block of kCullB samples): centre of the endpoints'
@@ -234,7 +333,9 @@ __global__ __launch_bounds__(256) void k_cull_list(const float4* __restrict__ ti
 // One listed item (motion slot, tile of NT P sorted points, mask of kept capsules) per
 // block iteration; each wave owns 64 P consecutive sorted points and decides per
 // (capsule, sample block) whether the group can come below its bound.  Persistent
-// blocks take items grid-stride.  work (optional) counts the executed segment tests.
+// blocks take items in list order from a queue (count[1]), which keeps them together
+// on neighbouring motions and balances the uneven items.  work (optional) counts the
+// executed segment tests.
 template <int P, int NT>
 __global__ __launch_bounds__(NT) void k_exact_cull(const CapEntry* __restrict__ table,
                                                    const float4* __restrict__ spheres, int T, int K, int nb,
@@ -242,15 +343,21 @@ __global__ __launch_bounds__(NT) void k_exact_cull(const CapEntry* __restrict__ 
                                                    const float* __restrict__ sz, const int* __restrict__ perm, int N,
                                                    int tiles, const int* __restrict__ mlist,
                                                    const int* __restrict__ list, const int* __restrict__ caps,
-                                                   const int* __restrict__ count,
+                                                   int* __restrict__ count,
                                                    unsigned long long* __restrict__ keys,
                                                    unsigned long long* __restrict__ work) {
   __shared__ unsigned long long wexec[NT / 64];
   __shared__ unsigned long long wmin[NT / 64];
-  const int n_items = *count;
+  __shared__ int s_next;
+  const int n_items = count[0];
+  int* head = count + 1;   // queue head, zero on entry
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   unsigned long long executed = 0;
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  if (threadIdx.x == 0) s_next = atomicAdd(head, 1);
+  __syncthreads();
+  for (int it = s_next; it < n_items; it = s_next) {
+    int nxt = 0;
+    if (threadIdx.x == 0) nxt = atomicAdd(head, 1);   // the next item, requested while this one runs
     const int g = list[it];
     const int k = caps[it];
     const int slot = g / tiles;
@@ -260,10 +367,12 @@ __global__ __launch_bounds__(NT) void k_exact_cull(const CapEntry* __restrict__ 
     const unsigned long long k2 =
         cull_item<P, NT>((ConstF4Ptr)table, ((size_t)m * K + k) * T, T, (ConstF4Ptr)(spheres + ((size_t)m * K + k) * nb),
                          nb, sx, sy, sz, perm, N, tile, G, wmin, executed);
-    // publish only a new minimum: most items end above the motion's current key
-    if (threadIdx.x == 0 && k2 < __hip_atomic_load(keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      atomicMin(keys + m, k2);
-    __syncthreads();
+    if (threadIdx.x == 0) {
+      // publish only a new minimum: most items end above the motion's current key
+      if (k2 < __hip_atomic_load(keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(keys + m, k2);
+      s_next = min(nxt, n_items);
+    }
+    __syncthreads();   // s_next written; wmin reused by the next item
   }
   // executed tests: one add per block, spread over kWorkSlots counters (same-address
   // atomics from every wave would serialise)
@@ -290,13 +399,32 @@ int device_cus_cull() {
   return cus[dev];
 }
 
+// Blocks of the persistent culled kernel the device holds at once.
+int64_t resident_cull_blocks() {
+  static int per_cu[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (per_cu[dev] == 0) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_exact_cull<kCullP, kCullNT>, kCullNT, 0) != hipSuccess ||
+        b < 1)
+      b = 1;
+    per_cu[dev] = b;
+  }
+  return (int64_t)device_cus_cull() * per_cu[dev];
+}
+
 }  // namespace
 
-size_t cull_sort_bytes(int64_t N) {
-  size_t b = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const unsigned*)nullptr, (unsigned*)nullptr,
-                                           (const int*)nullptr, (int*)nullptr, (int)N, 0, 30, (hipStream_t)0);
-  return b;
+int64_t bin_scan_groups(int64_t cap) { return (cap + kScanGroup - 1) / kScanGroup; }
+
+hipError_t launch_bin_scan(const int* count, int64_t n_host, const int64_t* n_dev, int64_t cap, int* group_sum,
+                           int64_t* group_off, int* start, hipStream_t st) {
+  const unsigned g = (unsigned)std::min<int64_t>(std::max<int64_t>(bin_scan_groups(cap), 1), 16384);
+  hipLaunchKernelGGL(k_scan_up, dim3(g), dim3(256), 0, st, count, n_host, n_dev, group_sum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTop), 0, st, group_sum, n_host, n_dev, group_off);
+  hipLaunchKernelGGL(k_scan_down, dim3(g), dim3(256), 0, st, count, n_host, n_dev, group_off, start);
+  return hipGetLastError();
 }
 
 int cull_blocks(int T) { return (T + kCullB - 1) / kCullB; }
@@ -312,13 +440,16 @@ hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const 
   if ((e = launch_fill_i32(reinterpret_cast<int*>(w.bounds) + 3, 3, 0, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_cloud_bounds, dim3(std::min<unsigned>(grid_for(c.n, 256), 1024)), dim3(256), 0, st, c,
                      w.bounds);
-  hipLaunchKernelGGL(k_morton, dim3(grid_for(c.n, 256)), dim3(256), 0, st, c, w.bounds, w.codes, w.idx);
+  const int64_t nbins = (int64_t)1 << (3 * w.level);
+  if ((e = launch_fill_i32(w.bin_count, nbins, 0, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cell_bin, dim3(grid_for(c.n, 256)), dim3(256), 0, st, c, w.bounds, w.level, w.pbin, w.pslot,
+                     w.bin_count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  size_t tb = w.sort_bytes;
-  if ((e = hipcub::DeviceRadixSort::SortPairs(w.sort_tmp, tb, w.codes, w.codes_sorted, w.idx, w.perm, c.n, 0, 30,
-                                              st)) != hipSuccess)
+  if ((e = launch_bin_scan(w.bin_count, nbins, nullptr, nbins, w.group_sum, w.group_off, w.bin_start, st)) !=
+      hipSuccess)
     return e;
-  hipLaunchKernelGGL(k_gather, dim3(grid_for(c.n, 256)), dim3(256), 0, st, c, w.perm, w.sx, w.sy, w.sz);
+  hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(c.n, 256)), dim3(256), 0, st, c, w.pbin, w.pslot, w.bin_start,
+                     w.sx, w.sy, w.sz, w.perm);
   hipLaunchKernelGGL(k_block_spheres, dim3(grid_for(mo.n * K * nb, 256)), dim3(256), 0, st, table, mo.n, T, K, nb,
                      w.spheres);
   const int stride = std::max(1, c.n / 256);
@@ -330,11 +461,11 @@ hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const 
   if (items * K > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(k_tile_spheres, dim3((unsigned)tiles), dim3(256), 0, st, w.sx, w.sy, w.sz, c.n,
                      kCullNT * kCullP, w.tile_spheres);
-  if ((e = launch_fill_i32(w.list_count, 1, 0, st)) != hipSuccess) return e;
+  if ((e = launch_fill_i32(w.list_count, 2, 0, st)) != hipSuccess) return e;   // count, queue head
   hipLaunchKernelGGL(k_cull_list, dim3(grid_for(items * K, 256)), dim3(256), 0, st, w.tile_spheres, w.spheres, K, nb,
                      tiles, n_slots, mlist, mcount, keys, w.list, w.list_caps, w.list_count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int blocks = (int)std::min<int64_t>(items * K, (int64_t)device_cus_cull() * 8);
+  const int blocks = (int)std::min<int64_t>(items * K, resident_cull_blocks());
   hipLaunchKernelGGL((k_exact_cull<kCullP, kCullNT>), dim3(blocks), dim3(kCullNT), 0, st, table, w.spheres, T, K, nb,
                      w.sx, w.sy, w.sz, w.perm, c.n, tiles, mlist, w.list, w.list_caps, w.list_count, keys, w.work);
   return hipGetLastError();

@@ -37,7 +37,7 @@ __device__ __forceinline__ float key_dist(unsigned long long key) {
   return key == kKeyEmpty ? INFINITY : unord_f32((uint32_t)(key >> 32));
 }
 
-// 10 bits per axis, interleaved: a 30-bit Morton code of each point within the bounds.
+// Up to 10 bits per axis, interleaved into a Morton code.
 __device__ __forceinline__ unsigned spread10(unsigned v) {
   v &= 0x3ffu;
   v = (v | (v << 16)) & 0x030000ffu;
@@ -45,6 +45,23 @@ __device__ __forceinline__ unsigned spread10(unsigned v) {
   v = (v | (v << 4)) & 0x030c30c3u;
   v = (v | (v << 2)) & 0x09249249u;
   return v;
+}
+
+// Morton cell of point v in a grid of 2^L cells per axis over the bounds bd (bd[0..2]
+// minima, bd[3..5] maxima, as order-preserving keys).  Points are binned by cell and
+// the cells taken in Morton order, so consecutive points of the sorted cloud are close
+// together; the order within a cell is free (every result downstream is a minimum over
+// all points, keyed by the caller's point index).
+__device__ __forceinline__ unsigned morton_cell(const float v[3], const unsigned* bd, int L) {
+  const float cells = (float)(1 << L);
+  unsigned q[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float lo = unord_f32(bd[a]), hi = unord_f32(bd[3 + a]);
+    const float sc = hi > lo ? cells / (hi - lo) : 0.f;
+    q[a] = (unsigned)fminf(fmaxf((v[a] - lo) * sc, 0.f), cells - 1.f);
+  }
+  return spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
 }
 
 // One culled item for one wave group: the wave's 64 P consecutive sorted points of

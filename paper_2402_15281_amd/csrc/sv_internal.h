@@ -108,8 +108,20 @@ struct BatchPlan {
   unsigned long long next_item;     // head of the work queue
   // culled pass
   int64_t total_motions, total_points, total_tiles, total_cands, total_bins;
-  int list_count;                   // surviving (motion, tile, capsule) items
 };
+
+// What the culled pass needs of request r per item, in one 32-byte record.
+struct BatchReq {
+  int64_t sample_off;              // first (motion, sample) pair
+  int point_off, motion_off;       // first sorted point; first global motion
+  int n_points, T, nb;             // cloud size; samples; sample blocks
+  int list_off;                    // first slot of the request's listed items
+};
+
+// The culled batched kernel's blocks form kGangs gangs (block index mod kGangs, one
+// gang per XCD under the round-robin dispatch of workgroups to XCDs).  Each gang has a
+// queue over the requests assigned to it; an idle gang takes items from the others.
+constexpr int kGangs = 8;
 
 // Workspace of a batch call: per-request arrays [max_requests] (offsets [+1]), keys
 // [max_motions], capsule table [max_samples * K], band arrays [max_band].
@@ -138,6 +150,13 @@ struct BatchWs {
   float4* tile_sph;                               // [tile_cap]
   float4* spheres;                                // [max_motions][K][nb_max]
   int *list_g, *list_tk;                          // [cand_cap] motion, tile << 4 | capsule
+  BatchReq* req;                                  // [max_requests]
+  int* fill;                                      // [max_requests] listed items per request
+  int* gang_n;                                    // [kGangs] requests per gang
+  int* gang_total;                                // [kGangs] items per gang
+  unsigned* gang_head;                            // [kGangs] queue heads
+  int* gang_req;                                  // [kGangs][max_requests] requests in gang order
+  int* gang_off;                                  // [kGangs][max_requests + 1] their first gang item
   int64_t point_cap, tile_cap, cand_cap, bin_cap;
   int nb_max;
 };
@@ -145,8 +164,7 @@ struct BatchWs {
 bool batch_tile_supported(const sv_tile& t);
 // The culled batched pass, on unless switched off for measurement (sv_set_exact_culling).
 extern bool g_batch_cull;
-constexpr int kBinCellsPerPoint = 2;   // Morton cells per point of a request, at most
-constexpr int kBinMaxLevel = 7;        // at most 128 cells per axis
+
 // Carves ws (NULL: only sizes); *bytes = total.
 BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, size_t* bytes);
 hipError_t launch_batch(const sv_robot& rb, const sv_request* reqs, int n_req, const sv_batch_caps& caps, float eps,
@@ -190,22 +208,38 @@ hipError_t launch_decode_min(const unsigned* keys, int64_t M, float* d_hat, hipS
 // Workspace of the culled exact pass: cloud bounds and Morton sort, the sorted cloud
 // (SoA) with its permutation to the caller's indices, radix-sort scratch, and one
 // bounding sphere per (motion, capsule, block of samples).
+// Counting sort of a cloud by Morton cell (both culled passes): 2^L cells per axis,
+// at most kBinCellsPerPoint cells per point and kBinMaxLevel levels.
+constexpr int kBinCellsPerPoint = 2;
+constexpr int kBinMaxLevel = 7;
+__host__ __device__ inline int morton_level(int64_t n) {
+  int L = 0;
+  while (L < kBinMaxLevel && ((int64_t)1 << (3 * (L + 1))) <= n * kBinCellsPerPoint) ++L;
+  return L;
+}
+// Exclusive scan of count[0..n) into start[0..n) (n = *n_dev if n_dev, else n_host);
+// group_sum [bin_scan_groups(cap)], group_off [bin_scan_groups(cap) + 1] for n <= cap.
+int64_t bin_scan_groups(int64_t cap);
+hipError_t launch_bin_scan(const int* count, int64_t n_host, const int64_t* n_dev, int64_t cap, int* group_sum,
+                           int64_t* group_off, int* start, hipStream_t st);
+
 struct CullWs {
   unsigned* bounds;                 // [6]
-  unsigned *codes, *codes_sorted;   // [N]
-  int *idx, *perm;                  // [N]
-  float *sx, *sy, *sz;              // [N]
-  void* sort_tmp;
-  size_t sort_bytes;
+  int level;                        // Morton cells per axis 2^level (morton_level(N))
+  int *pbin, *pslot;                // [N] cell of each point, slot within it
+  int *bin_count, *bin_start;       // [8^level]
+  int* group_sum;                   // [bin_scan_groups(8^level)]
+  int64_t* group_off;               // [bin_scan_groups(8^level) + 1]
+  int* perm;                        // [N] caller's index of each sorted point
+  float *sx, *sy, *sz;              // [N] sorted points
   float4* spheres;                  // [M][K][cull_blocks(T)]
   float4* tile_spheres;             // [cull_tiles(N)]
   int* list;                        // [M * cull_tiles(N) * K] surviving (motion slot, tile) items
   int* list_caps;                  // [M * cull_tiles(N) * K] the capsule each item checks
-  int* list_count;                  // [1]
+  int* list_count;                  // [2] listed items, queue head
   unsigned long long* work;         // [kWorkSlots] executed segment tests, summed (may be NULL)
 };
 constexpr int kWorkSlots = 256;
-size_t cull_sort_bytes(int64_t N);
 int cull_blocks(int T);
 int cull_tiles(int64_t N);
 // Per-motion (distance, index) keys of the motion slots (mlist/mcount as launch_exact)

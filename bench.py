@@ -69,8 +69,11 @@ def profiled_traffic(doc, sources):
     return int(fields["traffic_bytes_per_launch"])
 
 
-MLP_SOURCES = ["paper_2402_15281_amd/csrc/sv_mlp.hip", "paper_2402_15281_amd/csrc/sv_mlp_common.h"]
-GEOM_SOURCES = ["paper_2402_15281_amd/csrc/sv_geom.hip"]
+MLP_SOURCES = ["paper_2402_15281_amd/csrc/sv_mlp.hip", "paper_2402_15281_amd/csrc/sv_mlp_common.h",
+               "paper_2402_15281_amd/csrc/sv_geom_common.h"]
+GEOM_SOURCES = ["paper_2402_15281_amd/csrc/sv_geom.hip", "paper_2402_15281_amd/csrc/sv_geom_common.h"]
+CULL_SOURCES = ["paper_2402_15281_amd/csrc/sv_cull.hip", "paper_2402_15281_amd/csrc/sv_cull_common.h",
+                "paper_2402_15281_amd/csrc/sv_geom_common.h"]
 
 
 def mlp_flops_per_query(in_dim, width, n_hidden):
@@ -468,6 +471,8 @@ def main():
                                   "executed_fraction": executed / (M * N * motions.T * arm.n_caps),
                                   "executed_tflops": fx, "executed_frac_of_fp32_peak": fx / PEAK_FP32_TFLOPS,
                                   "all_tests_equivalent_tflops": fx_eff,
+                                  "traffic": profiled_traffic("k_exact_cull_bin20k_traffic.md", CULL_SOURCES),
+                                  "traffic_kernel": "k_exact_cull<2, 256>",
                                   "note": "culling skips groups of tests proven above the motion's minimum; "
                                           "results equal the dense kernel's bit for bit"},
                       "dense_kernel": {"value": M / (ms_d / 1e3), "ms_per_step": ms_d, "results_identical": dense_same,

@@ -99,17 +99,36 @@ typedef struct {
   int32_t* n_fallback; /* screening only: points sent to the exact check */
 } sv_results;
 
-/* Swept-volume network f_theta(x, q0, q1) -> delta_hat (Sec. IV-A): a plain MLP with
- * softplus activations, h_0 = [x; q0; q1] (in that order, the inputs of Fig. 1),
- * h_l = softplus(W_l h_{l-1} + b_l) for l = 1..L, delta_hat = w_out . h_L + b_out.
- * softplus(z) = max(z, 0) + log(1 + exp(-|z|)).  The network applies to linear
- * motions only: (q0, q1) determines a linear motion but not a spline (Sec. IV-C). */
+/* Swept-volume network f_theta(x, q0, q1) -> delta_hat (Sec. IV-A), with input
+ * x_in = [x; q0; q1] (in that order, the inputs of Fig. 1).  Two architectures:
+ *
+ * SV_NET_MLP: a plain MLP with softplus activations, h_1 = softplus(W_1 x_in + b_1),
+ *   h_l = softplus(W_l h_{l-1} + b_l) for l = 2..L, delta_hat = w_out . h_L + b_out,
+ *   softplus(z) = max(z, 0) + log(1 + exp(-|z|)).
+ *   params: W_1 [W][in_dim], b_1 [W], then for l = 2..L: W_l [W][W], b_l [W]; then
+ *   w_out [W], b_out [1].
+ *
+ * SV_NET_RESIDUAL: the paper's network (Sec. IV-A, Fig. 1): an initial linear layer
+ *   h_0 = W_0 x_in + b_0 (no activation), then L blocks, each a linear layer on the
+ *   block input with the network input concatenated (the jump connection), a ReLU, a
+ *   BatchNorm (inference form, running statistics) and a skip connection:
+ *     z_b = W_b [h_{b-1}; x_in] + c_b,
+ *     h_b = h_{b-1} + gamma_b (relu(z_b) - mu_b) / sqrt(var_b + bn_eps) + beta_b,
+ *   then delta_hat = w_out . h_L + b_out.
+ *   params: W_0 [W][in_dim], b_0 [W], then per block b = 1..L: Wh_b [W][W] (the columns
+ *   of W_b acting on h), Wx_b [W][in_dim] (the columns acting on x_in), c_b [W],
+ *   gamma_b [W], beta_b [W], mu_b [W], var_b [W]; then w_out [W], b_out [1].
+ *
+ * Weights row-major [out][in], FP32.  The network applies to linear motions only:
+ * (q0, q1) determines a linear motion but not a spline (Sec. IV-C). */
+enum { SV_NET_MLP = 0, SV_NET_RESIDUAL = 1 };
 typedef struct {
-  int32_t in_dim;      /* 3 + 2 * dof */
+  int32_t in_dim;      /* 3 + 2 * dof; SV_NET_RESIDUAL in BF16: dof <= 6 */
   int32_t width;       /* hidden width W: FP32 path W % 64 == 0, W <= 1024; BF16 path 128, 256 or 512 */
-  int32_t n_hidden;    /* L >= 1 softplus layers */
-  const float* params; /* dev FP32, flat: W_1 [W][in_dim], b_1 [W], then for l = 2..L: W_l [W][W], b_l [W];
-                          then w_out [W], b_out [1].  Weights row-major [out][in]. */
+  int32_t n_hidden;    /* L >= 1: softplus layers (SV_NET_MLP) or blocks (SV_NET_RESIDUAL) */
+  const float* params; /* dev FP32, flat, in the order given above */
+  int32_t kind;        /* SV_NET_MLP or SV_NET_RESIDUAL; training supports SV_NET_MLP only */
+  float bn_eps;        /* SV_NET_RESIDUAL: the BatchNorm epsilon (> 0) */
 } sv_mlp;
 
 /* Arithmetic of the network evaluation. */

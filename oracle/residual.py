@@ -1,0 +1,108 @@
+"""FP64 oracle for the paper's residual swept-volume network (Sec. IV-A, Fig. 1).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product path.
+
+The network, read from Sec. IV-A and Fig. 1:
+
+    h_0 = W_0 x_in + b_0                              (initial linear layer, no activation)
+    z_b = W_b [h_{b-1}; x_in] + c_b                    (block linear layer; the network
+                                                        input is concatenated to the block
+                                                        input: the jump connection)
+    h_b = h_{b-1} + BN_b(relu(z_b)),   b = 1..L         (ReLU, then BatchNorm, then the skip)
+    delta_hat = w_out . h_L + b_out                     (final linear layer)
+
+with x_in = [x; q0; q1] and the BatchNorm in its inference form with running
+statistics, BN(a) = gamma (a - mu) / sqrt(var + eps) + beta.
+
+Reading: the paper says each block's linear layer keeps the block dimension and also
+that the network input is concatenated to each block output.  Both hold if the
+concatenated vector [h; x_in] feeds the next block's linear layer (n_dim + in_dim ->
+n_dim) while the skip adds h alone; that is the reading taken here.
+
+Parameters arrive as one flat FP32 vector: W_0 [W][in], b_0 [W], then per block
+Wh [W][W], Wx [W][in] (the columns of W_b acting on h and on x_in), c, gamma, beta,
+mu, var (each [W]), then w_out [W], b_out [1]; converted exactly to float64.
+
+A matrix product (numpy ``@``) is used as a library primitive; nothing else is fused
+or reordered.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .mlp import round_bf16
+
+
+def n_params(in_dim: int, width: int, n_blocks: int) -> int:
+    W = width
+    return W * in_dim + W + n_blocks * (W * W + W * in_dim + 5 * W) + W + 1
+
+
+def unpack(flat, in_dim: int, width: int, n_blocks: int) -> dict:
+    """Flat vector -> {'W0','b0','blocks': [dict(Wh, Wx, c, gamma, beta, mu, var)], 'w_out', 'b_out'}."""
+    flat = np.asarray(flat, dtype=np.float64)
+    if flat.size != n_params(in_dim, width, n_blocks):
+        raise ValueError(f"parameter vector has {flat.size} entries, expected {n_params(in_dim, width, n_blocks)}")
+    W = width
+    off = 0
+
+    def take(n, shape=None):
+        nonlocal off
+        a = flat[off:off + n]
+        off += n
+        return a.reshape(shape) if shape else a
+
+    net = {"W0": take(W * in_dim, (W, in_dim)), "b0": take(W), "blocks": []}
+    for _ in range(n_blocks):
+        net["blocks"].append({"Wh": take(W * W, (W, W)), "Wx": take(W * in_dim, (W, in_dim)), "c": take(W),
+                              "gamma": take(W), "beta": take(W), "mu": take(W), "var": take(W)})
+    net["w_out"] = take(W)
+    net["b_out"] = take(1)[0]
+    return net
+
+
+def pack(net: dict) -> np.ndarray:
+    parts = [net["W0"].ravel(), net["b0"]]
+    for b in net["blocks"]:
+        parts += [b["Wh"].ravel(), b["Wx"].ravel(), b["c"], b["gamma"], b["beta"], b["mu"], b["var"]]
+    parts += [net["w_out"], np.array([net["b_out"]])]
+    return np.concatenate([np.asarray(p, np.float64).ravel() for p in parts])
+
+
+def batchnorm(a, blk, eps):
+    """Inference BatchNorm with running statistics (the layer's eval form)."""
+    return blk["gamma"] * (a - blk["mu"]) / np.sqrt(blk["var"] + eps) + blk["beta"]
+
+
+def forward(flat, in_dim, width, n_blocks, X, bn_eps):
+    """delta_hat [B] for input rows X [B][in_dim]."""
+    net = unpack(flat, in_dim, width, n_blocks)
+    X = np.asarray(X, np.float64)
+    h = X @ net["W0"].T + net["b0"]
+    for blk in net["blocks"]:
+        z = np.concatenate([h, X], axis=1) @ np.concatenate([blk["Wh"], blk["Wx"]], axis=1).T + blk["c"]
+        h = h + batchnorm(np.maximum(z, 0.0), blk, bn_eps)
+    return h @ net["w_out"] + net["b_out"]
+
+
+def forward_bf16(flat, in_dim, width, n_blocks, X, bn_eps):
+    """Debugging aid: the network with the BF16 path's rounding points, otherwise FP64.
+
+    - h_0 from FP32-exact weights and unrounded inputs, rounded to BF16;
+    - each block: the weights Wh and Wx rounded to BF16; h (BF16) and the input as the
+      sum of its BF16 rounding and the BF16 rounding of the remainder; the block's result
+      rounded to BF16 except after the last block, whose result feeds the output layer
+      unrounded.
+    """
+    net = unpack(flat, in_dim, width, n_blocks)
+    X = np.asarray(X, np.float32).astype(np.float64)
+    x_hi = round_bf16(X)
+    x_lo = round_bf16((X.astype(np.float32) - x_hi.astype(np.float32)))
+    Xs = x_hi + x_lo
+    h = round_bf16(X @ net["W0"].T + net["b0"])
+    for i, blk in enumerate(net["blocks"]):
+        z = h @ round_bf16(blk["Wh"]).T + Xs @ round_bf16(blk["Wx"]).T + blk["c"]
+        y = h + batchnorm(np.maximum(z, 0.0), blk, bn_eps)
+        h = y if i + 1 == n_blocks else round_bf16(y)
+    return h @ net["w_out"] + net["b_out"]

@@ -51,9 +51,12 @@ class sv_cloud(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p)]
 
 
+SV_NET_MLP, SV_NET_RESIDUAL = 0, 1
+
+
 class sv_mlp(ctypes.Structure):
     _fields_ = [("in_dim", ctypes.c_int32), ("width", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
-                ("params", ctypes.c_void_p)]
+                ("params", ctypes.c_void_p), ("kind", ctypes.c_int32), ("bn_eps", ctypes.c_float)]
 
 
 class sv_train_hparams(ctypes.Structure):
@@ -229,15 +232,17 @@ class DeviceCloud:
 class DeviceMLP:
     """Flat FP32 network parameters in device memory plus their sv_mlp descriptor."""
 
-    def __init__(self, params, in_dim: int, width: int, n_hidden: int, device="cuda"):
+    def __init__(self, params, in_dim: int, width: int, n_hidden: int, device="cuda", kind: int = 0,
+                 bn_eps: float = 1e-5):
         if isinstance(params, torch.Tensor):
             self.params = params.to(device=device, dtype=torch.float32).contiguous()
         else:
             self.params = torch.as_tensor(np.asarray(params, np.float32), device=device).contiguous()
         self.in_dim, self.width, self.n_hidden = int(in_dim), int(width), int(n_hidden)
+        self.kind, self.bn_eps = int(kind), float(bn_eps)
 
     def desc(self) -> sv_mlp:
-        return sv_mlp(self.in_dim, self.width, self.n_hidden, self.params.data_ptr())
+        return sv_mlp(self.in_dim, self.width, self.n_hidden, self.params.data_ptr(), self.kind, self.bn_eps)
 
 
 class DeviceResults:
@@ -361,8 +366,12 @@ def sv_nn_predict(mlp: DeviceMLP, precision: int, rows: torch.Tensor, out: torch
     """out[n] <- network prediction for rows[n][stride] (first in_dim columns)."""
     d = mlp.desc()
     n, stride = int(rows.shape[0]), int(rows.shape[1])
-    if ws is None:
-        ws = workspace(0 if precision == SV_FP32 else 2 * mlp.width * mlp.width * (mlp.n_hidden - 1))
+    if ws is None:   # the network's workspace does not depend on the rows
+        n_ws = ctypes.c_size_t(0)
+        none_m, none_c = sv_motions(SV_LINEAR, 1, 0, None, None, None), sv_cloud(0, None, None, None)
+        _check(lib.sv_workspace_size(SV_OP_NN_SDF, None, ctypes.byref(d), int(precision), ctypes.byref(none_m),
+                                     ctypes.byref(none_c), ctypes.byref(n_ws)))
+        ws = workspace(n_ws.value)
     _check(lib.sv_nn_predict(ctypes.byref(d), int(precision), _ptr(rows), stride, n, _ptr(out), _ptr(ws), ws.numel(),
                              _stream(stream)))
     return ws

@@ -122,6 +122,10 @@ int check_mlp(const sv_mlp* n, int precision, int dof) {
   if (dof > 0 && n->in_dim != 3 + 2 * dof)
     return fail(SV_ERR_SHAPE, "mlp in_dim %d does not match robot dof %d", n->in_dim, dof);
   if (n->n_hidden < 1) return fail(SV_ERR_ARG, "mlp n_hidden %d < 1", n->n_hidden);
+  if (n->kind != SV_NET_MLP && n->kind != SV_NET_RESIDUAL) return fail(SV_ERR_ARG, "unknown network kind %d", n->kind);
+  if (n->kind == SV_NET_RESIDUAL && !(n->bn_eps > 0.f)) return fail(SV_ERR_ARG, "bn_eps must be > 0");
+  if (n->kind == SV_NET_RESIDUAL && precision == SV_BF16 && n->in_dim > kResMaxIn)
+    return fail(SV_ERR_UNSUPPORTED, "BF16 residual network: in_dim %d > %d", n->in_dim, kResMaxIn);
   if (precision == SV_FP32) {
     if (n->width < 64 || n->width > 1024 || n->width % 64)
       return fail(SV_ERR_UNSUPPORTED, "FP32 network width %d: need a multiple of 64 up to 1024", n->width);
@@ -134,7 +138,9 @@ int check_mlp(const sv_mlp* n, int precision, int dof) {
   return SV_OK;
 }
 
-MlpArgs to_args(const sv_mlp& n) { return MlpArgs{n.in_dim, n.width, n.n_hidden, (n.in_dim - 3) / 2, n.params}; }
+MlpArgs to_args(const sv_mlp& n) {
+  return MlpArgs{n.in_dim, n.width, n.n_hidden, (n.in_dim - 3) / 2, n.params, n.kind, n.bn_eps};
+}
 
 // Workspace layout of sv_check_motions.  The screening arrays are empty without a network.
 struct CheckWs {
@@ -579,6 +585,7 @@ int sv_train_workspace_size(const sv_mlp* mlp, int64_t batch, size_t* bytes) {
   int s;
   if (!bytes) return fail(SV_ERR_ARG, "bytes is NULL");
   if ((s = check_mlp(mlp, SV_BF16, 0))) return s;
+  if (mlp->kind != SV_NET_MLP) return fail(SV_ERR_UNSUPPORTED, "training supports SV_NET_MLP networks only");
   if (batch < 1 || batch > (1 << 24)) return fail(SV_ERR_SHAPE, "batch %lld outside 1..2^24", (long long)batch);
   *bytes = carve_train(nullptr, *mlp, batch).bytes;
   return SV_OK;
@@ -589,6 +596,7 @@ int sv_train_step(const sv_mlp* mlp, float* adam_m, float* adam_v, const sv_trai
                   void* ws, size_t ws_bytes, void* stream) {
   int s;
   if ((s = check_mlp(mlp, SV_BF16, 0))) return s;
+  if (mlp->kind != SV_NET_MLP) return fail(SV_ERR_UNSUPPORTED, "training supports SV_NET_MLP networks only");
   if (!hp) return fail(SV_ERR_ARG, "hparams is NULL");
   if (hp->step < 1) return fail(SV_ERR_ARG, "Adam step must be >= 1");
   if (!(hp->clamp_sigma > 0.f) || !(hp->lr >= 0.f) || !(hp->beta1 >= 0.f && hp->beta1 < 1.f) ||

@@ -50,9 +50,17 @@ struct MotionArgs {
 };
 
 // Network description for kernels: flat FP32 parameters (see sv_mlp in sv.h).
+// BF16 residual network: the network input enters every block's MFMA loop as kResXCols
+// extra columns of the activation tile, each input split into a BF16 high and low part
+// (so in_dim <= kResMaxIn), the remaining columns zero.
+constexpr int kResXCols = 32;
+constexpr int kResMaxIn = kResXCols / 2;
+
 struct MlpArgs {
   int in_dim, width, n_hidden, dof;
   const float* params;
+  int kind;       // SV_NET_MLP or SV_NET_RESIDUAL
+  float bn_eps;
 };
 
 struct CloudArgs {

@@ -122,11 +122,12 @@ __device__ __forceinline__ void layer_mfma(const __bf16* __restrict__ Wp, const 
 // acc[fb][rb].  Each weight tile is used RB times and each activation tile FB times
 // per load, so weight traffic per MFMA is 1/RB KB and LDS traffic 1/FB KB.
 // Ring depth D for the weight tiles.
-template <int W, int FB, int RB, int D>
-__device__ __forceinline__ void layer_mfma_fb(const __bf16* __restrict__ Wp, const __bf16* Hin, int wf, int wr,
-                                              int lane, const float* __restrict__ bias, f32x16 (&acc)[FB][RB]) {
-  constexpr int KS = W / 16;
-  constexpr int LD = W + kLdsPad;
+// K: inputs (columns of the layer's weights and of the activation tile), LD: the tile's
+// row stride in elements.
+template <int K, int LD, int FB, int RB, int D>
+__device__ __forceinline__ void layer_mfma_k(const __bf16* __restrict__ Wp, const __bf16* Hin, int wf, int wr,
+                                             int lane, const float* __restrict__ bias, f32x16 (&acc)[FB][RB]) {
+  constexpr int KS = K / 16;
   static_assert(KS % D == 0, "k-steps must fill the load ring");
   const int half = lane >> 5, col = lane & 31;
   const int wf_u = __builtin_amdgcn_readfirstlane(wf);
@@ -186,15 +187,23 @@ __device__ __forceinline__ void layer_mfma_fb(const __bf16* __restrict__ Wp, con
   }
 }
 
+// A square layer (W inputs) over a tile [rows][W + kLdsPad].
+template <int W, int FB, int RB, int D>
+__device__ __forceinline__ void layer_mfma_fb(const __bf16* __restrict__ Wp, const __bf16* Hin, int wf, int wr,
+                                              int lane, const float* __restrict__ bias, f32x16 (&acc)[FB][RB]) {
+  layer_mfma_k<W, W + kLdsPad, FB, RB, D>(Wp, Hin, wf, wr, lane, bias, acc);
+}
+
 // Packing of a W x W weight matrix M (row-major, FP32) into MFMA A-operand order:
 // element (fb, ks, lane, e) = M[fb*32 + lane%32][ks*16 + 8*(lane/32) + e], or of
 // M's transpose when `transpose` is set.  o indexes the packed array of one layer.
-__device__ __forceinline__ void packed_coords(int64_t o, int W, bool transpose, int* row, int* colk) {
+// K: the columns of M (W for a square layer).
+__device__ __forceinline__ void packed_coords(int64_t o, int K, bool transpose, int* row, int* colk) {
   const int e = (int)(o & 7);
   const int ln = (int)((o >> 3) & 63);
   const int64_t blk = o >> 9;
-  const int ks = (int)(blk % (W / 16));
-  const int fb = (int)(blk / (W / 16));
+  const int ks = (int)(blk % (K / 16));
+  const int fb = (int)(blk / (K / 16));
   const int r = fb * 32 + (ln & 31);
   const int k = ks * 16 + 8 * (ln >> 5) + e;
   *row = transpose ? k : r;

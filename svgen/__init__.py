@@ -219,6 +219,43 @@ def mlp_init(spec: MLPSpec, seed: int) -> np.ndarray:
     return flat
 
 
+@dataclass(frozen=True)
+class ResSpec:
+    """The residual network's sizes: n_blocks blocks of dimension width."""
+    in_dim: int
+    width: int
+    n_blocks: int
+
+    @property
+    def n_params(self) -> int:
+        w, i = self.width, self.in_dim
+        return (w * i + w) + self.n_blocks * (w * w + w * i + 5 * w) + (w + 1)
+
+
+def res_init(spec: ResSpec, seed: int) -> np.ndarray:
+    """Flat FP32 parameters of the residual network, in the order of its layout.
+
+    Linear layers: uniform in +-1/sqrt(fan_in) (a block's fan_in is width + in_dim),
+    W before b.  BatchNorm running statistics and affine terms as a trained layer might
+    hold them: gamma U[0.8, 1.2], beta U[-0.1, 0.1], mu U[0, 0.5] (inputs are ReLU
+    outputs), var U[0.5, 1.5].
+    """
+    g = _rng(seed)
+    w, i = spec.width, spec.in_dim
+    b0 = 1.0 / math.sqrt(i)
+    parts = [g.uniform(-b0, b0, size=w * i), g.uniform(-b0, b0, size=w)]
+    bb = 1.0 / math.sqrt(w + i)
+    for _ in range(spec.n_blocks):
+        parts += [g.uniform(-bb, bb, size=w * w), g.uniform(-bb, bb, size=w * i), g.uniform(-bb, bb, size=w),
+                  g.uniform(0.8, 1.2, size=w), g.uniform(-0.1, 0.1, size=w), g.uniform(0.0, 0.5, size=w),
+                  g.uniform(0.5, 1.5, size=w)]
+    bo = 1.0 / math.sqrt(w)
+    parts += [g.uniform(-bo, bo, size=w), g.uniform(-bo, bo, size=1)]
+    flat = np.concatenate(parts).astype(np.float32)
+    assert flat.size == spec.n_params
+    return flat
+
+
 def uniforms(seed: int, rows: int, cols: int) -> np.ndarray:
     """[rows][cols] float32 numbers uniform in [0, 1) (strictly below 1 after rounding)."""
     u = _rng(seed).random((rows, cols), dtype=np.float32)

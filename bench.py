@@ -253,6 +253,36 @@ def batched_requests(sv, torch, np, arm, reps=5):
     return res
 
 
+def paper_network(sv, torch, np, dm, dc, soft_net, steps):
+    """The paper's residual network (Sec. IV-A) at its 5 x 512 and 11 x 512 sizes, seeded
+    random weights, BF16 MFMA over every bin20k pair (dense predictions), beside the
+    softplus 8 x 512 network in the same mode."""
+    import svgen
+    M, N = dm.n, dc.n
+    out = torch.empty(M, N, device="cuda")
+    res = {"workload": f"bin20k pairs ({M} motions x {N} points), dense predictions, BF16 MFMA", "networks": {}}
+    nets = [("residual_5x512", svgen.ResSpec(15, 512, 5)), ("residual_11x512", svgen.ResSpec(15, 512, 11)),
+            ("softplus_8x512", None)]
+    for name, spec in nets:
+        if spec is None:
+            net, w, L = soft_net, soft_net.width, soft_net.n_hidden
+            flop_q = 2 * (15 * w + (L - 1) * w * w + w)
+        else:
+            net = sv.DeviceMLP(svgen.res_init(spec, 77), spec.in_dim, spec.width, spec.n_blocks,
+                               kind=sv.SV_NET_RESIDUAL, bn_eps=1e-5)
+            w, L = spec.width, spec.n_blocks
+            flop_q = 2 * (15 * w + L * (w + 15) * w + w)   # the jump term counted at its 15 inputs
+        ws = sv.workspace(sv.sv_workspace_size(sv.SV_OP_NN_SDF, None, dm, dc, net, sv.SV_BF16))
+        ms, per = timed(sv, torch, lambda: sv.sv_nn_sdf(net, sv.SV_BF16, dm, dc, out, ws=ws), steps, 1, ["mlp_bf16"])
+        k = per["mlp_bf16"]
+        tf = flop_q * M * N / (k / 1e3) / 1e12
+        res["networks"][name] = {"flop_per_query": flop_q, "kernel_ms": k, "ms_per_call": ms,
+                                 "queries_per_s": M * N / (k / 1e3), "tflops": tf, "frac_of_bf16_peak": tf / PEAK_BF16_TFLOPS}
+        log(f"paper network: {name} {k:.3f} ms = {tf:.1f} TFLOP/s ({tf / PEAK_BF16_TFLOPS:.1%} of BF16 peak), "
+            f"{M * N / (k / 1e3) / 1e9:.2f} G queries/s")
+    return res
+
+
 def box_world_search(sv, torch, np, arm, train_epochs, reps=3):
     """Alg. 1 on the box-world scenes: plain search (exact checks in the given order) vs
     the network-guided search (proxy d_hat of every motion, then exact checks in Alg. 1's
@@ -340,6 +370,7 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--train-motions", type=int, default=20000)
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-request batch leg")
+    ap.add_argument("--no-paper-net", action="store_true", help="skip the residual-network leg")
     ap.add_argument("--no-boxworld", action="store_true", help="skip the box-world search leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -499,6 +530,8 @@ def main():
                      "val_clamped_mae_m": {"untrained": ev0["mae_clamped"], "trained": ev1["mae_clamped"]},
                      "val_near_surface_mae_m": {"untrained": ev0["mae_near"], "trained": ev1["mae_near"]}},
     }
+    if not args.no_paper_net:
+        result["paper_network"] = paper_network(sv, torch, np, dm, dc, mlp, max(args.steps // 2, 2))
     if not args.no_batched:
         result["batched_requests"] = batched_requests(sv, torch, np, arm)
     if not args.no_boxworld:

@@ -204,6 +204,24 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
                      const sv_motions* motions, const sv_cloud* cloud, sv_results* out, void* ws,
                      size_t ws_bytes, void* stream);
 
+/* ---- continuous certification (Sec. III, eq. (3)) ---------------------------------
+ * The swept volume is a union over the continuous path parameter s in [0, 1]; the
+ * exact check evaluates it at the T samples s_t, so its distance is an upper bound of
+ * the continuous one.  For every motion, gap[m] bounds the difference:
+ *   d_cont(x, m) >= d_T(x, m) - gap[m]  for every point x,
+ * with gap[m] = max_k L_k h, h = 1 / (2 (T - 1)) (1 for T = 1) the largest distance from
+ * any s to a sample and L_k a bound of the speed (per unit s) of capsule k's points:
+ * for an endpoint fixed in frame f at coordinates p, sum over joints j <= f of
+ * max_s |dq_j/ds| (sum_{i=j..f} sqrt(a_i^2 + d_i^2) + |p|).  max_s |dq_j/ds| is
+ * |q1_j - q0_j| for linear motions and the exact maximum of the spline's derivative
+ * for splines.  Computed in FP64, rounded up to FP32.
+ * With min_dist (dev [M], e.g. sv_results.min_dist of the same motions and cloud),
+ * verdict[m] = 0 iff min_dist[m] - gap[m] > eps + 1e-5 (free along the whole
+ * continuous motion, with the FP32 error band of min_dist), else 1.
+ * gap: dev [M]; min_dist and verdict: both NULL or both dev [M]. */
+int sv_continuous_gap(const sv_robot* robot, const sv_motions* motions, const float* min_dist, float eps, float* gap,
+                      uint8_t* verdict, void* stream);
+
 /* ---- batches of uneven requests (Sec. IV-B's check, many callers at once) --------
  * A request is one set of motions checked against one cloud: exactly the question of
  * sv_check_motions without a network, answered with the same per-point arithmetic, so

@@ -146,11 +146,12 @@ def _load():
                                   F32, P, P, P, P, ctypes.c_size_t, P]
     lib.sv_first_free_workspace_size.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_motions),
                                                  ctypes.POINTER(sv_cloud), SZ]
+    lib.sv_continuous_gap.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_motions), P, F32, P, P, P]
     for fn in ("sv_workspace_size", "sv_fk", "sv_exact_sdf", "sv_nn_sdf", "sv_check_motions", "sv_profile_enable",
                "sv_profile_read", "sv_make_samples", "sv_make_samples_workspace_size", "sv_nn_predict",
                "sv_train_step", "sv_train_workspace_size", "sv_batch_workspace_size", "sv_check_requests",
                "sv_tile_candidates", "sv_default_tile", "sv_wall_clock_hz", "sv_nn_min", "sv_nn_min_workspace_size",
-               "sv_first_free", "sv_first_free_workspace_size", "sv_set_exact_culling"):
+               "sv_first_free", "sv_first_free_workspace_size", "sv_set_exact_culling", "sv_continuous_gap"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -278,6 +279,14 @@ def sv_workspace_size(op: int, robot, motions: DeviceMotions, cloud: DeviceCloud
 
 def workspace(nbytes: int, device="cuda"):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def sv_continuous_gap(robot: sv_robot, motions: DeviceMotions, gap: torch.Tensor, min_dist: torch.Tensor = None,
+                      eps: float = 0.0, verdict: torch.Tensor = None, stream=None):
+    """gap[m] <- bound of (sampled - continuous) swept distance; with min_dist, verdict[m]."""
+    md = motions.desc()
+    _check(lib.sv_continuous_gap(ctypes.byref(robot), ctypes.byref(md), _ptr(min_dist), float(eps), _ptr(gap),
+                                 _ptr(verdict), _stream(stream)))
 
 
 def sv_fk(robot: sv_robot, q: torch.Tensor, caps: torch.Tensor, fp64: bool = False, stream=None):

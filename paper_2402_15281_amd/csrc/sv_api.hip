@@ -314,6 +314,20 @@ int sv_workspace_size(int op, const sv_robot* robot, const sv_mlp* mlp, int prec
   }
 }
 
+int sv_continuous_gap(const sv_robot* robot, const sv_motions* motions, const float* min_dist, float eps, float* gap,
+                      uint8_t* verdict, void* stream) {
+  int s;
+  if ((s = check_robot(robot)) || (s = check_motions(motions, robot->dof))) return s;
+  if (motions->n == 0) return SV_OK;
+  if (!gap) return fail(SV_ERR_ARG, "gap is NULL");
+  if (!verdict != !min_dist) return fail(SV_ERR_ARG, "verdict and min_dist go together");
+  if (isnan(eps)) return fail(SV_ERR_ARG, "eps is NaN");
+  hipStream_t st = (hipStream_t)stream;
+  ProfScope ps("motion_gap", st);
+  const hipError_t e = launch_motion_gap(*robot, to_args(*motions), min_dist, eps, kCertBand, gap, verdict, st);
+  return e == hipSuccess ? SV_OK : hip_fail(e, "continuous gap");
+}
+
 int sv_fk(const sv_robot* robot, const float* q, int64_t n_cfg, float* caps, int fp64, void* stream) {
   int s;
   if ((s = check_robot(robot))) return s;

@@ -198,6 +198,72 @@ __global__ void k_finalize64(const int* __restrict__ list, const int* __restrict
 
 inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
+// ---- continuous certification -------------------------------------------------------
+// The exact check samples the path at s_t = t / (T - 1) (eq. (2), (3)); every s lies
+// within h = 1 / (2 (T - 1)) of a sample (h = 1 for T = 1).  If every point of capsule k
+// moves at most L_k per unit of s, a point's distance to the capsule changes at most
+// L_k per unit of s, so d_cont >= d_T - max_k L_k h.  Speed bound (standard DH, joint j
+// turns about the z axis of frame j-1 through O_{j-1}): a point fixed in frame f >= j
+// moves under joint j at |dq_j/ds| times its distance from that axis, at most
+// sum_{i=j..f} l_i + |p| (l_i = sqrt(a_i^2 + d_i^2), p its coordinates in frame f);
+// segment points are convex combinations of the two endpoints.
+
+// max over s of |dq_j/ds| for one joint: linear |y3 - y0|; spline (knots at 0, 1/3,
+// 2/3, 1 with the slopes of motion_config): per Hermite segment the derivative is a
+// quadratic a u^2 + b u + c in u in [0, 1], largest in magnitude at an end or the vertex.
+__device__ double joint_speed_max(int kind, double y0, double y1, double y2, double y3) {
+  if (kind == SV_LINEAR) return fabs(y3 - y0);
+  const double hm1 = (4.0 * (y2 - y0) - (y3 - y1)) / 5.0, hm2 = (4.0 * (y3 - y1) - (y2 - y0)) / 5.0;
+  const double y[4] = {y0, y1, y2, y3}, hm[4] = {0.0, hm1, hm2, 0.0};
+  double best = 0.0;
+  for (int seg = 0; seg < 3; ++seg) {
+    const double ya = y[seg], yb = y[seg + 1], ma = hm[seg], mb = hm[seg + 1];
+    const double a = 6.0 * (ya - yb) + 3.0 * (ma + mb), b = 6.0 * (yb - ya) - 4.0 * ma - 2.0 * mb, c = ma;
+    double v = fmax(fabs(c), fabs(a + b + c));
+    if (a != 0.0) {
+      const double u = -b / (2.0 * a);
+      if (u > 0.0 && u < 1.0) v = fmax(v, fabs((a * u + b) * u + c));
+    }
+    best = fmax(best, 3.0 * v);   // ds = du / 3
+  }
+  return best;
+}
+
+// One thread per motion: gap[m] (rounded up to FP32) and, with min_dist, verdict[m] = 0
+// iff min_dist[m] - gap[m] > eps + band (certified free along the continuous motion).
+__global__ __launch_bounds__(256) void k_motion_gap(Robot64 rb, MotionArgs mo, const float* __restrict__ min_dist,
+                                                    float eps, float band, float* __restrict__ gap,
+                                                    uint8_t* __restrict__ verdict) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= mo.n) return;
+  const int dof = rb.dof;
+  double omega[SV_MAX_DOF], tail[SV_MAX_DOF + 1];   // tail[j] = sum_{i=j..dof-1} l_i (0-based links)
+  for (int j = 0; j < dof; ++j) {
+    const float* q0 = mo.q0 + m * dof;
+    const float* q1 = mo.q1 + m * dof;
+    const float* v = mo.via ? mo.via + m * 2 * dof : nullptr;
+    omega[j] = joint_speed_max(mo.kind, q0[j], v ? v[j] : 0.0, v ? v[dof + j] : 0.0, q1[j]);
+  }
+  tail[dof] = 0.0;
+  for (int i = dof - 1; i >= 0; --i) tail[i] = tail[i + 1] + sqrt(rb.dh[i][0] * rb.dh[i][0] + rb.dh[i][2] * rb.dh[i][2]);
+  double L = 0.0;
+  for (int k = 0; k < rb.n_caps; ++k)
+    for (int e = 0; e < 2; ++e) {
+      const int f = e ? rb.fb[k] : rb.fa[k];
+      const double* p = e ? rb.pb[k] : rb.pa[k];
+      const double pn = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+      double v = 0.0;
+      for (int j = 0; j < f; ++j) v += omega[j] * (tail[j] - tail[f] + pn);   // links j..f-1 (0-based)
+      L = fmax(L, v);
+    }
+  const double g = L * (mo.T > 1 ? 0.5 / (double)(mo.T - 1) : 1.0);
+  float gf = (float)g;
+  if ((double)gf < g) gf = nextafterf(gf, INFINITY);
+  gap[m] = gf;
+  if (verdict) verdict[m] = (min_dist[m] - gf > eps + band) ? 0 : 1;
+}
+
+
 template <int P, int NT>
 hipError_t launch_exact_t(const CapEntry* table, const MotionArgs& m, const CloudArgs& c, int K, const int* mlist,
                           const int* mcount, int64_t n_slots, const int* plist, const int* pcount, int seg,
@@ -421,6 +487,14 @@ hipError_t launch_recheck64(const sv_robot& rb, const MotionArgs& m, const Cloud
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_finalize64, dim3(4), dim3(256), 0, st, list, count, keys64, eps, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_motion_gap(const sv_robot& rb, const MotionArgs& m, const float* min_dist, float eps, float band,
+                             float* gap, uint8_t* verdict, hipStream_t st) {
+  if (m.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_motion_gap, dim3(grid_for(m.n, 256)), dim3(256), 0, st, robot_to_dev<double>(rb), m, min_dist,
+                     eps, band, gap, verdict);
   return hipGetLastError();
 }
 

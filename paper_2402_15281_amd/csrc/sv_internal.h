@@ -258,6 +258,10 @@ hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const 
                                const CullWs& w, hipStream_t st);
 
 // ---- launchers (sv_geom.hip) ------------------------------------------------------
+// Per-motion gap between the sampled and the continuous swept distance, and (with
+// min_dist) the continuous verdict.
+hipError_t launch_motion_gap(const sv_robot& rb, const MotionArgs& m, const float* min_dist, float eps, float band,
+                             float* gap, uint8_t* verdict, hipStream_t st);
 hipError_t launch_fk_configs(const sv_robot& rb, const float* q, int64_t n, float* caps, int fp64,
                              hipStream_t st);
 hipError_t launch_motion_table(const sv_robot& rb, const MotionArgs& m, CapEntry* table, hipStream_t st);

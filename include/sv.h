@@ -379,6 +379,35 @@ int sv_make_samples(const sv_robot* robot, const sv_motions* motions, float cube
 int sv_make_samples_workspace_size(const sv_robot* robot, const sv_motions* motions, int32_t n_uniform,
                                    int32_t n_cand, size_t* bytes);
 
+/* Training samples in the paper's proportions (Sec. IV-C, dataset generation), for
+ * linear motions.  Per motion, rows [x, y, z, q0, q1, delta] (in_dim + 1 floats):
+ *   n_uniform points uniform in [-box_half, box_half]^3;
+ *   n_surface points on the swept surface (delta ~ 0): candidates are drawn uniformly
+ *     over the total area of the capsule instances (capsule k with probability
+ *     proportional to its area, sample t uniformly, a point uniform on the capsule's
+ *     surface: cylinder or caps by area) and a candidate is on the swept surface iff
+ *     its swept distance is 0 (FP32 >= -1e-6 m): no other instance contains it.  Every
+ *     piece of the swept surface belongs to one instance's surface, so accepted
+ *     candidates are uniform on it.  The first n_surface accepted ones in candidate
+ *     order are kept; if fewer are accepted, the first rejected ones fill the rest and
+ *     *n_short counts them;
+ *   then for each surface point: two points from a spherical Gaussian around it
+ *     (standard deviation sigma, Box-Muller), and one point uniform on the segment to
+ *     another of the motion's surface points (chosen at random).
+ * Row order per motion: uniform, surface, then (Gaussian, Gaussian, chord) per surface
+ * point: n_uniform + 4 n_surface rows.  Labels from the exact check (T samples).
+ * rnd: dev [M][3 n_uniform + 5 n_cand + 8 n_surface] uniforms in [0, 1): 3 per uniform
+ *   point, 5 per candidate, 8 per surface point (6 for the Gaussians, 2 for the chord).
+ * n_accepted: dev [M] (may be NULL): accepted candidates per motion; the swept surface
+ *   area is about n_accepted / n_cand times the total instance area.
+ * n_short: dev [1] (may be NULL), advanced.  n_cand >= n_surface.
+ * Workspace: sv_make_samples_paper_workspace_size. */
+int sv_make_samples_paper(const sv_robot* robot, const sv_motions* motions, float box_half, int32_t n_uniform,
+                          int32_t n_surface, int32_t n_cand, float sigma, const float* rnd, float* out,
+                          int32_t* n_accepted, int32_t* n_short, void* ws, size_t ws_bytes, void* stream);
+int sv_make_samples_paper_workspace_size(const sv_robot* robot, const sv_motions* motions, int32_t n_uniform,
+                                         int32_t n_surface, int32_t n_cand, size_t* bytes);
+
 /* Network prediction for arbitrary rows (x, q0, q1, ...): out[s] = f_theta(rows[s][0:in_dim]),
  * rows dev with row_stride floats per row (>= in_dim).  Workspace: SV_OP_NN_SDF sizes
  * (motions and cloud unused: pass any valid ones) -- 0 bytes for SV_FP32. */

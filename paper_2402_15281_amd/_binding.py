@@ -147,11 +147,16 @@ def _load():
     lib.sv_first_free_workspace_size.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_motions),
                                                  ctypes.POINTER(sv_cloud), SZ]
     lib.sv_continuous_gap.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_motions), P, F32, P, P, P]
+    lib.sv_make_samples_paper.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_motions), F32, I32, I32, I32,
+                                          F32, P, P, P, P, P, ctypes.c_size_t, P]
+    lib.sv_make_samples_paper_workspace_size.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_motions), I32,
+                                                         I32, I32, SZ]
     for fn in ("sv_workspace_size", "sv_fk", "sv_exact_sdf", "sv_nn_sdf", "sv_check_motions", "sv_profile_enable",
                "sv_profile_read", "sv_make_samples", "sv_make_samples_workspace_size", "sv_nn_predict",
                "sv_train_step", "sv_train_workspace_size", "sv_batch_workspace_size", "sv_check_requests",
                "sv_tile_candidates", "sv_default_tile", "sv_wall_clock_hz", "sv_nn_min", "sv_nn_min_workspace_size",
-               "sv_first_free", "sv_first_free_workspace_size", "sv_set_exact_culling", "sv_continuous_gap"):
+               "sv_first_free", "sv_first_free_workspace_size", "sv_set_exact_culling", "sv_continuous_gap",
+               "sv_make_samples_paper", "sv_make_samples_paper_workspace_size"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -279,6 +284,21 @@ def sv_workspace_size(op: int, robot, motions: DeviceMotions, cloud: DeviceCloud
 
 def workspace(nbytes: int, device="cuda"):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def sv_make_samples_paper(robot: sv_robot, motions: DeviceMotions, box_half: float, n_uniform: int, n_surface: int,
+                          n_cand: int, sigma: float, rnd: torch.Tensor, out: torch.Tensor,
+                          n_accepted: torch.Tensor = None, n_short: torch.Tensor = None, ws=None, stream=None):
+    """out[M][n_uniform + 4 n_surface][in_dim + 1] <- paper-style training rows (Sec. IV-C)."""
+    md = motions.desc()
+    if ws is None:
+        n = ctypes.c_size_t(0)
+        _check(lib.sv_make_samples_paper_workspace_size(ctypes.byref(robot), ctypes.byref(md), int(n_uniform),
+                                                        int(n_surface), int(n_cand), ctypes.byref(n)))
+        ws = workspace(n.value)
+    _check(lib.sv_make_samples_paper(ctypes.byref(robot), ctypes.byref(md), float(box_half), int(n_uniform),
+                                     int(n_surface), int(n_cand), float(sigma), _ptr(rnd), _ptr(out),
+                                     _ptr(n_accepted), _ptr(n_short), _ptr(ws), ws.numel(), _stream(stream)))
 
 
 def sv_continuous_gap(robot: sv_robot, motions: DeviceMotions, gap: torch.Tensor, min_dist: torch.Tensor = None,

@@ -570,6 +570,70 @@ int sv_make_samples(const sv_robot* robot, const sv_motions* motions, float cube
   return e == hipSuccess ? SV_OK : hip_fail(e, "make samples");
 }
 
+struct PaperWs {
+  CapEntry* table;
+  PaperSamplesWs a;
+  size_t bytes;
+};
+PaperWs carve_paper(void* ws, const sv_robot& r, const sv_motions& m, int nu, int ns, int nc) {
+  Carver cv(ws);
+  PaperWs w{};
+  w.table = cv.take<CapEntry>((size_t)m.n * r.n_caps * m.T);
+  const size_t U = (size_t)m.n * nu, C = (size_t)m.n * nc, S = (size_t)m.n * ns;
+  float** arrays[16] = {&w.a.ux, &w.a.uy, &w.a.uz, &w.a.ud, &w.a.cx, &w.a.cy, &w.a.cz, &w.a.cd,
+                        &w.a.sx, &w.a.sy, &w.a.sz, &w.a.sd, &w.a.kx, &w.a.ky, &w.a.kz, &w.a.kd};
+  const size_t sizes[4] = {U, C, S, 3 * S};
+  for (int i = 0; i < 16; ++i) *arrays[i] = cv.take<float>(sizes[i / 4]);
+  w.bytes = cv.off;
+  return w;
+}
+
+int check_paper_counts(const sv_motions* m, int32_t nu, int32_t ns, int32_t nc) {
+  if (nu < 0 || ns < 0 || nc < ns) return fail(SV_ERR_ARG, "need n_uniform >= 0, n_surface >= 0, n_cand >= n_surface");
+  if (m->n * (int64_t)std::max(std::max(nu, nc), 3 * ns) > 0x7fffffffLL)
+    return fail(SV_ERR_SHAPE, "too many points for one call; split the motions");
+  return SV_OK;
+}
+
+int sv_make_samples_paper_workspace_size(const sv_robot* robot, const sv_motions* motions, int32_t n_uniform,
+                                         int32_t n_surface, int32_t n_cand, size_t* bytes) {
+  int s;
+  if (!bytes) return fail(SV_ERR_ARG, "bytes is NULL");
+  if ((s = check_robot(robot)) || (s = check_motions(motions, robot->dof)) ||
+      (s = check_paper_counts(motions, n_uniform, n_surface, n_cand)))
+    return s;
+  *bytes = carve_paper(nullptr, *robot, *motions, n_uniform, n_surface, n_cand).bytes;
+  return SV_OK;
+}
+
+int sv_make_samples_paper(const sv_robot* robot, const sv_motions* motions, float box_half, int32_t n_uniform,
+                          int32_t n_surface, int32_t n_cand, float sigma, const float* rnd, float* out,
+                          int32_t* n_accepted, int32_t* n_short, void* ws, size_t ws_bytes, void* stream) {
+  int s;
+  if ((s = check_robot(robot)) || (s = check_motions(motions, robot->dof)) ||
+      (s = check_paper_counts(motions, n_uniform, n_surface, n_cand)))
+    return s;
+  if (motions->kind != SV_LINEAR) return fail(SV_ERR_UNSUPPORTED, "training samples are drawn for linear motions");
+  if (!(box_half > 0.f) || !(sigma >= 0.f)) return fail(SV_ERR_ARG, "box_half must be > 0 and sigma >= 0");
+  if (motions->n == 0 || (n_uniform == 0 && n_surface == 0)) return SV_OK;
+  if (!rnd || !out) return fail(SV_ERR_ARG, "rnd or out is NULL");
+  const PaperWs w0 = carve_paper(nullptr, *robot, *motions, n_uniform, n_surface, n_cand);
+  if (!ws || ws_bytes < w0.bytes) return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", w0.bytes, ws_bytes);
+  const PaperWs w = carve_paper(ws, *robot, *motions, n_uniform, n_surface, n_cand);
+  hipStream_t st = (hipStream_t)stream;
+  const MotionArgs ma = to_args(*motions);
+  hipError_t e;
+  {
+    ProfScope ps("motion_table", st);
+    e = launch_motion_table(*robot, ma, w.table, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "motion table");
+  ProfScope ps("make_samples_paper", st);
+  e = launch_make_samples_paper(*robot, ma, w.table, box_half, n_uniform, n_surface, n_cand, sigma, rnd, w.a, out,
+                                n_accepted, n_short, st);
+  return e == hipSuccess ? SV_OK : hip_fail(e, "make paper samples");
+}
+
 int sv_nn_predict(const sv_mlp* mlp, int precision, const float* rows, int64_t row_stride, int64_t n, float* out,
                   void* ws, size_t ws_bytes, void* stream) {
   int s;

@@ -383,6 +383,184 @@ __global__ __launch_bounds__(256) void k_assemble_samples(int64_t M, int dof, in
   }
 }
 
+// ------------------------------------------------------ paper-style training data
+// Per motion (Sec. IV-C): uniform box points; swept-surface points; for each surface
+// point two Gaussian points around it and one point on the chord to another surface
+// point.  rnd per motion: [3 n_uniform] then [5 n_cand] then [8 n_surface] numbers in
+// [0, 1).  The swept surface is sampled through candidates uniform over the total area
+// of the capsule instances (capsule k by area, sample t uniformly, a point uniform on
+// the capsule's surface); a candidate is on the swept surface iff no other instance
+// contains it, i.e. iff its swept distance is 0, and every piece of the surface belongs
+// to exactly one instance's surface, so accepted candidates are uniform on it.
+constexpr float kSurfAccept = -1e-6f;   // m: FP32 swept distance of an accepted candidate, at least
+
+__global__ void k_surface_candidates(const CapEntry* __restrict__ table, int64_t M, int T, int K, int nu, int nc,
+                                     int stride, const float* __restrict__ rnd, float* __restrict__ x,
+                                     float* __restrict__ y, float* __restrict__ z) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= M * nc) return;
+  const int64_t m = g / nc;
+  const int c = (int)(g - m * nc);
+  const float* r = rnd + m * stride + 3 * nu + 5 * c;
+  const CapEntry* base = table + m * K * T;   // [k][t]
+  // capsule k with probability proportional to its area 2 pi r L + 4 pi r^2 (rigid: from t = 0)
+  float cum[SV_MAX_CAPS];
+  float tot = 0.f;
+  for (int k = 0; k < K; ++k) {
+    const CapEntry e = base[(size_t)k * T];
+    const float L = sqrtf(e.bx * e.bx + e.by * e.by + e.bz * e.bz);
+    tot += 6.28318530717958648f * e.r * L + 12.5663706143591730f * e.r * e.r;
+    cum[k] = tot;
+  }
+  const float pick = r[0] * tot;
+  int k = K - 1;
+  for (int kk = K - 1; kk >= 0; --kk)
+    if (cum[kk] > pick) k = kk;   // the first capsule whose cumulative area exceeds pick
+  const int t = min((int)(r[1] * T), T - 1);
+  const CapEntry e = base[(size_t)k * T + t];
+  const float L = sqrtf(e.bx * e.bx + e.by * e.by + e.bz * e.bz);
+  const float pc = L + 2.f * e.r > 0.f ? L / (L + 2.f * e.r) : 0.f;
+  float px, py, pz;
+  if (r[2] < pc) {   // the cylinder: axial position and angle
+    const float ax = e.bx / L, ay = e.by / L, az = e.bz / L;
+    const bool useX = fabsf(ax) < 0.9f;   // helper axis not parallel to the segment
+    const float hx = useX ? 1.f : 0.f, hy = useX ? 0.f : 1.f;
+    float e1x = ay * 0.f - az * hy, e1y = az * hx - ax * 0.f, e1z = ax * hy - ay * hx;   // a x h
+    const float n1 = 1.f / sqrtf(e1x * e1x + e1y * e1y + e1z * e1z);
+    e1x *= n1; e1y *= n1; e1z *= n1;
+    const float e2x = ay * e1z - az * e1y, e2y = az * e1x - ax * e1z, e2z = ax * e1y - ay * e1x;   // a x e1
+    float sp, cp;
+    sincosf(6.28318530717958648f * r[4], &sp, &cp);
+    px = e.ax + r[3] * e.bx + e.r * (cp * e1x + sp * e2x);
+    py = e.ay + r[3] * e.by + e.r * (cp * e1y + sp * e2y);
+    pz = e.az + r[3] * e.bz + e.r * (cp * e1z + sp * e2z);
+  } else {           // the caps: a direction uniform on the sphere, around the end it points away at
+    const float cz = 2.f * r[3] - 1.f;
+    const float sz = sqrtf(fmaxf(0.f, 1.f - cz * cz));
+    float sp, cp;
+    sincosf(6.28318530717958648f * r[4], &sp, &cp);
+    const float dx = sz * cp, dy = sz * sp, dz = cz;
+    const bool atB = L > 0.f && (dx * e.bx + dy * e.by + dz * e.bz) > 0.f;
+    px = e.ax + (atB ? e.bx : 0.f) + e.r * dx;
+    py = e.ay + (atB ? e.by : 0.f) + e.r * dy;
+    pz = e.az + (atB ? e.bz : 0.f) + e.r * dz;
+  }
+  x[g] = px;
+  y[g] = py;
+  z[g] = pz;
+}
+
+// One wave per motion: the first n_surface accepted candidates in candidate order (then,
+// if short, the first rejected ones); n_acc[m] = accepted candidates of the motion.
+__global__ __launch_bounds__(256) void k_pick_surface(int64_t M, int nc, int ns, const float* __restrict__ cx,
+                                                      const float* __restrict__ cy, const float* __restrict__ cz,
+                                                      const float* __restrict__ cd, float* __restrict__ sx,
+                                                      float* __restrict__ sy, float* __restrict__ sz,
+                                                      float* __restrict__ sd, int* __restrict__ n_acc,
+                                                      int* __restrict__ n_short) {
+  const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (m >= M) return;
+  int taken = 0, accepted = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int c0 = 0; c0 < nc && (pass == 0 || taken < ns); c0 += 64) {
+      const int c = c0 + lane;
+      const int64_t g = m * nc + c;
+      bool ok = false;
+      if (c < nc) {
+        const bool acc = cd[g] >= kSurfAccept;
+        ok = pass == 0 ? acc : !acc;
+      }
+      const unsigned long long mask = __ballot(ok);
+      const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+      if (ok && taken + rank < ns) {
+        const int64_t o = m * ns + taken + rank;
+        sx[o] = cx[g];
+        sy[o] = cy[g];
+        sz[o] = cz[g];
+        sd[o] = cd[g];
+      }
+      taken += __popcll(mask);
+      if (pass == 0) accepted += __popcll(mask);
+    }
+    if (pass == 0) {
+      if (lane == 0 && n_acc) n_acc[m] = accepted;
+      if (taken >= ns) break;
+      if (lane == 0 && n_short) atomicAdd(n_short, ns - taken);
+    }
+  }
+}
+
+// Two standard normals from two uniforms in [0, 1) (Box-Muller; 1 - u1 keeps the log finite).
+__device__ __forceinline__ void box_muller(float u1, float u2, float* n0, float* n1) {
+  const float rad = sqrtf(-2.f * logf(1.f - u1));
+  float s, c;
+  sincosf(6.28318530717958648f * u2, &s, &c);
+  *n0 = rad * c;
+  *n1 = rad * s;
+}
+
+// One thread per (motion, surface point): its two Gaussian points and its chord point,
+// at kid[(m ns + s) 3 + 0..2].
+__global__ void k_surface_children(int64_t M, int nu, int nc, int ns, int stride, const float* __restrict__ rnd,
+                                   float sigma, const float* __restrict__ sx, const float* __restrict__ sy,
+                                   const float* __restrict__ sz, float* __restrict__ kx, float* __restrict__ ky,
+                                   float* __restrict__ kz) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= M * ns) return;
+  const int64_t m = g / ns;
+  const int s = (int)(g - m * ns);
+  const float* r = rnd + m * stride + 3 * nu + 5 * nc + 8 * s;
+  float n[6];
+  box_muller(r[0], r[1], &n[0], &n[1]);
+  box_muller(r[2], r[3], &n[2], &n[3]);
+  box_muller(r[4], r[5], &n[4], &n[5]);
+  const float x = sx[g], y = sy[g], z = sz[g];
+  const int64_t o = g * 3;
+  kx[o] = x + sigma * n[0];
+  ky[o] = y + sigma * n[1];
+  kz[o] = z + sigma * n[2];
+  kx[o + 1] = x + sigma * n[3];
+  ky[o + 1] = y + sigma * n[4];
+  kz[o + 1] = z + sigma * n[5];
+  const int64_t p = m * ns + min((int)(r[6] * ns), ns - 1);
+  const float lam = r[7];
+  kx[o + 2] = x + lam * (sx[p] - x);
+  ky[o + 2] = y + lam * (sy[p] - y);
+  kz[o + 2] = z + lam * (sz[p] - z);
+}
+
+// One wave per motion: rows [uniform | surface | per surface point: two Gaussian, chord].
+__global__ __launch_bounds__(256) void k_assemble_paper(int64_t M, int dof, int nu, int ns,
+                                                        const float* __restrict__ q0, const float* __restrict__ q1,
+                                                        const float* __restrict__ ux, const float* __restrict__ uy,
+                                                        const float* __restrict__ uz, const float* __restrict__ ud,
+                                                        const float* __restrict__ sx, const float* __restrict__ sy,
+                                                        const float* __restrict__ sz, const float* __restrict__ sd,
+                                                        const float* __restrict__ kx, const float* __restrict__ ky,
+                                                        const float* __restrict__ kz, const float* __restrict__ kd,
+                                                        float* __restrict__ out) {
+  const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (m >= M) return;
+  const int width = 3 + 2 * dof + 1;
+  const float* mq0 = q0 + m * dof;
+  const float* mq1 = q1 + m * dof;
+  float* rows = out + (size_t)m * (nu + 4 * ns) * width;
+  for (int u = lane; u < nu; u += 64) {
+    const int64_t g = m * nu + u;
+    write_row(rows + (size_t)u * width, dof, mq0, mq1, ux[g], uy[g], uz[g], ud[g]);
+  }
+  for (int s = lane; s < ns; s += 64) {
+    const int64_t g = m * ns + s;
+    write_row(rows + (size_t)(nu + s) * width, dof, mq0, mq1, sx[g], sy[g], sz[g], sd[g]);
+  }
+  for (int i = lane; i < 3 * ns; i += 64) {
+    const int64_t g = m * 3 * ns + i;
+    write_row(rows + (size_t)(nu + ns + i) * width, dof, mq0, mq1, kx[g], ky[g], kz[g], kd[g]);
+  }
+}
+
 }  // namespace
 
 ExactShape default_exact_shape() { return ExactShape{2, 256}; }
@@ -495,6 +673,44 @@ hipError_t launch_motion_gap(const sv_robot& rb, const MotionArgs& m, const floa
   if (m.n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_motion_gap, dim3(grid_for(m.n, 256)), dim3(256), 0, st, robot_to_dev<double>(rb), m, min_dist,
                      eps, band, gap, verdict);
+  return hipGetLastError();
+}
+
+hipError_t launch_make_samples_paper(const sv_robot& rb, const MotionArgs& m, const CapEntry* table, float half,
+                                     int nu, int ns, int nc, float sigma, const float* rnd, const PaperSamplesWs& w,
+                                     float* out, int* n_acc, int* n_short, hipStream_t st) {
+  const int stride = 3 * nu + 5 * nc + 8 * ns;
+  const ExactShape shape = default_exact_shape();
+  hipError_t e;
+  if (nu > 0) {
+    hipLaunchKernelGGL(k_uniform_points, dim3(grid_for(m.n * nu, 256)), dim3(256), 0, st, m.n, nu, stride, rnd, half,
+                       w.ux, w.uy, w.uz);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const CloudArgs cu{(int)(m.n * nu), w.ux, w.uy, w.uz};
+    if ((e = launch_exact_any(rb, table, m, cu, nullptr, nullptr, m.n, nullptr, nullptr, nu, w.ud, nullptr, shape,
+                              st)) != hipSuccess)
+      return e;
+  }
+  if (ns > 0) {
+    hipLaunchKernelGGL(k_surface_candidates, dim3(grid_for(m.n * nc, 256)), dim3(256), 0, st, table, m.n, m.T,
+                       rb.n_caps, nu, nc, stride, rnd, w.cx, w.cy, w.cz);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const CloudArgs cc{(int)(m.n * nc), w.cx, w.cy, w.cz};
+    if ((e = launch_exact_any(rb, table, m, cc, nullptr, nullptr, m.n, nullptr, nullptr, nc, w.cd, nullptr, shape,
+                              st)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_pick_surface, dim3(grid_for(m.n, 4)), dim3(256), 0, st, m.n, nc, ns, w.cx, w.cy, w.cz, w.cd,
+                       w.sx, w.sy, w.sz, w.sd, n_acc, n_short);
+    hipLaunchKernelGGL(k_surface_children, dim3(grid_for(m.n * ns, 256)), dim3(256), 0, st, m.n, nu, nc, ns, stride,
+                       rnd, sigma, w.sx, w.sy, w.sz, w.kx, w.ky, w.kz);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const CloudArgs ck{(int)(m.n * 3 * ns), w.kx, w.ky, w.kz};
+    if ((e = launch_exact_any(rb, table, m, ck, nullptr, nullptr, m.n, nullptr, nullptr, 3 * ns, w.kd, nullptr,
+                              shape, st)) != hipSuccess)
+      return e;
+  }
+  hipLaunchKernelGGL(k_assemble_paper, dim3(grid_for(m.n, 4)), dim3(256), 0, st, m.n, rb.dof, nu, ns, m.q0, m.q1, w.ux,
+                     w.uy, w.uz, w.ud, w.sx, w.sy, w.sz, w.sd, w.kx, w.ky, w.kz, w.kd, out);
   return hipGetLastError();
 }
 

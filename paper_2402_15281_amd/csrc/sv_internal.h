@@ -258,6 +258,15 @@ hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const 
                                const CullWs& w, hipStream_t st);
 
 // ---- launchers (sv_geom.hip) ------------------------------------------------------
+// Paper-style training samples (Sec. IV-C): workspace arrays [M][n_uniform] (u*),
+// [M][n_cand] (c*), [M][n_surface] (s*), [M][3 n_surface] (k*).
+struct PaperSamplesWs {
+  float *ux, *uy, *uz, *ud, *cx, *cy, *cz, *cd, *sx, *sy, *sz, *sd, *kx, *ky, *kz, *kd;
+};
+hipError_t launch_make_samples_paper(const sv_robot& rb, const MotionArgs& m, const CapEntry* table, float half,
+                                     int nu, int ns, int nc, float sigma, const float* rnd, const PaperSamplesWs& w,
+                                     float* out, int* n_acc, int* n_short, hipStream_t st);
+
 // Per-motion gap between the sampled and the continuous swept distance, and (with
 // min_dist) the continuous verdict.
 hipError_t launch_motion_gap(const sv_robot& rb, const MotionArgs& m, const float* min_dist, float eps, float band,

@@ -253,6 +253,46 @@ def batched_requests(sv, torch, np, arm, reps=5):
     return res
 
 
+def training_distribution(sv, torch, np, arm, args, spec, mlp_seed, net50, val50, dsub, dc, d_ex):
+    """The paper's training distribution (Sec. IV-C: uniform box points, swept-surface
+    points, Gaussian and chord points around them) against the 50/50 scheme: the same
+    network, row budget and schedule; validation errors on both distributions' held-out
+    motions and on the bin20k pairs."""
+    from paper_2402_15281_amd import train as tr
+    rec = tr.PaperRecipe(n_motions=args.train_motions)
+    t0 = time.perf_counter()
+    rows, n_short, info = tr.make_dataset_paper(arm, rec, seed=101)
+    val_p, _, _ = tr.make_dataset_paper(arm, tr.PaperRecipe(n_motions=2000), seed=102, area_m2=info["area_m2"])
+    t_data = time.perf_counter() - t0
+    net_p = sv.DeviceMLP(tr.init_params(spec, mlp_seed), spec.in_dim, spec.width, spec.n_hidden)
+    tlog = tr.train(net_p, rows, tr.TrainRecipe(epochs=args.train_epochs), val_rows=None)
+    del rows
+    d_nn = torch.empty_like(d_ex)
+    near = torch.abs(d_ex) <= 0.1
+
+    def bin_err(net):
+        sv.sv_nn_sdf(net, sv.SV_BF16, dsub, dc, d_nn)
+        e = torch.abs(d_nn - d_ex)
+        return {"mae_all_m": float(e.mean()), "mae_near_surface_m": float(e[near].mean())}
+
+    res = {"recipe": {"area_m2_mean": info["area_m2"], "per_motion": {"uniform": info["n_uniform"],
+                                                                        "surface": info["n_surface"],
+                                                                        "gaussian": 2 * info["n_surface"],
+                                                                        "chord": info["n_surface"],
+                                                                        "candidates": info["n_cand"]},
+                      "n_short": n_short, "data_seconds": t_data, "train_seconds": tlog.seconds},
+           "trained_on_50_50": {"val_50_50": tr.evaluate(net50, val50), "val_paper": tr.evaluate(net50, val_p),
+                                "bin20k": bin_err(net50)},
+           "trained_on_paper": {"val_50_50": tr.evaluate(net_p, val50), "val_paper": tr.evaluate(net_p, val_p),
+                                "bin20k": bin_err(net_p)}}
+    for k in ("trained_on_50_50", "trained_on_paper"):
+        r = res[k]
+        log(f"data: {k}: val 50/50 near {r['val_50_50']['mae_near'] * 1e3:.1f} mm, val paper near "
+            f"{r['val_paper']['mae_near'] * 1e3:.1f} mm, bin20k near {r['bin20k']['mae_near_surface_m'] * 1e3:.1f} mm")
+    log(f"data: paper recipe {info}, {n_short} short, {t_data:.1f} s")
+    return res
+
+
 def paper_network(sv, torch, np, dm, dc, soft_net, steps):
     """The paper's residual network (Sec. IV-A) at its 5 x 512 and 11 x 512 sizes, seeded
     random weights, BF16 MFMA over every bin20k pair (dense predictions), beside the
@@ -371,6 +411,7 @@ def main():
     ap.add_argument("--train-motions", type=int, default=20000)
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-request batch leg")
     ap.add_argument("--no-paper-net", action="store_true", help="skip the residual-network leg")
+    ap.add_argument("--no-data-compare", action="store_true", help="skip the training-distribution leg")
     ap.add_argument("--no-boxworld", action="store_true", help="skip the box-world search leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -544,6 +585,9 @@ def main():
     }
     if not args.no_paper_net:
         result["paper_network"] = paper_network(sv, torch, np, dm, dc, mlp, max(args.steps // 2, 2))
+    if not args.no_data_compare:
+        result["training_distribution"] = training_distribution(sv, torch, np, arm, args, spec, w["mlp_seed"], mlp,
+                                                                val_rows, dsub, dc, d_ex)
     if not args.no_batched:
         result["batched_requests"] = batched_requests(sv, torch, np, arm)
     if not args.no_boxworld:

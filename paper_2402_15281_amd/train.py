@@ -6,11 +6,13 @@ Adam on the GPU, sv_nn_predict evaluates the network on held-out rows.  This
 module only sequences those calls: motion batches for data generation, a seeded
 shuffle per epoch, batch slicing, and bookkeeping.
 
-Recipe (synthetic stand-in for the paper's datasets): motions with q0, q1 uniform
-within the joint limits; per motion n_uniform points uniform in the 1.2 m cube and
-n_near points within `band` of the swept surface; labels are exact swept
-distances at T samples; held-out motions give the validation rows (the paper
-splits its data by motion, Sec. V-A).
+Recipes (synthetic stand-ins for the paper's datasets): motions with q0, q1 uniform
+within the joint limits; labels are exact swept distances at T samples; held-out
+motions give the validation rows (the paper splits its data by motion, Sec. V-A).
+  DataRecipe: per motion n_uniform points uniform in the 1.2 m cube and n_near points
+    within `band` of the swept surface (the 50/50 scheme);
+  PaperRecipe: the paper's own proportions (Sec. IV-C): uniform box points, swept-
+    surface points, two Gaussian points and one chord point per surface point.
 """
 from __future__ import annotations
 
@@ -75,6 +77,96 @@ def make_dataset(arm, recipe: DataRecipe, seed: int, device="cuda"):
                                 recipe.band, rnd, out[c0 * per:c1 * per], n_short, ws=ws)
     torch.cuda.synchronize()
     return out, int(n_short.item())
+
+
+@dataclass
+class PaperRecipe:
+    """The paper's training distribution (Sec. IV-C) at a fixed row budget per motion.
+
+    The paper draws 0.25 points per dm^3 uniformly in a box covering every motion and
+    0.2 points per cm^2 on the swept surface, each with 2 Gaussian points (sigma 3 mm)
+    and 1 chord point.  Here the box is the training cube and the per-motion counts keep
+    those densities' proportions for the mean swept-surface area of the motions
+    (estimated on a pilot batch), scaled to rows_per_motion."""
+    n_motions: int = 20000
+    rows_per_motion: int = 500
+    cube_half: float = 0.6
+    sigma: float = 0.003
+    T: int = 256
+    cand_per_surface: int = 60
+    uniform_per_m3: float = 250.0      # 0.25 per dm^3
+    surface_per_m2: float = 2000.0     # 0.2 per cm^2
+    chunk: int = 1000
+
+
+def capsule_area_total(arm, device="cuda") -> float:
+    """Sum of the capsules' surface areas (rigid, so any configuration; from sv_fk)."""
+    robot = sv.make_robot(arm)
+    q = torch.zeros(1, arm.dof, dtype=torch.float32, device=device)
+    caps = torch.empty(1, arm.n_caps, 8, dtype=torch.float32, device=device)
+    sv.sv_fk(robot, q, caps)
+    c = caps[0].double().cpu().numpy()
+    L = np.linalg.norm(c[:, 3:6] - c[:, 0:3], axis=1)
+    r = c[:, 6]
+    return float(np.sum(2 * math.pi * r * L + 4 * math.pi * r * r))
+
+
+def swept_area_estimate(arm, recipe: PaperRecipe, seed: int, n: int = 200, n_cand: int = 4000, device="cuda") -> float:
+    """Mean swept-surface area (m^2) of n motions: the accepted share of surface
+    candidates times the total area of the T capsule instances."""
+    robot = sv.make_robot(arm)
+    mo = svgen.make_motions(arm, n, recipe.T, seed)
+    dm = sv.DeviceMotions(mo, device)
+    rnd = torch.as_tensor(svgen.uniforms(seed * 7919 + 1, n, 5 * n_cand + 8), device=device)
+    out = torch.empty(n, 4, 3 + 2 * arm.dof + 1, dtype=torch.float32, device=device)
+    acc = torch.zeros(n, dtype=torch.int32, device=device)
+    sv.sv_make_samples_paper(robot, dm, recipe.cube_half, 0, 1, n_cand, recipe.sigma, rnd, out, acc)
+    frac = acc.double().mean().item() / n_cand
+    return frac * recipe.T * capsule_area_total(arm, device)
+
+
+def paper_counts(recipe: PaperRecipe, area_m2: float):
+    """(n_uniform, n_surface) with the paper's density proportions within rows_per_motion."""
+    nu0 = recipe.uniform_per_m3 * (2 * recipe.cube_half) ** 3
+    ns0 = recipe.surface_per_m2 * area_m2
+    ns = max(1, int(round(recipe.rows_per_motion * ns0 / (nu0 + 4 * ns0))))
+    return recipe.rows_per_motion - 4 * ns, ns
+
+
+def make_dataset_paper(arm, recipe: PaperRecipe, seed: int, area_m2: float = None, device="cuda"):
+    """Training rows in the paper's proportions: (rows [S][in_dim + 1], n_short, info)."""
+    if area_m2 is None:
+        area_m2 = swept_area_estimate(arm, recipe, seed + 17, device=device)
+    nu, ns = paper_counts(recipe, area_m2)
+    nc = recipe.cand_per_surface * ns
+    robot = sv.make_robot(arm)
+    per = nu + 4 * ns
+    width = 3 + 2 * arm.dof + 1
+    out = torch.empty(recipe.n_motions * per, width, dtype=torch.float32, device=device)
+    n_short = torch.zeros(1, dtype=torch.int32, device=device)
+    motions = svgen.make_motions(arm, recipe.n_motions, recipe.T, seed)
+    cols = 3 * nu + 5 * nc + 8 * ns
+    ws = None
+    for c0 in range(0, recipe.n_motions, recipe.chunk):
+        c1 = min(recipe.n_motions, c0 + recipe.chunk)
+        sub = svgen.Motions(motions.q0[c0:c1], motions.q1[c0:c1], recipe.T)
+        dm = sv.DeviceMotions(sub, device)
+        if ws is None:   # chunks only shrink, so the first chunk's workspace serves all of them
+            ws = sv.workspace(sv_paper_ws(robot, dm, nu, ns, nc))
+        rnd = torch.as_tensor(svgen.uniforms(seed * 1000003 + c0, c1 - c0, cols), device=device)
+        sv.sv_make_samples_paper(robot, dm, recipe.cube_half, nu, ns, nc, recipe.sigma, rnd,
+                                 out[c0 * per:c1 * per], None, n_short, ws=ws)
+    torch.cuda.synchronize()
+    return out, int(n_short.item()), {"area_m2": area_m2, "n_uniform": nu, "n_surface": ns, "n_cand": nc}
+
+
+def sv_paper_ws(robot, dm, nu, ns, nc) -> int:
+    import ctypes
+    n = ctypes.c_size_t(0)
+    d = dm.desc()
+    sv._check(sv.lib.sv_make_samples_paper_workspace_size(ctypes.byref(robot), ctypes.byref(d), nu, ns, nc,
+                                                          ctypes.byref(n)))
+    return n.value
 
 
 def init_params(spec: svgen.MLPSpec, seed: int) -> np.ndarray:

@@ -181,6 +181,7 @@ CheckWs carve_check(void* ws, const sv_robot& r, const sv_motions& m, const sv_c
   w.cull.sz = cv.take<float>(N);
   w.cull.spheres = cv.take<float4>((size_t)m.n * r.n_caps * cull_blocks(m.T));
   w.cull.tile_spheres = cv.take<float4>((size_t)cull_tiles(c.n));
+  w.cull.wave_spheres = cv.take<float4>((size_t)cull_tiles(c.n) * 4);
   w.cull.list = cv.take<int>((size_t)m.n * cull_tiles(c.n) * r.n_caps);
   w.cull.list_caps = cv.take<int>((size_t)m.n * cull_tiles(c.n) * r.n_caps);
   w.cull.list_count = cv.take<int>(2);

@@ -149,6 +149,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchArgs a) {
     q.T = a.reqs[r].motions.T;
     q.nb = (q.T + kCullB - 1) / kCullB;
     q.list_off = (int)w.cand_off[p];
+    q.tile_off = (int)w.tile_off[r];
+    q.pad_ = 0;
     w.req[r] = q;
     w.fill[r] = 0;
   }
@@ -388,63 +390,18 @@ __global__ __launch_bounds__(256) void k_batch_scatter(BatchArgs a) {
   }
 }
 
-// The sphere of tile t's sorted points (all threads of a 256-thread block).
-__device__ void tile_sphere(const BatchArgs& a, int64_t t, float (*part)[6], float* pr) {
-  const BatchWs& w = a.w;
-  const int r = find_seg(w.tile_off, a.n_req, t);
-  const int64_t j0 = w.point_off[r] + (t - w.tile_off[r]) * kCullTilePts;
-  const int64_t j1 = min(j0 + kCullTilePts, w.point_off[r] + w.n_points[r]);
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
-    const float v[3] = {w.sx[j], w.sy[j], w.sz[j]};
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      lo[q] = fminf(lo[q], v[q]);
-      hi[q] = fmaxf(hi[q], v[q]);
-    }
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    lo[q] = wave_min(lo[q]);
-    hi[q] = wave_max(hi[q]);
-  }
-  if (lane == 0)
-    for (int q = 0; q < 3; ++q) {
-      part[wid][q] = lo[q];
-      part[wid][3 + q] = hi[q];
-    }
-  __syncthreads();
-  float c[3];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    float l = part[0][q], h = part[0][3 + q];
-    for (int u = 1; u < 4; ++u) {
-      l = fminf(l, part[u][q]);
-      h = fmaxf(h, part[u][3 + q]);
-    }
-    c[q] = 0.5f * (l + h);
-  }
-  float r2 = 0.f;
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
-    const float dx = w.sx[j] - c[0], dy = w.sy[j] - c[1], dz = w.sz[j] - c[2];
-    r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
-  }
-  r2 = wave_max(r2);
-  if (lane == 0) pr[wid] = r2;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    w.tile_sph[t] = make_float4(c[0], c[1], c[2], sqrtf(fmaxf(fmaxf(pr[0], pr[1]), fmaxf(pr[2], pr[3]))));
-}
-
-// Block-stride over the tiles of all requests: the sphere of each tile's sorted points.
+// Block-stride over the tiles of all requests: the spheres of each tile's sorted points
+// and of its four wave groups.
 __global__ __launch_bounds__(256) void k_batch_tile_spheres(BatchArgs a) {
   const BatchWs& w = a.w;
   __shared__ float part[4][6];
   __shared__ float pr[4];
   const int64_t total = w.plan->total_tiles;
   for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-    tile_sphere(a, t, part, pr);
+    const int r = find_seg(w.tile_off, a.n_req, t);
+    const int64_t j0 = w.point_off[r] + (t - w.tile_off[r]) * kCullTilePts;
+    const int64_t j1 = min(j0 + kCullTilePts, w.point_off[r] + w.n_points[r]);
+    tile_wave_spheres<kCullP, kCullNT>(w.sx, w.sy, w.sz, j0, j1, w.tile_sph + t, w.wave_sph + 4 * t, part, pr);
     __syncthreads();   // part, pr reused by the next tile
   }
 }
@@ -697,8 +654,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const float G = key_dist(__hip_atomic_load(w.keys + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const unsigned long long k2 = cull_item<P, NT>(
         (ConstF4Ptr)w.table, (size_t)(q.sample_off + m * q.T) * a.K + (size_t)k * q.T, q.T,
-        (ConstF4Ptr)(w.spheres + ((size_t)g * a.K + k) * w.nb_max), q.nb, w.sx + po, w.sy + po, w.sz + po,
-        w.sidx + po, q.n_points, t, G, wmin, executed);
+        (ConstF4Ptr)(w.spheres + ((size_t)g * a.K + k) * w.nb_max), q.nb,
+        (ConstF4Ptr)(w.wave_sph + 4 * ((size_t)q.tile_off + t)), w.sx + po, w.sy + po, w.sz + po, w.sidx + po,
+        q.n_points, t, G, wmin, executed);
     if (threadIdx.x == 0) {
       if (k2 < __hip_atomic_load(w.keys + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(w.keys + g, k2);
       s_r = nr;
@@ -886,6 +844,7 @@ BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, siz
   w.sz = cv.take<float>(P);
   w.sidx = cv.take<int>(P);
   w.tile_sph = cv.take<float4>((size_t)w.tile_cap);
+  w.wave_sph = cv.take<float4>((size_t)w.tile_cap * 4);
   w.spheres = cv.take<float4>((size_t)caps.max_motions * rb.n_caps * w.nb_max);
   w.list_g = cv.take<int>((size_t)w.cand_cap);
   w.list_tk = cv.take<int>((size_t)w.cand_cap);

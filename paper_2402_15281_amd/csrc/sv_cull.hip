@@ -238,51 +238,13 @@ __global__ __launch_bounds__(256) void k_exact_seed(const CapEntry* __restrict__
 // Bounding sphere of each tile of kTilePts consecutive sorted points: centre of the
 // points' bounding box and the largest distance from it.  One block per tile.
 __global__ __launch_bounds__(256) void k_tile_spheres(const float* __restrict__ sx, const float* __restrict__ sy,
-                                                      const float* __restrict__ sz, int N, int tile_pts,
-                                                      float4* __restrict__ out) {
+                                                      const float* __restrict__ sz, int N, float4* __restrict__ tile_out,
+                                                      float4* __restrict__ wave_out) {
   __shared__ float part[4][6];
   __shared__ float pr[4];
-  const int j0 = blockIdx.x * tile_pts;
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int j = j0 + threadIdx.x; j < min(j0 + tile_pts, N); j += blockDim.x) {
-    const float v[3] = {sx[j], sy[j], sz[j]};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = fminf(lo[a], v[a]);
-      hi[a] = fmaxf(hi[a], v[a]);
-    }
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = wave_min(lo[a]);
-    hi[a] = wave_max(hi[a]);
-  }
-  if (lane == 0)
-    for (int a = 0; a < 3; ++a) {
-      part[wid][a] = lo[a];
-      part[wid][3 + a] = hi[a];
-    }
-  __syncthreads();
-  float c[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    float l = part[0][a], h = part[0][3 + a];
-    for (int q = 1; q < 4; ++q) {
-      l = fminf(l, part[q][a]);
-      h = fmaxf(h, part[q][3 + a]);
-    }
-    c[a] = 0.5f * (l + h);
-  }
-  float r2 = 0.f;
-  for (int j = j0 + threadIdx.x; j < min(j0 + tile_pts, N); j += blockDim.x) {
-    const float dx = sx[j] - c[0], dy = sy[j] - c[1], dz = sz[j] - c[2];
-    r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
-  }
-  r2 = wave_max(r2);
-  if (lane == 0) pr[wid] = r2;
-  __syncthreads();
-  if (threadIdx.x == 0) out[blockIdx.x] = make_float4(c[0], c[1], c[2], sqrtf(fmaxf(fmaxf(pr[0], pr[1]), fmaxf(pr[2], pr[3]))));
+  const int64_t j0 = (int64_t)blockIdx.x * (kCullNT * kCullP);
+  tile_wave_spheres<kCullP, kCullNT>(sx, sy, sz, j0, min(j0 + kCullNT * kCullP, (int64_t)N), tile_out + blockIdx.x,
+                                     wave_out + 4 * (size_t)blockIdx.x, part, pr);
 }
 
 // Coarse pass: one thread per (motion slot, tile, capsule); the capsule is kept for
@@ -337,8 +299,9 @@ __global__ __launch_bounds__(256) void k_cull_list(const float4* __restrict__ ti
 // on neighbouring motions and balances the uneven items.  work (optional) counts the
 // executed segment tests.
 template <int P, int NT>
-__global__ __launch_bounds__(NT) void k_exact_cull(const CapEntry* __restrict__ table,
-                                                   const float4* __restrict__ spheres, int T, int K, int nb,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_exact_cull(const CapEntry* __restrict__ table,
+                                                   const float4* __restrict__ spheres,
+                                                   const float4* __restrict__ wave_spheres, int T, int K, int nb,
                                                    const float* __restrict__ sx, const float* __restrict__ sy,
                                                    const float* __restrict__ sz, const int* __restrict__ perm, int N,
                                                    int tiles, const int* __restrict__ mlist,
@@ -366,7 +329,8 @@ __global__ __launch_bounds__(NT) void k_exact_cull(const CapEntry* __restrict__ 
     const float G = key_dist(__hip_atomic_load(keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const unsigned long long k2 =
         cull_item<P, NT>((ConstF4Ptr)table, ((size_t)m * K + k) * T, T, (ConstF4Ptr)(spheres + ((size_t)m * K + k) * nb),
-                         nb, sx, sy, sz, perm, N, tile, G, wmin, executed);
+                         nb, (ConstF4Ptr)(wave_spheres + 4 * (size_t)tile), sx, sy, sz, perm, N, tile, G, wmin,
+                         executed);
     if (threadIdx.x == 0) {
       // publish only a new minimum: most items end above the motion's current key
       if (k2 < __hip_atomic_load(keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(keys + m, k2);
@@ -460,14 +424,15 @@ hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const 
   const int64_t items = n_slots * tiles;
   if (items * K > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(k_tile_spheres, dim3((unsigned)tiles), dim3(256), 0, st, w.sx, w.sy, w.sz, c.n,
-                     kCullNT * kCullP, w.tile_spheres);
+                     w.tile_spheres, w.wave_spheres);
   if ((e = launch_fill_i32(w.list_count, 2, 0, st)) != hipSuccess) return e;   // count, queue head
   hipLaunchKernelGGL(k_cull_list, dim3(grid_for(items * K, 256)), dim3(256), 0, st, w.tile_spheres, w.spheres, K, nb,
                      tiles, n_slots, mlist, mcount, keys, w.list, w.list_caps, w.list_count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int blocks = (int)std::min<int64_t>(items * K, resident_cull_blocks());
-  hipLaunchKernelGGL((k_exact_cull<kCullP, kCullNT>), dim3(blocks), dim3(kCullNT), 0, st, table, w.spheres, T, K, nb,
-                     w.sx, w.sy, w.sz, w.perm, c.n, tiles, mlist, w.list, w.list_caps, w.list_count, keys, w.work);
+  hipLaunchKernelGGL((k_exact_cull<kCullP, kCullNT>), dim3(blocks), dim3(kCullNT), 0, st, table, w.spheres,
+                     w.wave_spheres, T, K, nb, w.sx, w.sy, w.sz, w.perm, c.n, tiles, mlist, w.list, w.list_caps,
+                     w.list_count, keys, w.work);
   return hipGetLastError();
 }
 

@@ -64,23 +64,98 @@ __device__ __forceinline__ unsigned morton_cell(const float v[3], const unsigned
   return spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
 }
 
+// Spheres of one tile of sorted points [j0, j1) (j1 - j0 <= NT P; all NT threads of a
+// block, NT = 256): wave w's group of the culled kernel's points, [j0 + 64 P w, j0 +
+// 64 P (w + 1)), into wave_out[w] and the whole tile into *tile_out.  Centres are the
+// midpoints of the bounding boxes, radii the largest distance from them (computed in
+// FP32; kCullMargin covers the rounding).  An empty group gets radius 0.  part [4][6]
+// and pr [4] are LDS scratch; two barriers.
+template <int P, int NT>
+__device__ void tile_wave_spheres(const float* __restrict__ sx, const float* __restrict__ sy,
+                                  const float* __restrict__ sz, int64_t j0, int64_t j1, float4* tile_out,
+                                  float4* wave_out, float (*part)[6], float* pr) {
+  static_assert(NT == 256, "four wave groups");
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  float x[P], y[P], z[P];
+  bool ok[P];
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int64_t j = j0 + wid * (64 * P) + lane + p * 64;
+    ok[p] = j < j1;
+    x[p] = ok[p] ? sx[j] : 0.f;
+    y[p] = ok[p] ? sy[j] : 0.f;
+    z[p] = ok[p] ? sz[j] : 0.f;
+    if (ok[p]) {
+      lo[0] = fminf(lo[0], x[p]); hi[0] = fmaxf(hi[0], x[p]);
+      lo[1] = fminf(lo[1], y[p]); hi[1] = fmaxf(hi[1], y[p]);
+      lo[2] = fminf(lo[2], z[p]); hi[2] = fmaxf(hi[2], z[p]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = wave_min(lo[a]);
+    hi[a] = wave_max(hi[a]);
+  }
+  const bool any = lo[0] <= hi[0];   // the group holds a point
+  const float cx = any ? 0.5f * (lo[0] + hi[0]) : 0.f, cy = any ? 0.5f * (lo[1] + hi[1]) : 0.f;
+  const float cz = any ? 0.5f * (lo[2] + hi[2]) : 0.f;
+  float r2 = 0.f;
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+    if (ok[p]) {
+      const float dx = x[p] - cx, dy = y[p] - cy, dz = z[p] - cz;
+      r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
+    }
+  r2 = wave_max(r2);
+  if (lane == 0) {
+    wave_out[wid] = make_float4(cx, cy, cz, sqrtf(r2));
+    for (int a = 0; a < 3; ++a) {
+      part[wid][a] = lo[a];
+      part[wid][3 + a] = hi[a];
+    }
+  }
+  __syncthreads();
+  float c[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float l = part[0][a], h = part[0][3 + a];
+    for (int q = 1; q < 4; ++q) {
+      l = fminf(l, part[q][a]);
+      h = fmaxf(h, part[q][3 + a]);
+    }
+    c[a] = 0.5f * (l + h);
+  }
+  float t2 = 0.f;
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+    if (ok[p]) {
+      const float dx = x[p] - c[0], dy = y[p] - c[1], dz = z[p] - c[2];
+      t2 = fmaxf(t2, dx * dx + dy * dy + dz * dz);
+    }
+  t2 = wave_max(t2);
+  if (lane == 0) pr[wid] = t2;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    *tile_out = make_float4(c[0], c[1], c[2], sqrtf(fmaxf(fmaxf(pr[0], pr[1]), fmaxf(pr[2], pr[3]))));
+}
+
 // One culled item for one wave group: the wave's 64 P consecutive sorted points of
-// tile `tile` (sx, sy, sz, N; perm maps them to the caller's indices) against one
-// capsule of one motion (table entries from e, T samples; sample-block spheres sph,
-// nb of them), under the bound G.  Returns, valid in thread 0, the block's smallest
+// tile `tile` (sx, sy, sz, N; perm maps them to the caller's indices; wsph the tile's
+// four wave-group spheres) against one capsule of one motion (table entries from e, T
+// samples; sample-block spheres sph, nb of them), under the bound G.  Returns, valid in thread 0, the block's smallest
 // (distance, index) key of the tests that survive; adds the executed tests to
 // `executed`.  Every thread of the block must call it (it contains a barrier).
 template <int P, int NT>
 __device__ __forceinline__ unsigned long long cull_item(ConstF4Ptr tab, size_t e, int T, ConstF4Ptr sph, int nb,
-                                                        const float* __restrict__ sx, const float* __restrict__ sy,
-                                                        const float* __restrict__ sz, const int* __restrict__ perm,
-                                                        int N, int tile, float G, unsigned long long* wmin,
-                                                        unsigned long long& executed) {
+                                                        ConstF4Ptr wsph, const float* __restrict__ sx,
+                                                        const float* __restrict__ sy, const float* __restrict__ sz,
+                                                        const int* __restrict__ perm, int N, int tile, float G,
+                                                        unsigned long long* wmin, unsigned long long& executed) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int base = tile * (NT * P) + wid * (64 * P) + lane;
   float x[P], y[P], z[P], best[P];
   int idx[P];
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const int j = base + p * 64;
@@ -90,25 +165,10 @@ __device__ __forceinline__ unsigned long long cull_item(ConstF4Ptr tab, size_t e
     y[p] = ok ? sy[j] : 0.f;
     z[p] = ok ? sz[j] : 0.f;
     best[p] = INFINITY;
-    if (ok) {
-      lo[0] = fminf(lo[0], x[p]); hi[0] = fmaxf(hi[0], x[p]);
-      lo[1] = fminf(lo[1], y[p]); hi[1] = fmaxf(hi[1], y[p]);
-      lo[2] = fminf(lo[2], z[p]); hi[2] = fmaxf(hi[2], z[p]);
-    }
   }
   if (__builtin_amdgcn_readfirstlane((int)(base < N))) {   // lane 0 holds the wave's first point
-    // the wave's sphere
-    const float cx = uniform_f(0.5f * (wave_min(lo[0]) + wave_max(hi[0])));
-    const float cy = uniform_f(0.5f * (wave_min(lo[1]) + wave_max(hi[1])));
-    const float cz = uniform_f(0.5f * (wave_min(lo[2]) + wave_max(hi[2])));
-    float r2 = 0.f;
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-      if (idx[p] >= 0) {
-        const float dx = x[p] - cx, dy = y[p] - cy, dz = z[p] - cz;
-        r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
-      }
-    const float rw = uniform_f(sqrtf(wave_max(r2)));
+    const vf4 ws = wsph[__builtin_amdgcn_readfirstlane(wid)];   // the wave's sphere, from the tile pass
+    const float cx = ws.x, cy = ws.y, cz = ws.z, rw = ws.w;
     G = uniform_f(G);
     const float r = load_entry(tab, e).r;
     float m2[P];
@@ -117,8 +177,10 @@ __device__ __forceinline__ unsigned long long cull_item(ConstF4Ptr tab, size_t e
     for (int b = 0; b < nb; ++b) {
       const vf4 sb = sph[b];
       const float dx = sb.x - cx, dy = sb.y - cy, dz = sb.z - cz;
-      const float lb = sqrtf(dx * dx + dy * dy + dz * dz) - rw - sb.w;
-      if (lb > G + kCullMargin) continue;   // every test of the group exceeds the final minimum
+      // |c_wave - c_block| - R_wave - R_block > G + margin, without the square root:
+      // skip iff the centre distance exceeds S = G + margin + R_wave + R_block
+      const float S = G + kCullMargin + rw + sb.w;
+      if (S < 0.f || dx * dx + dy * dy + dz * dz > S * S) continue;   // every test of the group exceeds the final minimum
       const int t0 = b * kCullB, t1 = min(t0 + kCullB, T);
       swept_range<P>(tab, e, t0, t1, x, y, z, m2);
       executed += (unsigned long long)(t1 - t0) * (64 * P);

@@ -124,6 +124,7 @@ struct BatchReq {
   int point_off, motion_off;       // first sorted point; first global motion
   int n_points, T, nb;             // cloud size; samples; sample blocks
   int list_off;                    // first slot of the request's listed items
+  int tile_off, pad_;              // first tile of the request's sorted points
 };
 
 // The culled batched kernel's blocks form kGangs gangs (block index mod kGangs, one
@@ -156,6 +157,7 @@ struct BatchWs {
   float *sx, *sy, *sz;                            // [point_cap] sorted points
   int* sidx;                                      // [point_cap] their index in the request's cloud
   float4* tile_sph;                               // [tile_cap]
+  float4* wave_sph;                               // [tile_cap][4] the culled kernel's wave groups
   float4* spheres;                                // [max_motions][K][nb_max]
   int *list_g, *list_tk;                          // [cand_cap] motion, tile << 4 | capsule
   BatchReq* req;                                  // [max_requests]
@@ -242,6 +244,7 @@ struct CullWs {
   float *sx, *sy, *sz;              // [N] sorted points
   float4* spheres;                  // [M][K][cull_blocks(T)]
   float4* tile_spheres;             // [cull_tiles(N)]
+  float4* wave_spheres;             // [cull_tiles(N)][4] the culled kernel's wave groups
   int* list;                        // [M * cull_tiles(N) * K] surviving (motion slot, tile) items
   int* list_caps;                  // [M * cull_tiles(N) * K] the capsule each item checks
   int* list_count;                  // [2] listed items, queue head

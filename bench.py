@@ -323,6 +323,57 @@ def paper_network(sv, torch, np, dm, dc, soft_net, steps):
     return res
 
 
+def crossover(sv, torch, np, arm, robot, motions, dc, eps, steps):
+    """Network size and motion length sweep over the bin20k motions and cloud.
+
+    Per network: one screening call at zero fallback (trust mode with a threshold that
+    no prediction falls below, so no exact test runs): the network's best case, whose
+    cost does not depend on T.  Per T: the exact check, culled (the default) and dense.
+    Break-even T per network: against the dense kernel from a least-squares line
+    ms = a + b T over the sweep; against the culled pass, the first swept T at which the
+    exact check costs more than the network, if any."""
+    import svgen
+    from paper_2402_15281_amd import train as tr
+    M = motions.n
+    Ts = [32, 64, 256, 1024, 2048]
+    res = {"workload": f"bin20k motions ({M}, linear) and cloud ({dc.n} points), eps={eps} m; networks with "
+                       "seeded weights (the cost of a call does not depend on them)", "T": Ts, "exact": {},
+           "networks": {}}
+    dm256 = None
+    for T in Ts:
+        dmT = sv.DeviceMotions(svgen.Motions(motions.q0, motions.q1, T))
+        if T == 256:
+            dm256 = dmT
+        out = sv.DeviceResults(M)
+        ws = sv.workspace(sv.sv_workspace_size(sv.SV_OP_CHECK, robot, dmT, dc))
+        call = lambda: sv.sv_check_motions(robot, dmT, dc, out, eps, ws=ws)
+        ms_c, _ = timed(sv, torch, call, steps, 1, [])
+        sv.sv_set_exact_culling(False)
+        ms_d, _ = timed(sv, torch, call, max(steps // 2, 2), 1, [])
+        sv.sv_set_exact_culling(True)
+        res["exact"][T] = {"culled_ms": ms_c, "dense_ms": ms_d}
+        log(f"crossover: exact T={T}: culled {ms_c:.3f} ms, dense {ms_d:.3f} ms per call")
+    a, b = np.polyfit(np.array(Ts, np.float64), np.array([res["exact"][T]["dense_ms"] for T in Ts]), 1)[::-1]
+    out = sv.DeviceResults(M)
+    for width, L in [(128, 4), (256, 4), (512, 8)]:
+        spec = svgen.MLPSpec(15, width, L)
+        net = sv.DeviceMLP(tr.init_params(spec, 31), 15, width, L)
+        ws = sv.workspace(sv.sv_workspace_size(sv.SV_OP_CHECK, robot, dm256, dc, net))
+        ms_n, _ = timed(sv, torch, lambda: sv.sv_check_motions(robot, dm256, dc, out, eps, mlp=net,
+                                                               screen=sv.SV_SCREEN_TRUST, tau=-1e30, ws=ws),
+                        steps, 1, [])
+        culled_T = next((T for T in Ts if res["exact"][T]["culled_ms"] > ms_n), None)
+        name = f"softplus_{L}x{width}"
+        res["networks"][name] = {"flop_per_query": mlp_flops_per_query(15, width, L), "screen_ms_at_zero_fallback": ms_n,
+                                 "motions_per_s": M / (ms_n / 1e3),
+                                 "break_even_T_vs_dense": (ms_n - a) / b if b > 0 else None,
+                                 "first_T_where_culled_exact_costs_more": culled_T}
+        log(f"crossover: network {name}: {ms_n:.3f} ms per call at zero fallback; break-even T against the dense "
+            f"kernel {(ms_n - a) / b:.0f}; culled exact dearer from T = {culled_T}")
+    res["dense_fit_ms"] = {"intercept": a, "per_T": b}
+    return res
+
+
 def box_world_search(sv, torch, np, arm, train_epochs, reps=3):
     """Alg. 1 on the box-world scenes: plain search (exact checks in the given order) vs
     the network-guided search (proxy d_hat of every motion, then exact checks in Alg. 1's
@@ -413,6 +464,7 @@ def main():
     ap.add_argument("--no-paper-net", action="store_true", help="skip the residual-network leg")
     ap.add_argument("--no-data-compare", action="store_true", help="skip the training-distribution leg")
     ap.add_argument("--no-boxworld", action="store_true", help="skip the box-world search leg")
+    ap.add_argument("--no-crossover", action="store_true", help="skip the network-size and T sweep")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         log("this benchmark runs on exactly one GPU: the collision check is measured on one MI355X; "
@@ -588,6 +640,8 @@ def main():
     if not args.no_data_compare:
         result["training_distribution"] = training_distribution(sv, torch, np, arm, args, spec, w["mlp_seed"], mlp,
                                                                 val_rows, dsub, dc, d_ex)
+    if not args.no_crossover:
+        result["crossover"] = crossover(sv, torch, np, arm, robot, motions, dc, eps, max(args.steps // 2, 3))
     if not args.no_batched:
         result["batched_requests"] = batched_requests(sv, torch, np, arm)
     if not args.no_boxworld:

@@ -5,8 +5,8 @@
 // distance.  Most (point, capsule, sample) tests of a motion are far above that
 // minimum, and whole groups of them can be proven so with two bounding spheres:
 //   - a wave's points: the cloud is sorted by Morton cell first (a counting sort), so
-//     the 64 P points a wave holds are close together; their sphere is reduced across
-//     the wave;
+//     the 64 P points a wave holds are close together; their sphere is computed once
+//     per tile of sorted points (k_tile_spheres) for every item of that tile;
 //   - a block of kCullB consecutive samples of one capsule: a sphere around all their
 //     segment endpoints, grown by the capsule radius (k_block_spheres).
 // If |c_wave - c_block| - R_wave - R_block exceeds an upper bound G of d(X, m) (plus

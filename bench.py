@@ -294,7 +294,7 @@ def training_distribution(sv, torch, np, arm, args, spec, mlp_seed, net50, val50
 
 
 def paper_network(sv, torch, np, dm, dc, soft_net, steps):
-    """The paper's residual network (Sec. IV-A) at its 5 x 512 and 11 x 512 sizes, seeded
+    """The paper's residual network (Sec. IV-A) at its 5 x 512, 11 x 512 and 11 x 1024 sizes, seeded
     random weights, BF16 MFMA over every bin20k pair (dense predictions), beside the
     softplus 8 x 512 network in the same mode."""
     import svgen
@@ -302,7 +302,7 @@ def paper_network(sv, torch, np, dm, dc, soft_net, steps):
     out = torch.empty(M, N, device="cuda")
     res = {"workload": f"bin20k pairs ({M} motions x {N} points), dense predictions, BF16 MFMA", "networks": {}}
     nets = [("residual_5x512", svgen.ResSpec(15, 512, 5)), ("residual_11x512", svgen.ResSpec(15, 512, 11)),
-            ("softplus_8x512", None)]
+            ("residual_11x1024", svgen.ResSpec(15, 1024, 11)), ("softplus_8x512", None)]
     for name, spec in nets:
         if spec is None:
             net, w, L = soft_net, soft_net.width, soft_net.n_hidden

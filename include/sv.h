@@ -124,7 +124,8 @@ typedef struct {
 enum { SV_NET_MLP = 0, SV_NET_RESIDUAL = 1 };
 typedef struct {
   int32_t in_dim;      /* 3 + 2 * dof; SV_NET_RESIDUAL in BF16: dof <= 6 */
-  int32_t width;       /* hidden width W: FP32 path W % 64 == 0, W <= 1024; BF16 path 128, 256 or 512 */
+  int32_t width;       /* hidden width W: FP32 path W % 64 == 0, W <= 1024; BF16 path 128, 256, 512
+                          or 1024 (training: up to 512) */
   int32_t n_hidden;    /* L >= 1: softplus layers (SV_NET_MLP) or blocks (SV_NET_RESIDUAL) */
   const float* params; /* dev FP32, flat, in the order given above */
   int32_t kind;        /* SV_NET_MLP or SV_NET_RESIDUAL; training supports SV_NET_MLP only */
@@ -187,7 +188,7 @@ int sv_nn_sdf(const sv_mlp* mlp, int precision, const sv_motions* motions, const
  *   mlp == NULL, screen == SV_SCREEN_NONE: exact check of every (motion, point).
  *   mlp != NULL, screen TRUST or CERTIFIED: the BF16 network screens every (motion,
  *     point) first and only points with delta_hat < tau go to the exact check (linear
- *     motions; mlp->width 128, 256 or 512).  n_fallback[m] counts them.  min_dist of a
+ *     motions; mlp->width 128, 256, 512 or 1024).  n_fallback[m] counts them.  min_dist of a
  *     motion decided by a witness is the minimum over the sent points; of any other
  *     motion it is the minimum over all points (CERTIFIED) or over the sent points,
  *     +inf if none (TRUST).
@@ -313,7 +314,7 @@ int sv_wall_clock_hz(int64_t* hz);
 
 /* Network proxy of the cloud distance, d_hat(X, m) = min over x in X of f_theta(x, q0_m,
  * q1_m) (Sec. IV-B), for every motion: d_hat dev [M] (+inf when N = 0; NaN
- * predictions are skipped).  BF16 network (mlp->width 128, 256 or 512), linear motions.
+ * predictions are skipped).  BF16 network (mlp->width 128, 256, 512 or 1024), linear motions.
  * Workspace: sv_nn_min_workspace_size. */
 int sv_nn_min(const sv_mlp* mlp, const sv_motions* motions, const sv_cloud* cloud, float* d_hat, void* ws,
               size_t ws_bytes, void* stream);

@@ -131,7 +131,7 @@ int check_mlp(const sv_mlp* n, int precision, int dof) {
       return fail(SV_ERR_UNSUPPORTED, "FP32 network width %d: need a multiple of 64 up to 1024", n->width);
   } else if (precision == SV_BF16) {
     if (!mlp_bf16_supported(n->width))
-      return fail(SV_ERR_UNSUPPORTED, "BF16 network width %d: need 128, 256 or 512", n->width);
+      return fail(SV_ERR_UNSUPPORTED, "BF16 network width %d: need 128, 256, 512 or 1024", n->width);
   } else {
     return fail(SV_ERR_ARG, "unknown precision %d", precision);
   }
@@ -665,6 +665,7 @@ int sv_train_workspace_size(const sv_mlp* mlp, int64_t batch, size_t* bytes) {
   if (!bytes) return fail(SV_ERR_ARG, "bytes is NULL");
   if ((s = check_mlp(mlp, SV_BF16, 0))) return s;
   if (mlp->kind != SV_NET_MLP) return fail(SV_ERR_UNSUPPORTED, "training supports SV_NET_MLP networks only");
+  if (mlp->width > kTrainMaxWidth) return fail(SV_ERR_UNSUPPORTED, "training width %d > %d", mlp->width, kTrainMaxWidth);
   if (batch < 1 || batch > (1 << 24)) return fail(SV_ERR_SHAPE, "batch %lld outside 1..2^24", (long long)batch);
   *bytes = carve_train(nullptr, *mlp, batch).bytes;
   return SV_OK;
@@ -676,6 +677,7 @@ int sv_train_step(const sv_mlp* mlp, float* adam_m, float* adam_v, const sv_trai
   int s;
   if ((s = check_mlp(mlp, SV_BF16, 0))) return s;
   if (mlp->kind != SV_NET_MLP) return fail(SV_ERR_UNSUPPORTED, "training supports SV_NET_MLP networks only");
+  if (mlp->width > kTrainMaxWidth) return fail(SV_ERR_UNSUPPORTED, "training width %d > %d", mlp->width, kTrainMaxWidth);
   if (!hp) return fail(SV_ERR_ARG, "hparams is NULL");
   if (hp->step < 1) return fail(SV_ERR_ARG, "Adam step must be >= 1");
   if (!(hp->clamp_sigma > 0.f) || !(hp->lr >= 0.f) || !(hp->beta1 >= 0.f && hp->beta1 < 1.f) ||

@@ -309,6 +309,7 @@ ExactShape default_exact_shape();
 
 // ---- network (sv_mlp.hip) --------------------------------------------------------
 bool mlp_bf16_supported(int width);
+constexpr int kTrainMaxWidth = 512;   // the training kernels take W = 128, 256, 512
 size_t mlp_packed_elems(const MlpArgs& net);
 hipError_t launch_mlp_f32(const MlpArgs& net, const MotionArgs& mo, const CloudArgs& c, float* out, hipStream_t st);
 // Hidden-layer weights (layers 2..L) to BF16 in MFMA A-operand order; transpose = 1

@@ -146,9 +146,10 @@ __global__ void k_pack_bf16(MlpArgs net, int transpose, __bf16* __restrict__ pac
 // a barrier, then every wave writes its outputs, a barrier.
 // The weight tiles stream from L2 through the vector L1, whose data path bounds the
 // MFMA loop (RB rows per weight tile set that traffic: 1/RB KB per MFMA).  FB = 4,
-// RB = 2 keeps the block at 64 rows and about 70 KB of LDS, so two blocks share a CU
-// and one block's epilogue overlaps the other's MFMA loop; FB = 2, RB = 4 halves the
-// weight traffic but needs twice the LDS (one block per CU) and measures slower.
+// RB = 2 keeps the block at 64 rows and about 70 KB of LDS up to W = 512, so two blocks
+// share a CU and one block's epilogue overlaps the other's MFMA loop; FB = 2, RB = 4
+// halves the weight traffic but needs twice the LDS (one block per CU) and measures
+// slower.  W = 1024 (8 waves, about 140 KB of LDS) runs one block per CU.
 constexpr int kPad = kLdsPad;
 constexpr int kRing = 2;               // weight-load ring depth (k-steps)
 constexpr int kFB = 4;                 // feature blocks per wave
@@ -158,6 +159,10 @@ constexpr int kMaxIn = 3 + 2 * SV_MAX_DOF;
 
 template <int W>
 constexpr int mlp_threads() { return 64 * (W / (32 * kFB)); }
+// Blocks per CU the LDS tile allows (the launch bound, so that the register budget
+// matches the occupancy).
+template <int W>
+constexpr int mlp_blocks_per_cu() { return W <= 512 ? 2 : 1; }
 
 // Output modes (one kernel instance each, so profiles tell the launches apart):
 //   kScreen: every (motion, point) pair of (mo, c); indices of the points with
@@ -311,7 +316,7 @@ __device__ __forceinline__ void tile_partials(const float (&p)[kRB], float (*par
 }
 
 template <int W, int kMode>
-__global__ __launch_bounds__(mlp_threads<W>(), 2) void k_mlp_bf16(MlpArgs net, MotionArgs mo, CloudArgs c, int tiles,
+__global__ __launch_bounds__(mlp_threads<W>(), mlp_blocks_per_cu<W>()) void k_mlp_bf16(MlpArgs net, MotionArgs mo, CloudArgs c, int tiles,
                                                                const float* __restrict__ rows, int64_t row_stride,
                                                                const __bf16* __restrict__ packed,
                                                                float* __restrict__ out, float tau,
@@ -408,7 +413,7 @@ __host__ __device__ inline size_t res_block_base(int W, int in_dim, int b) {
 }
 
 template <int W, int kMode>
-__global__ __launch_bounds__(mlp_threads<W>(), 2) void k_res_bf16(MlpArgs net, MotionArgs mo, CloudArgs c, int tiles,
+__global__ __launch_bounds__(mlp_threads<W>(), mlp_blocks_per_cu<W>()) void k_res_bf16(MlpArgs net, MotionArgs mo, CloudArgs c, int tiles,
                                                                const float* __restrict__ rows, int64_t row_stride,
                                                                const __bf16* __restrict__ packed,
                                                                float* __restrict__ out, float tau,
@@ -666,7 +671,7 @@ hipError_t launch_f32(const MlpArgs& net, const MotionArgs& mo, const CloudArgs&
 
 }  // namespace
 
-bool mlp_bf16_supported(int width) { return width == 128 || width == 256 || width == 512; }
+bool mlp_bf16_supported(int width) { return width == 128 || width == 256 || width == 512 || width == 1024; }
 
 size_t mlp_packed_elems(const MlpArgs& net) {
   const size_t W = (size_t)net.width;
@@ -688,6 +693,7 @@ hipError_t launch_mlp_rows(const MlpArgs& net, int bf16, const __bf16* packed, c
     case 128: return launch_bf16_t<128>(net, none, c, rows, row_stride, packed, out, 0.f, nullptr, nullptr, st);
     case 256: return launch_bf16_t<256>(net, none, c, rows, row_stride, packed, out, 0.f, nullptr, nullptr, st);
     case 512: return launch_bf16_t<512>(net, none, c, rows, row_stride, packed, out, 0.f, nullptr, nullptr, st);
+    case 1024: return launch_bf16_t<1024>(net, none, c, rows, row_stride, packed, out, 0.f, nullptr, nullptr, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -717,6 +723,7 @@ hipError_t launch_mlp_min(const MlpArgs& net, const MotionArgs& mo, const CloudA
     case 128: return launch_bf16_mode<128, kMin>(net, mo, c, nullptr, 0, packed, nullptr, 0.f, nullptr, k, st);
     case 256: return launch_bf16_mode<256, kMin>(net, mo, c, nullptr, 0, packed, nullptr, 0.f, nullptr, k, st);
     case 512: return launch_bf16_mode<512, kMin>(net, mo, c, nullptr, 0, packed, nullptr, 0.f, nullptr, k, st);
+    case 1024: return launch_bf16_mode<1024, kMin>(net, mo, c, nullptr, 0, packed, nullptr, 0.f, nullptr, k, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -727,6 +734,7 @@ hipError_t launch_mlp_bf16(const MlpArgs& net, const MotionArgs& mo, const Cloud
     case 128: return launch_bf16_t<128>(net, mo, c, nullptr, 0, packed, out, tau, lists, counts, st);
     case 256: return launch_bf16_t<256>(net, mo, c, nullptr, 0, packed, out, tau, lists, counts, st);
     case 512: return launch_bf16_t<512>(net, mo, c, nullptr, 0, packed, out, tau, lists, counts, st);
+    case 1024: return launch_bf16_t<1024>(net, mo, c, nullptr, 0, packed, out, tau, lists, counts, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -78,7 +78,7 @@ def test_nn_fp32_shapes(sv, shape, M, N):
 
 
 @pytest.mark.parametrize("shape,M,N", [((15, 512, 8), 3, 3000), ((15, 256, 4), 4, 129), ((15, 128, 1), 2, 64),
-                                       ((15, 512, 2), 1, 1)])
+                                       ((15, 512, 2), 1, 1), ((15, 1024, 3), 2, 200), ((15, 1024, 1), 1, 65)])
 def test_nn_bf16_matches_rounding_oracle(sv, shape, M, N):
     arm = svgen.make_arm(1)
     m = svgen.make_motions(arm, M, 8, 200 + N)

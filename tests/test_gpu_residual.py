@@ -3,17 +3,19 @@
 Bars (as for the softplus network):
   FP32 path: |y - y_ref| <= 1e-4 |y_ref| + 1e-4 rms(y_ref) per element (FP64 oracle).
   BF16 path: against the oracle's BF16-rounding forward (same rounding points, FP64
-    elsewhere): |y - y_bf| <= max(2e-3, 5e-4 L) (1 + |y_bf|) per element for L blocks,
-    and the median of that error <= 2e-4.  The block outputs are rounded to BF16 and
-    the skip connections carry every rounding forward, so a last-bit difference of
-    FP32 against FP64 accumulation that moves one rounding by an ulp (2^-8 relative)
-    survives to the output; the bar grows with the number of rounding stages, while
-    the median stays at the level of rows with no such flip.  The error against FP64
-    is reported.
+    elsewhere): |y - y_bf| <= max(2e-3, 5e-4 L) sqrt(max(1, W / 512)) (1 + |y_bf|) per
+    element for L blocks of width W, and the median of that error <= 2e-4.  The block
+    outputs are rounded to BF16 and the skip connections carry every rounding forward,
+    so a last-bit difference of FP32 against FP64 accumulation that moves one rounding
+    by an ulp (2^-8 relative) survives to the output; the bar grows with the number of
+    rounding stages and, as a sum of independent flips, with the square root of the
+    activations rounded per stage, while the median stays at the level of rows with no
+    such flip.  The error against FP64 is reported.
+  W = 1024 (one block of 8 waves per CU): the same bars, the kMin and screening modes.
   Modes of one kernel: the per-motion minimum (sv_nn_min) equals the minimum of the
     dense predictions bit for bit, and trust screening sends exactly the points whose
     dense prediction is below tau; certified verdicts equal the exact oracle's.
-  Host checks: training rejects the architecture; bn_eps must be positive.
+  Host checks: training rejects the architecture and width 1024; bn_eps must be positive.
 """
 import numpy as np
 import pytest
@@ -54,6 +56,17 @@ def dense(sv, dnet, motions, pts, precision):
     return out.cpu().numpy().astype(np.float64)
 
 
+def bf16_bar(width, n_blocks):
+    """Largest error of a row against the BF16 emulation.  The two sides round the same
+    values to BF16, but from FP32 and FP64 sums, so an activation within a last-bit
+    difference of a rounding boundary can round the other way; the skips carry each such
+    flip to the output.  Flips are rare (the median row agrees to FP32 precision) and
+    their number per row grows with the rounded activations, W per block: the bar is
+    max(2e-3, 5e-4 L) at W = 512 and grows with sqrt(W / 512) for wider blocks, as a sum
+    of independent flips of either sign does."""
+    return max(2e-3, 5e-4 * n_blocks) * max(1.0, np.sqrt(width / 512))
+
+
 def rel_ok(y, ref, rtol=1e-4):
     rms = np.sqrt(np.mean(ref ** 2))
     return np.all(np.abs(y - ref) <= rtol * np.abs(ref) + rtol * rms)
@@ -72,9 +85,11 @@ def test_residual_fp32(sv, width, n_blocks, M, N):
 
 
 @pytest.mark.parametrize("width,n_blocks,M,N", [(512, 5, 3, 1000), (512, 11, 1, 129), (256, 3, 4, 257),
-                                                (128, 1, 2, 64), (128, 2, 1, 1)])
+                                                (128, 1, 2, 64), (128, 2, 1, 1), (1024, 3, 2, 150),
+                                                (1024, 11, 1, 70)])
 def test_residual_bf16(sv, width, n_blocks, M, N):
-    """Several tiles of 64 rows with a ragged last tile; the paper's 5 x 512 and 11 x 512."""
+    """Several tiles of 64 rows with a ragged last tile; the paper's 5 x 512, 11 x 512 and
+    11 x 1024 (one block of 8 waves per CU)."""
     arm = svgen.make_arm(1)
     m = svgen.make_motions(arm, M, 8, 300 + N)
     pts = svgen.bin_cloud(N, 301 + N)
@@ -84,9 +99,10 @@ def test_residual_bf16(sv, width, n_blocks, M, N):
     ref_bf = ores.forward_bf16(flat, IN, width, n_blocks, X, EPS_BN)
     ref = ores.forward(flat, IN, width, n_blocks, X, EPS_BN)
     err = np.abs(y - ref_bf) / (1.0 + np.abs(ref_bf))
-    print(f"bf16 residual {width}x{n_blocks}: vs emulation max {err.max():.2e}, median {np.median(err):.2e}; "
+    print(f"bf16 residual {width}x{n_blocks}: vs emulation max {err.max():.2e}, largest five "
+          f"{np.sort(err)[-5:][::-1]}, median {np.median(err):.2e}; "
           f"vs FP64 max {np.max(np.abs(y - ref) / (1 + np.abs(ref))):.2e}")
-    assert err.max() <= max(2e-3, 5e-4 * n_blocks)
+    assert err.max() <= bf16_bar(width, n_blocks)
     assert np.median(err) <= 2e-4
 
 
@@ -106,7 +122,7 @@ def test_residual_rows_mode(sv):
             assert rel_ok(y, ores.forward(flat, IN, width, n_blocks, X, EPS_BN))
         else:
             ref_bf = ores.forward_bf16(flat, IN, width, n_blocks, X, EPS_BN)
-            assert np.max(np.abs(y - ref_bf) / (1 + np.abs(ref_bf))) <= max(2e-3, 5e-4 * n_blocks)
+            assert np.max(np.abs(y - ref_bf) / (1 + np.abs(ref_bf))) <= bf16_bar(width, n_blocks)
 
 
 def test_residual_min_and_screening_modes(sv, orc):
@@ -149,3 +165,32 @@ def test_residual_host_checks(sv):
     with pytest.raises(sv.SvError) as e:
         dense(sv, wrong, m, svgen.bin_cloud(10, 602), sv.SV_FP32)
     assert e.value.status == -1
+
+
+def test_residual_1024_min_and_screening(sv):
+    """W = 1024: kMin equals the dense minimum bit for bit, and trust screening sends
+    exactly the dense predictions below tau to the fallback."""
+    arm = svgen.make_arm(1)
+    robot = sv.make_robot(arm)
+    m = svgen.make_motions(arm, 3, 16, 510)
+    pts = svgen.bin_cloud(300, 511)
+    flat, dnet = device_net(sv, 1024, 2, 512)
+    y = dense(sv, dnet, m, pts, sv.SV_BF16).astype(np.float32)
+    dm, dc = sv.DeviceMotions(m), sv.DeviceCloud(pts)
+    d_hat = torch.empty(m.n, device="cuda")
+    sv.sv_nn_min(dnet, dm, dc, d_hat)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(d_hat.cpu().numpy().view(np.int32), y.min(axis=1).view(np.int32))
+    tau = float(np.median(y))
+    out = sv.DeviceResults(m.n)
+    sv.sv_check_motions(robot, dm, dc, out, 0.01, mlp=dnet, screen=sv.SV_SCREEN_TRUST, tau=tau)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.n_fallback.cpu().numpy(), (y < np.float32(tau)).sum(axis=1))
+
+
+def test_training_rejects_width_1024(sv):
+    spec = svgen.MLPSpec(IN, 1024, 2)
+    dnet = sv.DeviceMLP(svgen.mlp_init(spec, 5), IN, 1024, 2)
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_train_workspace_size(dnet, 1024)
+    assert e.value.status == -4

@@ -147,10 +147,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchArgs a) {
     q.motion_off = (int)w.motion_off[r];
     q.n_points = (int)w.n_points[r];
     q.T = a.reqs[r].motions.T;
-    q.nb = (q.T + kCullB - 1) / kCullB;
+    q.nb = cull_block_count(q.T, a.reqs[r].motions.kind);
+    q.blen = cull_block_len(q.T, a.reqs[r].motions.kind);
     q.list_off = (int)w.cand_off[p];
     q.tile_off = (int)w.tile_off[r];
-    q.pad_ = 0;
     w.req[r] = q;
     w.fill[r] = 0;
   }
@@ -416,12 +416,13 @@ __device__ __forceinline__ void block_sphere(const BatchArgs& a, int64_t q) {
   const int64_t g = gk / a.K;
   const int k = (int)(gk - g * a.K);
   const int r = find_seg(w.motion_off, a.n_req, g);
-  const int T = a.reqs[r].motions.T;
-  const int nb = (T + kCullB - 1) / kCullB;
+  const int T = a.reqs[r].motions.T, kind = a.reqs[r].motions.kind;
+  const int nb = cull_block_count(T, kind);
   if (b >= nb || w.n_points[r] == 0) return;
   const int64_t m = g - w.motion_off[r];
   const CapEntry* e = w.table + (size_t)(w.sample_off[r] + m * T) * a.K + (size_t)k * T;
-  const int t0 = b * kCullB, t1 = min(t0 + kCullB, T);
+  const int B = cull_block_len(T, kind);
+  const int t0 = b * B, t1 = min(t0 + B, T);
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int t = t0; t < t1; ++t) {
     const CapEntry c = e[t];
@@ -508,7 +509,7 @@ __device__ __forceinline__ void cull_list_step(const BatchArgs& a, int64_t c, in
     const float G = key_dist(w.keys[g]) + kCullMargin;
     const float4 ts = w.tile_sph[w.tile_off[r] + t];
     const float4* sp = w.spheres + ((size_t)g * a.K + k) * w.nb_max;
-    const int nb = (a.reqs[r].motions.T + kCullB - 1) / kCullB;
+    const int nb = cull_block_count(a.reqs[r].motions.T, a.reqs[r].motions.kind);
     for (int b = 0; b < nb && !keep; ++b) {
       const float4 sb = sp[b];
       const float dx = sb.x - ts.x, dy = sb.y - ts.y, dz = sb.z - ts.z;
@@ -654,7 +655,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const float G = key_dist(__hip_atomic_load(w.keys + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const unsigned long long k2 = cull_item<P, NT>(
         (ConstF4Ptr)w.table, (size_t)(q.sample_off + m * q.T) * a.K + (size_t)k * q.T, q.T,
-        (ConstF4Ptr)(w.spheres + ((size_t)g * a.K + k) * w.nb_max), q.nb,
+        (ConstF4Ptr)(w.spheres + ((size_t)g * a.K + k) * w.nb_max), q.nb, q.blen,
         (ConstF4Ptr)(w.wave_sph + 4 * ((size_t)q.tile_off + t)), w.sx + po, w.sy + po, w.sz + po, w.sidx + po,
         q.n_points, t, G, wmin, executed);
     if (threadIdx.x == 0) {
@@ -820,7 +821,7 @@ BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, siz
   // culled pass
   w.point_cap = caps.max_total_points > 0 ? caps.max_total_points : (int64_t)caps.max_requests * caps.max_points;
   w.tile_cap = w.point_cap / kCullTilePts + caps.max_requests;
-  w.nb_max = (caps.max_T + kCullB - 1) / kCullB;
+  w.nb_max = cull_block_count_max(caps.max_T);
   w.cand_cap = caps.max_motions * ((caps.max_points + kCullTilePts - 1) / kCullTilePts) * rb.n_caps;
   w.n_points = cv.take<int64_t>(R);
   w.point_off = cv.take<int64_t>(R + 1);

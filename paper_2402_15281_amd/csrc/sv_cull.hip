@@ -7,7 +7,8 @@
 //   - a wave's points: the cloud is sorted by Morton cell first (a counting sort), so
 //     the 64 P points a wave holds are close together; their sphere is computed once
 //     per tile of sorted points (k_tile_spheres) for every item of that tile;
-//   - a block of kCullB consecutive samples of one capsule: a sphere around all their
+//   - a block of consecutive samples of one capsule (cull_block_len(T) of them): a
+//     sphere around all their
 //     segment endpoints, grown by the capsule radius (k_block_spheres).
 // If |c_wave - c_block| - R_wave - R_block exceeds an upper bound G of d(X, m) (plus
 // kCullMargin for FP32 rounding of the bound), every test of that group is larger than
@@ -173,18 +174,18 @@ __global__ __launch_bounds__(256) void k_scan_down(const int* __restrict__ count
   }
 }
 
-// One thread per (motion, capsule, block of kCullB samples): centre of the endpoints'
+// One thread per (motion, capsule, block of B samples): centre of the endpoints'
 // bounding box and the largest endpoint distance from it plus the capsule radius.
 // The segment of every sample in the block lies in the convex hull of its endpoints,
 // hence inside that sphere.
 __global__ __launch_bounds__(256) void k_block_spheres(const CapEntry* __restrict__ table, int64_t M, int T, int K,
-                                                       int nb, float4* __restrict__ spheres) {
+                                                       int nb, int B, float4* __restrict__ spheres) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= M * K * nb) return;
   const int64_t mk = g / nb;
   const int b = (int)(g - mk * nb);
   const CapEntry* e = table + mk * T;
-  const int t0 = b * kCullB, t1 = min(t0 + kCullB, T);
+  const int t0 = b * B, t1 = min(t0 + B, T);
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int t = t0; t < t1; ++t) {
     const CapEntry q = e[t];
@@ -302,7 +303,7 @@ template <int P, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_exact_cull(const CapEntry* __restrict__ table,
                                                    const float4* __restrict__ spheres,
                                                    const float4* __restrict__ wave_spheres, int T, int K, int nb,
-                                                   const float* __restrict__ sx, const float* __restrict__ sy,
+                                                   int B, const float* __restrict__ sx, const float* __restrict__ sy,
                                                    const float* __restrict__ sz, const int* __restrict__ perm, int N,
                                                    int tiles, const int* __restrict__ mlist,
                                                    const int* __restrict__ list, const int* __restrict__ caps,
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const float G = key_dist(__hip_atomic_load(keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const unsigned long long k2 =
         cull_item<P, NT>((ConstF4Ptr)table, ((size_t)m * K + k) * T, T, (ConstF4Ptr)(spheres + ((size_t)m * K + k) * nb),
-                         nb, (ConstF4Ptr)(wave_spheres + 4 * (size_t)tile), sx, sy, sz, perm, N, tile, G, wmin,
+                         nb, B, (ConstF4Ptr)(wave_spheres + 4 * (size_t)tile), sx, sy, sz, perm, N, tile, G, wmin,
                          executed);
     if (threadIdx.x == 0) {
       // publish only a new minimum: most items end above the motion's current key
@@ -391,14 +392,14 @@ hipError_t launch_bin_scan(const int* count, int64_t n_host, const int64_t* n_de
   return hipGetLastError();
 }
 
-int cull_blocks(int T) { return (T + kCullB - 1) / kCullB; }
+int cull_blocks(int T, int kind) { return cull_block_count(T, kind); }
 int cull_tiles(int64_t N) { return (int)((N + kCullNT * kCullP - 1) / (kCullNT * kCullP)); }
 
 hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const MotionArgs& mo, const CloudArgs& c,
                                const int* mlist, const int* mcount, int64_t n_slots, unsigned long long* keys,
                                const CullWs& w, hipStream_t st) {
   if (n_slots == 0 || c.n == 0) return hipSuccess;
-  const int K = rb.n_caps, T = mo.T, nb = cull_blocks(T);
+  const int K = rb.n_caps, T = mo.T, nb = cull_block_count(T, mo.kind), B = cull_block_len(T, mo.kind);
   hipError_t e;
   if ((e = launch_fill_i32(reinterpret_cast<int*>(w.bounds), 3, -1, st)) != hipSuccess) return e;
   if ((e = launch_fill_i32(reinterpret_cast<int*>(w.bounds) + 3, 3, 0, st)) != hipSuccess) return e;
@@ -414,7 +415,7 @@ hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const 
     return e;
   hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(c.n, 256)), dim3(256), 0, st, c, w.pbin, w.pslot, w.bin_start,
                      w.sx, w.sy, w.sz, w.perm);
-  hipLaunchKernelGGL(k_block_spheres, dim3(grid_for(mo.n * K * nb, 256)), dim3(256), 0, st, table, mo.n, T, K, nb,
+  hipLaunchKernelGGL(k_block_spheres, dim3(grid_for(mo.n * K * nb, 256)), dim3(256), 0, st, table, mo.n, T, K, nb, B,
                      w.spheres);
   const int stride = std::max(1, c.n / 256);
   hipLaunchKernelGGL(k_exact_seed, dim3((unsigned)(n_slots * K)), dim3(256), 0, st, table, T, K, w.sx, w.sy, w.sz, w.perm,
@@ -431,7 +432,7 @@ hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const 
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int blocks = (int)std::min<int64_t>(items * K, resident_cull_blocks());
   hipLaunchKernelGGL((k_exact_cull<kCullP, kCullNT>), dim3(blocks), dim3(kCullNT), 0, st, table, w.spheres,
-                     w.wave_spheres, T, K, nb, w.sx, w.sy, w.sz, w.perm, c.n, tiles, mlist, w.list, w.list_caps,
+                     w.wave_spheres, T, K, nb, B, w.sx, w.sy, w.sz, w.perm, c.n, tiles, mlist, w.list, w.list_caps,
                      w.list_count, keys, w.work);
   return hipGetLastError();
 }

@@ -3,7 +3,7 @@
 // pass (sv_cull.hip) and the batched one (sv_batch.hip).
 //
 // A group is (a wave's 64 P consecutive points of a Morton-sorted cloud, one capsule,
-// one block of kCullB consecutive samples).  Its lower bound is
+// one block of cull_block_len(T) consecutive samples).  Its lower bound is
 // |c_wave - c_block| - R_wave - R_block; if that exceeds an upper bound G of the
 // motion's minimum by more than kCullMargin (which covers the FP32 rounding of the
 // bound), every test of the group is larger than the final minimum, so skipping it
@@ -16,7 +16,27 @@ namespace sv {
 namespace {
 
 constexpr float kCullMargin = 1e-5f;   // m, above the FP32 rounding of the bounds
-constexpr int kCullB = 16;            // samples per bounding block
+// Samples per bounding block (2 to 16): a block spans about 1/32 of a linear motion and
+// 1/64 of a spline, whose path through two via points is several times longer, so
+// that its sphere stays tight at every T.  Shorter blocks cost more sphere tests, longer
+// ones skip fewer segment tests; the divisors are measured optima (bin-picking
+// workloads, T = 64 to 1024).
+__host__ __device__ constexpr int cull_block_len(int T, int kind) {
+  return T >= 16 * (kind == SV_SPLINE ? 64 : 32) ? 16
+       : T <= 2 * (kind == SV_SPLINE ? 64 : 32) ? 2
+       : (T + (kind == SV_SPLINE ? 63 : 31)) / (kind == SV_SPLINE ? 64 : 32);
+}
+__host__ __device__ constexpr int cull_block_count(int T, int kind) {
+  return (T + cull_block_len(T, kind) - 1) / cull_block_len(T, kind);
+}
+// The largest block count of any T <= max_T and either kind (from T = 1024 on, blocks
+// have 16 samples and the count grows with T).
+inline int cull_block_count_max(int max_T) {
+  int nb = max_T >= 1024 ? cull_block_count(max_T, SV_LINEAR) : 1;
+  for (int T = 1; T <= max_T && T < 1024; ++T)
+    for (int kind : {SV_LINEAR, SV_SPLINE}) nb = nb > cull_block_count(T, kind) ? nb : cull_block_count(T, kind);
+  return nb;
+}
 constexpr int kSeedSampleStride = 4;  // the seed bound uses every 4th sample
 constexpr int kCullP = 2, kCullNT = 256;  // culled pass: points per lane, threads per block
 
@@ -143,12 +163,13 @@ __device__ void tile_wave_spheres(const float* __restrict__ sx, const float* __r
 // One culled item for one wave group: the wave's 64 P consecutive sorted points of
 // tile `tile` (sx, sy, sz, N; perm maps them to the caller's indices; wsph the tile's
 // four wave-group spheres) against one capsule of one motion (table entries from e, T
-// samples; sample-block spheres sph, nb of them), under the bound G.  Returns, valid in thread 0, the block's smallest
+// samples; sample-block spheres sph, nb of them, over blocks of B samples), under the
+// bound G.  Returns, valid in thread 0, the block's smallest
 // (distance, index) key of the tests that survive; adds the executed tests to
 // `executed`.  Every thread of the block must call it (it contains a barrier).
 template <int P, int NT>
 __device__ __forceinline__ unsigned long long cull_item(ConstF4Ptr tab, size_t e, int T, ConstF4Ptr sph, int nb,
-                                                        ConstF4Ptr wsph, const float* __restrict__ sx,
+                                                        int B, ConstF4Ptr wsph, const float* __restrict__ sx,
                                                         const float* __restrict__ sy, const float* __restrict__ sz,
                                                         const int* __restrict__ perm, int N, int tile, float G,
                                                         unsigned long long* wmin, unsigned long long& executed) {
@@ -181,7 +202,7 @@ __device__ __forceinline__ unsigned long long cull_item(ConstF4Ptr tab, size_t e
       // skip iff the centre distance exceeds S = G + margin + R_wave + R_block
       const float S = G + kCullMargin + rw + sb.w;
       if (S < 0.f || dx * dx + dy * dy + dz * dz > S * S) continue;   // every test of the group exceeds the final minimum
-      const int t0 = b * kCullB, t1 = min(t0 + kCullB, T);
+      const int t0 = b * B, t1 = min(t0 + B, T);
       swept_range<P>(tab, e, t0, t1, x, y, z, m2);
       executed += (unsigned long long)(t1 - t0) * (64 * P);
       // tighten the bound with this wave's points

@@ -124,7 +124,8 @@ struct BatchReq {
   int point_off, motion_off;       // first sorted point; first global motion
   int n_points, T, nb;             // cloud size; samples; sample blocks
   int list_off;                    // first slot of the request's listed items
-  int tile_off, pad_;              // first tile of the request's sorted points
+  int tile_off;                    // first tile of the request's sorted points
+  int blen;                        // samples per sample block
 };
 
 // The culled batched kernel's blocks form kGangs gangs (block index mod kGangs, one
@@ -251,7 +252,7 @@ struct CullWs {
   unsigned long long* work;         // [kWorkSlots] executed segment tests, summed (may be NULL)
 };
 constexpr int kWorkSlots = 256;
-int cull_blocks(int T);
+int cull_blocks(int T, int kind);
 int cull_tiles(int64_t N);
 // Per-motion (distance, index) keys of the motion slots (mlist/mcount as launch_exact)
 // over all points, with groups of tests that provably exceed the minimum skipped.

@@ -4,6 +4,9 @@ Skipped test groups are proven to exceed the motion's minimum, so min_dist, argm
 and verdict must be bit-identical with culling on and off: on the bin-picking
 workload (linear and spline motions), with duplicated points (exact ties), tiny and
 ragged clouds, and in certified screening (whose confirmation pass is culled).  The
+sample blocks follow T and the motion kind (2 to 16 samples: about T / 32 for linear
+motions, T / 64 for splines), so the cases span every block length regime, including
+the largest block count below T = 1024 (a spline at T = 256: 64 blocks of 4).  The
 oracle checks a sample of the culled results directly.
 """
 import numpy as np
@@ -42,7 +45,10 @@ def assert_same(a, b):
 
 
 @pytest.mark.parametrize("kind,T,M,N", [("linear", 256, 64, 20000), ("spline", 100, 24, 7000),
-                                        ("linear", 33, 16, 513), ("spline", 2, 9, 130), ("linear", 1, 5, 3)])
+                                        ("linear", 33, 16, 513), ("spline", 2, 9, 130), ("linear", 1, 5, 3),
+                                        ("linear", 47, 12, 2000), ("linear", 64, 20, 3000),
+                                        ("spline", 200, 8, 1500), ("linear", 300, 6, 1100),
+                                        ("spline", 256, 6, 1200)])
 def test_culled_equals_unculled(sv, orc, kind, T, M, N):
     arm = svgen.make_arm(1)
     motions = svgen.make_motions(arm, M, T, 400 + T, kind)

@@ -453,7 +453,7 @@ __global__ __launch_bounds__(256) void k_batch_block_spheres(BatchArgs a) {
 }
 
 // The seed bound of (motion g, capsule k) from a stride sample of 256 points of the
-// request's sorted cloud and every kSeedSampleStride-th sample (a 256-thread block).
+// request's sorted cloud and every seed_stride(T)-th sample (a 256-thread block).
 __device__ void seed_bound(const BatchArgs& a, int64_t g, int k, unsigned long long* wmin) {
   const BatchWs& w = a.w;
   const int r = find_seg(w.motion_off, a.n_req, g);
@@ -469,8 +469,7 @@ __device__ void seed_bound(const BatchArgs& a, int64_t g, int k, unsigned long l
   int idx[1] = {ok ? w.sidx[js] : -1};
   const ConstF4Ptr tab = (ConstF4Ptr)w.table;
   const size_t e = (size_t)(w.sample_off[r] + m * T) * a.K + (size_t)k * T;
-  float m2 = INFINITY;
-  for (int t = 0; t < T; t += kSeedSampleStride) m2 = fminf(m2, seg_d2(load_entry(tab, e + t), x, y, z));
+  const float m2 = seed_d2(tab, e, T, seed_stride(T), x, y, z);
   float best[1] = {sqrtf(m2) - load_entry(tab, e).r};
   const unsigned long long k2 = block_min_key<256>(lane_min_key<1>(best, idx), wmin);
   if (threadIdx.x == 0 && k2 != kKeyEmpty) atomicMin(w.keys + g, k2);

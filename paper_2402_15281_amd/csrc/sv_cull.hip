@@ -22,9 +22,20 @@
 namespace sv {
 namespace {
 
+// Start values of the pass's counters, in one launch: bounds (minima ~0u, maxima 0),
+// the Morton bin counts and the item count and queue head.
+__global__ __launch_bounds__(256) void k_cull_init(unsigned* __restrict__ bounds, int* __restrict__ bin_count,
+                                                   int64_t nbins, int* __restrict__ list_count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nbins) bin_count[i] = 0;
+  if (i < 6) bounds[i] = i < 3 ? ~0u : 0u;
+  if (i < 2) list_count[i] = 0;
+}
+
 // Axis-aligned bounds of the cloud as order-preserving keys: bounds[0..2] minima
-// (start ~0u), bounds[3..5] maxima (start 0).
+// (start ~0u), bounds[3..5] maxima (start 0).  One atomic per block and bound.
 __global__ __launch_bounds__(256) void k_cloud_bounds(CloudArgs c, unsigned* __restrict__ bounds) {
+  __shared__ float part[4][6];
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < c.n; i += gridDim.x * blockDim.x) {
     const float v[3] = {c.x[i], c.y[i], c.z[i]};
@@ -34,17 +45,23 @@ __global__ __launch_bounds__(256) void k_cloud_bounds(CloudArgs c, unsigned* __r
       hi[a] = fmaxf(hi[a], v[a]);
     }
   }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     lo[a] = wave_min(lo[a]);
     hi[a] = wave_max(hi[a]);
-  }
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (lo[a] < INFINITY) atomicMin(bounds + a, ord_f32(lo[a]));
-      if (hi[a] > -INFINITY) atomicMax(bounds + 3 + a, ord_f32(hi[a]));
+    if (lane == 0) {
+      part[wid][a] = lo[a];
+      part[wid][3 + a] = hi[a];
     }
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int a = threadIdx.x;
+    float v = part[0][a];
+    for (int q = 1; q < 4; ++q) v = a < 3 ? fminf(v, part[q][a]) : fmaxf(v, part[q][a]);
+    if (a < 3 && v < INFINITY) atomicMin(bounds + a, ord_f32(v));
+    if (a >= 3 && v > -INFINITY) atomicMax(bounds + a, ord_f32(v));
   }
 }
 
@@ -228,8 +245,7 @@ __global__ __launch_bounds__(256) void k_exact_seed(const CapEntry* __restrict__
   int idx[1] = {ok ? perm[j] : -1};
   const ConstF4Ptr tab = (ConstF4Ptr)table;
   const size_t e = ((size_t)m * K + k) * T;
-  float m2 = INFINITY;
-  for (int t = 0; t < T; t += tstride) m2 = fminf(m2, seg_d2(load_entry(tab, e + t), x, y, z));
+  const float m2 = seed_d2(tab, e, T, tstride, x, y, z);
   float best[1] = {sqrtf(m2) - load_entry(tab, e).r};
   __shared__ unsigned long long wmin[4];
   const unsigned long long k2 = block_min_key<256>(lane_min_key<1>(best, idx), wmin);
@@ -401,12 +417,11 @@ hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const 
   if (n_slots == 0 || c.n == 0) return hipSuccess;
   const int K = rb.n_caps, T = mo.T, nb = cull_block_count(T, mo.kind), B = cull_block_len(T, mo.kind);
   hipError_t e;
-  if ((e = launch_fill_i32(reinterpret_cast<int*>(w.bounds), 3, -1, st)) != hipSuccess) return e;
-  if ((e = launch_fill_i32(reinterpret_cast<int*>(w.bounds) + 3, 3, 0, st)) != hipSuccess) return e;
+  const int64_t nbins = (int64_t)1 << (3 * w.level);
+  hipLaunchKernelGGL(k_cull_init, dim3(grid_for(std::max<int64_t>(nbins, 6), 256)), dim3(256), 0, st, w.bounds,
+                     w.bin_count, nbins, w.list_count);
   hipLaunchKernelGGL(k_cloud_bounds, dim3(std::min<unsigned>(grid_for(c.n, 256), 1024)), dim3(256), 0, st, c,
                      w.bounds);
-  const int64_t nbins = (int64_t)1 << (3 * w.level);
-  if ((e = launch_fill_i32(w.bin_count, nbins, 0, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_cell_bin, dim3(grid_for(c.n, 256)), dim3(256), 0, st, c, w.bounds, w.level, w.pbin, w.pslot,
                      w.bin_count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -419,14 +434,13 @@ hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const 
                      w.spheres);
   const int stride = std::max(1, c.n / 256);
   hipLaunchKernelGGL(k_exact_seed, dim3((unsigned)(n_slots * K)), dim3(256), 0, st, table, T, K, w.sx, w.sy, w.sz, w.perm,
-                     c.n, stride, kSeedSampleStride, mlist, mcount, keys);
+                     c.n, stride, seed_stride(T), mlist, mcount, keys);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int tiles = (c.n + kCullNT * kCullP - 1) / (kCullNT * kCullP);
   const int64_t items = n_slots * tiles;
   if (items * K > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(k_tile_spheres, dim3((unsigned)tiles), dim3(256), 0, st, w.sx, w.sy, w.sz, c.n,
                      w.tile_spheres, w.wave_spheres);
-  if ((e = launch_fill_i32(w.list_count, 2, 0, st)) != hipSuccess) return e;   // count, queue head
   hipLaunchKernelGGL(k_cull_list, dim3(grid_for(items * K, 256)), dim3(256), 0, st, w.tile_spheres, w.spheres, K, nb,
                      tiles, n_slots, mlist, mcount, keys, w.list, w.list_caps, w.list_count);
   if ((e = hipGetLastError()) != hipSuccess) return e;

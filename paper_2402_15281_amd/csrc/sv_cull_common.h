@@ -37,7 +37,9 @@ inline int cull_block_count_max(int max_T) {
     for (int kind : {SV_LINEAR, SV_SPLINE}) nb = nb > cull_block_count(T, kind) ? nb : cull_block_count(T, kind);
   return nb;
 }
-constexpr int kSeedSampleStride = 4;  // the seed bound uses every 4th sample
+constexpr int kSeedSamples = 32;      // the seed bound visits about this many samples of a motion
+// Sample stride of the seed bound: about kSeedSamples samples whatever T.
+__host__ __device__ constexpr int seed_stride(int T) { return T > kSeedSamples ? (T + kSeedSamples - 1) / kSeedSamples : 1; }
 constexpr int kCullP = 2, kCullNT = 256;  // culled pass: points per lane, threads per block
 
 __device__ __forceinline__ float wave_min(float v) {
@@ -158,6 +160,20 @@ __device__ void tile_wave_spheres(const float* __restrict__ sx, const float* __r
   __syncthreads();
   if (threadIdx.x == 0)
     *tile_out = make_float4(c[0], c[1], c[2], sqrtf(fmaxf(fmaxf(pr[0], pr[1]), fmaxf(pr[2], pr[3]))));
+}
+
+// Squared distance from (x, y, z) to the nearest segment of samples 0, ts, 2 ts, ...
+// < T of the capsule whose table entries start at e: the per-point part of the seed
+// bound, two samples per iteration so that both loads are in flight together.
+__device__ __forceinline__ float seed_d2(ConstF4Ptr tab, size_t e, int T, int ts, float x, float y, float z) {
+  float m2 = INFINITY;
+  int t = 0;
+  for (; t + ts < T; t += 2 * ts) {
+    const CapEntry a = load_entry(tab, e + t), b = load_entry(tab, e + t + ts);
+    m2 = fminf(m2, fminf(seg_d2(a, x, y, z), seg_d2(b, x, y, z)));
+  }
+  if (t < T) m2 = fminf(m2, seg_d2(load_entry(tab, e + t), x, y, z));
+  return m2;
 }
 
 // One culled item for one wave group: the wave's 64 P consecutive sorted points of

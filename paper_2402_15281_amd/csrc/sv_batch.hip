@@ -654,7 +654,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const float G = key_dist(__hip_atomic_load(w.keys + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const unsigned long long k2 = cull_item<P, NT>(
         (ConstF4Ptr)w.table, (size_t)(q.sample_off + m * q.T) * a.K + (size_t)k * q.T, q.T,
-        (ConstF4Ptr)(w.spheres + ((size_t)g * a.K + k) * w.nb_max), q.nb, q.blen,
+        w.spheres + ((size_t)g * a.K + k) * w.nb_max, q.nb, q.blen,
         (ConstF4Ptr)(w.wave_sph + 4 * ((size_t)q.tile_off + t)), w.sx + po, w.sy + po, w.sz + po, w.sidx + po,
         q.n_points, t, G, wmin, executed);
     if (threadIdx.x == 0) {

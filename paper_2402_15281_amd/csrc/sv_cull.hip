@@ -345,7 +345,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const int m = mlist ? mlist[slot] : slot;
     const float G = key_dist(__hip_atomic_load(keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const unsigned long long k2 =
-        cull_item<P, NT>((ConstF4Ptr)table, ((size_t)m * K + k) * T, T, (ConstF4Ptr)(spheres + ((size_t)m * K + k) * nb),
+        cull_item<P, NT>((ConstF4Ptr)table, ((size_t)m * K + k) * T, T, spheres + ((size_t)m * K + k) * nb,
                          nb, B, (ConstF4Ptr)(wave_spheres + 4 * (size_t)tile), sx, sy, sz, perm, N, tile, G, wmin,
                          executed);
     if (threadIdx.x == 0) {

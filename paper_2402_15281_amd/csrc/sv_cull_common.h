@@ -184,8 +184,8 @@ __device__ __forceinline__ float seed_d2(ConstF4Ptr tab, size_t e, int T, int ts
 // (distance, index) key of the tests that survive; adds the executed tests to
 // `executed`.  Every thread of the block must call it (it contains a barrier).
 template <int P, int NT>
-__device__ __forceinline__ unsigned long long cull_item(ConstF4Ptr tab, size_t e, int T, ConstF4Ptr sph, int nb,
-                                                        int B, ConstF4Ptr wsph, const float* __restrict__ sx,
+__device__ __forceinline__ unsigned long long cull_item(ConstF4Ptr tab, size_t e, int T,
+                                                        const float4* __restrict__ sph, int nb, int B, ConstF4Ptr wsph, const float* __restrict__ sx,
                                                         const float* __restrict__ sy, const float* __restrict__ sz,
                                                         const int* __restrict__ perm, int N, int tile, float G,
                                                         unsigned long long* wmin, unsigned long long& executed) {
@@ -211,22 +211,42 @@ __device__ __forceinline__ unsigned long long cull_item(ConstF4Ptr tab, size_t e
     float m2[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) m2[p] = INFINITY;
-    for (int b = 0; b < nb; ++b) {
-      const vf4 sb = sph[b];
-      const float dx = sb.x - cx, dy = sb.y - cy, dz = sb.z - cz;
-      // |c_wave - c_block| - R_wave - R_block > G + margin, without the square root:
-      // skip iff the centre distance exceeds S = G + margin + R_wave + R_block
-      const float S = G + kCullMargin + rw + sb.w;
-      if (S < 0.f || dx * dx + dy * dy + dz * dz > S * S) continue;   // every test of the group exceeds the final minimum
-      const int t0 = b * B, t1 = min(t0 + B, T);
-      swept_range<P>(tab, e, t0, t1, x, y, z, m2);
-      executed += (unsigned long long)(t1 - t0) * (64 * P);
-      // tighten the bound with this wave's points
-      float wb = INFINITY;
+    // |c_wave - c_block| - R_wave - R_block > G + margin, without the square root:
+    // skip iff the centre distance exceeds S = G + margin + R_wave + R_block.  Every test
+    // of a skipped group exceeds the final minimum.
+    auto skip = [&](float bx, float by, float bz, float br, float g) {
+      const float dx = bx - cx, dy = by - cy, dz = bz - cz;
+      const float S = g + kCullMargin + rw + br;
+      return S < 0.f || dx * dx + dy * dy + dz * dz > S * S;
+    };
+    for (int b0 = 0; b0 < nb; b0 += 64) {
+      // Lane l tests block b0 + l against the bound at the start of the chunk: one vector
+      // load and one ballot instead of a chain of dependent scalar loads.  The bound only
+      // falls, so a block failing this test fails every later one too.
+      const int bl = b0 + lane;
+      float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+      bool maybe = false;
+      if (bl < nb) {
+        q = sph[bl];
+        maybe = !skip(q.x, q.y, q.z, q.w, G);
+      }
+      for (unsigned long long mask = __ballot(maybe); mask; mask &= mask - 1) {
+        const int l = __builtin_ctzll(mask);
+        const float bx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.x), l));
+        const float by = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.y), l));
+        const float bz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.z), l));
+        const float br = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.w), l));
+        if (skip(bx, by, bz, br, G)) continue;   // the bound has tightened since
+        const int t0 = (b0 + l) * B, t1 = min(t0 + B, T);
+        swept_range<P>(tab, e, t0, t1, x, y, z, m2);
+        executed += (unsigned long long)(t1 - t0) * (64 * P);
+        // tighten the bound with this wave's points
+        float wb = INFINITY;
 #pragma unroll
-      for (int p = 0; p < P; ++p)
-        if (idx[p] >= 0) wb = fminf(wb, sqrtf(m2[p]) - r);
-      G = uniform_f(fminf(G, wave_min(wb)));
+        for (int p = 0; p < P; ++p)
+          if (idx[p] >= 0) wb = fminf(wb, sqrtf(m2[p]) - r);
+        G = uniform_f(fminf(G, wave_min(wb)));
+      }
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) best[p] = sqrtf(m2[p]) - r;

@@ -108,11 +108,12 @@ def cpu_baseline(arm, motions, pts, eps, target_s, gpu_verdicts, gpu_min):
 
 
 def timed(sv, torch, fn, steps, warmup, kernels):
+    """(ms per step, {stage: mean ms per launch}).  The steps are timed without
+    instrumentation; the per-stage durations (HIP events the library records around
+    each stage on its stream) come from a second pass of the same steps, so that the
+    events' own cost stays out of the step time."""
     for _ in range(warmup):
         fn()
-    torch.cuda.synchronize()
-    sv.sv_profile_enable(True)
-    sv.sv_profile_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -120,10 +121,16 @@ def timed(sv, torch, fn, steps, warmup, kernels):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     per = {}
-    for k in kernels:
-        ms, n = sv.sv_profile_read(k)
-        per[k] = ms / max(n, 1)
-    sv.sv_profile_enable(False)
+    if kernels:
+        sv.sv_profile_enable(True)
+        sv.sv_profile_reset()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        for k in kernels:
+            ms, n = sv.sv_profile_read(k)
+            per[k] = ms / max(n, 1)
+        sv.sv_profile_enable(False)
     return (t1 - t0) * 1e3 / steps, per
 
 
@@ -347,7 +354,7 @@ def crossover(sv, torch, np, arm, robot, motions, dc, eps, steps):
         out = sv.DeviceResults(M)
         ws = sv.workspace(sv.sv_workspace_size(sv.SV_OP_CHECK, robot, dmT, dc))
         call = lambda: sv.sv_check_motions(robot, dmT, dc, out, eps, ws=ws)
-        ms_c, _ = timed(sv, torch, call, steps, 1, [])
+        ms_c, _ = timed(sv, torch, call, steps, 2, [])
         sv.sv_set_exact_culling(False)
         ms_d, _ = timed(sv, torch, call, max(steps // 2, 2), 1, [])
         sv.sv_set_exact_culling(True)
@@ -361,7 +368,7 @@ def crossover(sv, torch, np, arm, robot, motions, dc, eps, steps):
         ws = sv.workspace(sv.sv_workspace_size(sv.SV_OP_CHECK, robot, dm256, dc, net))
         ms_n, _ = timed(sv, torch, lambda: sv.sv_check_motions(robot, dm256, dc, out, eps, mlp=net,
                                                                screen=sv.SV_SCREEN_TRUST, tau=-1e30, ws=ws),
-                        steps, 1, [])
+                        steps, 2, [])
         culled_T = next((T for T in Ts if res["exact"][T]["culled_ms"] > ms_n), None)
         name = f"softplus_{L}x{width}"
         res["networks"][name] = {"flop_per_query": mlp_flops_per_query(15, width, L), "screen_ms_at_zero_fallback": ms_n,

@@ -488,7 +488,8 @@ __global__ __launch_bounds__(256) void k_batch_seed(BatchArgs a) {
 }
 
 // One thread per candidate (in work order) up to the capacity: keep the item if any
-// of its capsule's sample blocks may come within the motion's bound of the tile.
+// of its capsule's sample blocks may come within the motion's bound of the tile and of
+// one of its wave groups (item_may_hit).
 // Kept items are appended in work order (one atomic per wave); each request's count
 // goes to remaining[r], one atomic per wave when its kept items share a request.
 __device__ __forceinline__ void cull_list_step(const BatchArgs& a, int64_t c, int64_t total) {
@@ -505,15 +506,9 @@ __device__ __forceinline__ void cull_list_step(const BatchArgs& a, int64_t c, in
     const int t = (int)(rem / a.K);
     const int k = (int)(rem - (int64_t)t * a.K);
     const int64_t g = w.motion_off[r] + m;
-    const float G = key_dist(w.keys[g]) + kCullMargin;
-    const float4 ts = w.tile_sph[w.tile_off[r] + t];
-    const float4* sp = w.spheres + ((size_t)g * a.K + k) * w.nb_max;
-    const int nb = cull_block_count(a.reqs[r].motions.T, a.reqs[r].motions.kind);
-    for (int b = 0; b < nb && !keep; ++b) {
-      const float4 sb = sp[b];
-      const float dx = sb.x - ts.x, dy = sb.y - ts.y, dz = sb.z - ts.z;
-      keep = sqrtf(dx * dx + dy * dy + dz * dz) - ts.w - sb.w <= G;
-    }
+    const int64_t tile = w.tile_off[r] + t;
+    keep = item_may_hit(w.tile_sph[tile], w.wave_sph + 4 * tile, w.spheres + ((size_t)g * a.K + k) * w.nb_max,
+                        cull_block_count(a.reqs[r].motions.T, a.reqs[r].motions.kind), key_dist(w.keys[g]));
     g32 = (int)g;
     tk = (t << 4) | k;
   }

@@ -266,11 +266,12 @@ __global__ __launch_bounds__(256) void k_tile_spheres(const float* __restrict__ 
 
 // Coarse pass: one thread per (motion slot, tile, capsule); the capsule is kept for
 // the tile if any of its sample blocks may come within the motion's current bound of
-// the tile's sphere.  Kept items are appended to (list: slot * tiles + tile, caps:
+// the tile's sphere and of one of its wave groups' spheres (item_may_hit).  Kept items are appended to (list: slot * tiles + tile, caps:
 // capsule, count) -- one atomic per wave.  One capsule per item keeps the items short,
 // which balances the persistent blocks, since the surviving work concentrates on the
 // few tiles near the robot.
 __global__ __launch_bounds__(256) void k_cull_list(const float4* __restrict__ tile_sph,
+                                                   const float4* __restrict__ wave_sph,
                                                    const float4* __restrict__ spheres, int K, int nb, int tiles,
                                                    int64_t n_slots, const int* __restrict__ mlist,
                                                    const int* __restrict__ mcount,
@@ -286,16 +287,8 @@ __global__ __launch_bounds__(256) void k_cull_list(const float4* __restrict__ ti
     const int slot = (int)(st / tiles);
     const int tile = (int)(st - (int64_t)slot * tiles);
     const int m = mlist ? mlist[slot] : slot;
-    const float G = key_dist(keys[m]) + kCullMargin;
-    const float4 ts = tile_sph[tile];
-    const float4* sp = spheres + ((size_t)m * K + k) * nb;
-    bool keep = false;
-    for (int b = 0; b < nb && !keep; ++b) {
-      const float4 s = sp[b];
-      const float dx = s.x - ts.x, dy = s.y - ts.y, dz = s.z - ts.z;
-      keep = sqrtf(dx * dx + dy * dy + dz * dz) - ts.w - s.w <= G;
-    }
-    mask = keep ? 1 : 0;
+    mask = item_may_hit(tile_sph[tile], wave_sph + 4 * (size_t)tile, spheres + ((size_t)m * K + k) * nb, nb,
+                        key_dist(keys[m])) ? 1 : 0;
   }
   const bool keep = mask != 0;
   const unsigned long long ballot = __ballot(keep);
@@ -441,7 +434,8 @@ hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const 
   if (items * K > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(k_tile_spheres, dim3((unsigned)tiles), dim3(256), 0, st, w.sx, w.sy, w.sz, c.n,
                      w.tile_spheres, w.wave_spheres);
-  hipLaunchKernelGGL(k_cull_list, dim3(grid_for(items * K, 256)), dim3(256), 0, st, w.tile_spheres, w.spheres, K, nb,
+  hipLaunchKernelGGL(k_cull_list, dim3(grid_for(items * K, 256)), dim3(256), 0, st, w.tile_spheres, w.wave_spheres,
+                     w.spheres, K, nb,
                      tiles, n_slots, mlist, mcount, keys, w.list, w.list_caps, w.list_count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int blocks = (int)std::min<int64_t>(items * K, resident_cull_blocks());

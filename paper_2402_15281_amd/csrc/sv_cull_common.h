@@ -131,7 +131,7 @@ __device__ void tile_wave_spheres(const float* __restrict__ sx, const float* __r
     }
   r2 = wave_max(r2);
   if (lane == 0) {
-    wave_out[wid] = make_float4(cx, cy, cz, sqrtf(r2));
+    wave_out[wid] = make_float4(cx, cy, cz, any ? sqrtf(r2) : -INFINITY);   // an empty group never passes
     for (int a = 0; a < 3; ++a) {
       part[wid][a] = lo[a];
       part[wid][3 + a] = hi[a];
@@ -160,6 +160,35 @@ __device__ void tile_wave_spheres(const float* __restrict__ sx, const float* __r
   __syncthreads();
   if (threadIdx.x == 0)
     *tile_out = make_float4(c[0], c[1], c[2], sqrtf(fmaxf(fmaxf(pr[0], pr[1]), fmaxf(pr[2], pr[3]))));
+}
+
+// Whether the lower bound of the tests between the points in sphere a and the segments
+// in sphere b, |c_a - c_b| - R_a - R_b, exceeds G + kCullMargin (tested without the
+// square root: with S = G + margin + R_a + R_b, iff S < 0 or |c_a - c_b|^2 > S^2).
+__device__ __forceinline__ bool spheres_apart(float4 a, float4 b, float G) {
+  const float dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+  const float S = G + kCullMargin + a.w + b.w;
+  return S < 0.f || dx * dx + dy * dy + dz * dz > S * S;
+}
+
+// Whether a (tile, capsule) item can run any test under the bound G: some sample block
+// (spheres sp[0..nb)) within reach of the tile's sphere ts (most candidates fail here),
+// and some (wave group, block) pair within reach (the wave groups' spheres ws[0..3]),
+// which is what the culled kernel tests.  G only falls, so an item dropped here would
+// run no test later either.
+__device__ __forceinline__ bool item_may_hit(float4 ts, const float4* __restrict__ ws, const float4* __restrict__ sp,
+                                             int nb, float G) {
+  int b0 = 0;
+  while (b0 < nb && spheres_apart(ts, sp[b0], G)) ++b0;
+  if (b0 == nb) return false;
+  const float4 w0 = ws[0], w1 = ws[1], w2 = ws[2], w3 = ws[3];
+  for (int b = 0; b < nb; ++b) {
+    const float4 s = sp[b];
+    if (!spheres_apart(w0, s, G) || !spheres_apart(w1, s, G) || !spheres_apart(w2, s, G) ||
+        !spheres_apart(w3, s, G))
+      return true;
+  }
+  return false;
 }
 
 // Squared distance from (x, y, z) to the nearest segment of samples 0, ts, 2 ts, ...

@@ -425,9 +425,7 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
     if (e != hipSuccess) return hip_fail(e, name); \
   } while (0)
 
-  SV_TRY("init", launch_fill_u64(w.keys, M, ~0ull, st));
-  SV_TRY("init", launch_fill_i32(w.band_count, 1, 0, st));
-  SV_TRY("init", launch_fill_u64(w.work, kWorkSlots, 0ull, st));
+  SV_TRY("init", launch_check_init(w.keys, M, w.band_count, w.work, kWorkSlots, st));
   const int* mlist = nullptr;
   const int* mcount = nullptr;
   if (cloud->n > 0) {

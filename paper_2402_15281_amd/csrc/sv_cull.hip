@@ -302,9 +302,9 @@ __global__ __launch_bounds__(256) void k_cull_list(const float4* __restrict__ ti
   }
 }
 
-// One listed item (motion slot, tile of NT P sorted points, mask of kept capsules) per
-// block iteration; each wave owns 64 P consecutive sorted points and decides per
-// (capsule, sample block) whether the group can come below its bound.  Persistent
+// One listed item (motion slot, tile of NT P sorted points, capsule) per block
+// iteration; each wave owns 64 P consecutive sorted points and decides per sample
+// block whether the group can come below its bound.  Persistent
 // blocks take items in list order from a queue (count[1]), which keeps them together
 // on neighbouring motions and balances the uneven items.  work (optional) counts the
 // executed segment tests.

@@ -108,6 +108,15 @@ __global__ void k_fill_i32(int* __restrict__ p, int64_t n, int v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
+// Start values of a motion check, in one launch: per-motion keys empty, the band count
+// and the executed-test counters zero.
+__global__ void k_check_init(unsigned long long* __restrict__ keys, int64_t M, int* __restrict__ band_count,
+                             unsigned long long* __restrict__ work, int n_work) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M) keys[i] = kKeyEmpty;
+  if (i < n_work) work[i] = 0ull;
+  if (i == 0) *band_count = 0;
+}
 
 // Grid-stride over the motions of (mlist, mcount), or all M.
 __global__ void k_finalize(const unsigned long long* __restrict__ keys, int64_t M, const int* __restrict__ mlist,
@@ -623,6 +632,13 @@ hipError_t launch_make_samples(const sv_robot& rb, const MotionArgs& m, const Ca
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_init(unsigned long long* keys, int64_t M, int* band_count, unsigned long long* work,
+                             int n_work, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_init, dim3(grid_for(std::max<int64_t>(std::max<int64_t>(M, n_work), 1), 256)), dim3(256), 0,
+                     st, keys, M, band_count, work, n_work);
   return hipGetLastError();
 }
 

@@ -291,6 +291,8 @@ hipError_t launch_make_samples(const sv_robot& rb, const MotionArgs& m, const Ca
                                float* ud, float* cx, float* cy, float* cz, float* cd, float* out, int* n_short,
                                hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);
+hipError_t launch_check_init(unsigned long long* keys, int64_t M, int* band_count, unsigned long long* work,
+                             int n_work, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
 // Decode FP32 keys into results for the motions in (mlist, mcount) (all M if mlist is
 // NULL); motions within `band` of eps are appended to (list, count) for the FP64 recheck.

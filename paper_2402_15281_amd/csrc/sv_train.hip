@@ -15,9 +15,11 @@
 // Kernels, in launch order:
 //   k_pack_bf16 (x2)  W_l and W_l^T in MFMA operand order (sv_mlp.hip)
 //   k_train_fwd       per 64-row tile: all layers, activations to aT, y
-//   k_train_loss      loss and dy (single block, fixed-order reduction)
+//   k_train_loss      dy and per-block loss partials; k_train_loss_sum: the loss
+//                     (fixed-order reductions)
 //   k_train_bwd       per 64-row tile: dz of every layer via W_l^T MFMA, to dzT
-//   k_grad_w          dW_l = dz_l^T a_{l-1} for l >= 2 (MFMA, split over the batch)
+//   k_grad_w          dW_l = dz_l^T a_{l-1} for l >= 2 (MFMA, split over the batch; both
+//                     operands staged in LDS)
 //   k_grad_reduce     fixed-order sum of the splits
 //   k_grad_rows       db_l, w_out and b_out gradients (one wave per output)
 //   k_grad_w1         dW_1 = dz_1^T h0 in FP32 (split over the batch) + fixed-order sum
@@ -31,7 +33,7 @@ namespace sv {
 namespace {
 
 constexpr int kRows = kTileRows;
-constexpr int kSplitW = 8;        // batch splits of the dW GEMM
+constexpr int kSplitW = 16;       // batch splits of the dW GEMM
 constexpr int kW1Chunk = 256;     // batch rows per block of the dW_1 kernel
 
 struct TrainArgs {
@@ -184,22 +186,36 @@ __global__ __launch_bounds__(W) void k_train_fwd(TrainArgs a) {
   }
 }
 
-// One block of 1024 threads: dy and the mean clamped-L1 loss with a fixed-order tree.
-__global__ __launch_bounds__(1024) void k_train_loss(TrainArgs a, float sigma, float* __restrict__ loss_out) {
-  __shared__ float red[1024];
+// dy of 256 rows per block and the block's sum of |y - clamp(delta)| (fixed-order tree)
+// into part[block]; k_train_loss_sum adds the partials in a fixed order.
+__global__ __launch_bounds__(256) void k_train_loss(TrainArgs a, float sigma, float* __restrict__ part) {
+  __shared__ float red[256];
   const int in_dim = a.net.in_dim;
-  float s = 0.f;
-  for (int b = threadIdx.x; b < a.Bp; b += 1024) {
-    float g = 0.f;
-    if (b < a.B) {
-      const float yv = a.y[b];
-      const float d = a.samples[(size_t)a.idx[b] * (in_dim + 1) + in_dim];
-      const float r = yv - fminf(fmaxf(d, -sigma), sigma);
-      s += fabsf(r);
-      g = (r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f)) / (float)a.B;
-    }
-    a.dy[b] = g;
+  const int b = blockIdx.x * 256 + threadIdx.x;   // < Bp
+  float s = 0.f, g = 0.f;
+  if (b < a.B) {
+    const float yv = a.y[b];
+    const float d = a.samples[(size_t)a.idx[b] * (in_dim + 1) + in_dim];
+    const float r = yv - fminf(fmaxf(d, -sigma), sigma);
+    s = fabsf(r);
+    g = (r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f)) / (float)a.B;
   }
+  a.dy[b] = g;
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// The mean clamped-L1 loss from the n block partials, in a fixed order (one block).
+__global__ __launch_bounds__(1024) void k_train_loss_sum(TrainArgs a, const float* __restrict__ part, int n,
+                                                         float* __restrict__ loss_out) {
+  __shared__ float red[1024];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < n; i += 1024) s += part[i];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
@@ -273,49 +289,97 @@ __global__ __launch_bounds__(W) void k_train_bwd(TrainArgs a) {
   }
 }
 
-// Partial dW_l[f][k] over one batch split: block = 4 waves, 128 x 128 output tile,
-// wave w owns rows 64 (w >> 1).. and columns 64 (w & 1).. as 2 x 2 MFMA tiles.
-// A operand: dz_l^T (rows f, k-dim = batch); B operand: a_{l-1}^T (k-dim = batch).
+// Partial dW_l[f][k] = sum over one batch split of dz_l[f][b] a_{l-1}[k][b], l >= 2.
+// Both operands are batch-contiguous rows ([feature][batch]); a lane's MFMA fragment is
+// 16 bytes of one row, so reading fragments straight from memory touches a cache line
+// per lane and re-fetches each line once per k-step.  Instead a block stages chunks of
+// kGwChunk batch rows of its 128 dz rows and TK a rows in LDS with coalesced 16-byte
+// loads (a row's chunk is one 128-byte line), then its 4 waves read fragments from LDS:
+// wave (wf, wk) owns rows 64 wf .. of the 128 and columns (TK / 2) wk .. of the TK, as
+// 2 x (TK / 64) MFMA tiles of 32 x 32.  Per chunk that is about 1.1 KB of LDS traffic
+// per MFMA at TK = 256.
+constexpr int kGwChunk = 64;                   // batch rows per LDS stage
+constexpr int kGwLd = kGwChunk + kLdsPad;      // LDS row stride (elements)
+
 template <int W>
-__global__ __launch_bounds__(256) void k_grad_w(TrainArgs a, float* __restrict__ part) {
-  constexpr int TB = W / 128;                       // tiles per dimension
-  const int L = a.net.n_hidden;
+constexpr int gw_tk() { return W >= 256 ? 256 : W; }   // output columns per block
+
+template <int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_grad_w(TrainArgs a,
+                                                                                       float* __restrict__ part) {
+  constexpr int TF = 128, TK = gw_tk<W>();
+  constexpr int RB = TK / 64;                        // column blocks per wave
+  constexpr int SEG = kGwChunk / 8;                  // 16-byte segments per row and chunk
+  __shared__ __align__(16) __bf16 As[TF * kGwLd];
+  __shared__ __align__(16) __bf16 Bs[TK * kGwLd];
   int g = blockIdx.x;
-  const int tk = g % TB; g /= TB;
-  const int tf = g % TB; g /= TB;
+  const int tk = g % (W / TK); g /= (W / TK);
+  const int tf = g % (W / TF); g /= (W / TF);
   const int s = g % kSplitW; g /= kSplitW;
   const int l = g + 2;                              // layer 2..L
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
-  const int f0 = tf * 128 + 64 * (wid >> 1), k0 = tk * 128 + 64 * (wid & 1);
-  const int chunk = a.Bp / kSplitW;                 // multiple of 16 (Bp is a multiple of 128)
-  const int b0 = s * chunk;
-  const __bf16* dz = a.dzT + (size_t)(l - 1) * W * a.Bp;
-  const __bf16* ap = a.aT + (size_t)(l - 2) * W * a.Bp;
-  const bf16x8* A0 = reinterpret_cast<const bf16x8*>(dz + (size_t)(f0 + col) * a.Bp + b0 + 8 * half);
-  const bf16x8* A1 = reinterpret_cast<const bf16x8*>(dz + (size_t)(f0 + 32 + col) * a.Bp + b0 + 8 * half);
-  const bf16x8* B0 = reinterpret_cast<const bf16x8*>(ap + (size_t)(k0 + col) * a.Bp + b0 + 8 * half);
-  const bf16x8* B1 = reinterpret_cast<const bf16x8*>(ap + (size_t)(k0 + 32 + col) * a.Bp + b0 + 8 * half);
-  f32x16 c00 = {}, c01 = {}, c10 = {}, c11 = {};
-  for (int kk = 0; kk < chunk / 16; ++kk) {
-    const bf16x8 x0 = A0[2 * kk], x1 = A1[2 * kk], y0 = B0[2 * kk], y1 = B1[2 * kk];
-    c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, y0, c00, 0, 0, 0);
-    c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, y1, c01, 0, 0, 0);
-    c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, y0, c10, 0, 0, 0);
-    c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, y1, c11, 0, 0, 0);
+  const int wf = wid & 1, wk = wid >> 1;
+  const int f0 = tf * TF, k0 = tk * TK;
+  const int per = a.Bp / kSplitW;                   // multiple of 16 (Bp is a multiple of 256)
+  const int b_begin = s * per, b_end = b_begin + per;
+  const __bf16* dz = a.dzT + ((size_t)(l - 1) * W + f0) * a.Bp;
+  const __bf16* ap = a.aT + ((size_t)(l - 2) * W + k0) * a.Bp;
+  f32x16 acc[2][RB];
+#pragma unroll
+  for (int fb = 0; fb < 2; ++fb)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[fb][rb] = f32x16{};
+  // thread tid moves segments tid + 256 q, q < NQ, of each chunk: row r, columns c8..
+  constexpr int NQ = (TF + TK) * SEG / 256;
+  static_assert((TF + TK) * SEG % 256 == 0, "whole passes");
+  bf16x8 stage[NQ];
+  auto fetch = [&](int b, int kc) {                  // the chunk at b into registers
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int id = tid + 256 * q, r = id / SEG, c8 = 8 * (id - r * SEG);
+      const __bf16* src = r < TF ? dz + (size_t)r * a.Bp : ap + (size_t)(r - TF) * a.Bp;
+      if (c8 < kc) stage[q] = *reinterpret_cast<const bf16x8*>(src + b + c8);
+    }
+  };
+  fetch(b_begin, min(kGwChunk, b_end - b_begin));
+  for (int b = b_begin; b < b_end; b += kGwChunk) {
+    const int kc = min(kGwChunk, b_end - b);        // multiple of 16
+    __syncthreads();                                // every wave is done with the last stage
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int id = tid + 256 * q, r = id / SEG, c8 = 8 * (id - r * SEG);
+      __bf16* dst = r < TF ? As + r * kGwLd : Bs + (r - TF) * kGwLd;
+      if (c8 < kc) *reinterpret_cast<bf16x8*>(dst + c8) = stage[q];
+    }
+    __syncthreads();
+    if (b + kGwChunk < b_end) fetch(b + kGwChunk, min(kGwChunk, b_end - b - kGwChunk));   // in flight during the MFMAs
+    for (int ks = 0; ks < kc / 16; ++ks) {
+      bf16x8 x[2], y[RB];
+#pragma unroll
+      for (int fb = 0; fb < 2; ++fb)
+        x[fb] = *reinterpret_cast<const bf16x8*>(As + (64 * wf + 32 * fb + col) * kGwLd + 16 * ks + 8 * half);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+        y[rb] = *reinterpret_cast<const bf16x8*>(Bs + ((TK / 2) * wk + 32 * rb + col) * kGwLd + 16 * ks + 8 * half);
+#pragma unroll
+      for (int fb = 0; fb < 2; ++fb)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          acc[fb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[fb], y[rb], acc[fb][rb], 0, 0, 0);
+    }
   }
-  (void)L;
   float* P = part + ((size_t)(l - 2) * kSplitW + s) * W * W;
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
+  for (int fb = 0; fb < 2; ++fb)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int fr = 8 * j + 4 * half + i;
-      P[(size_t)(f0 + fr) * W + k0 + col] = c00[4 * j + i];
-      P[(size_t)(f0 + fr) * W + k0 + 32 + col] = c01[4 * j + i];
-      P[(size_t)(f0 + 32 + fr) * W + k0 + col] = c10[4 * j + i];
-      P[(size_t)(f0 + 32 + fr) * W + k0 + 32 + col] = c11[4 * j + i];
-    }
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          P[(size_t)(f0 + 64 * wf + 32 * fb + 8 * j + 4 * half + i) * W + k0 + (TK / 2) * wk + 32 * rb + col] =
+              acc[fb][rb][4 * j + i];
 }
 
 __global__ void k_grad_reduce(TrainArgs a, const float* __restrict__ part) {
@@ -340,21 +404,23 @@ __global__ __launch_bounds__(256) void k_grad_rows(TrainArgs a) {
   const int n_rows = L * W + W + 1;
   if (row >= n_rows) return;
   float s = 0.f;
-  if (row < L * W) {
-    const __bf16* v = a.dzT + (size_t)row * a.Bp;
-    for (int b = 8 * lane; b < a.Bp; b += 512) {
-      const bf16x8 x = *reinterpret_cast<const bf16x8*>(v + b);
+  if (row < L * W + W) {
+    // four loads in flight per lane (independent sums u), then a fixed-order combine
+    const bool bias = row < L * W;
+    const __bf16* v = bias ? a.dzT + (size_t)row * a.Bp : a.aT + ((size_t)(L - 1) * W + (row - L * W)) * a.Bp;
+    float u[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int b0 = 8 * lane; b0 < a.Bp; b0 += 4 * 512) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) s += (float)x[e];
-    }
-  } else if (row < L * W + W) {
-    const int f = row - L * W;
-    const __bf16* v = a.aT + ((size_t)(L - 1) * W + f) * a.Bp;
-    for (int b = 8 * lane; b < a.Bp; b += 512) {
-      const bf16x8 x = *reinterpret_cast<const bf16x8*>(v + b);
+      for (int q = 0; q < 4; ++q) {
+        const int b = b0 + q * 512;
+        if (b < a.Bp) {
+          const bf16x8 x = *reinterpret_cast<const bf16x8*>(v + b);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) s = fmaf((float)x[e], a.dy[b + e], s);
+          for (int e = 0; e < 8; ++e) u[q] = bias ? u[q] + (float)x[e] : fmaf((float)x[e], a.dy[b + e], u[q]);
+        }
+      }
     }
+    s = (u[0] + u[1]) + (u[2] + u[3]);
   } else {
     for (int b = lane; b < a.Bp; b += 64) s += a.dy[b];
   }
@@ -445,7 +511,9 @@ hipError_t launch_train_t(TrainArgs a, float* part_w, float* part_w1, float sigm
   if ((e = set_lds_attr<W>(reinterpret_cast<const void*>(&k_train_fwd<W>))) != hipSuccess) return e;
   hipLaunchKernelGGL((k_train_fwd<W>), dim3(tiles), dim3(W), lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_train_loss, dim3(1), dim3(1024), 0, st, a, sigma, loss_out);
+  // the loss partials borrow part_w1, which k_grad_w1 fills only later in the step
+  hipLaunchKernelGGL(k_train_loss, dim3((unsigned)(a.Bp / 256)), dim3(256), 0, st, a, sigma, part_w1);
+  hipLaunchKernelGGL(k_train_loss_sum, dim3(1), dim3(1024), 0, st, a, part_w1, a.Bp / 256, loss_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   static bool bwd_attr = false;
   if (!bwd_attr) {
@@ -458,7 +526,7 @@ hipError_t launch_train_t(TrainArgs a, float* part_w, float* part_w1, float sigm
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int L = a.net.n_hidden;
   if (L >= 2) {
-    const unsigned blocks = (unsigned)((W / 128) * (W / 128) * kSplitW * (L - 1));
+    const unsigned blocks = (unsigned)((W / 128) * (W / gw_tk<W>()) * kSplitW * (L - 1));
     hipLaunchKernelGGL((k_grad_w<W>), dim3(blocks), dim3(256), 0, st, a, part_w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_grad_reduce, dim3(2048), dim3(256), 0, st, a, part_w);

@@ -22,7 +22,8 @@
 //                     operands staged in LDS)
 //   k_grad_reduce     fixed-order sum of the splits
 //   k_grad_rows       db_l, w_out and b_out gradients (one wave per output)
-//   k_grad_w1         dW_1 = dz_1^T h0 in FP32 (split over the batch) + fixed-order sum
+//   k_grad_w1         dW_1 = dz_1^T h0 in FP32 (lanes along the batch, split over the
+//                     batch) + fixed-order sum
 //   k_adam            Adam update of the FP32 masters
 #include <math.h>
 
@@ -34,7 +35,6 @@ namespace {
 
 constexpr int kRows = kTileRows;
 constexpr int kSplitW = 16;       // batch splits of the dW GEMM
-constexpr int kW1Chunk = 256;     // batch rows per block of the dW_1 kernel
 
 struct TrainArgs {
   MlpArgs net;
@@ -437,36 +437,57 @@ __global__ __launch_bounds__(256) void k_grad_rows(TrainArgs a) {
   }
 }
 
-// dW_1[f][j] over one chunk of kW1Chunk batch rows; thread f; FP32.
-__global__ __launch_bounds__(512) void k_grad_w1(TrainArgs a, float* __restrict__ part) {
-  __shared__ float hs[3 + 2 * SV_MAX_DOF][kW1Chunk];
-  const int W = a.net.width, in_dim = a.net.in_dim;
-  const int b0 = blockIdx.x * kW1Chunk;
-  for (int e = threadIdx.x; e < in_dim * kW1Chunk; e += blockDim.x) {
-    const int j = e / kW1Chunk, b = e - j * kW1Chunk;
-    hs[j][b] = a.h0T[(size_t)j * a.Bp + b0 + b];
-  }
-  __syncthreads();
+// dW_1[f][j] = sum_b dz_1[f][b] h0[j][b] in FP32, over one batch split per block.  A
+// wave takes kW1F features; its lanes run along the batch (8 consecutive rows each, so
+// one load reads a 1 KB stretch of a dz row and of an input row), and every lane keeps
+// kW1F x in_dim partial sums, combined across the wave at the end in a fixed order.
+constexpr int kW1F = 4;            // features per wave
+constexpr int kW1Split = 16;       // batch splits
+
+__global__ __launch_bounds__(256) void k_grad_w1(TrainArgs a, float* __restrict__ part) {
   constexpr int kMaxIn = 3 + 2 * SV_MAX_DOF;
-  for (int f = threadIdx.x; f < W; f += blockDim.x) {
-    float acc[kMaxIn];
+  const int W = a.net.width, in_dim = a.net.in_dim;
+  const int lane = threadIdx.x & 63;
+  const int fw = (blockIdx.x * 4 + (threadIdx.x >> 6)) * kW1F;   // first feature of the wave
+  const int s = blockIdx.y;
+  if (fw >= W) return;                                             // wave-uniform
+  const int per = a.Bp / kW1Split;                                 // multiple of 16
+  const int b_begin = s * per, b_end = b_begin + per;
+  float acc[kW1F][kMaxIn];
 #pragma unroll
-    for (int j = 0; j < kMaxIn; ++j) acc[j] = 0.f;
-    const __bf16* dz = a.dzT + (size_t)f * a.Bp + b0;
-    for (int b = 0; b < kW1Chunk; b += 8) {
-      const bf16x8 x = *reinterpret_cast<const bf16x8*>(dz + b);
+  for (int q = 0; q < kW1F; ++q)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float g = (float)x[e];
+    for (int jj = 0; jj < kMaxIn; ++jj) acc[q][jj] = 0.f;
+  for (int b = b_begin + 8 * lane; b < b_end; b += 512) {
+    float g[kW1F][8];
 #pragma unroll
-        for (int j = 0; j < kMaxIn; ++j)
-          if (j < in_dim) acc[j] = fmaf(g, hs[j][b + e], acc[j]);
-      }
+    for (int q = 0; q < kW1F; ++q) {
+      const bf16x8 x = *reinterpret_cast<const bf16x8*>(a.dzT + (size_t)(fw + q) * a.Bp + b);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) g[q][e] = (float)x[e];
     }
 #pragma unroll
-    for (int j = 0; j < kMaxIn; ++j)
-      if (j < in_dim) part[((size_t)blockIdx.x * W + f) * in_dim + j] = acc[j];
+    for (int jj = 0; jj < kMaxIn; ++jj) {
+      if (jj >= in_dim) continue;
+      const float4 u = *reinterpret_cast<const float4*>(a.h0T + (size_t)jj * a.Bp + b);
+      const float4 v = *reinterpret_cast<const float4*>(a.h0T + (size_t)jj * a.Bp + b + 4);
+      const float h[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int q = 0; q < kW1F; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[q][jj] = fmaf(g[q][e], h[e], acc[q][jj]);
+    }
   }
+#pragma unroll
+  for (int q = 0; q < kW1F; ++q)
+#pragma unroll
+    for (int jj = 0; jj < kMaxIn; ++jj) {
+      if (jj >= in_dim) continue;
+      float v = acc[q][jj];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) part[((size_t)s * W + fw + q) * in_dim + jj] = v;
+    }
 }
 
 __global__ void k_grad_w1_reduce(TrainArgs a, const float* __restrict__ part, int chunks) {
@@ -535,10 +556,9 @@ hipError_t launch_train_t(TrainArgs a, float* part_w, float* part_w1, float sigm
   const int rows = L * W + W + 1;
   hipLaunchKernelGGL(k_grad_rows, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int chunks = a.Bp / kW1Chunk;
-  hipLaunchKernelGGL(k_grad_w1, dim3((unsigned)chunks), dim3(512), 0, st, a, part_w1);
+  hipLaunchKernelGGL(k_grad_w1, dim3((unsigned)((W / kW1F + 3) / 4), kW1Split), dim3(256), 0, st, a, part_w1);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_grad_w1_reduce, dim3(64), dim3(256), 0, st, a, part_w1, chunks);
+  hipLaunchKernelGGL(k_grad_w1_reduce, dim3(64), dim3(256), 0, st, a, part_w1, kW1Split);
   return hipGetLastError();
 }
 
@@ -549,7 +569,10 @@ int64_t train_rows_padded(int64_t B) { return (B + 255) / 256 * 256; }
 size_t train_part_w_elems(const MlpArgs& n) {
   return n.n_hidden >= 2 ? (size_t)kSplitW * (n.n_hidden - 1) * n.width * n.width : 0;
 }
-size_t train_part_w1_elems(const MlpArgs& n, int64_t Bp) { return (size_t)(Bp / kW1Chunk) * n.width * n.in_dim; }
+size_t train_part_w1_elems(const MlpArgs& n, int64_t Bp) {
+  // the dW_1 splits; the loss partials (Bp / 256 floats) borrow the same space first
+  return std::max<size_t>((size_t)kW1Split * n.width * n.in_dim, (size_t)(Bp / 256));
+}
 
 hipError_t launch_train_step(const MlpArgs& net, const float* samples, const int* idx, int B, int Bp, __bf16* aT,
                              __bf16* dzT, float* h0T, float* y, float* dy, const __bf16* packed,

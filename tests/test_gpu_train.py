@@ -179,7 +179,9 @@ def test_training_fits_one_swept_volume(sv):
     shape = (15, 256, 4)
     mlp = sv.DeviceMLP(tr.init_params(svgen.MLPSpec(*shape), 43), *shape)
     mae0 = tr.val_mae(mlp, val)
-    log = tr.train(mlp, samples, tr.TrainRecipe(epochs=60, batch=4096, lr=1e-3), val_rows=val)
+    # 60 epochs left the held-out MAE at the edge of the bar (33.0-34.1 mm against 33.2 mm,
+    # depending on the summation order of the gradients); 120 leave a clear margin
+    log = tr.train(mlp, samples, tr.TrainRecipe(epochs=120, batch=4096, lr=1e-3), val_rows=val)
     print(f"one motion: untrained val clamped MAE {mae0 * 1e3:.1f} mm -> {log.val_mae[-1] * 1e3:.1f} mm; "
           f"loss {log.epoch_loss[0]:.4f} -> {log.epoch_loss[-1]:.4f} in {log.steps} steps")
     assert log.epoch_loss[-1] < 0.5 * log.epoch_loss[0]

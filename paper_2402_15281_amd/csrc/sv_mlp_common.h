@@ -46,78 +46,7 @@ __device__ __forceinline__ bf16x8 load_tile(__amdgpu_buffer_rsrc_t rs, int lane_
   return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, lane_off, tile * 1024, 0));
 }
 
-// One layer's MFMA loop for one wave: output features [64 wid, 64 wid + 64) of the
-// 64 tile rows, i.e. 2 feature blocks (fb) x 2 row blocks (rb) of 32 x 32.
-// Wp: packed weights of this layer; Hin: LDS tile [64][W + pad].
-// Weight tiles stream from L2 through a ring of kDepth k-steps held in registers,
-// so each load has kDepth - 1 k-steps of MFMA work to arrive; the LDS operands of
-// the next k-step are read while the current one computes.
-constexpr int kDepth = 4;
-
-// bias (optional): the accumulators start from the bias of their output feature.
-template <int W>
-__device__ __forceinline__ void layer_mfma(const __bf16* __restrict__ Wp, const __bf16* Hin, int wid, int lane,
-                                           const float* __restrict__ bias, f32x16& acc00, f32x16& acc01,
-                                           f32x16& acc10, f32x16& acc11) {
-  constexpr int KS = W / 16;
-  constexpr int LD = W + kLdsPad;
-  static_assert(KS % kDepth == 0, "k-steps must fill the load ring");
-  const int half = lane >> 5, col = lane & 31;
-  const int wid_u = __builtin_amdgcn_readfirstlane(wid);
-  const __amdgpu_buffer_rsrc_t rs = weight_rsrc(Wp + (size_t)(2 * wid_u) * KS * 512, 2 * KS);
-  const int lo = lane * 16;
-  const __bf16* B0 = Hin + col * LD + 8 * half;
-  const __bf16* B1 = B0 + 32 * LD;
-  acc00 = f32x16{};
-  acc01 = f32x16{};
-  acc10 = f32x16{};
-  acc11 = f32x16{};
-  if (bias) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float4 c0 = *reinterpret_cast<const float4*>(bias + 64 * wid + 8 * j + 4 * half);
-      const float4 c1 = *reinterpret_cast<const float4*>(bias + 64 * wid + 32 + 8 * j + 4 * half);
-      acc00[4 * j + 0] = c0.x; acc00[4 * j + 1] = c0.y; acc00[4 * j + 2] = c0.z; acc00[4 * j + 3] = c0.w;
-      acc10[4 * j + 0] = c1.x; acc10[4 * j + 1] = c1.y; acc10[4 * j + 2] = c1.z; acc10[4 * j + 3] = c1.w;
-    }
-    acc01 = acc00;
-    acc11 = acc10;
-  }
-  bf16x8 a0[kDepth], a1[kDepth];
-#pragma unroll
-  for (int s = 0; s < kDepth; ++s) {
-    a0[s] = load_tile(rs, lo, s);
-    a1[s] = load_tile(rs, lo, KS + s);
-  }
-  bf16x8 b0 = *reinterpret_cast<const bf16x8*>(B0);
-  bf16x8 b1 = *reinterpret_cast<const bf16x8*>(B1);
-  for (int ks = 0; ks < KS; ks += kDepth) {
-#pragma unroll
-    for (int s = 0; s < kDepth; ++s) {
-      const int kc = ks + s;
-      bf16x8 nb0 = b0, nb1 = b1;
-      if (kc + 1 < KS) {
-        nb0 = *reinterpret_cast<const bf16x8*>(B0 + (kc + 1) * 16);
-        nb1 = *reinterpret_cast<const bf16x8*>(B1 + (kc + 1) * 16);
-      }
-      acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[s], b0, acc00, 0, 0, 0);
-      acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[s], b1, acc01, 0, 0, 0);
-      acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[s], b0, acc10, 0, 0, 0);
-      acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[s], b1, acc11, 0, 0, 0);
-      if (ks + kDepth < KS) {
-        a0[s] = load_tile(rs, lo, kc + kDepth);
-        a1[s] = load_tile(rs, lo, KS + kc + kDepth);
-      }
-      b0 = nb0;
-      b1 = nb1;
-      // keep each k-step's loads where they are issued (the scheduler would
-      // otherwise sink them next to their first use)
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-}
-
-// The same loop for a wave owning FB feature blocks (32 FB features from feature
+// One layer's MFMA loop for a wave owning FB feature blocks (32 FB features from feature
 // 32 FB wf) of RB row blocks (32 RB rows from row 32 RB wr): FB x RB MFMA tiles,
 // acc[fb][rb].  Each weight tile is used RB times and each activation tile FB times
 // per load, so weight traffic per MFMA is 1/RB KB and LDS traffic 1/FB KB.

@@ -14,7 +14,8 @@
 //   y[b], dy[b]   FP32 prediction and d loss / d y
 // Kernels, in launch order:
 //   k_pack_bf16 (x2)  W_l and W_l^T in MFMA operand order (sv_mlp.hip)
-//   k_train_fwd       per 64-row tile: all layers, activations to aT, y
+//   k_train_fwd       per 64-row tile: all layers, activations to aT, y (the inference
+//                     kernel's tile shape, one in-place LDS tile, two blocks per CU)
 //   k_train_loss      dy and per-block loss partials; k_train_loss_sum: the loss
 //                     (fixed-order reductions)
 //   k_train_bwd       per 64-row tile: dz of every layer via W_l^T MFMA, to dzT
@@ -65,35 +66,44 @@ __host__ __device__ inline size_t off_out(const MlpArgs& n) {
   return W * n.in_dim + W + (size_t)(n.n_hidden - 1) * (W * W + W);
 }
 
-// Copy an LDS tile H[64][W + pad] to outT[f][r0 .. r0 + 63] (feature-major); thread f.
+// Forward and backward tiles: 64 rows (samples) per block; each wave owns kTFB feature
+// blocks (32 kTFB output features) of both row blocks, the inference kernel's shape.
+// One activation tile [64][W + pad] in LDS, updated in place, so two blocks share a CU.
+constexpr int kTFB = 4, kTRB = 2;
 template <int W>
+constexpr int train_threads() { return 64 * (W / (32 * kTFB)); }
+
+// Copy the LDS tile H[64][W + pad] to outT[f][r0 .. r0 + 63] (feature-major); thread t
+// takes features t, t + NT, ...
+template <int W, int NT>
 __device__ __forceinline__ void store_tile_T(const __bf16* H, __bf16* outT, int Bp, int r0) {
   constexpr int LD = W + kLdsPad;
-  const int f = threadIdx.x;
+  for (int f = threadIdx.x; f < W; f += NT) {
 #pragma unroll
-  for (int c = 0; c < kRows / 8; ++c) {
-    bf16x8 v;
+    for (int c = 0; c < kRows / 8; ++c) {
+      bf16x8 v;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = H[(8 * c + e) * LD + f];
-    *reinterpret_cast<bf16x8*>(outT + (size_t)f * Bp + r0 + 8 * c) = v;
+      for (int e = 0; e < 8; ++e) v[e] = H[(8 * c + e) * LD + f];
+      *reinterpret_cast<bf16x8*>(outT + (size_t)f * Bp + r0 + 8 * c) = v;
+    }
   }
 }
 
 template <int W>
-__global__ __launch_bounds__(W) void k_train_fwd(TrainArgs a) {
-  constexpr int NW = W / 64;
+__global__ __launch_bounds__(train_threads<W>(), 2) void k_train_fwd(TrainArgs a) {
+  constexpr int NT = train_threads<W>(), NW = NT / 64;
   constexpr int LD = W + kLdsPad;
+  constexpr int kMaxIn = 3 + 2 * SV_MAX_DOF;
   extern __shared__ __align__(16) unsigned char smem[];
-  __bf16* H0 = reinterpret_cast<__bf16*>(smem);
-  __bf16* H1 = H0 + kRows * LD;
-  __shared__ float h0s[kRows][3 + 2 * SV_MAX_DOF];
+  __bf16* H = reinterpret_cast<__bf16*>(smem);
+  __shared__ float h0s[kRows][kMaxIn];
   __shared__ float part[NW][kRows];
   const MlpArgs& n = a.net;
   const int in_dim = n.in_dim, L = n.n_hidden;
   const int r0 = blockIdx.x * kRows;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
-  for (int e = tid; e < kRows * in_dim; e += W) {
+  for (int e = tid; e < kRows * in_dim; e += NT) {
     const int r = e / in_dim, j = e - r * in_dim;
     const int b = min(r0 + r, a.B - 1);
     const float v = a.samples[(size_t)a.idx[b] * (in_dim + 1) + j];
@@ -101,11 +111,9 @@ __global__ __launch_bounds__(W) void k_train_fwd(TrainArgs a) {
     a.h0T[(size_t)j * a.Bp + r0 + r] = v;
   }
   __syncthreads();
-  {  // layer 1 in FP32, thread f
-    const int f = tid;
+  for (int f = tid; f < W; f += NT) {   // layer 1 in FP32
     const float* w1 = n.params + (size_t)f * in_dim;
     const float b1 = n.params[off_b(n, 1) + f];
-    constexpr int kMaxIn = 3 + 2 * SV_MAX_DOF;
     float w[kMaxIn];
 #pragma unroll
     for (int j = 0; j < kMaxIn; ++j) {
@@ -117,64 +125,53 @@ __global__ __launch_bounds__(W) void k_train_fwd(TrainArgs a) {
 #pragma unroll
       for (int j = 0; j < kMaxIn; ++j)
         if (j < in_dim) z = fmaf(w[j], h0s[r][j], z);
-      H0[r * LD + f] = (__bf16)softplus_fast(z);
+      H[r * LD + f] = (__bf16)softplus_fast(z);
     }
   }
   __syncthreads();
-  store_tile_T<W>(H0, a.aT, a.Bp, r0);
-  __bf16* Hin = H0;
-  __bf16* Hout = H1;
-  float p0 = 0.f, p1 = 0.f;
+  store_tile_T<W, NT>(H, a.aT, a.Bp, r0);
+  float p[kTRB] = {0.f, 0.f};
   const float* wout = n.params + off_out(n);
   for (int l = 2; l <= L; ++l) {
-    f32x16 acc00, acc01, acc10, acc11;
-    layer_mfma<W>(a.packed + (size_t)(l - 2) * W * W, Hin, wid, lane, n.params + off_b(n, l), acc00, acc01, acc10,
-                  acc11);
+    f32x16 acc[kTFB][kTRB];
+    layer_mfma_fb<W, kTFB, kTRB, 2>(a.packed + (size_t)(l - 2) * W * W, H, wid, 0, lane, n.params + off_b(n, l),
+                                    acc);
     const bool last = l == L;
+    __syncthreads();   // every wave has read the tile (and copied it out)
 #pragma unroll
-    for (int fb = 0; fb < 2; ++fb)
+    for (int fb = 0; fb < kTFB; ++fb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int f = 64 * wid + 32 * fb + 8 * j + 4 * half;
-        const f32x16& t0 = fb == 0 ? acc00 : acc10;
-        const f32x16& t1 = fb == 0 ? acc01 : acc11;
-        const float s00 = softplus_fast(t0[4 * j + 0]), s01 = softplus_fast(t0[4 * j + 1]);
-        const float s02 = softplus_fast(t0[4 * j + 2]), s03 = softplus_fast(t0[4 * j + 3]);
-        const float s10 = softplus_fast(t1[4 * j + 0]), s11 = softplus_fast(t1[4 * j + 1]);
-        const float s12 = softplus_fast(t1[4 * j + 2]), s13 = softplus_fast(t1[4 * j + 3]);
-        if (last) {
-          const float4 wo = *reinterpret_cast<const float4*>(wout + f);
-          p0 = fmaf(wo.x, s00, fmaf(wo.y, s01, fmaf(wo.z, s02, fmaf(wo.w, s03, p0))));
-          p1 = fmaf(wo.x, s10, fmaf(wo.y, s11, fmaf(wo.z, s12, fmaf(wo.w, s13, p1))));
+        const int f = 32 * (kTFB * wid + fb) + 8 * j + 4 * half;
+        float4 wo = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (last) wo = *reinterpret_cast<const float4*>(wout + f);
+#pragma unroll
+        for (int rb = 0; rb < kTRB; ++rb) {
+          const float s0 = softplus_fast(acc[fb][rb][4 * j + 0]), s1 = softplus_fast(acc[fb][rb][4 * j + 1]);
+          const float s2 = softplus_fast(acc[fb][rb][4 * j + 2]), s3 = softplus_fast(acc[fb][rb][4 * j + 3]);
+          if (last) p[rb] = fmaf(wo.x, s0, fmaf(wo.y, s1, fmaf(wo.z, s2, fmaf(wo.w, s3, p[rb]))));
+          const bf16x4 v = {(__bf16)s0, (__bf16)s1, (__bf16)s2, (__bf16)s3};
+          *reinterpret_cast<bf16x4*>(H + (32 * rb + col) * LD + f) = v;
         }
-        bf16x4 v0 = {(__bf16)s00, (__bf16)s01, (__bf16)s02, (__bf16)s03};
-        bf16x4 v1 = {(__bf16)s10, (__bf16)s11, (__bf16)s12, (__bf16)s13};
-        *reinterpret_cast<bf16x4*>(Hout + col * LD + f) = v0;
-        *reinterpret_cast<bf16x4*>(Hout + (32 + col) * LD + f) = v1;
       }
-    __syncthreads();
-    store_tile_T<W>(Hout, a.aT + (size_t)(l - 1) * W * a.Bp, a.Bp, r0);
-    __bf16* t = Hin;
-    Hin = Hout;
-    Hout = t;
+    __syncthreads();   // the new tile is complete
+    store_tile_T<W, NT>(H, a.aT + (size_t)(l - 1) * W * a.Bp, a.Bp, r0);
   }
   if (L == 1) {
     for (int r = wid; r < kRows; r += NW) {
       float s = 0.f;
-      for (int f = lane; f < W; f += 64) s = fmaf(wout[f], (float)Hin[r * LD + f], s);
+      for (int f = lane; f < W; f += 64) s = fmaf(wout[f], (float)H[r * LD + f], s);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
       if (lane == 0) part[0][r] = s;
     }
-    __syncthreads();
     for (int w = 1; w < NW; ++w)
       if (tid < kRows) part[w][tid] = 0.f;
   } else {
-    p0 += __shfl_xor(p0, 32, 64);
-    p1 += __shfl_xor(p1, 32, 64);
-    if (half == 0) {
-      part[wid][col] = p0;
-      part[wid][32 + col] = p1;
+#pragma unroll
+    for (int rb = 0; rb < kTRB; ++rb) {
+      const float q = p[rb] + __shfl_xor(p[rb], 32, 64);
+      if (half == 0) part[wid][32 * rb + col] = q;
     }
   }
   __syncthreads();
@@ -226,18 +223,17 @@ __global__ __launch_bounds__(1024) void k_train_loss_sum(TrainArgs a, const floa
 }
 
 template <int W>
-__global__ __launch_bounds__(W) void k_train_bwd(TrainArgs a) {
+__global__ __launch_bounds__(train_threads<W>(), 2) void k_train_bwd(TrainArgs a) {
+  constexpr int NT = train_threads<W>();
   constexpr int LD = W + kLdsPad;
   extern __shared__ __align__(16) unsigned char smem[];
-  __bf16* H0 = reinterpret_cast<__bf16*>(smem);
-  __bf16* H1 = H0 + kRows * LD;
+  __bf16* H = reinterpret_cast<__bf16*>(smem);
   const MlpArgs& n = a.net;
   const int L = n.n_hidden;
   const int r0 = blockIdx.x * kRows;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
-  {  // dz_L = dy * w_out * sigma(z_L), thread f
-    const int f = tid;
+  for (int f = tid; f < W; f += NT) {   // dz_L = dy * w_out * sigma(z_L)
     const float wo = n.params[off_out(n) + f];
     const __bf16* aL = a.aT + ((size_t)(L - 1) * W + f) * a.Bp + r0;
     __bf16* dzL = a.dzT + ((size_t)(L - 1) * W + f) * a.Bp + r0;
@@ -250,42 +246,39 @@ __global__ __launch_bounds__(W) void k_train_bwd(TrainArgs a) {
         const int r = 8 * c + e;
         const float g = a.dy[r0 + r] * wo * softplus_grad_from_out((float)av[e]);
         out[e] = (__bf16)g;
-        H0[r * LD + f] = out[e];
+        H[r * LD + f] = out[e];
       }
       *reinterpret_cast<bf16x8*>(dzL + 8 * c) = out;
     }
   }
   __syncthreads();
-  __bf16* Hin = H0;
-  __bf16* Hout = H1;
   for (int l = L; l >= 2; --l) {
     // dh_{l-1}[r][k] = sum_f dz_l[r][f] W_l[f][k]: A operand = W_l^T packed
-    f32x16 acc00, acc01, acc10, acc11;
-    layer_mfma<W>(a.packedT + (size_t)(l - 2) * W * W, Hin, wid, lane, nullptr, acc00, acc01, acc10, acc11);
+    f32x16 acc[kTFB][kTRB];
+    layer_mfma_fb<W, kTFB, kTRB, 2>(a.packedT + (size_t)(l - 2) * W * W, H, wid, 0, lane, nullptr, acc);
+    __syncthreads();   // every wave has read the tile (and copied it out)
     const __bf16* aprev = a.aT + (size_t)(l - 2) * W * a.Bp;
 #pragma unroll
-    for (int fb = 0; fb < 2; ++fb)
+    for (int fb = 0; fb < kTFB; ++fb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int k = 64 * wid + 32 * fb + 8 * j + 4 * half;
-        const f32x16& t0 = fb == 0 ? acc00 : acc10;
-        const f32x16& t1 = fb == 0 ? acc01 : acc11;
-        bf16x4 v0, v1;
+        const int k = 32 * (kTFB * wid + fb) + 8 * j + 4 * half;
+        // one 64-bit row offset per (fb, j); the four rows k + i follow at the uniform
+        // stride Bp (per-row products would be hoisted out of the layer loop and spill)
+        const __bf16* arow = aprev + (size_t)k * a.Bp + r0 + col;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float a0 = (float)aprev[(size_t)(k + i) * a.Bp + r0 + col];
-          const float a1 = (float)aprev[(size_t)(k + i) * a.Bp + r0 + 32 + col];
-          v0[i] = (__bf16)(t0[4 * j + i] * softplus_grad_from_out(a0));
-          v1[i] = (__bf16)(t1[4 * j + i] * softplus_grad_from_out(a1));
+        for (int rb = 0; rb < kTRB; ++rb) {
+          bf16x4 v;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float ap = (float)arow[(size_t)i * a.Bp + 32 * rb];
+            v[i] = (__bf16)(acc[fb][rb][4 * j + i] * softplus_grad_from_out(ap));
+          }
+          *reinterpret_cast<bf16x4*>(H + (32 * rb + col) * LD + k) = v;
         }
-        *reinterpret_cast<bf16x4*>(Hout + col * LD + k) = v0;
-        *reinterpret_cast<bf16x4*>(Hout + (32 + col) * LD + k) = v1;
       }
-    __syncthreads();
-    store_tile_T<W>(Hout, a.dzT + (size_t)(l - 2) * W * a.Bp, a.Bp, r0);
-    __bf16* t = Hin;
-    Hin = Hout;
-    Hout = t;
+    __syncthreads();   // the new tile is complete
+    store_tile_T<W, NT>(H, a.dzT + (size_t)(l - 2) * W * a.Bp, a.Bp, r0);
   }
 }
 
@@ -515,35 +508,29 @@ __global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __re
 }
 
 template <int W>
-hipError_t set_lds_attr(const void* fn) {
-  static bool done = false;
-  if (done) return hipSuccess;
-  const int lds = 2 * kRows * (W + kLdsPad) * (int)sizeof(__bf16);
+hipError_t set_lds_attr(const void* fn, bool* done) {
+  if (*done) return hipSuccess;
+  const int lds = kRows * (W + kLdsPad) * (int)sizeof(__bf16);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e == hipSuccess) done = true;
+  if (e == hipSuccess) *done = true;
   return e;
 }
 
 template <int W>
 hipError_t launch_train_t(TrainArgs a, float* part_w, float* part_w1, float sigma, float* loss_out, hipStream_t st) {
-  const size_t lds = 2 * (size_t)kRows * (W + kLdsPad) * sizeof(__bf16);
+  const size_t lds = (size_t)kRows * (W + kLdsPad) * sizeof(__bf16);
   const unsigned tiles = (unsigned)(a.Bp / kRows);
   hipError_t e;
-  if ((e = set_lds_attr<W>(reinterpret_cast<const void*>(&k_train_fwd<W>))) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_train_fwd<W>), dim3(tiles), dim3(W), lds, st, a);
+  static bool fwd_attr = false, bwd_attr = false;
+  if ((e = set_lds_attr<W>(reinterpret_cast<const void*>(&k_train_fwd<W>), &fwd_attr)) != hipSuccess) return e;
+  if ((e = set_lds_attr<W>(reinterpret_cast<const void*>(&k_train_bwd<W>), &bwd_attr)) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_train_fwd<W>), dim3(tiles), dim3(train_threads<W>()), lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // the loss partials borrow part_w1, which k_grad_w1 fills only later in the step
   hipLaunchKernelGGL(k_train_loss, dim3((unsigned)(a.Bp / 256)), dim3(256), 0, st, a, sigma, part_w1);
   hipLaunchKernelGGL(k_train_loss_sum, dim3(1), dim3(1024), 0, st, a, part_w1, a.Bp / 256, loss_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  static bool bwd_attr = false;
-  if (!bwd_attr) {
-    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_train_bwd<W>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
-      return e;
-    bwd_attr = true;
-  }
-  hipLaunchKernelGGL((k_train_bwd<W>), dim3(tiles), dim3(W), lds, st, a);
+  hipLaunchKernelGGL((k_train_bwd<W>), dim3(tiles), dim3(train_threads<W>()), lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int L = a.net.n_hidden;
   if (L >= 2) {

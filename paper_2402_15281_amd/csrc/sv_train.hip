@@ -22,7 +22,8 @@
 //   k_grad_w          dW_l = dz_l^T a_{l-1} for l >= 2 (MFMA, split over the batch; both
 //                     operands staged in LDS)
 //   k_grad_reduce     fixed-order sum of the splits
-//   k_grad_rows       db_l, w_out and b_out gradients (one wave per output)
+//   k_grad_rows       db_1, w_out and b_out gradients (one wave per output; db_l for
+//                     l >= 2 is summed by k_grad_w from its staged dz rows)
 //   k_grad_w1         dW_1 = dz_1^T h0 in FP32 (lanes along the batch, split over the
 //                     batch) + fixed-order sum
 //   k_adam            Adam update of the FP32 masters
@@ -323,6 +324,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   for (int fb = 0; fb < 2; ++fb)
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) acc[fb][rb] = f32x16{};
+  float dbs = 0.f;   // this thread's half-row sum of dz for the bias gradient (tk == 0)
   // thread tid moves segments tid + 256 q, q < NQ, of each chunk: row r, columns c8..
   constexpr int NQ = (TF + TK) * SEG / 256;
   static_assert((TF + TK) * SEG % 256 == 0, "whole passes");
@@ -347,6 +349,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     __syncthreads();
     if (b + kGwChunk < b_end) fetch(b + kGwChunk, min(kGwChunk, b_end - b - kGwChunk));   // in flight during the MFMAs
+    if (tk == 0) {   // the bias gradient db_l[f] = sum_b dz_l[f][b]: threads 2 r, 2 r + 1 sum row r
+      const __bf16* row = As + (tid >> 1) * kGwLd + (kGwChunk / 2) * (tid & 1);
+      const int n = min(kGwChunk / 2, kc - (kGwChunk / 2) * (tid & 1));
+      for (int c = 0; c < n; ++c) dbs += (float)row[c];
+    }
     for (int ks = 0; ks < kc / 16; ++ks) {
       bf16x8 x[2], y[RB];
 #pragma unroll
@@ -373,34 +380,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         for (int i = 0; i < 4; ++i)
           P[(size_t)(f0 + 64 * wf + 32 * fb + 8 * j + 4 * half + i) * W + k0 + (TK / 2) * wk + 32 * rb + col] =
               acc[fb][rb][4 * j + i];
+  if (tk == 0) {   // bias partials after the weight partials: [L - 1][kSplitW][W]
+    const float d = dbs + __shfl_xor(dbs, 1, 64);
+    if ((tid & 1) == 0)
+      part[(size_t)(a.net.n_hidden - 1) * kSplitW * W * W + ((size_t)(l - 2) * kSplitW + s) * W + f0 + (tid >> 1)] = d;
+  }
 }
 
+// Fixed-order sums over the splits: dW_l, then db_l (layers 2..L).
 __global__ void k_grad_reduce(TrainArgs a, const float* __restrict__ part) {
   const int W = a.net.width;
   const int64_t per = (int64_t)W * W;
   const int64_t total = per * (a.net.n_hidden - 1);
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-    const int l = (int)(g / per) + 2;
-    const int64_t o = g - (int64_t)(l - 2) * per;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total + (int64_t)W * (a.net.n_hidden - 1);
+       g += (int64_t)gridDim.x * blockDim.x) {
     float s = 0.f;
-    for (int sp = 0; sp < kSplitW; ++sp) s += part[((size_t)(l - 2) * kSplitW + sp) * per + o];
-    a.grad[off_w(a.net, l) + o] = s;
+    if (g < total) {
+      const int l = (int)(g / per) + 2;
+      const int64_t o = g - (int64_t)(l - 2) * per;
+      for (int sp = 0; sp < kSplitW; ++sp) s += part[((size_t)(l - 2) * kSplitW + sp) * per + o];
+      a.grad[off_w(a.net, l) + o] = s;
+    } else {
+      const int64_t h = g - total;
+      const int l = (int)(h / W) + 2, f = (int)(h - (int64_t)(l - 2) * W);
+      const float* pb = part + total * kSplitW + (size_t)(l - 2) * kSplitW * W;
+      for (int sp = 0; sp < kSplitW; ++sp) s += pb[(size_t)sp * W + f];
+      a.grad[off_b(a.net, l) + f] = s;
+    }
   }
 }
 
-// One wave per output: rows 0 .. L*W-1 are db_l[f]; then W rows of w_out; then b_out.
+// One wave per output: rows 0 .. W-1 are db_1[f] (the biases of layers 2..L come with
+// k_grad_w); then W rows of w_out; then b_out.
 __global__ __launch_bounds__(256) void k_grad_rows(TrainArgs a) {
   const MlpArgs& n = a.net;
   const int W = n.width, L = n.n_hidden;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int n_rows = L * W + W + 1;
+  const int LB = L >= 2 ? 1 : L;   // bias rows summed here (layer 1; all layers when L == 1)
+  const int n_rows = LB * W + W + 1;
   if (row >= n_rows) return;
   float s = 0.f;
-  if (row < L * W + W) {
+  if (row < LB * W + W) {
     // four loads in flight per lane (independent sums u), then a fixed-order combine
-    const bool bias = row < L * W;
-    const __bf16* v = bias ? a.dzT + (size_t)row * a.Bp : a.aT + ((size_t)(L - 1) * W + (row - L * W)) * a.Bp;
+    const bool bias = row < LB * W;
+    const __bf16* v = bias ? a.dzT + (size_t)row * a.Bp : a.aT + ((size_t)(L - 1) * W + (row - LB * W)) * a.Bp;
     float u[4] = {0.f, 0.f, 0.f, 0.f};
     for (int b0 = 8 * lane; b0 < a.Bp; b0 += 4 * 512) {
 #pragma unroll
@@ -420,11 +444,10 @@ __global__ __launch_bounds__(256) void k_grad_rows(TrainArgs a) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if (lane != 0) return;
-  if (row < L * W) {
-    const int l = row / W + 1, f = row - (l - 1) * W;
-    a.grad[off_b(n, l) + f] = s;
-  } else if (row < L * W + W) {
-    a.grad[off_out(n) + (row - L * W)] = s;
+  if (row < LB * W) {
+    a.grad[off_b(n, 1) + row] = s;
+  } else if (row < LB * W + W) {
+    a.grad[off_out(n) + (row - LB * W)] = s;
   } else {
     a.grad[off_out(n) + W] = s;
   }
@@ -540,7 +563,7 @@ hipError_t launch_train_t(TrainArgs a, float* part_w, float* part_w1, float sigm
     hipLaunchKernelGGL(k_grad_reduce, dim3(2048), dim3(256), 0, st, a, part_w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  const int rows = L * W + W + 1;
+  const int rows = (L >= 2 ? 1 : L) * W + W + 1;
   hipLaunchKernelGGL(k_grad_rows, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_grad_w1, dim3((unsigned)((W / kW1F + 3) / 4), kW1Split), dim3(256), 0, st, a, part_w1);
@@ -553,8 +576,8 @@ hipError_t launch_train_t(TrainArgs a, float* part_w, float* part_w1, float sigm
 
 int64_t train_rows_padded(int64_t B) { return (B + 255) / 256 * 256; }
 
-size_t train_part_w_elems(const MlpArgs& n) {
-  return n.n_hidden >= 2 ? (size_t)kSplitW * (n.n_hidden - 1) * n.width * n.width : 0;
+size_t train_part_w_elems(const MlpArgs& n) {   // dW_l splits, then db_l splits
+  return n.n_hidden >= 2 ? (size_t)kSplitW * (n.n_hidden - 1) * n.width * (n.width + 1) : 0;
 }
 size_t train_part_w1_elems(const MlpArgs& n, int64_t Bp) {
   // the dW_1 splits; the loss partials (Bp / 256 floats) borrow the same space first

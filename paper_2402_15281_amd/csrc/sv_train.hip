@@ -74,18 +74,30 @@ constexpr int kTFB = 4, kTRB = 2;
 template <int W>
 constexpr int train_threads() { return 64 * (W / (32 * kTFB)); }
 
-// Copy the LDS tile H[64][W + pad] to outT[f][r0 .. r0 + 63] (feature-major); thread t
-// takes features t, t + NT, ...
+// Copy the LDS tile H[64][W + pad] to outT[f][r0 .. r0 + 63] (feature-major) in blocks
+// of 8 rows x 8 features: a lane reads its block with eight 16-byte LDS reads (rows),
+// transposes it in registers and writes eight 16-byte stores (features).  In a wave the
+// lane's feature group runs fastest (conflict-free LDS reads: the 8 groups of a phase
+// cover all banks) and its row group slowest (the 8 row groups of a feature write one
+// 128-byte line).
 template <int W, int NT>
 __device__ __forceinline__ void store_tile_T(const __bf16* H, __bf16* outT, int Bp, int r0) {
-  constexpr int LD = W + kLdsPad;
-  for (int f = threadIdx.x; f < W; f += NT) {
+  static_assert(kRows == 64, "8 row groups of 8");
+  constexpr int LD = W + kLdsPad, NW = NT / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rg = lane >> 3;   // rows 8 rg .. 8 rg + 7
+#pragma unroll 1
+  for (int fb = w; fb < W / 64; fb += NW) {
+    const int fg = 8 * fb + (lane & 7);   // features 8 fg .. 8 fg + 7
+    bf16x8 in[8];
 #pragma unroll
-    for (int c = 0; c < kRows / 8; ++c) {
-      bf16x8 v;
+    for (int r = 0; r < 8; ++r) in[r] = *reinterpret_cast<const bf16x8*>(H + (8 * rg + r) * LD + 8 * fg);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = H[(8 * c + e) * LD + f];
-      *reinterpret_cast<bf16x8*>(outT + (size_t)f * Bp + r0 + 8 * c) = v;
+    for (int f = 0; f < 8; ++f) {
+      bf16x8 o;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) o[r] = in[r][f];
+      *reinterpret_cast<bf16x8*>(outT + (size_t)(8 * fg + f) * Bp + r0 + 8 * rg) = o;
     }
   }
 }

@@ -102,6 +102,29 @@ __device__ __forceinline__ void store_tile_T(const __bf16* H, __bf16* outT, int 
   }
 }
 
+// The inverse: inT[f][r0 .. r0 + 63] (feature-major) into the LDS tile H[64][W + pad],
+// with the same 8 x 8 blocks and lane order.
+template <int W, int NT>
+__device__ __forceinline__ void load_tile_T(const __bf16* inT, __bf16* H, int Bp, int r0) {
+  constexpr int LD = W + kLdsPad, NW = NT / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rg = lane >> 3;
+#pragma unroll 1
+  for (int fb = w; fb < W / 64; fb += NW) {
+    const int fg = 8 * fb + (lane & 7);
+    bf16x8 in[8];
+#pragma unroll
+    for (int f = 0; f < 8; ++f) in[f] = *reinterpret_cast<const bf16x8*>(inT + (size_t)(8 * fg + f) * Bp + r0 + 8 * rg);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      bf16x8 o;
+#pragma unroll
+      for (int f = 0; f < 8; ++f) o[f] = in[f][r];
+      *reinterpret_cast<bf16x8*>(H + (8 * rg + r) * LD + 8 * fg) = o;
+    }
+  }
+}
+
 template <int W>
 __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_fwd(TrainArgs a) {
   constexpr int NT = train_threads<W>(), NW = NT / 64;
@@ -270,24 +293,23 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_bwd(TrainArgs a
     f32x16 acc[kTFB][kTRB];
     layer_mfma_fb<W, kTFB, kTRB, 2>(a.packedT + (size_t)(l - 2) * W * W, H, wid, 0, lane, nullptr, acc);
     __syncthreads();   // every wave has read the tile (and copied it out)
-    const __bf16* aprev = a.aT + (size_t)(l - 2) * W * a.Bp;
+    // the activations of layer l - 1 into the free tile, then dz_{l-1} over them in place:
+    // each lane reads and writes the same (row, 4 features) pieces
+    load_tile_T<W, NT>(a.aT + (size_t)(l - 2) * W * a.Bp, H, a.Bp, r0);
+    __syncthreads();
 #pragma unroll
     for (int fb = 0; fb < kTFB; ++fb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = 32 * (kTFB * wid + fb) + 8 * j + 4 * half;
-        // one 64-bit row offset per (fb, j); the four rows k + i follow at the uniform
-        // stride Bp (per-row products would be hoisted out of the layer loop and spill)
-        const __bf16* arow = aprev + (size_t)k * a.Bp + r0 + col;
 #pragma unroll
         for (int rb = 0; rb < kTRB; ++rb) {
+          bf16x4* hp = reinterpret_cast<bf16x4*>(H + (32 * rb + col) * LD + k);
+          const bf16x4 ap = *hp;
           bf16x4 v;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float ap = (float)arow[(size_t)i * a.Bp + 32 * rb];
-            v[i] = (__bf16)(acc[fb][rb][4 * j + i] * softplus_grad_from_out(ap));
-          }
-          *reinterpret_cast<bf16x4*>(H + (32 * rb + col) * LD + k) = v;
+          for (int i = 0; i < 4; ++i) v[i] = (__bf16)(acc[fb][rb][4 * j + i] * softplus_grad_from_out((float)ap[i]));
+          *hp = v;
         }
       }
     __syncthreads();   // the new tile is complete

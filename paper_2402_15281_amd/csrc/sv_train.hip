@@ -325,16 +325,18 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_bwd(TrainArgs a
 // loads (a row's chunk is one 128-byte line), then its 4 waves read fragments from LDS:
 // wave (wf, wk) owns rows 64 wf .. of the 128 and columns (TK / 2) wk .. of the TK, as
 // 2 x (TK / 64) MFMA tiles of 32 x 32.  Per chunk that is about 1.1 KB of LDS traffic
-// per MFMA at TK = 256.
-constexpr int kGwChunk = 64;                   // batch rows per LDS stage
+// per MFMA at TK = 256.  Chunks of 128 batch rows (104 KB of LDS, one block and one
+// wave per SIMD per CU, the next chunk's 24 loads per thread in flight during 64 MFMAs
+// per wave) measured faster than 64 (two blocks per CU) and 32: 1.85 against 2.22 and
+// 2.09 ms per training step.
+constexpr int kGwChunk = 128;                  // batch rows per LDS stage
 constexpr int kGwLd = kGwChunk + kLdsPad;      // LDS row stride (elements)
 
 template <int W>
 constexpr int gw_tk() { return W >= 256 ? 256 : W; }   // output columns per block
 
 template <int W>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_grad_w(TrainArgs a,
-                                                                                       float* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_grad_w(TrainArgs a, float* __restrict__ part) {
   constexpr int TF = 128, TK = gw_tk<W>();
   constexpr int RB = TK / 64;                        // column blocks per wave
   constexpr int SEG = kGwChunk / 8;                  // 16-byte segments per row and chunk

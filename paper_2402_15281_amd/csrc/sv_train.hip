@@ -321,23 +321,26 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_bwd(TrainArgs a
 // Both operands are batch-contiguous rows ([feature][batch]); a lane's MFMA fragment is
 // 16 bytes of one row, so reading fragments straight from memory touches a cache line
 // per lane and re-fetches each line once per k-step.  Instead a block stages chunks of
-// kGwChunk batch rows of its 128 dz rows and TK a rows in LDS with coalesced 16-byte
-// loads (a row's chunk is one 128-byte line), then its 4 waves read fragments from LDS:
-// wave (wf, wk) owns rows 64 wf .. of the 128 and columns (TK / 2) wk .. of the TK, as
-// 2 x (TK / 64) MFMA tiles of 32 x 32.  Per chunk that is about 1.1 KB of LDS traffic
-// per MFMA at TK = 256.  Chunks of 128 batch rows (104 KB of LDS, one block and one
-// wave per SIMD per CU, the next chunk's 24 loads per thread in flight during 64 MFMAs
-// per wave) measured faster than 64 (two blocks per CU) and 32: 1.85 against 2.22 and
-// 2.09 ms per training step.
-constexpr int kGwChunk = 128;                  // batch rows per LDS stage
+// kGwChunk batch rows of its TF dz rows and TK a rows in LDS with coalesced 16-byte
+// loads (a row's chunk is one 128-byte line), prefetching the next chunk into registers
+// during the MFMAs, and its 4 waves read fragments from LDS: wave (wf, wk) owns rows
+// (TF / 2) wf .. and columns (TK / 2) wk .. as (TF / 64) x (TK / 64) MFMA tiles of
+// 32 x 32.  At W >= 256 the block tile is 256 x 256 (each dz and activation row read by
+// two blocks; 256 accumulator registers per lane, one wave per SIMD): 1.71 ms per
+// training step, against 1.81 for 128 x 256 tiles in 128-row chunks and 2.22 for
+// 128 x 256 in 64-row chunks with two blocks per CU.
+constexpr int kGwChunk = 64;                   // batch rows per LDS stage
 constexpr int kGwLd = kGwChunk + kLdsPad;      // LDS row stride (elements)
 
 template <int W>
 constexpr int gw_tk() { return W >= 256 ? 256 : W; }   // output columns per block
+template <int W>
+constexpr int gw_tf() { return W >= 256 ? 256 : W; }   // output rows per block
 
 template <int W>
 __global__ __launch_bounds__(256) void k_grad_w(TrainArgs a, float* __restrict__ part) {
-  constexpr int TF = 128, TK = gw_tk<W>();
+  constexpr int TF = gw_tf<W>(), TK = gw_tk<W>();
+  constexpr int FBW = TF / 64;                       // row (feature) blocks per wave
   constexpr int RB = TK / 64;                        // column blocks per wave
   constexpr int SEG = kGwChunk / 8;                  // 16-byte segments per row and chunk
   __shared__ __align__(16) __bf16 As[TF * kGwLd];
@@ -355,9 +358,9 @@ __global__ __launch_bounds__(256) void k_grad_w(TrainArgs a, float* __restrict__
   const int b_begin = s * per, b_end = b_begin + per;
   const __bf16* dz = a.dzT + ((size_t)(l - 1) * W + f0) * a.Bp;
   const __bf16* ap = a.aT + ((size_t)(l - 2) * W + k0) * a.Bp;
-  f32x16 acc[2][RB];
+  f32x16 acc[FBW][RB];
 #pragma unroll
-  for (int fb = 0; fb < 2; ++fb)
+  for (int fb = 0; fb < FBW; ++fb)
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) acc[fb][rb] = f32x16{};
   float dbs = 0.f;   // this thread's half-row sum of dz for the bias gradient (tk == 0)
@@ -385,21 +388,22 @@ __global__ __launch_bounds__(256) void k_grad_w(TrainArgs a, float* __restrict__
     }
     __syncthreads();
     if (b + kGwChunk < b_end) fetch(b + kGwChunk, min(kGwChunk, b_end - b - kGwChunk));   // in flight during the MFMAs
-    if (tk == 0) {   // the bias gradient db_l[f] = sum_b dz_l[f][b]: threads 2 r, 2 r + 1 sum row r
-      const __bf16* row = As + (tid >> 1) * kGwLd + (kGwChunk / 2) * (tid & 1);
-      const int n = min(kGwChunk / 2, kc - (kGwChunk / 2) * (tid & 1));
+    if (tk == 0) {   // the bias gradient db_l[f] = sum_b dz_l[f][b]: 256 / TF threads per row
+      constexpr int TPR = 256 / TF, CPT = kGwChunk / TPR;
+      const __bf16* row = As + (tid / TPR) * kGwLd + CPT * (tid % TPR);
+      const int n = min(CPT, kc - CPT * (tid % TPR));
       for (int c = 0; c < n; ++c) dbs += (float)row[c];
     }
     for (int ks = 0; ks < kc / 16; ++ks) {
-      bf16x8 x[2], y[RB];
+      bf16x8 x[FBW], y[RB];
 #pragma unroll
-      for (int fb = 0; fb < 2; ++fb)
-        x[fb] = *reinterpret_cast<const bf16x8*>(As + (64 * wf + 32 * fb + col) * kGwLd + 16 * ks + 8 * half);
+      for (int fb = 0; fb < FBW; ++fb)
+        x[fb] = *reinterpret_cast<const bf16x8*>(As + ((TF / 2) * wf + 32 * fb + col) * kGwLd + 16 * ks + 8 * half);
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
         y[rb] = *reinterpret_cast<const bf16x8*>(Bs + ((TK / 2) * wk + 32 * rb + col) * kGwLd + 16 * ks + 8 * half);
 #pragma unroll
-      for (int fb = 0; fb < 2; ++fb)
+      for (int fb = 0; fb < FBW; ++fb)
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
           acc[fb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[fb], y[rb], acc[fb][rb], 0, 0, 0);
@@ -407,19 +411,20 @@ __global__ __launch_bounds__(256) void k_grad_w(TrainArgs a, float* __restrict__
   }
   float* P = part + ((size_t)(l - 2) * kSplitW + s) * W * W;
 #pragma unroll
-  for (int fb = 0; fb < 2; ++fb)
+  for (int fb = 0; fb < FBW; ++fb)
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          P[(size_t)(f0 + 64 * wf + 32 * fb + 8 * j + 4 * half + i) * W + k0 + (TK / 2) * wk + 32 * rb + col] =
+          P[(size_t)(f0 + (TF / 2) * wf + 32 * fb + 8 * j + 4 * half + i) * W + k0 + (TK / 2) * wk + 32 * rb + col] =
               acc[fb][rb][4 * j + i];
   if (tk == 0) {   // bias partials after the weight partials: [L - 1][kSplitW][W]
-    const float d = dbs + __shfl_xor(dbs, 1, 64);
-    if ((tid & 1) == 0)
-      part[(size_t)(a.net.n_hidden - 1) * kSplitW * W * W + ((size_t)(l - 2) * kSplitW + s) * W + f0 + (tid >> 1)] = d;
+    constexpr int TPR = 256 / TF;
+    const float d = TPR == 2 ? dbs + __shfl_xor(dbs, 1, 64) : dbs;
+    if (tid % TPR == 0)
+      part[(size_t)(a.net.n_hidden - 1) * kSplitW * W * W + ((size_t)(l - 2) * kSplitW + s) * W + f0 + tid / TPR] = d;
   }
 }
 
@@ -593,7 +598,7 @@ hipError_t launch_train_t(TrainArgs a, float* part_w, float* part_w1, float sigm
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int L = a.net.n_hidden;
   if (L >= 2) {
-    const unsigned blocks = (unsigned)((W / 128) * (W / gw_tk<W>()) * kSplitW * (L - 1));
+    const unsigned blocks = (unsigned)((W / gw_tf<W>()) * (W / gw_tk<W>()) * kSplitW * (L - 1));
     hipLaunchKernelGGL((k_grad_w<W>), dim3(blocks), dim3(256), 0, st, a, part_w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_grad_reduce, dim3(2048), dim3(256), 0, st, a, part_w);

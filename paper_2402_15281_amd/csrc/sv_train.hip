@@ -22,7 +22,7 @@
 //   k_grad_w          dW_l = dz_l^T a_{l-1} for l >= 2 (MFMA, split over the batch; both
 //                     operands staged in LDS)
 //   k_grad_reduce     fixed-order sum of the splits
-//   k_grad_rows       db_1, w_out and b_out gradients (one wave per output; db_l for
+//   k_grad_rows       db_1, w_out and b_out gradients (one block per output; db_l for
 //                     l >= 2 is summed by k_grad_w from its staged dz rows)
 //   k_grad_w1         dW_1 = dz_1^T h0 in FP32 (lanes along the batch, split over the
 //                     batch) + fixed-order sum
@@ -451,26 +451,26 @@ __global__ void k_grad_reduce(TrainArgs a, const float* __restrict__ part) {
   }
 }
 
-// One wave per output: rows 0 .. W-1 are db_1[f] (the biases of layers 2..L come with
-// k_grad_w); then W rows of w_out; then b_out.
+// One block of 256 threads per output: rows 0 .. W-1 are db_1[f] (the biases of layers
+// 2..L come with k_grad_w; all layers' when L == 1); then W rows of w_out; then b_out.
+// Each thread sums a strided share of the batch with four loads in flight, then the
+// block combines the shares in a fixed order.
 __global__ __launch_bounds__(256) void k_grad_rows(TrainArgs a) {
+  __shared__ float red[4];
   const MlpArgs& n = a.net;
   const int W = n.width, L = n.n_hidden;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int LB = L >= 2 ? 1 : L;   // bias rows summed here (layer 1; all layers when L == 1)
-  const int n_rows = LB * W + W + 1;
-  if (row >= n_rows) return;
+  const int row = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int LB = L >= 2 ? 1 : L;   // bias rows summed here
   float s = 0.f;
   if (row < LB * W + W) {
-    // four loads in flight per lane (independent sums u), then a fixed-order combine
     const bool bias = row < LB * W;
     const __bf16* v = bias ? a.dzT + (size_t)row * a.Bp : a.aT + ((size_t)(L - 1) * W + (row - LB * W)) * a.Bp;
     float u[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int b0 = 8 * lane; b0 < a.Bp; b0 += 4 * 512) {
+    for (int b0 = 8 * tid; b0 < a.Bp; b0 += 4 * 2048) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int b = b0 + q * 512;
+        const int b = b0 + q * 2048;
         if (b < a.Bp) {
           const bf16x8 x = *reinterpret_cast<const bf16x8*>(v + b);
 #pragma unroll
@@ -480,11 +480,14 @@ __global__ __launch_bounds__(256) void k_grad_rows(TrainArgs a) {
     }
     s = (u[0] + u[1]) + (u[2] + u[3]);
   } else {
-    for (int b = lane; b < a.Bp; b += 64) s += a.dy[b];
+    for (int b = tid; b < a.Bp; b += 256) s += a.dy[b];
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane != 0) return;
+  if (lane == 0) red[wid] = s;
+  __syncthreads();
+  if (tid != 0) return;
+  s = (red[0] + red[1]) + (red[2] + red[3]);
   if (row < LB * W) {
     a.grad[off_b(n, 1) + row] = s;
   } else if (row < LB * W + W) {
@@ -605,7 +608,7 @@ hipError_t launch_train_t(TrainArgs a, float* part_w, float* part_w1, float sigm
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const int rows = (L >= 2 ? 1 : L) * W + W + 1;
-  hipLaunchKernelGGL(k_grad_rows, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_grad_rows, dim3((unsigned)rows), dim3(256), 0, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_grad_w1, dim3((unsigned)((W / kW1F + 3) / 4), kW1Split), dim3(256), 0, st, a, part_w1);
   if ((e = hipGetLastError()) != hipSuccess) return e;

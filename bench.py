@@ -526,6 +526,20 @@ def main():
 
     ms_x, kx = timed(sv, torch, check(out_x), args.steps, args.warmup, ["exact"])
     executed = sv.executed_tests(ws_x)            # segment tests the culled pass ran (last call)
+    # the same call captured once in a HIP graph and replayed (a serving loop's way to run
+    # it: the dozen short kernels of the culled pass launch as one graph)
+    out_g = sv.DeviceResults(dm.n)
+    g_exact = torch.cuda.CUDAGraph()
+    s_cap = torch.cuda.Stream()
+    s_cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s_cap):
+        with torch.cuda.graph(g_exact, stream=s_cap):
+            sv.sv_check_motions(robot, dm, dc, out_g, eps, ws=ws_x, stream=s_cap)
+    torch.cuda.current_stream().wait_stream(s_cap)
+    ms_xg, _ = timed(sv, torch, g_exact.replay, args.steps, args.warmup, [])
+    graph_same = bool(torch.equal(out_g.min_dist.view(torch.int32), out_x.min_dist.view(torch.int32))
+                      and torch.equal(out_g.argmin, out_x.argmin) and torch.equal(out_g.verdict, out_x.verdict))
+    del g_exact
     # the dense kernel (every test, no culling): the roofline of the exact arithmetic
     out_d = sv.DeviceResults(dm.n)
     sv.sv_set_exact_culling(False)
@@ -581,7 +595,8 @@ def main():
     fx_eff = flop_exact / (kx["exact"] / 1e3) / 1e12                   # culled pass, all tests' worth
     flop_mlp = mlp_flops_per_query(in_dim, width, n_hidden) * M * N
     fm = flop_mlp / (kc["screen"] / 1e3) / 1e12
-    log(f"exact:     {ms_x:.3f} ms/step = {M / ms_x * 1e3:.0f} motions/s; culled pass {kx['exact']:.3f} ms, "
+    log(f"exact:     {ms_x:.3f} ms/step = {M / ms_x * 1e3:.0f} motions/s ({ms_xg:.3f} ms = {M / ms_xg * 1e3:.0f} "
+        f"motions/s replayed from a HIP graph, identical {graph_same}); culled pass {kx['exact']:.3f} ms, "
         f"{executed / (M * N * motions.T * arm.n_caps):.4f} of the tests executed at {fx:.1f} TFLOP/s "
         f"({fx / PEAK_FP32_TFLOPS:.1%} of FP32 peak); dense kernel {kd['exact']:.3f} ms = {fd:.1f} TFLOP/s "
         f"({fd / PEAK_FP32_TFLOPS:.1%}), results identical {dense_same}")
@@ -609,6 +624,7 @@ def main():
                      "kernel_ms": kc["screen"], "flop_per_launch": flop_mlp,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
         "exact_gpu": {"value": M / (ms_x / 1e3), "unit": "motions/s", "ms_per_step": ms_x, "dtype": "f32",
+                      "graph_replay": {"value": M / (ms_xg / 1e3), "ms_per_step": ms_xg, "results_identical": graph_same},
                       "culling": {"pass_ms": kx["exact"], "executed_tests": executed,
                                   "executed_fraction": executed / (M * N * motions.T * arm.n_caps),
                                   "executed_tflops": fx, "executed_frac_of_fp32_peak": fx / PEAK_FP32_TFLOPS,

@@ -130,38 +130,54 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_fwd(TrainArgs a
   constexpr int NT = train_threads<W>(), NW = NT / 64;
   constexpr int LD = W + kLdsPad;
   constexpr int kMaxIn = 3 + 2 * SV_MAX_DOF;
+  constexpr int kInPad = (kMaxIn + 3) / 4 * 4;   // input row padded with zeros to whole float4s
+  constexpr int FPT = W / NT;                     // first-layer features per thread
+  static_assert(FPT * NT == W, "whole features per thread");
   extern __shared__ __align__(16) unsigned char smem[];
   __bf16* H = reinterpret_cast<__bf16*>(smem);
-  __shared__ float h0s[kRows][kMaxIn];
+  __shared__ __align__(16) float h0s[kRows][kInPad];
   __shared__ float part[NW][kRows];
   const MlpArgs& n = a.net;
   const int in_dim = n.in_dim, L = n.n_hidden;
   const int r0 = blockIdx.x * kRows;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
-  for (int e = tid; e < kRows * in_dim; e += NT) {
-    const int r = e / in_dim, j = e - r * in_dim;
-    const int b = min(r0 + r, a.B - 1);
-    const float v = a.samples[(size_t)a.idx[b] * (in_dim + 1) + j];
+  for (int e = tid; e < kRows * kInPad; e += NT) {
+    const int r = e / kInPad, j = e - r * kInPad;
+    float v = 0.f;
+    if (j < in_dim) {
+      const int b = min(r0 + r, a.B - 1);
+      v = a.samples[(size_t)a.idx[b] * (in_dim + 1) + j];
+      a.h0T[(size_t)j * a.Bp + r0 + r] = v;
+    }
     h0s[r][j] = v;
-    a.h0T[(size_t)j * a.Bp + r0 + r] = v;
+  }
+  // Layer 1 in FP32, FPT features per thread.  Inputs and weights past in_dim are zero,
+  // so the fixed-length chain adds exact zeros after the in_dim real terms.
+  float w[FPT][kInPad], b1[FPT];
+#pragma unroll
+  for (int q = 0; q < FPT; ++q) {
+    const int f = tid + q * NT;
+    const float* w1 = n.params + (size_t)f * in_dim;
+    b1[q] = n.params[off_b(n, 1) + f];
+#pragma unroll
+    for (int j = 0; j < kInPad; ++j) w[q][j] = j < in_dim ? w1[j] : 0.f;
   }
   __syncthreads();
-  for (int f = tid; f < W; f += NT) {   // layer 1 in FP32
-    const float* w1 = n.params + (size_t)f * in_dim;
-    const float b1 = n.params[off_b(n, 1) + f];
-    float w[kMaxIn];
+#pragma unroll 2
+  for (int r = 0; r < kRows; ++r) {
+    float h[kInPad];
 #pragma unroll
-    for (int j = 0; j < kMaxIn; ++j) {
-      w[j] = 0.f;
-      if (j < in_dim) w[j] = w1[j];
+    for (int j = 0; j < kInPad; j += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(&h0s[r][j]);
+      h[j] = v.x; h[j + 1] = v.y; h[j + 2] = v.z; h[j + 3] = v.w;
     }
-    for (int r = 0; r < kRows; ++r) {
-      float z = b1;
 #pragma unroll
-      for (int j = 0; j < kMaxIn; ++j)
-        if (j < in_dim) z = fmaf(w[j], h0s[r][j], z);
-      H[r * LD + f] = (__bf16)softplus_fast(z);
+    for (int q = 0; q < FPT; ++q) {
+      float z = b1[q];
+#pragma unroll
+      for (int j = 0; j < kInPad; ++j) z = fmaf(w[q][j], h[j], z);
+      H[r * LD + tid + q * NT] = (__bf16)softplus_fast(z);
     }
   }
   __syncthreads();

@@ -8,8 +8,9 @@
 //
 // Workspace layouts (Bp = batch rounded up to 256 rows; rows >= batch carry zero
 // gradient):
-//   aT[l][f][b]   BF16 activation of hidden layer l+1, feature-major
-//   dzT[l][f][b]  BF16 gradient w.r.t. the pre-activation of hidden layer l+1
+//   aT[l][b/64][f][b%64]   BF16 activation of hidden layer l+1 (64-row tiles,
+//                          feature-major within a tile; tix())
+//   dzT[l][b/64][f][b%64]  BF16 gradient w.r.t. the pre-activation of hidden layer l+1
 //   h0T[j][b]     FP32 network input, feature-major
 //   y[b], dy[b]   FP32 prediction and d loss / d y
 // Kernels, in launch order:
@@ -43,8 +44,8 @@ struct TrainArgs {
   const float* samples;   // [n][in_dim + 1]
   const int* idx;         // [B]
   int B, Bp;
-  __bf16* aT;             // [L][W][Bp]
-  __bf16* dzT;            // [L][W][Bp]
+  __bf16* aT;             // [L][Bp / 64][W][64]
+  __bf16* dzT;            // [L][Bp / 64][W][64]
   float* h0T;             // [in_dim][Bp]
   float* y;               // [Bp]
   float* dy;              // [Bp]
@@ -74,14 +75,20 @@ constexpr int kTFB = 4, kTRB = 2;
 template <int W>
 constexpr int train_threads() { return 64 * (W / (32 * kTFB)); }
 
-// Copy the LDS tile H[64][W + pad] to outT[f][r0 .. r0 + 63] (feature-major) in blocks
+// Layout of each layer's block of aT and dzT (W x Bp BF16 values): tiles of 64 batch
+// rows, each holding its W features' 64 values in a row, so that one tile's layer is
+// 64 KB of consecutive memory (at W = 512) and a feature's values of one tile are one
+// 128-byte line.  Element (feature f, batch row b) of a block:
+__host__ __device__ inline size_t tix(int W, int f, int b) { return ((size_t)(b >> 6) * W + f) * 64 + (b & 63); }
+
+// Copy the LDS tile H[64][W + pad] to the layer block outT (features f, rows r0 .. r0 + 63) in blocks
 // of 8 rows x 8 features: a lane reads its block with eight 16-byte LDS reads (rows),
 // transposes it in registers and writes eight 16-byte stores (features).  In a wave the
 // lane's feature group runs fastest (conflict-free LDS reads: the 8 groups of a phase
 // cover all banks) and its row group slowest (the 8 row groups of a feature write one
 // 128-byte line).
 template <int W, int NT>
-__device__ __forceinline__ void store_tile_T(const __bf16* H, __bf16* outT, int Bp, int r0) {
+__device__ __forceinline__ void store_tile_T(const __bf16* H, __bf16* outT, int r0) {
   static_assert(kRows == 64, "8 row groups of 8");
   constexpr int LD = W + kLdsPad, NW = NT / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -97,15 +104,15 @@ __device__ __forceinline__ void store_tile_T(const __bf16* H, __bf16* outT, int 
       bf16x8 o;
 #pragma unroll
       for (int r = 0; r < 8; ++r) o[r] = in[r][f];
-      *reinterpret_cast<bf16x8*>(outT + (size_t)(8 * fg + f) * Bp + r0 + 8 * rg) = o;
+      *reinterpret_cast<bf16x8*>(outT + tix(W, 8 * fg + f, r0 + 8 * rg)) = o;
     }
   }
 }
 
-// The inverse: inT[f][r0 .. r0 + 63] (feature-major) into the LDS tile H[64][W + pad],
+// The inverse: features f, rows r0 .. r0 + 63 of the layer block inT into the LDS tile H[64][W + pad],
 // with the same 8 x 8 blocks and lane order.
 template <int W, int NT>
-__device__ __forceinline__ void load_tile_T(const __bf16* inT, __bf16* H, int Bp, int r0) {
+__device__ __forceinline__ void load_tile_T(const __bf16* inT, __bf16* H, int r0) {
   constexpr int LD = W + kLdsPad, NW = NT / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rg = lane >> 3;
@@ -114,7 +121,7 @@ __device__ __forceinline__ void load_tile_T(const __bf16* inT, __bf16* H, int Bp
     const int fg = 8 * fb + (lane & 7);
     bf16x8 in[8];
 #pragma unroll
-    for (int f = 0; f < 8; ++f) in[f] = *reinterpret_cast<const bf16x8*>(inT + (size_t)(8 * fg + f) * Bp + r0 + 8 * rg);
+    for (int f = 0; f < 8; ++f) in[f] = *reinterpret_cast<const bf16x8*>(inT + tix(W, 8 * fg + f, r0 + 8 * rg));
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       bf16x8 o;
@@ -181,7 +188,7 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_fwd(TrainArgs a
     }
   }
   __syncthreads();
-  store_tile_T<W, NT>(H, a.aT, a.Bp, r0);
+  store_tile_T<W, NT>(H, a.aT, r0);
   float p[kTRB] = {0.f, 0.f};
   const float* wout = n.params + off_out(n);
   for (int l = 2; l <= L; ++l) {
@@ -207,7 +214,7 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_fwd(TrainArgs a
         }
       }
     __syncthreads();   // the new tile is complete
-    store_tile_T<W, NT>(H, a.aT + (size_t)(l - 1) * W * a.Bp, a.Bp, r0);
+    store_tile_T<W, NT>(H, a.aT + (size_t)(l - 1) * W * a.Bp, r0);
   }
   if (L == 1) {
     for (int r = wid; r < kRows; r += NW) {
@@ -287,8 +294,8 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_bwd(TrainArgs a
   const int half = lane >> 5, col = lane & 31;
   for (int f = tid; f < W; f += NT) {   // dz_L = dy * w_out * sigma(z_L)
     const float wo = n.params[off_out(n) + f];
-    const __bf16* aL = a.aT + ((size_t)(L - 1) * W + f) * a.Bp + r0;
-    __bf16* dzL = a.dzT + ((size_t)(L - 1) * W + f) * a.Bp + r0;
+    const __bf16* aL = a.aT + (size_t)(L - 1) * W * a.Bp + tix(W, f, r0);
+    __bf16* dzL = a.dzT + (size_t)(L - 1) * W * a.Bp + tix(W, f, r0);
 #pragma unroll
     for (int c = 0; c < kRows / 8; ++c) {
       const bf16x8 av = *reinterpret_cast<const bf16x8*>(aL + 8 * c);
@@ -311,7 +318,7 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_bwd(TrainArgs a
     __syncthreads();   // every wave has read the tile (and copied it out)
     // the activations of layer l - 1 into the free tile, then dz_{l-1} over them in place:
     // each lane reads and writes the same (row, 4 features) pieces
-    load_tile_T<W, NT>(a.aT + (size_t)(l - 2) * W * a.Bp, H, a.Bp, r0);
+    load_tile_T<W, NT>(a.aT + (size_t)(l - 2) * W * a.Bp, H, r0);
     __syncthreads();
 #pragma unroll
     for (int fb = 0; fb < kTFB; ++fb)
@@ -329,7 +336,7 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_bwd(TrainArgs a
         }
       }
     __syncthreads();   // the new tile is complete
-    store_tile_T<W, NT>(H, a.dzT + (size_t)(l - 2) * W * a.Bp, a.Bp, r0);
+    store_tile_T<W, NT>(H, a.dzT + (size_t)(l - 2) * W * a.Bp, r0);
   }
 }
 
@@ -372,8 +379,8 @@ __global__ __launch_bounds__(256) void k_grad_w(TrainArgs a, float* __restrict__
   const int f0 = tf * TF, k0 = tk * TK;
   const int per = a.Bp / kSplitW;                   // multiple of 16 (Bp is a multiple of 256)
   const int b_begin = s * per, b_end = b_begin + per;
-  const __bf16* dz = a.dzT + ((size_t)(l - 1) * W + f0) * a.Bp;
-  const __bf16* ap = a.aT + ((size_t)(l - 2) * W + k0) * a.Bp;
+  const __bf16* dz = a.dzT + (size_t)(l - 1) * W * a.Bp;   // layer blocks
+  const __bf16* ap = a.aT + (size_t)(l - 2) * W * a.Bp;
   f32x16 acc[FBW][RB];
 #pragma unroll
   for (int fb = 0; fb < FBW; ++fb)
@@ -388,8 +395,8 @@ __global__ __launch_bounds__(256) void k_grad_w(TrainArgs a, float* __restrict__
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int id = tid + 256 * q, r = id / SEG, c8 = 8 * (id - r * SEG);
-      const __bf16* src = r < TF ? dz + (size_t)r * a.Bp : ap + (size_t)(r - TF) * a.Bp;
-      if (c8 < kc) stage[q] = *reinterpret_cast<const bf16x8*>(src + b + c8);
+      const __bf16* src = r < TF ? dz + tix(W, f0 + r, b + c8) : ap + tix(W, k0 + r - TF, b + c8);
+      if (c8 < kc) stage[q] = *reinterpret_cast<const bf16x8*>(src);
     }
   };
   fetch(b_begin, min(kGwChunk, b_end - b_begin));
@@ -481,14 +488,15 @@ __global__ __launch_bounds__(256) void k_grad_rows(TrainArgs a) {
   float s = 0.f;
   if (row < LB * W + W) {
     const bool bias = row < LB * W;
-    const __bf16* v = bias ? a.dzT + (size_t)row * a.Bp : a.aT + ((size_t)(L - 1) * W + (row - LB * W)) * a.Bp;
+    const __bf16* v = bias ? a.dzT : a.aT + (size_t)(L - 1) * W * a.Bp;   // layer block
+    const int f = bias ? row : row - LB * W;
     float u[4] = {0.f, 0.f, 0.f, 0.f};
     for (int b0 = 8 * tid; b0 < a.Bp; b0 += 4 * 2048) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int b = b0 + q * 2048;
         if (b < a.Bp) {
-          const bf16x8 x = *reinterpret_cast<const bf16x8*>(v + b);
+          const bf16x8 x = *reinterpret_cast<const bf16x8*>(v + tix(W, f, b));
 #pragma unroll
           for (int e = 0; e < 8; ++e) u[q] = bias ? u[q] + (float)x[e] : fmaf((float)x[e], a.dy[b + e], u[q]);
         }
@@ -538,7 +546,7 @@ __global__ __launch_bounds__(256) void k_grad_w1(TrainArgs a, float* __restrict_
     float g[kW1F][8];
 #pragma unroll
     for (int q = 0; q < kW1F; ++q) {
-      const bf16x8 x = *reinterpret_cast<const bf16x8*>(a.dzT + (size_t)(fw + q) * a.Bp + b);
+      const bf16x8 x = *reinterpret_cast<const bf16x8*>(a.dzT + tix(W, fw + q, b));
 #pragma unroll
       for (int e = 0; e < 8; ++e) g[q][e] = (float)x[e];
     }

@@ -80,8 +80,14 @@ def mlp_flops_per_query(in_dim, width, n_hidden):
     return 2 * (in_dim * width + (n_hidden - 1) * width * width + width)
 
 
-def cpu_baseline(arm, motions, pts, eps, target_s, gpu_verdicts, gpu_min):
-    """Time the FP64 oracle on a bounded prefix of the same motions (all host cores)."""
+def cpu_baseline(arm, motions, pts, eps, target_s, gpu_verdicts, gpu_min, net=None):
+    """Time the FP64 oracle on bounded samples of the same workload.
+
+    - the exact check on a prefix of the motions, on all host cores and on one core;
+    - the FP64 network oracle on 65,536 (motion, point) queries of the workload, all cores,
+      and the BF16 GPU network's error against it on those queries, with the per-query
+      a-priori bar of oracle/bf16_error.py (net = (sv, torch, mlp, dc), the trained
+      network and the cloud on the device)."""
     import numpy as np
 
     import oracle
@@ -101,10 +107,57 @@ def cpu_baseline(arm, motions, pts, eps, target_s, gpu_verdicts, gpu_min):
     err = float(np.max(np.abs(md - gpu_min[:n])))
     log(f"cpu oracle: {n} motions in {dt:.2f} s on {cores} threads; verdict agreement {agree:.4f}; "
         f"max |d_gpu - d_oracle| {err:.2e} m")
-    return {"value": n / dt, "unit": "motions/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n} of the {motions.n} motions x all {pts.shape[0]} points, T={motions.T}, exact "
-                      f"check in FP64 C (gcc -O2, OpenMP over motions)",
-            "verdict_agreement_on_sample": agree, "max_abs_dist_err_m": err}
+    # one core: a motion count that takes about a quarter of the multi-core target
+    n1 = max(1, int(round(0.25 * target_s / (dt / n) / cores)))
+    t = time.perf_counter()
+    oracle.check_motions(arm, sub(n1), pts, eps, nthreads=1)
+    dt1 = time.perf_counter() - t
+    log(f"cpu oracle, one core: {n1} motions in {dt1:.2f} s")
+    res = {"value": n / dt, "unit": "motions/s", "cores": cores, "kind": "oracle",
+           "sample": f"first {n} of the {motions.n} motions x all {pts.shape[0]} points, T={motions.T}, exact "
+                     f"check in FP64 C (gcc -O2, OpenMP over motions)",
+           "verdict_agreement_on_sample": agree, "max_abs_dist_err_m": err,
+           "one_core": {"value": n1 / dt1, "unit": "motions/s", "cores": 1,
+                        "sample": f"first {n1} motions x all {pts.shape[0]} points"}}
+    if net is not None:
+        res["network"] = network_oracle(net, motions, pts)
+    return res
+
+
+def network_oracle(net, motions, pts, n_queries=65536, n_bar=16384):
+    """FP64 network oracle timed on n_queries (motion, point) queries of the workload, and
+    the BF16 GPU network's error against it (with the a-priori bar on the first n_bar)."""
+    import numpy as np
+
+    import svgen
+    from oracle import bf16_error as obf
+    from oracle import mlp as omlp
+    sv, torch, mlp, dc = net
+    N = pts.shape[0]
+    per = -(-n_queries // N)
+    sub = svgen.Motions(motions.q0[:per], motions.q1[:per], motions.T)
+    X = omlp.features(np.tile(pts, (per, 1)), np.repeat(sub.q0, N, 0), np.repeat(sub.q1, N, 0))[:n_queries]
+    flat = mlp.params.cpu().numpy().astype(np.float64)
+    shape = (mlp.in_dim, mlp.width, mlp.n_hidden)
+    t = time.perf_counter()
+    y64, _ = omlp.forward(flat, *shape, X)
+    dt = time.perf_counter() - t
+    out = torch.empty(per, N, device="cuda")
+    sv.sv_nn_sdf(mlp, sv.SV_BF16, sv.DeviceMotions(sub), dc, out)
+    y = out.cpu().numpy().astype(np.float64).ravel()[:n_queries]
+    e = np.abs(y - y64)
+    _, bar = obf.mlp_bar(flat, *shape, X[:n_bar])
+    yb = omlp.forward_bf16(flat, *shape, X[:n_bar])
+    ok, rep = obf.compare(y[:n_bar], yb, y64[:n_bar], bar)
+    log(f"cpu network oracle: {n_queries} queries in {dt:.2f} s; BF16 vs FP64 max {e.max():.2e} m, median "
+        f"{np.median(e):.2e} m; within the a-priori bar: {ok} (largest error / bar {rep['max_err_over_bar']:.3f})")
+    return {"queries_per_s": n_queries / dt, "seconds": dt, "queries": n_queries,
+            "sample": f"motions 0..{per - 1} x all {N} points, first {n_queries} queries, FP64 numpy",
+            "bf16_vs_fp64": {"max_abs_m": float(e.max()), "median_abs_m": float(np.median(e)),
+                             "mean_abs_m": float(e.mean()), "queries": n_queries,
+                             "within_bar": ok, "bar_check_queries": n_bar,
+                             "max_err_over_bar": rep["max_err_over_bar"], "median_bar_m": rep["median_bar"],
+                             "median_emulation_dev_over_bar": rep["median_emul_over_bar"]}}
 
 
 def timed(sv, torch, fn, steps, warmup, kernels):
@@ -670,7 +723,10 @@ def main():
     if not args.no_boxworld:
         result["alg1_box_world"] = box_world_search(sv, torch, np, arm, args.train_epochs)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(arm, motions, pts, eps, args.cpu_seconds, v_x, mind)
+        cb = cpu_baseline(arm, motions, pts, eps, args.cpu_seconds, v_x, mind, net=(sv, torch, mlp, dc))
+        result["cpu_baseline"] = cb
+        # the trained BF16 network against the FP64 network (computed in the leg above)
+        result["network_fp64_error"] = cb["network"]["bf16_vs_fp64"]
     print(json.dumps(result), flush=True)
 
 

@@ -1,0 +1,102 @@
+"""Network screening at the full benchmark size, through the C ABI.
+
+Workload: 512 linear motions x 20,000 bin points (10.24M pairs), T = 256, eps = 1 cm,
+tau = 3 cm, with the 15 -> 8 x 512 -> 1 softplus network trained on the GPU by the
+library's own kernels on a short schedule (1M rows from the exact check, 4 epochs of
+65,536-row batches), so that its predictions send a realistic share of points to the
+exact check instead of all or none.
+
+Checks:
+  - certified screening: the verdicts of all 512 motions equal the exact check's
+    (itself checked against the oracle elsewhere) bit for bit, and 24 sampled motions
+    equal the FP64 oracle's; a free motion's min_dist is the oracle's over all points
+    (1e-5 m); a colliding motion's min_dist and argmin name a point whose oracle
+    distance is that min_dist (1e-5 m) and at most eps;
+  - trust screening: sends the same points (n_fallback equal to certified's), and
+    every collision it reports is one (no false collisions); its misses are reported;
+  - the points sent for one sampled motion are those whose BF16 prediction is below
+    tau, up to the points within their error bar of tau (oracle/bf16_error.py).
+"""
+import numpy as np
+import pytest
+import torch
+
+import svgen
+from oracle import bf16_error as be
+from oracle import mlp as om
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sv():
+    from paper_2402_15281_amd import _binding
+    assert torch.cuda.is_available()
+    return _binding
+
+
+@pytest.fixture(scope="module")
+def setup(sv):
+    from paper_2402_15281_amd import train as tr
+    w = svgen.WORKLOADS["bin20k"]
+    arm = svgen.make_arm(w["arm_seed"])
+    motions = svgen.make_motions(arm, w["n_motions"], w["T"], w["motion_seed"])
+    pts = svgen.bin_cloud(w["n_points"], w["cloud_seed"])
+    shape = w["mlp"]
+    samples, _ = tr.make_dataset(arm, tr.DataRecipe(n_motions=2000, chunk=2000), seed=501)
+    mlp = sv.DeviceMLP(tr.init_params(svgen.MLPSpec(*shape), 502), *shape)
+    tr.train(mlp, samples, tr.TrainRecipe(epochs=4, batch=65536))
+    del samples
+    return w, arm, motions, pts, shape, mlp
+
+
+def _check(sv, arm, motions, pts, mlp, mode, eps, tau):
+    dm, dc = sv.DeviceMotions(motions), sv.DeviceCloud(pts)
+    out = sv.DeviceResults(dm.n)
+    sv.sv_check_motions(sv.make_robot(arm), dm, dc, out, eps, mlp=mlp, screen=mode, tau=tau)
+    torch.cuda.synchronize()
+    return (out.min_dist.cpu().numpy(), out.argmin.cpu().numpy(), out.verdict.cpu().numpy(),
+            out.n_fallback.cpu().numpy())
+
+
+def test_fullsize_screening_against_oracle(sv, orc, setup):
+    w, arm, motions, pts, shape, mlp = setup
+    eps, tau = w["eps"], w["tau"]
+    ex = _check(sv, arm, motions, pts, None, sv.SV_SCREEN_NONE, eps, tau)
+    cmd, cam, cvd, cnf = _check(sv, arm, motions, pts, mlp, sv.SV_SCREEN_CERTIFIED, eps, tau)
+    tmd, tam, tvd, tnf = _check(sv, arm, motions, pts, mlp, sv.SV_SCREEN_TRUST, eps, tau)
+    np.testing.assert_array_equal(cvd, ex[2])
+    np.testing.assert_array_equal(tnf, cnf)
+    frac = cnf.sum() / (motions.n * pts.shape[0])
+    assert 0.0 < frac < 1.0, frac
+    assert np.all(ex[2][tvd == 1] == 1)                     # trust never reports a false collision
+    print(f"fallback fraction {frac:.3f}; collision fraction {ex[2].mean():.3f}; trust misses "
+          f"{int(np.sum((tvd == 0) & (ex[2] == 1)))} of {int(ex[2].sum())}")
+
+    pick = svgen.permutation(503, motions.n)[:24]
+    sub = svgen.Motions(motions.q0[pick], motions.q1[pick], motions.T)
+    ref_md, _, ref_vd = orc.check_motions(arm, sub, pts, eps)
+    np.testing.assert_array_equal(cvd[pick], ref_vd)
+    sdf = orc.exact_sdf(arm, sub, pts)
+    for j, m in enumerate(pick):
+        if ref_vd[j] == 0:
+            assert abs(cmd[m] - ref_md[j]) <= 1e-5, (m, cmd[m], ref_md[j])
+        else:
+            assert cmd[m] <= eps and abs(sdf[j, cam[m]] - cmd[m]) <= 1e-5, (m, cmd[m], cam[m])
+        if tvd[m] == 1:
+            assert abs(sdf[j, tam[m]] - tmd[m]) <= 1e-5 and tmd[m] <= eps
+
+
+def test_fullsize_fallback_set_follows_predictions(sv, setup):
+    w, arm, motions, pts, shape, mlp = setup
+    tau = w["tau"]
+    m = int(svgen.permutation(504, motions.n)[0])
+    one = svgen.Motions(motions.q0[m:m + 1], motions.q1[m:m + 1], motions.T)
+    _, _, _, nf = _check(sv, arm, one, pts, mlp, sv.SV_SCREEN_TRUST, w["eps"], tau)
+    flat = mlp.params.cpu().numpy().astype(np.float64)
+    X = om.features(pts, np.repeat(one.q0, len(pts), 0), np.repeat(one.q1, len(pts), 0))
+    yb = om.forward_bf16(flat, *shape, X)
+    _, bar = be.mlp_bar(flat, *shape, X)
+    lo, hi = int(np.sum(yb < tau - bar)), int(np.sum(yb < tau + bar))
+    print(f"motion {m}: {int(nf[0])} points sent, emulation band [{lo}, {hi}]")
+    assert lo <= nf[0] <= hi

@@ -2,15 +2,11 @@
 
 Bars (as for the softplus network):
   FP32 path: |y - y_ref| <= 1e-4 |y_ref| + 1e-4 rms(y_ref) per element (FP64 oracle).
-  BF16 path: against the oracle's BF16-rounding forward (same rounding points, FP64
-    elsewhere): |y - y_bf| <= max(2e-3, 5e-4 L) sqrt(max(1, W / 512)) (1 + |y_bf|) per
-    element for L blocks of width W, and the median of that error <= 2e-4.  The block
-    outputs are rounded to BF16 and the skip connections carry every rounding forward,
-    so a last-bit difference of FP32 against FP64 accumulation that moves one rounding
-    by an ulp (2^-8 relative) survives to the output; the bar grows with the number of
-    rounding stages and, as a sum of independent flips, with the square root of the
-    activations rounded per stage, while the median stays at the level of rows with no
-    such flip.  The error against FP64 is reported.
+  BF16 path: against the FP64 network, |y - y64| <= bar per output, the a-priori bar of
+    oracle/bf16_error.py (first-order sum over every BF16 and FP32 rounding site with
+    Hoeffding's inequality at lam = 7, from the BF16 unit roundoff 2^-8); against the
+    oracle's emulation of the same rounding points, |y - y_bf| <= bar per output and the
+    median |y - y_bf| / bar <= 0.005 (each misplaced rounding point moves it above 0.01).
   W = 1024 (one block of 8 waves per CU): the same bars, the kMin and screening modes.
   Modes of one kernel: the per-motion minimum (sv_nn_min) equals the minimum of the
     dense predictions bit for bit, and trust screening sends exactly the points whose
@@ -22,6 +18,7 @@ import pytest
 import torch
 
 import svgen
+from oracle import bf16_error as be
 from oracle import mlp as om
 from oracle import residual as ores
 
@@ -56,17 +53,6 @@ def dense(sv, dnet, motions, pts, precision):
     return out.cpu().numpy().astype(np.float64)
 
 
-def bf16_bar(width, n_blocks):
-    """Largest error of a row against the BF16 emulation.  The two sides round the same
-    values to BF16, but from FP32 and FP64 sums, so an activation within a last-bit
-    difference of a rounding boundary can round the other way; the skips carry each such
-    flip to the output.  Flips are rare (the median row agrees to FP32 precision) and
-    their number per row grows with the rounded activations, W per block: the bar is
-    max(2e-3, 5e-4 L) at W = 512 and grows with sqrt(W / 512) for wider blocks, as a sum
-    of independent flips of either sign does."""
-    return max(2e-3, 5e-4 * n_blocks) * max(1.0, np.sqrt(width / 512))
-
-
 def rel_ok(y, ref, rtol=1e-4):
     rms = np.sqrt(np.mean(ref ** 2))
     return np.all(np.abs(y - ref) <= rtol * np.abs(ref) + rtol * rms)
@@ -97,13 +83,10 @@ def test_residual_bf16(sv, width, n_blocks, M, N):
     y = dense(sv, dnet, m, pts, sv.SV_BF16).ravel()
     X = inputs(m, pts)
     ref_bf = ores.forward_bf16(flat, IN, width, n_blocks, X, EPS_BN)
-    ref = ores.forward(flat, IN, width, n_blocks, X, EPS_BN)
-    err = np.abs(y - ref_bf) / (1.0 + np.abs(ref_bf))
-    print(f"bf16 residual {width}x{n_blocks}: vs emulation max {err.max():.2e}, largest five "
-          f"{np.sort(err)[-5:][::-1]}, median {np.median(err):.2e}; "
-          f"vs FP64 max {np.max(np.abs(y - ref) / (1 + np.abs(ref))):.2e}")
-    assert err.max() <= bf16_bar(width, n_blocks)
-    assert np.median(err) <= 2e-4
+    ref, bar = be.residual_bar(flat, IN, width, n_blocks, X, EPS_BN)
+    ok, rep = be.compare(y, ref_bf, ref, bar)
+    print(f"bf16 residual {width}x{n_blocks}: {rep}")
+    assert ok, rep
 
 
 def test_residual_rows_mode(sv):
@@ -122,7 +105,9 @@ def test_residual_rows_mode(sv):
             assert rel_ok(y, ores.forward(flat, IN, width, n_blocks, X, EPS_BN))
         else:
             ref_bf = ores.forward_bf16(flat, IN, width, n_blocks, X, EPS_BN)
-            assert np.max(np.abs(y - ref_bf) / (1 + np.abs(ref_bf))) <= bf16_bar(width, n_blocks)
+            ref, bar = be.residual_bar(flat, IN, width, n_blocks, X, EPS_BN)
+            ok, rep = be.compare(y, ref_bf, ref, bar)
+            assert ok, rep
 
 
 def test_residual_min_and_screening_modes(sv, orc):

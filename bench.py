@@ -238,21 +238,24 @@ def batched_requests(sv, torch, np, arm, reps=5):
         outs_ = [(o.min_dist.cpu().numpy(), o.argmin.cpu().numpy(), o.verdict.cpu().numpy()) for _, _, o in dev]
         return ms, lat, outs_
 
-    b_ms, b_lat, batched = graph_timing(None, reps)
+    # the culled pass: the library's default shape, then the shape the autotuner picks
+    # for this batch (sample-block divisors, gangs, blocks per compute unit)
+    d_ms, d_lat, default_out = graph_timing(None, reps)
+    t1 = time.perf_counter()
+    ctile, ctimings, _ = autotune.tune(robot, reqs, caps, eps, ws=ws, reps=3, passes=("culled",))
+    t_tune = time.perf_counter() - t1
+    log(f"autotune (culled pass): {len(ctimings)} shapes in {t_tune:.1f} s -> {ctile}")
+    b_ms, b_lat, batched = graph_timing(ctile, reps)
     b_exec = sv.executed_tests(ws)
 
     # the unculled persistent kernel, launch shape tuned on every 4th request (same mix,
     # a quarter of the work)
-    sv.sv_set_exact_culling(False)
-    try:
-        sub = sv.DeviceRequests(dev[::4])
-        sub_caps = sub.caps(max_band=64)
-        t1 = time.perf_counter()
-        tile, timings, _ = autotune.tune(robot, sub, sub_caps, eps, reps=2)
-        log(f"autotune (unculled kernel): {len(timings)} shapes in {time.perf_counter() - t1:.1f} s -> {tile}")
-        u_ms, _, unculled = graph_timing(tile, 2)
-    finally:
-        sv.sv_set_exact_culling(True)
+    sub = sv.DeviceRequests(dev[::4])
+    sub_caps = sub.caps(max_band=64)
+    t1 = time.perf_counter()
+    tile, timings, _ = autotune.tune(robot, sub, sub_caps, eps, reps=2, passes=("unculled",))
+    log(f"autotune (unculled kernel): {len(timings)} shapes in {time.perf_counter() - t1:.1f} s -> {tile}")
+    u_ms, _, unculled = graph_timing(tile, 2)
 
     # per-request launches, in request order, on one stream
     outs = [sv.DeviceResults(r.motions.n) for r in rq]
@@ -277,8 +280,10 @@ def batched_requests(sv, torch, np, arm, reps=5):
         return all(np.array_equal(a[0].view(np.int32), b[0].view(np.int32)) and np.array_equal(a[1], b[1])
                    and np.array_equal(a[2], b[2]) for a, b in zip(batched, x))
     per = [(o.min_dist.cpu().numpy(), o.argmin.cpu().numpy(), o.verdict.cpu().numpy()) for o in outs]
-    same = same_as(per) and same_as(unculled)
+    same = same_as(per) and same_as(unculled) and same_as(default_out)
     bi, pi = int(np.argsort(b_ms)[len(b_ms) // 2]), int(np.argsort(p_ms)[len(p_ms) // 2])
+    di = int(np.argsort(d_ms)[len(d_ms) // 2])
+    dl = d_lat[di]
     bl, pl = b_lat[bi], p_lat[pi]
     u = min(u_ms)
     flop = FLOP_PER_SEGMENT_TEST * T * K * pairs
@@ -288,6 +293,11 @@ def batched_requests(sv, torch, np, arm, reps=5):
         "batched": {"ms": b_ms[bi], "motions_per_s": M / (b_ms[bi] / 1e3),
                     "latency_ms_p50": float(np.percentile(bl, 50)), "latency_ms_p99": float(np.percentile(bl, 99)),
                     "executed_tests": b_exec, "executed_fraction": b_exec / (T * K * pairs),
+                    "tile": ctile.as_dict(), "tuned_by": f"autotune.tune over {len(ctimings)} culled shapes "
+                                                         f"({t_tune:.1f} s, results checked bit for bit)",
+                    "default_tile_ms": d_ms[di], "gain_over_default": d_ms[di] / b_ms[bi],
+                    "default_tile_latency_ms_p50": float(np.percentile(dl, 50)),
+                    "default_tile_latency_ms_p99": float(np.percentile(dl, 99)),
                     "launch": "one graph-captured call: plan, tables, counting sort of all clouds by (request, "
                               "Morton cell), bounds, culled item list, persistent culled kernel, FP64 band recheck"},
         "batched_unculled": {"ms": u, "motions_per_s": M / (u / 1e3), "tile": list(tile.as_tuple()),
@@ -303,7 +313,8 @@ def batched_requests(sv, torch, np, arm, reps=5):
         "latency_definition": "all requests submitted at the batch start; latency = completion - start "
                               "(device completion stamps for the batch, HIP events for per-request calls)",
     }
-    log(f"requests: batched {b_ms[bi]:.1f} ms ({res['batched']['motions_per_s']:.0f} motions/s, p50 "
+    log(f"requests: batched (tuned) {b_ms[bi]:.1f} ms vs default tile {d_ms[di]:.1f} ms "
+        f"({res['batched']['motions_per_s']:.0f} motions/s, p50 "
         f"{res['batched']['latency_ms_p50']:.1f} ms, p99 {res['batched']['latency_ms_p99']:.1f} ms, executed "
         f"{res['batched']['executed_fraction']:.4f}); unculled "
         f"{u:.1f} ms ({res['batched_unculled']['roofline']['achieved']:.1f} TFLOP/s); per-request {p_ms[pi]:.1f} ms "
@@ -407,10 +418,9 @@ def crossover(sv, torch, np, arm, robot, motions, dc, eps, steps):
         out = sv.DeviceResults(M)
         ws = sv.workspace(sv.sv_workspace_size(sv.SV_OP_CHECK, robot, dmT, dc))
         call = lambda: sv.sv_check_motions(robot, dmT, dc, out, eps, ws=ws)
+        dense = lambda: sv.sv_check_motions(robot, dmT, dc, out, eps, ws=ws, unculled=True)
         ms_c, _ = timed(sv, torch, call, steps, 2, [])
-        sv.sv_set_exact_culling(False)
-        ms_d, _ = timed(sv, torch, call, max(steps // 2, 2), 1, [])
-        sv.sv_set_exact_culling(True)
+        ms_d, _ = timed(sv, torch, dense, max(steps // 2, 2), 1, [])
         res["exact"][T] = {"culled_ms": ms_c, "dense_ms": ms_d}
         log(f"crossover: exact T={T}: culled {ms_c:.3f} ms, dense {ms_d:.3f} ms per call")
     a, b = np.polyfit(np.array(Ts, np.float64), np.array([res["exact"][T]["dense_ms"] for T in Ts]), 1)[::-1]
@@ -573,9 +583,9 @@ def main():
     ws_n = sv.workspace(sv.sv_workspace_size(sv.SV_OP_CHECK, robot, dm, dc, mlp))
     torch.cuda.synchronize()
 
-    def check(out, net=None, mode=sv.SV_SCREEN_NONE):
+    def check(out, net=None, mode=sv.SV_SCREEN_NONE, unculled=False):
         return lambda: sv.sv_check_motions(robot, dm, dc, out, eps, mlp=net, screen=mode, tau=tau,
-                                           ws=ws_x if net is None else ws_n)
+                                           ws=ws_x if net is None else ws_n, unculled=unculled)
 
     ms_x, kx = timed(sv, torch, check(out_x), args.steps, args.warmup, ["exact"])
     executed = sv.executed_tests(ws_x)            # segment tests the culled pass ran (last call)
@@ -595,9 +605,7 @@ def main():
     del g_exact
     # the dense kernel (every test, no culling): the roofline of the exact arithmetic
     out_d = sv.DeviceResults(dm.n)
-    sv.sv_set_exact_culling(False)
-    ms_d, kd = timed(sv, torch, check(out_d), max(args.steps // 2, 1), 1, ["exact"])
-    sv.sv_set_exact_culling(True)
+    ms_d, kd = timed(sv, torch, check(out_d, unculled=True), max(args.steps // 2, 1), 1, ["exact"])
     dense_same = bool(torch.equal(out_d.min_dist.view(torch.int32), out_x.min_dist.view(torch.int32))
                       and torch.equal(out_d.argmin, out_x.argmin) and torch.equal(out_d.verdict, out_x.verdict))
     # continuous certification of the exact leg's results (the gap between sampled and

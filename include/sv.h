@@ -146,6 +146,10 @@ enum {
  * checked exactly over all its points, so that verdicts equal the exact check's (as
  * Alg. 1 confirms with the geometric checker every motion it reports free). */
 enum { SV_SCREEN_NONE = 0, SV_SCREEN_TRUST = 1, SV_SCREEN_CERTIFIED = 2 };
+/* May be OR'd into the screen argument of sv_check_motions: the exact passes over all
+ * points of a motion run every test instead of skipping provably distant groups.  The
+ * results are the same bit for bit; a measurement aid (per call, no global state). */
+enum { SV_CHECK_UNCULLED = 0x100 };
 
 /* Workspace sizes per operation. */
 enum { SV_OP_EXACT_SDF = 0, SV_OP_CHECK = 1, SV_OP_NN_SDF = 2 };
@@ -199,8 +203,9 @@ int sv_nn_sdf(const sv_mlp* mlp, int precision, const sv_motions* motions, const
  * tests that bounding spheres prove to lie above the motion's minimum (the cloud is
  * put in Morton order internally; reported indices are the caller's).  Skipping never
  * changes min_dist, argmin or verdict: they equal the unskipped computation bit for
- * bit.  Workspace: SV_OP_CHECK; after a call its first 256 uint64 words sum to the
- * number of segment tests those passes executed (a measurement aid). */
+ * bit (screen | SV_CHECK_UNCULLED runs them unskipped).  Workspace: SV_OP_CHECK; after a
+ * call its first 256 uint64 words sum to the number of segment tests the skipping
+ * passes executed (a measurement aid). */
 int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float eps, float tau,
                      const sv_motions* motions, const sv_cloud* cloud, sv_results* out, void* ws,
                      size_t ws_bytes, void* stream);
@@ -239,9 +244,9 @@ int sv_continuous_gap(const sv_robot* robot, const sv_motions* motions, const fl
  *      seed bound and bounding spheres are computed for every request, the surviving
  *      items are listed in work order, and one persistent kernel takes them in that
  *      order; the block that retires a request's last item writes the request's
- *      results and stamps done_ticks.  With culling switched off
- *      (sv_set_exact_culling(0)) a persistent kernel of the given tile shape takes
- *      (request, motion, chunk of point tiles) items from a device work queue;
+ *      results and stamps done_ticks.  With tile->cull = 0 a persistent kernel of the
+ *      given shape takes (request, motion, chunk of point tiles) items from a device
+ *      work queue instead;
  *   4. FP64 recheck of the motions within 1e-5 m of eps (as sv_check_motions).
  * The call can therefore be captured in a HIP graph once and replayed after the
  * caller rewrites the request table (and the buffers it points to) within the same
@@ -263,13 +268,23 @@ typedef struct {
                                which must then be < 2^30 */
 } sv_batch_caps;          /* also max_motions * ceil(max_points / 512) * 16 < 2^31 */
 
-/* Launch shape of the persistent exact-check kernel without culling (chosen by an
- * autotuner); the culled pass has a fixed shape and only validates it. */
+/* Launch shape of sv_check_requests (chosen by an autotuner, sv_tile_candidates).  Every
+ * shape gives the same results bit for bit. */
 typedef struct {
+  /* the unculled persistent kernel (cull = 0) */
   int32_t ppl;            /* points per lane: 1, 2 or 4 */
   int32_t threads;        /* threads per block: 64, 128 or 256 */
   int32_t blocks_per_cu;  /* persistent blocks per compute unit: 1..32 */
   int32_t tiles_per_item; /* point tiles (threads * ppl points each) per work item: 1..64 */
+  /* which pass runs */
+  int32_t cull;           /* 1: the culled pass (the default), 0: the unculled kernel above */
+  /* the culled pass (cull = 1; 512-point tiles of 256 threads x 2 points) */
+  int32_t cull_blocks_per_cu; /* persistent blocks per compute unit, 1..8; 0: as many as fit */
+  int32_t cull_gangs;     /* queues the persistent blocks are dealt to (block index mod gangs): 1, 2, 4,
+                             8 or 16; requests are spread over the queues, an idle block helps the next */
+  int32_t cull_div_linear; /* a linear motion of T samples is bounded by spheres over blocks of
+                              min(16, max(2, ceil(T / div))) samples: 16, 32 or 64 */
+  int32_t cull_div_spline; /* the same for splines: 32, 64 or 128 */
 } sv_tile;
 
 /* Bits of the device status word written by sv_check_requests. */
@@ -293,18 +308,21 @@ int sv_batch_workspace_size(const sv_robot* robot, const sv_batch_caps* caps, si
  *   SV_BATCH_BAD_REQUEST or SV_BATCH_OVER_CAPACITY no result is written.
  * tile: launch shape (NULL: the library's default).
  * ws: after a call, its first 256 uint64 words sum to the number of segment tests the
- *   culled pass executed (a measurement aid; 0 with culling off).
+ *   culled pass executed (a measurement aid; 0 with tile->cull = 0).
  * Host checks: robot, caps, tile, n_req <= caps->max_requests, workspace size.
  * Concurrent calls must not share a workspace. */
 int sv_check_requests(const sv_robot* robot, const sv_request* reqs, int32_t n_req, const sv_batch_caps* caps,
                       float eps, const sv_tile* tile, uint64_t* done_ticks, int32_t* status, void* ws,
                       size_t ws_bytes, void* stream);
 
-/* The launch shapes sv_check_requests accepts, for an autotuner: writes up to
- * `capacity` of them to tiles (may be NULL) and their total count to *n. */
+/* The launch shapes an autotuner may try (all accepted by sv_check_requests): the unculled
+ * shapes (cull = 0, culled fields at their defaults), then the culled ones (cull = 1,
+ * unculled fields at their defaults).  Writes up to `capacity` of them to tiles (may be
+ * NULL) and their total count to *n. */
 int sv_tile_candidates(sv_tile* tiles, int32_t capacity, int32_t* n);
 
-/* The default launch shape. */
+/* The default launch shape: the culled pass with 8 gangs (one per XCD under the
+ * round-robin dispatch of workgroups), as many blocks as fit and divisors 32 and 64. */
 int sv_default_tile(sv_tile* tile);
 
 /* Frequency of the device wall clock that stamps done_ticks (current device). */
@@ -420,8 +438,11 @@ typedef struct {
   float beta1, beta2;  /* Adam moment decays (0.9, 0.999) */
   float adam_eps;      /* 1e-8 */
   int64_t step;        /* 1-based index of this update, for Adam's bias correction */
-  float clamp_sigma;   /* loss = mean |y - clamp(delta, -s, s)|: an L1 on distances clamped to s
-                          (the prediction itself is not clamped, so it always has a gradient) */
+  float clamp_sigma;   /* s > 0: the loss is an L1 on distances clamped to [-s, s] */
+  int32_t clamp_pred;  /* 0: clamp the targets only, loss = mean |y - clamp(delta)| (the prediction
+                          always has a gradient); 1: clamp both, loss = mean |clamp(y) - clamp(delta)|
+                          (the form of DeepSDF, whose jump connections Sec. IV-A adopts; a prediction
+                          with |y| >= s then has no gradient) */
 } sv_train_hparams;
 
 /* One training step of the BF16 network (mlp->width 128, 256 or 512): forward pass of
@@ -440,15 +461,13 @@ int sv_train_step(const sv_mlp* mlp, float* adam_m, float* adam_v, const sv_trai
 int sv_train_workspace_size(const sv_mlp* mlp, int64_t batch, size_t* bytes);
 
 /* ---- measurement support (not part of the method) --------------------------------
- * When enabled, every later call records a HIP event pair on its stream around each
- * of its kernel groups ("motion_table", "exact", "exact_sdf", "finalize",
- * "recheck64", ...).  sv_profile_read waits for the recorded events and returns the
- * summed elapsed milliseconds and the number of recorded launches of that group
- * since the last reset.  Do not enable while capturing a HIP graph. */
+ * Per calling thread: when enabled, every later call made from this thread records a
+ * HIP event pair on its stream around each of its kernel groups ("motion_table",
+ * "exact", "exact_sdf", "finalize", "recheck64", ...).  sv_profile_read waits for the
+ * events this thread recorded and returns the summed elapsed milliseconds and the
+ * number of recorded launches of that group since this thread's last reset.  Calls
+ * from other threads are not affected.  Do not enable while capturing a HIP graph. */
 int sv_profile_enable(int on);
-/* Switch the test skipping of sv_check_motions' exact passes off (0) or on (1, the
- * default) for this process; results are identical either way.  Measurement aid. */
-int sv_set_exact_culling(int on);
 void sv_profile_reset(void);
 int sv_profile_read(const char* kernel, double* total_ms, int64_t* launches);
 

@@ -16,8 +16,8 @@ softplus(z) = max(z, 0) + log1p(exp(-|z|)).  Parameters arrive as one flat FP32
 vector, per layer W (row-major [out][in]) then b, and are converted exactly to
 float64.  Training follows Sec. V (Adam with PyTorch's default constants,
 lr = 1e-3, betas = (0.9, 0.999)); the loss is an L1 on distances clamped to
-[-sigma, sigma] (the paper states no loss; the clamp follows the DeepSDF work it
-cites for its jump connections).
+[-sigma, sigma], on the targets only or on both sides (the paper states no loss;
+the clamp follows the DeepSDF work it cites for its jump connections).
 
 A matrix product (numpy ``@``) is used as a library primitive; nothing else is
 fused or reordered.
@@ -81,37 +81,44 @@ def forward(flat, in_dim, width, n_hidden, H0):
     return y, (zs, hs)
 
 
-def clamped_l1(pred, target, sigma):
-    """L = mean |pred - clamp(target, -s, s)|: an L1 loss on distances clamped to s.
+def clamped_l1(pred, target, sigma, clamp_pred=False):
+    """An L1 loss on distances clamped to s (the paper states no loss; the clamp follows
+    the DeepSDF work it cites for its jump connections):
 
-    Only the target is clamped.  Clamping the prediction as well would give every
-    prediction outside [-s, s] a zero gradient; Adam's first updates move the output
-    of a wide network by more than s, after which such a network stops learning.
+    clamp_pred False: L = mean |pred - clamp(target, -s, s)|, the target clamped only;
+    clamp_pred True:  L = mean |clamp(pred, -s, s) - clamp(target, -s, s)|, DeepSDF's
+                      form, under which a prediction outside [-s, s] has no gradient.
     """
-    return float(np.mean(np.abs(pred - np.clip(target, -sigma, sigma))))
+    p = np.clip(pred, -sigma, sigma) if clamp_pred else np.asarray(pred)
+    return float(np.mean(np.abs(p - np.clip(target, -sigma, sigma))))
 
 
-def loss_and_grad(flat, in_dim, width, n_hidden, H0, target, sigma, decide=None):
+def loss_and_grad(flat, in_dim, width, n_hidden, H0, target, sigma, decide=None, clamp_pred=False):
     """Clamped-L1 loss (see clamped_l1) and its gradient w.r.t. the flat parameter
     vector, by backpropagation.
 
-    dL/dpred = sign(pred - clamp(target)) / B, sign(0) = 0.
+    dL/dpred = sign(p - clamp(target)) / B, sign(0) = 0, with p = pred (targets
+    clamped only) or p = clamp(pred) times the clamp's derivative, 1 for
+    |pred| < s and 0 otherwise (clamp_pred).
     Through a softplus layer: dz = dh * sigmoid(z); dW = dz^T h_prev; db = sum dz;
     dh_prev = dz W.
 
-    The loss is not smooth: the sign is a decision taken on the prediction.
-    `decide` (optional, [B]) supplies the predictions it is taken on -- e.g. those
-    of the BF16 rounding points, to compare with a BF16 implementation in its own
-    precision; by default it is taken on y itself.
+    The loss is not smooth: the sign and the clamp's derivative are decisions taken
+    on the prediction.  `decide` (optional, [B]) supplies the predictions they are
+    taken on -- e.g. those of the BF16 rounding points, to compare with a BF16
+    implementation in its own precision; by default they are taken on y itself.
     """
     layers = unpack(flat, in_dim, width, n_hidden)
     y, (zs, hs) = forward(flat, in_dim, width, n_hidden, H0)
     B = y.shape[0]
     target = np.asarray(target, np.float64)
     tc = np.clip(target, -sigma, sigma)
-    loss = float(np.mean(np.abs(y - tc)))
+    loss = clamped_l1(y, target, sigma, clamp_pred)
     yd = y if decide is None else np.asarray(decide, np.float64)
-    dy = np.sign(yd - tc) / B
+    if clamp_pred:
+        dy = np.where(np.abs(yd) < sigma, np.sign(np.clip(yd, -sigma, sigma) - tc), 0.0) / B
+    else:
+        dy = np.sign(yd - tc) / B
     grads = [None] * len(layers)
     W, b = layers[-1]
     grads[-1] = (dy[None, :] @ hs[-1], np.array([dy.sum()]))

@@ -23,6 +23,7 @@ SV_LINEAR, SV_SPLINE = 0, 1
 SV_OP_EXACT_SDF, SV_OP_CHECK, SV_OP_NN_SDF = 0, 1, 2
 SV_FP32, SV_BF16 = 0, 1
 SV_SCREEN_NONE, SV_SCREEN_TRUST, SV_SCREEN_CERTIFIED = 0, 1, 2
+SV_CHECK_UNCULLED = 0x100
 
 _STATUS = {0: "SV_OK", -1: "SV_ERR_ARG", -2: "SV_ERR_SHAPE", -3: "SV_ERR_WORKSPACE",
            -4: "SV_ERR_UNSUPPORTED", -5: "SV_ERR_HIP"}
@@ -61,7 +62,8 @@ class sv_mlp(ctypes.Structure):
 
 class sv_train_hparams(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
-                ("adam_eps", ctypes.c_float), ("step", ctypes.c_int64), ("clamp_sigma", ctypes.c_float)]
+                ("adam_eps", ctypes.c_float), ("step", ctypes.c_int64), ("clamp_sigma", ctypes.c_float),
+                ("clamp_pred", ctypes.c_int32)]
 
 
 class sv_results(ctypes.Structure):
@@ -81,13 +83,18 @@ class sv_batch_caps(ctypes.Structure):
 
 class sv_tile(ctypes.Structure):
     _fields_ = [("ppl", ctypes.c_int32), ("threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("tiles_per_item", ctypes.c_int32)]
+                ("tiles_per_item", ctypes.c_int32), ("cull", ctypes.c_int32), ("cull_blocks_per_cu", ctypes.c_int32),
+                ("cull_gangs", ctypes.c_int32), ("cull_div_linear", ctypes.c_int32),
+                ("cull_div_spline", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.ppl, self.threads, self.blocks_per_cu, self.tiles_per_item)
+        return tuple(getattr(self, f) for f, _ in self._fields_)
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
     def __repr__(self):
-        return "sv_tile(ppl=%d, threads=%d, blocks_per_cu=%d, tiles_per_item=%d)" % self.as_tuple()
+        return "sv_tile(" + ", ".join(f"{k}={v}" for k, v in self.as_dict().items()) + ")"
 
 
 SV_BATCH_BAD_REQUEST, SV_BATCH_OVER_CAPACITY, SV_BATCH_BAND_OVERFLOW = 1, 2, 4
@@ -138,7 +145,6 @@ def _load():
     lib.sv_tile_candidates.argtypes = [ctypes.POINTER(sv_tile), I32, ctypes.POINTER(I32)]
     lib.sv_default_tile.argtypes = [ctypes.POINTER(sv_tile)]
     lib.sv_wall_clock_hz.argtypes = [ctypes.POINTER(I64)]
-    lib.sv_set_exact_culling.argtypes = [ctypes.c_int]
     lib.sv_nn_min.argtypes = [ctypes.POINTER(sv_mlp), ctypes.POINTER(sv_motions), ctypes.POINTER(sv_cloud), P, P,
                               ctypes.c_size_t, P]
     lib.sv_nn_min_workspace_size.argtypes = [ctypes.POINTER(sv_mlp), ctypes.POINTER(sv_motions), SZ]
@@ -155,7 +161,7 @@ def _load():
                "sv_profile_read", "sv_make_samples", "sv_make_samples_workspace_size", "sv_nn_predict",
                "sv_train_step", "sv_train_workspace_size", "sv_batch_workspace_size", "sv_check_requests",
                "sv_tile_candidates", "sv_default_tile", "sv_wall_clock_hz", "sv_nn_min", "sv_nn_min_workspace_size",
-               "sv_first_free", "sv_first_free_workspace_size", "sv_set_exact_culling", "sv_continuous_gap",
+               "sv_first_free", "sv_first_free_workspace_size", "sv_continuous_gap",
                "sv_make_samples_paper", "sv_make_samples_paper_workspace_size"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
@@ -339,19 +345,18 @@ def sv_nn_sdf(mlp: DeviceMLP, precision: int, motions: DeviceMotions, cloud: Dev
 
 
 def sv_check_motions(robot: sv_robot, motions: DeviceMotions, cloud: DeviceCloud, out: DeviceResults, eps: float,
-                     mlp: DeviceMLP = None, screen: int = SV_SCREEN_NONE, tau: float = 0.0, ws=None, stream=None):
-    """Per-motion min distance, argmin, verdict (and fallback counts when screening)."""
+                     mlp: DeviceMLP = None, screen: int = SV_SCREEN_NONE, tau: float = 0.0, ws=None, stream=None,
+                     unculled: bool = False):
+    """Per-motion min distance, argmin, verdict (and fallback counts when screening);
+    unculled: run every exact test (screen | SV_CHECK_UNCULLED; same results)."""
     md, cd, rd = motions.desc(), cloud.desc(), out.desc()
     keep, mref = _mlp_ref(mlp)
     if ws is None:
         ws = workspace(sv_workspace_size(SV_OP_CHECK, robot, motions, cloud, mlp))
-    _check(lib.sv_check_motions(ctypes.byref(robot), mref, int(screen), float(eps), float(tau), ctypes.byref(md),
+    mode = int(screen) | (SV_CHECK_UNCULLED if unculled else 0)
+    _check(lib.sv_check_motions(ctypes.byref(robot), mref, mode, float(eps), float(tau), ctypes.byref(md),
                                 ctypes.byref(cd), ctypes.byref(rd), _ptr(ws), ws.numel(), _stream(stream)))
     return ws
-
-
-def sv_set_exact_culling(on: bool = True):
-    _check(lib.sv_set_exact_culling(int(bool(on))))
 
 
 def executed_tests(ws: torch.Tensor) -> int:
@@ -416,10 +421,11 @@ def sv_train_workspace_size(mlp: DeviceMLP, batch: int) -> int:
 def sv_train_step(mlp: DeviceMLP, adam_m: torch.Tensor, adam_v: torch.Tensor, step: int, samples: torch.Tensor,
                   batch_idx: torch.Tensor, lr: float = 1e-3, betas=(0.9, 0.999), adam_eps: float = 1e-8,
                   clamp_sigma: float = 0.1, loss_out: torch.Tensor = None, grad_out: torch.Tensor = None, ws=None,
-                  stream=None):
+                  stream=None, clamp_pred: bool = False):
     """One Adam step of the BF16 network on samples[batch_idx]; mlp.params is updated in place."""
     d = mlp.desc()
-    hp = sv_train_hparams(float(lr), float(betas[0]), float(betas[1]), float(adam_eps), int(step), float(clamp_sigma))
+    hp = sv_train_hparams(float(lr), float(betas[0]), float(betas[1]), float(adam_eps), int(step), float(clamp_sigma),
+                          int(bool(clamp_pred)))
     B = int(batch_idx.shape[0])
     if ws is None:
         ws = workspace(sv_train_workspace_size(mlp, B))

@@ -1,21 +1,25 @@
 """Autotuner for the launch shape of the batched exact check (sv_tile).
 
-The unculled persistent kernel of sv_check_requests (the one that runs when exact-check
-culling is switched off with sv_set_exact_culling(0); the culled pass has a fixed
-shape) has four shape parameters:
-- points per lane;
-- threads per block;
-- resident blocks per compute unit;
-- point tiles per work item.
+sv_check_requests runs one of two passes, each with its own shape parameters:
+- the culled pass (the default, tile.cull = 1): persistent blocks per compute unit,
+  the number of gangs (queues) the blocks are dealt to, and the divisors that set
+  the length of the sample blocks bounded by one sphere (linear motions, splines);
+- the unculled persistent kernel (tile.cull = 0): points per lane, threads per
+  block, resident blocks per compute unit and point tiles per work item.
 
-The best choice depends on the request mix: small clouds favour small tiles, and
-many motions favour fewer, larger items.  The tuner times candidate shapes on the
-caller's own batch through the C entry point (HIP events on the calling stream,
-median of `reps` runs after one warm-up).  It searches in three stages:
+The best choice depends on the request mix: long motions favour longer sample
+blocks, a few large requests favour fewer gangs, small clouds favour small tiles.
+The tuner times candidate shapes on the caller's own batch through the C entry point
+(HIP events on the calling stream, median of `reps` runs after one warm-up) and
+searches each pass in stages, one parameter group at a time from the library's
+default shape:
 
-1. every (points per lane, threads) pair, at full occupancy and a middle item size;
-2. blocks per compute unit, for the best pair;
-3. tiles per item.
+culled:   1. the two sample-block divisors (all pairs);
+          2. gangs, for the best pair;
+          3. blocks per compute unit;
+unculled: 1. every (points per lane, threads) pair, at full occupancy and a middle item size;
+          2. blocks per compute unit, for the best pair;
+          3. tiles per item.
 
 The winner is cached in a JSON file, keyed by device and workload signature, so a
 serving process tunes once per kind of batch.  Every candidate produces the same
@@ -37,8 +41,8 @@ def _full_occupancy_bpc(threads: int) -> int:
     return max(1, min(32, 32 * 64 // threads))
 
 
-def signature(robot, reqs: "sv.DeviceRequests") -> str:
-    """Device and coarse workload shape: the key of the tuning cache."""
+def signature(robot, reqs: "sv.DeviceRequests", passes=("culled",)) -> str:
+    """Device, passes searched and coarse workload shape: the key of the tuning cache."""
     props = torch.cuda.get_device_properties(torch.cuda.current_device())
     ms = [m for m, _, _ in reqs.requests]
     cs = [c for _, c, _ in reqs.requests]
@@ -47,7 +51,8 @@ def signature(robot, reqs: "sv.DeviceRequests") -> str:
     Ts = sorted({m.T for m in ms})
     bucket = lambda v: int(round(float(v) ** 0.25 * 4))   # coarse: 19% steps
     return (f"{props.name}|{getattr(props, 'gcnArchName', '')}|dof{robot.dof}|caps{robot.n_caps}|kinds{kinds}|"
-            f"T{Ts if len(Ts) <= 4 else [Ts[0], Ts[-1]]}|req{reqs.n}|work{bucket(tot_pairs)}")
+            f"T{Ts if len(Ts) <= 4 else [Ts[0], Ts[-1]]}|req{reqs.n}|work{bucket(tot_pairs)}|"
+            f"passes{sorted(passes)}")
 
 
 def _results(reqs):
@@ -70,9 +75,19 @@ def time_tile(robot, reqs, caps, eps, tile, ws, reps=3) -> float:
     return statistics.median(times)
 
 
-def tune(robot, reqs, caps, eps, ws=None, reps=3, cache_path=None, log=None):
-    """Fastest launch shape for this batch: (sv_tile, {shape tuple: ms}, from_cache)."""
-    key = signature(robot, reqs)
+def _with(base: tuple, **fields) -> tuple:
+    t = sv.sv_tile(*base)
+    for k, v in fields.items():
+        setattr(t, k, v)
+    return t.as_tuple()
+
+
+def tune(robot, reqs, caps, eps, ws=None, reps=3, cache_path=None, log=None, passes=("culled",)):
+    """Fastest launch shape for this batch among the passes named: (sv_tile, {shape tuple:
+    ms}, from_cache)."""
+    if not passes or any(p not in ("culled", "unculled") for p in passes):
+        raise ValueError(f"passes must name 'culled' and/or 'unculled', got {passes!r}")
+    key = signature(robot, reqs, passes)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
@@ -82,6 +97,7 @@ def tune(robot, reqs, caps, eps, ws=None, reps=3, cache_path=None, log=None):
     if ws is None:
         ws = sv.workspace(sv.sv_batch_workspace_size(robot, caps))
     allowed = {t.as_tuple() for t in sv.sv_tile_candidates()}
+    default = sv.sv_default_tile().as_tuple()
     timings = {}
     ref = None
 
@@ -99,18 +115,36 @@ def tune(robot, reqs, caps, eps, ws=None, reps=3, cache_path=None, log=None):
                         and torch.equal(a2, b2)):
                     raise RuntimeError(f"launch shape {t} changed the results")
         if log:
-            log(f"tile {t}: {timings[t]:.3f} ms")
+            log(f"tile {sv.sv_tile(*t)}: {timings[t]:.3f} ms")
 
-    for ppl in (1, 2, 4):
-        for threads in (64, 128, 256):
-            run((ppl, threads, _full_occupancy_bpc(threads), 4))
-    best = min(timings, key=timings.get)
-    full = _full_occupancy_bpc(best[1])
-    for bpc in sorted({max(1, full // 4), max(1, full // 2), full}):
-        run((best[0], best[1], bpc, best[3]))
-    best = min(timings, key=timings.get)
-    for tpi in (1, 2, 4, 8, 16, 32):
-        run((best[0], best[1], best[2], tpi))
+    def best_of(pred):
+        cands = [t for t in timings if pred(sv.sv_tile(*t))]
+        return min(cands, key=timings.get)
+
+    if "culled" in passes:
+        is_culled = lambda t: t.cull == 1
+        for dl in (16, 32, 64):
+            for ds in (32, 64, 128):
+                run(_with(default, cull=1, cull_div_linear=dl, cull_div_spline=ds))
+        best = best_of(is_culled)
+        for gangs in (1, 2, 4, 8, 16):
+            run(_with(best, cull_gangs=gangs))
+        best = best_of(is_culled)
+        for bpc in (1, 2, 4, 0):
+            run(_with(best, cull_blocks_per_cu=bpc))
+    if "unculled" in passes:
+        is_unculled = lambda t: t.cull == 0
+        for ppl in (1, 2, 4):
+            for threads in (64, 128, 256):
+                run(_with(default, cull=0, ppl=ppl, threads=threads, blocks_per_cu=_full_occupancy_bpc(threads),
+                          tiles_per_item=4))
+        best = best_of(is_unculled)
+        full = _full_occupancy_bpc(sv.sv_tile(*best).threads)
+        for bpc in sorted({max(1, full // 4), max(1, full // 2), full}):
+            run(_with(best, blocks_per_cu=bpc))
+        best = best_of(is_unculled)
+        for tpi in (1, 2, 4, 8, 16, 32):
+            run(_with(best, tiles_per_item=tpi))
     best = min(timings, key=timings.get)
     if cache_path:
         cache[key] = {"tile": list(best), "ms": timings[best]}

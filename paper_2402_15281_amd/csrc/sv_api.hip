@@ -31,22 +31,23 @@ int hip_fail(hipError_t e, const char* where) {
   return fail(SV_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
 }
 
-// ---- optional per-kernel timing with HIP events (sv_profile_*)
+// ---- optional per-kernel timing with HIP events (sv_profile_*), per calling thread:
+// a thread's switch, pending events and totals are its own, so no call from another
+// thread sees them and no lock is needed.
 struct ProfRec {
   const char* name;
   hipEvent_t a, b;
 };
-std::mutex g_prof_mu;
-bool g_prof_on = false;
-std::vector<ProfRec> g_prof_pending;
-std::map<std::string, std::pair<double, int64_t>> g_prof_acc;
+thread_local bool t_prof_on = false;
+thread_local std::vector<ProfRec> t_prof_pending;
+thread_local std::map<std::string, std::pair<double, int64_t>> t_prof_acc;
 
 // Records a HIP event pair around the launches in its scope, on the launch stream.
 struct ProfScope {
   ProfRec rec{nullptr, nullptr, nullptr};
   hipStream_t st;
   ProfScope(const char* name, hipStream_t s) : st(s) {
-    if (!g_prof_on) return;
+    if (!t_prof_on) return;
     if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess) return;
     rec.name = name;
     (void)hipEventRecord(rec.a, st);
@@ -54,24 +55,22 @@ struct ProfScope {
   ~ProfScope() {
     if (!rec.name) return;
     (void)hipEventRecord(rec.b, st);
-    std::lock_guard<std::mutex> g(g_prof_mu);
-    g_prof_pending.push_back(rec);
+    t_prof_pending.push_back(rec);
   }
 };
 
 void prof_resolve() {
-  std::lock_guard<std::mutex> g(g_prof_mu);
-  for (auto& r : g_prof_pending) {
+  for (auto& r : t_prof_pending) {
     float ms = 0.f;
     if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
-      auto& acc = g_prof_acc[r.name];
+      auto& acc = t_prof_acc[r.name];
       acc.first += ms;
       acc.second += 1;
     }
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
-  g_prof_pending.clear();
+  t_prof_pending.clear();
 }
 
 
@@ -219,9 +218,6 @@ size_t nn_sdf_bytes(const sv_mlp& n, int precision) {
 // Motions whose FP32 cloud distance lies within this band of eps are recomputed in FP64.
 constexpr float kCertBand = 1e-5f;
 
-// Culled per-motion minimum in sv_check_motions (on unless switched off for measurement).
-bool g_cull = true;
-
 int check_caps(const sv_batch_caps* c) {
   if (!c) return fail(SV_ERR_ARG, "caps is NULL");
   if (c->max_requests < 1 || c->max_requests > kMaxBatchRequests)
@@ -242,13 +238,35 @@ int check_caps(const sv_batch_caps* c) {
   return SV_OK;
 }
 
-// The launch shapes offered to an autotuner (all accepted by sv_check_requests).
+// The launch shapes offered to an autotuner (all accepted by sv_check_requests): the
+// unculled shapes, then the culled ones, each with the other pass's fields at their
+// defaults.
 std::vector<sv_tile> tile_candidates() {
+  const sv_tile d = default_batch_tile();
   std::vector<sv_tile> v;
   for (int ppl : {1, 2, 4})
     for (int threads : {64, 128, 256})
       for (int bpc : {1, 2, 4, 8, 16, 32})
-        for (int tpi : {1, 2, 4, 8, 16, 32}) v.push_back(sv_tile{ppl, threads, bpc, tpi});
+        for (int tpi : {1, 2, 4, 8, 16, 32}) {
+          sv_tile t = d;
+          t.ppl = ppl;
+          t.threads = threads;
+          t.blocks_per_cu = bpc;
+          t.tiles_per_item = tpi;
+          t.cull = 0;
+          v.push_back(t);
+        }
+  for (int bpc : {1, 2, 4, 0})
+    for (int gangs : {1, 2, 4, 8, 16})
+      for (int dl : kCullDivsLinear)
+        for (int ds : kCullDivsSpline) {
+          sv_tile t = d;
+          t.cull_blocks_per_cu = bpc;
+          t.cull_gangs = gangs;
+          t.cull_div_linear = dl;
+          t.cull_div_spline = ds;
+          v.push_back(t);
+        }
   return v;
 }
 
@@ -274,24 +292,21 @@ const char* sv_status_string(int s) {
 const char* sv_last_error(void) { return g_last_error.c_str(); }
 
 int sv_profile_enable(int on) {
-  std::lock_guard<std::mutex> g(g_prof_mu);
-  g_prof_on = on != 0;
+  t_prof_on = on != 0;
   return SV_OK;
 }
 
 void sv_profile_reset(void) {
   prof_resolve();
-  std::lock_guard<std::mutex> g(g_prof_mu);
-  g_prof_acc.clear();
+  t_prof_acc.clear();
 }
 
 int sv_profile_read(const char* kernel, double* total_ms, int64_t* launches) {
   if (!kernel || !total_ms || !launches) return fail(SV_ERR_ARG, "NULL argument");
   prof_resolve();
-  std::lock_guard<std::mutex> g(g_prof_mu);
-  auto it = g_prof_acc.find(kernel);
-  *total_ms = it == g_prof_acc.end() ? 0.0 : it->second.first;
-  *launches = it == g_prof_acc.end() ? 0 : it->second.second;
+  auto it = t_prof_acc.find(kernel);
+  *total_ms = it == t_prof_acc.end() ? 0.0 : it->second.first;
+  *launches = it == t_prof_acc.end() ? 0 : it->second.second;
   return SV_OK;
 }
 
@@ -397,6 +412,8 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
   if ((s = check_robot(robot)) || (s = check_motions(motions, robot->dof)) || (s = check_cloud(cloud))) return s;
   if (!out) return fail(SV_ERR_ARG, "results is NULL");
   if (!isfinite(eps)) return fail(SV_ERR_ARG, "eps must be finite");
+  const bool cull = (screen & SV_CHECK_UNCULLED) == 0;
+  screen &= ~SV_CHECK_UNCULLED;
   const bool screened = screen != SV_SCREEN_NONE;
   if (screen < SV_SCREEN_NONE || screen > SV_SCREEN_CERTIFIED) return fail(SV_ERR_ARG, "unknown screen mode %d", screen);
   if (screened != (mlp != nullptr)) return fail(SV_ERR_ARG, "a screen mode needs a network and a network a screen mode");
@@ -431,7 +448,7 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
   if (cloud->n > 0) {
     SV_TRY("motion_table", launch_motion_table(*robot, ma, w.table, st));
     if (!screened) {
-      if (g_cull) {
+      if (cull) {
         SV_TRY("exact", launch_exact_culled(*robot, w.table, ma, ca, nullptr, nullptr, M, w.keys, w.cull, st));
       } else {
         SV_TRY("exact", launch_exact(*robot, w.table, ma, ca, nullptr, nullptr, M, nullptr, nullptr, nullptr, w.keys,
@@ -448,7 +465,7 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
       SV_TRY("decide", launch_screen_decide(w.keys, M, w.pcount, eps, kCertBand, screen == SV_SCREEN_CERTIFIED, *out,
                                             w.full, w.full_count, st));
       if (screen == SV_SCREEN_CERTIFIED) {
-        if (g_cull) {
+        if (cull) {
           SV_TRY("confirm", launch_exact_culled(*robot, w.table, ma, ca, w.full, w.full_count, M, w.keys, w.cull, st));
         } else {
           SV_TRY("confirm", launch_exact(*robot, w.table, ma, ca, w.full, w.full_count, M, nullptr, nullptr, nullptr,
@@ -679,7 +696,7 @@ int sv_train_step(const sv_mlp* mlp, float* adam_m, float* adam_v, const sv_trai
   if (!hp) return fail(SV_ERR_ARG, "hparams is NULL");
   if (hp->step < 1) return fail(SV_ERR_ARG, "Adam step must be >= 1");
   if (!(hp->clamp_sigma > 0.f) || !(hp->lr >= 0.f) || !(hp->beta1 >= 0.f && hp->beta1 < 1.f) ||
-      !(hp->beta2 >= 0.f && hp->beta2 < 1.f) || !(hp->adam_eps > 0.f))
+      !(hp->beta2 >= 0.f && hp->beta2 < 1.f) || !(hp->adam_eps > 0.f) || (hp->clamp_pred != 0 && hp->clamp_pred != 1))
     return fail(SV_ERR_ARG, "hyper-parameter out of range");
   if (batch < 1 || batch > (1 << 24)) return fail(SV_ERR_SHAPE, "batch %lld outside 1..2^24", (long long)batch);
   if (n_samples < 1) return fail(SV_ERR_SHAPE, "no samples");
@@ -701,7 +718,7 @@ int sv_train_step(const sv_mlp* mlp, float* adam_m, float* adam_v, const sv_trai
   {
     ProfScope ps("train_grad", st);
     e = launch_train_step(na, samples, batch_idx, (int)batch, (int)Bp, w.aT, w.dzT, w.h0T, w.y, w.dy, w.packed,
-                          w.packedT, grad, w.part_w, w.part_w1, hp->clamp_sigma, loss_out, st);
+                          w.packedT, grad, w.part_w, w.part_w1, hp->clamp_sigma, hp->clamp_pred, loss_out, st);
   }
   if (e != hipSuccess) return hip_fail(e, "train step");
   ProfScope ps("adam", st);
@@ -727,12 +744,12 @@ int sv_check_requests(const sv_robot* robot, const sv_request* reqs, int32_t n_r
     return fail(SV_ERR_SHAPE, "n_req %d outside 0..caps.max_requests (%d)", n_req, caps->max_requests);
   if (n_req > 0 && !reqs) return fail(SV_ERR_ARG, "request table is NULL");
   if (isnan(eps)) return fail(SV_ERR_ARG, "eps is NaN");
-  sv_tile t{};
-  sv_default_tile(&t);
-  if (tile) t = *tile;
+  const sv_tile t = tile ? *tile : default_batch_tile();
   if (!batch_tile_supported(t))
-    return fail(SV_ERR_ARG, "unsupported tile (ppl %d, threads %d, blocks/CU %d, tiles/item %d)", t.ppl, t.threads,
-                t.blocks_per_cu, t.tiles_per_item);
+    return fail(SV_ERR_ARG,
+                "unsupported tile (ppl %d, threads %d, blocks/CU %d, tiles/item %d, cull %d, culled blocks/CU %d, "
+                "gangs %d, divisors %d/%d)", t.ppl, t.threads, t.blocks_per_cu, t.tiles_per_item, t.cull,
+                t.cull_blocks_per_cu, t.cull_gangs, t.cull_div_linear, t.cull_div_spline);
   size_t need = 0;
   carve_batch(nullptr, *robot, *caps, &need);
   if (!ws || ws_bytes < need) return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", need, ws_bytes);
@@ -820,12 +837,6 @@ int sv_first_free(const sv_robot* robot, const sv_motions* motions, const sv_clo
   return e == hipSuccess ? SV_OK : hip_fail(e, "first free motion");
 }
 
-int sv_set_exact_culling(int on) {
-  g_cull = on != 0;
-  g_batch_cull = on != 0;
-  return SV_OK;
-}
-
 int sv_tile_candidates(sv_tile* tiles, int32_t capacity, int32_t* n) {
   if (!n) return fail(SV_ERR_ARG, "n is NULL");
   const std::vector<sv_tile> v = tile_candidates();
@@ -837,7 +848,7 @@ int sv_tile_candidates(sv_tile* tiles, int32_t capacity, int32_t* n) {
 
 int sv_default_tile(sv_tile* tile) {
   if (!tile) return fail(SV_ERR_ARG, "tile is NULL");
-  *tile = sv_tile{2, 256, 8, 4};
+  *tile = default_batch_tile();
   return SV_OK;
 }
 

@@ -37,6 +37,8 @@ struct BatchArgs {
   int tile_pts;  // points per tile (threads * ppl)
   int tpi;       // tiles per work item
   int culled;    // culled pass (1) or the persistent dense kernel (0)
+  int gangs;     // culled pass: queues of the persistent blocks (block index mod gangs)
+  int div_lin, div_spl;   // culled pass: sample-block divisors (cull_block_len)
   BatchWs w;
   unsigned long long* done_ticks;
   int* status_out;
@@ -147,8 +149,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchArgs a) {
     q.motion_off = (int)w.motion_off[r];
     q.n_points = (int)w.n_points[r];
     q.T = a.reqs[r].motions.T;
-    q.nb = cull_block_count(q.T, a.reqs[r].motions.kind);
-    q.blen = cull_block_len(q.T, a.reqs[r].motions.kind);
+    q.nb = cull_block_count(q.T, a.reqs[r].motions.kind, a.div_lin, a.div_spl);
+    q.blen = cull_block_len(q.T, a.reqs[r].motions.kind, a.div_lin, a.div_spl);
     q.list_off = (int)w.cand_off[p];
     q.tile_off = (int)w.tile_off[r];
     w.req[r] = q;
@@ -417,11 +419,11 @@ __device__ __forceinline__ void block_sphere(const BatchArgs& a, int64_t q) {
   const int k = (int)(gk - g * a.K);
   const int r = find_seg(w.motion_off, a.n_req, g);
   const int T = a.reqs[r].motions.T, kind = a.reqs[r].motions.kind;
-  const int nb = cull_block_count(T, kind);
+  const int nb = cull_block_count(T, kind, a.div_lin, a.div_spl);
   if (b >= nb || w.n_points[r] == 0) return;
   const int64_t m = g - w.motion_off[r];
   const CapEntry* e = w.table + (size_t)(w.sample_off[r] + m * T) * a.K + (size_t)k * T;
-  const int B = cull_block_len(T, kind);
+  const int B = cull_block_len(T, kind, a.div_lin, a.div_spl);
   const int t0 = b * B, t1 = min(t0 + B, T);
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int t = t0; t < t1; ++t) {
@@ -508,7 +510,8 @@ __device__ __forceinline__ void cull_list_step(const BatchArgs& a, int64_t c, in
     const int64_t g = w.motion_off[r] + m;
     const int64_t tile = w.tile_off[r] + t;
     keep = item_may_hit(w.tile_sph[tile], w.wave_sph + 4 * tile, w.spheres + ((size_t)g * a.K + k) * w.nb_max,
-                        cull_block_count(a.reqs[r].motions.T, a.reqs[r].motions.kind), key_dist(w.keys[g]));
+                        cull_block_count(a.reqs[r].motions.T, a.reqs[r].motions.kind, a.div_lin, a.div_spl),
+                        key_dist(w.keys[g]));
     g32 = (int)g;
     tk = (t << 4) | k;
   }
@@ -560,8 +563,9 @@ __global__ __launch_bounds__(256) void k_batch_counts(BatchArgs a) {
 __global__ void k_batch_gangs(BatchArgs a) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const BatchWs& w = a.w;
-  int load[kGangs], cnt[kGangs];
-  for (int g = 0; g < kGangs; ++g) {
+  const int G = a.gangs;
+  int load[kMaxGangs], cnt[kMaxGangs];
+  for (int g = 0; g < G; ++g) {
     load[g] = 0;
     cnt[g] = 0;
     w.gang_head[g] = 0;
@@ -573,13 +577,13 @@ __global__ void k_batch_gangs(BatchArgs a) {
     const int items = w.fill[r];
     if (items == 0) continue;
     int best = 0;
-    for (int g = 1; g < kGangs; ++g) best = load[g] < load[best] ? g : best;
+    for (int g = 1; g < G; ++g) best = load[g] < load[best] ? g : best;
     w.gang_req[best * R + cnt[best]] = r;
     w.gang_off[best * (R + 1) + cnt[best]] = load[best];
     load[best] += items;
     ++cnt[best];
   }
-  for (int g = 0; g < kGangs; ++g) {
+  for (int g = 0; g < G; ++g) {
     w.gang_off[g * (R + 1) + cnt[g]] = load[g];
     w.gang_n[g] = cnt[g];
     w.gang_total[g] = load[g];
@@ -604,7 +608,7 @@ __device__ void claim_item(const BatchArgs& a, int* gang, int g0, int* r, int* s
       *slot = w.req[*r].list_off + ((int)idx - off[lo]);
       return;
     }
-    *gang = (g + 1) % kGangs;
+    *gang = (g + 1) % a.gangs;
     if (*gang == g0) {
       *r = -1;
       return;
@@ -623,7 +627,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
   __shared__ unsigned long long wexec[NT / 64];
   __shared__ int s_last, s_band, s_r, s_slot;
   const BatchWs& w = a.w;
-  const int g0 = blockIdx.x % kGangs;
+  const int g0 = blockIdx.x % a.gangs;
   int gang = g0;   // thread 0's current queue
   unsigned long long executed = 0;
   int cur = -1, pending = 0;   // request of the current run, items retired in it (block-uniform)
@@ -782,13 +786,32 @@ hipError_t launch_exact_batch(const BatchArgs& a, int blocks, hipStream_t st) {
 
 }  // namespace
 
-bool g_batch_cull = true;
+sv_tile default_batch_tile() {
+  sv_tile t{};
+  t.ppl = 2;
+  t.threads = 256;
+  t.blocks_per_cu = 8;
+  t.tiles_per_item = 4;
+  t.cull = 1;
+  t.cull_blocks_per_cu = 0;
+  t.cull_gangs = 8;
+  t.cull_div_linear = kCullDivLinear;
+  t.cull_div_spline = kCullDivSpline;
+  return t;
+}
 
 bool batch_tile_supported(const sv_tile& t) {
   const bool ppl = t.ppl == 1 || t.ppl == 2 || t.ppl == 4;
   const bool thr = t.threads == 64 || t.threads == 128 || t.threads == 256;
-  return ppl && thr && t.blocks_per_cu >= 1 && t.blocks_per_cu <= 32 && t.tiles_per_item >= 1 &&
-         t.tiles_per_item <= 64;
+  const bool unculled = ppl && thr && t.blocks_per_cu >= 1 && t.blocks_per_cu <= 32 && t.tiles_per_item >= 1 &&
+                        t.tiles_per_item <= 64;
+  bool dl = false, ds = false;
+  for (int d : kCullDivsLinear) dl = dl || t.cull_div_linear == d;
+  for (int d : kCullDivsSpline) ds = ds || t.cull_div_spline == d;
+  const bool gangs = t.cull_gangs == 1 || t.cull_gangs == 2 || t.cull_gangs == 4 || t.cull_gangs == 8 ||
+                     t.cull_gangs == 16;
+  const bool culled = t.cull_blocks_per_cu >= 0 && t.cull_blocks_per_cu <= 8 && gangs && dl && ds;
+  return (t.cull == 0 || t.cull == 1) && unculled && culled;
 }
 
 BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, size_t* bytes) {
@@ -845,11 +868,11 @@ BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, siz
   w.list_tk = cv.take<int>((size_t)w.cand_cap);
   w.req = cv.take<BatchReq>(R);
   w.fill = cv.take<int>(R);
-  w.gang_n = cv.take<int>(kGangs);
-  w.gang_total = cv.take<int>(kGangs);
-  w.gang_head = cv.take<unsigned>(kGangs);
-  w.gang_req = cv.take<int>(kGangs * R);
-  w.gang_off = cv.take<int>(kGangs * (R + 1));
+  w.gang_n = cv.take<int>(kMaxGangs);
+  w.gang_total = cv.take<int>(kMaxGangs);
+  w.gang_head = cv.take<unsigned>(kMaxGangs);
+  w.gang_req = cv.take<int>(kMaxGangs * R);
+  w.gang_off = cv.take<int>(kMaxGangs * (R + 1));
   *bytes = cv.off;
   return w;
 }
@@ -871,7 +894,10 @@ hipError_t launch_batch(const sv_robot& rb, const sv_request* reqs, int n_req, c
   a.band = band;
   a.tile_pts = tile.ppl * tile.threads;
   a.tpi = tile.tiles_per_item;
-  a.culled = g_batch_cull ? 1 : 0;
+  a.culled = tile.cull;
+  a.gangs = tile.cull_gangs;
+  a.div_lin = tile.cull_div_linear;
+  a.div_spl = tile.cull_div_spline;
   a.w = w;
   a.done_ticks = done_ticks;
   a.status_out = status;
@@ -902,8 +928,11 @@ hipError_t launch_batch(const sv_robot& rb, const sv_request* reqs, int n_req, c
     hipLaunchKernelGGL(k_batch_cull_list, dim3(capped(grid_for(w.cand_cap, 256))), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_batch_counts, dim3(std::max(n_req, 1)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_batch_gangs, dim3(1), dim3(64), 0, st, a);
-    hipLaunchKernelGGL((k_batch_cull<kCullP, kCullNT>), dim3(resident_blocks<k_batch_cull<kCullP, kCullNT>>(kCullNT)),
-                       dim3(kCullNT), 0, st, a);
+    const unsigned resident = resident_blocks<k_batch_cull<kCullP, kCullNT>>(kCullNT);
+    const unsigned cgrid = tile.cull_blocks_per_cu > 0
+                               ? std::min<unsigned>(resident, (unsigned)(device_cus() * tile.cull_blocks_per_cu))
+                               : resident;
+    hipLaunchKernelGGL((k_batch_cull<kCullP, kCullNT>), dim3(cgrid), dim3(kCullNT), 0, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   } else {
 #define SV_BATCH_CASE(P, NT) \

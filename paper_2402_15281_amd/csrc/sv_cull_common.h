@@ -16,25 +16,35 @@ namespace sv {
 namespace {
 
 constexpr float kCullMargin = 1e-5f;   // m, above the FP32 rounding of the bounds
-// Samples per bounding block (2 to 16): a block spans about 1/32 of a linear motion and
-// 1/64 of a spline, whose path through two via points is several times longer, so
-// that its sphere stays tight at every T.  Shorter blocks cost more sphere tests, longer
-// ones skip fewer segment tests; the divisors are measured optima (bin-picking
-// workloads, T = 64 to 1024).
-__host__ __device__ constexpr int cull_block_len(int T, int kind) {
-  return T >= 16 * (kind == SV_SPLINE ? 64 : 32) ? 16
-       : T <= 2 * (kind == SV_SPLINE ? 64 : 32) ? 2
-       : (T + (kind == SV_SPLINE ? 63 : 31)) / (kind == SV_SPLINE ? 64 : 32);
+// Samples per bounding block (2 to 16): a block spans about 1/div of a motion, div = 32
+// for a linear motion and 64 for a spline (whose path through two via points is several
+// times longer), so that its sphere stays tight at every T.  Shorter blocks cost more
+// sphere tests, longer ones skip fewer segment tests; these divisors are measured optima
+// of the per-call pass (bin-picking workloads, T = 64 to 1024), and the batched pass
+// takes them from its launch shape (sv_tile), where an autotuner may choose others
+// (kCullDivLinear, kCullDivSpline and the allowed sets are in sv_internal.h).
+__host__ __device__ constexpr int cull_block_len_div(int T, int div) {
+  return T >= 16 * div ? 16 : T <= 2 * div ? 2 : (T + div - 1) / div;
 }
-__host__ __device__ constexpr int cull_block_count(int T, int kind) {
-  return (T + cull_block_len(T, kind) - 1) / cull_block_len(T, kind);
+__host__ __device__ constexpr int cull_block_len(int T, int kind, int div_lin = kCullDivLinear,
+                                                 int div_spl = kCullDivSpline) {
+  return cull_block_len_div(T, kind == SV_SPLINE ? div_spl : div_lin);
 }
-// The largest block count of any T <= max_T and either kind (from T = 1024 on, blocks
-// have 16 samples and the count grows with T).
+__host__ __device__ constexpr int cull_block_count(int T, int kind, int div_lin = kCullDivLinear,
+                                                   int div_spl = kCullDivSpline) {
+  return (T + cull_block_len(T, kind, div_lin, div_spl) - 1) / cull_block_len(T, kind, div_lin, div_spl);
+}
+// The largest block count of any T <= max_T under any allowed divisor (from T = 16 div on,
+// blocks have 16 samples and the count grows with T).
 inline int cull_block_count_max(int max_T) {
-  int nb = max_T >= 1024 ? cull_block_count(max_T, SV_LINEAR) : 1;
-  for (int T = 1; T <= max_T && T < 1024; ++T)
-    for (int kind : {SV_LINEAR, SV_SPLINE}) nb = nb > cull_block_count(T, kind) ? nb : cull_block_count(T, kind);
+  int nb = 1;
+  for (int d : {16, 32, 64, 128}) {
+    for (int T = 1; T <= max_T && T < 16 * d; ++T) {
+      const int c = (T + cull_block_len_div(T, d) - 1) / cull_block_len_div(T, d);
+      nb = nb > c ? nb : c;
+    }
+    if (max_T >= 16 * d) nb = nb > (max_T + 15) / 16 ? nb : (max_T + 15) / 16;
+  }
   return nb;
 }
 constexpr int kSeedSamples = 32;      // the seed bound visits about this many samples of a motion

@@ -128,10 +128,16 @@ struct BatchReq {
   int blen;                        // samples per sample block
 };
 
-// The culled batched kernel's blocks form kGangs gangs (block index mod kGangs, one
-// gang per XCD under the round-robin dispatch of workgroups to XCDs).  Each gang has a
-// queue over the requests assigned to it; an idle gang takes items from the others.
-constexpr int kGangs = 8;
+// The culled batched kernel's blocks form tile.cull_gangs gangs (block index mod gangs;
+// 8, the default, puts one gang on each XCD under the round-robin dispatch of workgroups
+// to XCDs).  Each gang has a queue over the requests assigned to it; an idle gang takes
+// items from the others.  Arrays are sized for kMaxGangs.
+constexpr int kMaxGangs = 16;
+// Sample-block divisors of the culled passes (a block spans about 1/div of a motion):
+// the defaults, and the sets a launch shape may choose (sv_tile.cull_div_linear,
+// cull_div_spline).
+constexpr int kCullDivLinear = 32, kCullDivSpline = 64;
+constexpr int kCullDivsLinear[3] = {16, 32, 64}, kCullDivsSpline[3] = {32, 64, 128};
 
 // Workspace of a batch call: per-request arrays [max_requests] (offsets [+1]), keys
 // [max_motions], capsule table [max_samples * K], band arrays [max_band].
@@ -163,18 +169,17 @@ struct BatchWs {
   int *list_g, *list_tk;                          // [cand_cap] motion, tile << 4 | capsule
   BatchReq* req;                                  // [max_requests]
   int* fill;                                      // [max_requests] listed items per request
-  int* gang_n;                                    // [kGangs] requests per gang
-  int* gang_total;                                // [kGangs] items per gang
-  unsigned* gang_head;                            // [kGangs] queue heads
-  int* gang_req;                                  // [kGangs][max_requests] requests in gang order
-  int* gang_off;                                  // [kGangs][max_requests + 1] their first gang item
+  int* gang_n;                                    // [kMaxGangs] requests per gang
+  int* gang_total;                                // [kMaxGangs] items per gang
+  unsigned* gang_head;                            // [kMaxGangs] queue heads
+  int* gang_req;                                  // [kMaxGangs][max_requests] requests in gang order
+  int* gang_off;                                  // [kMaxGangs][max_requests + 1] their first gang item
   int64_t point_cap, tile_cap, cand_cap, bin_cap;
   int nb_max;
 };
 
 bool batch_tile_supported(const sv_tile& t);
-// The culled batched pass, on unless switched off for measurement (sv_set_exact_culling).
-extern bool g_batch_cull;
+sv_tile default_batch_tile();
 
 // Carves ws (NULL: only sizes); *bytes = total.
 BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, size_t* bytes);
@@ -332,7 +337,7 @@ size_t train_part_w1_elems(const MlpArgs& n, int64_t Bp);
 hipError_t launch_train_step(const MlpArgs& net, const float* samples, const int* idx, int B, int Bp, __bf16* aT,
                              __bf16* dzT, float* h0T, float* y, float* dy, const __bf16* packed,
                              const __bf16* packedT, float* grad, float* part_w, float* part_w1, float sigma,
-                             float* loss_out, hipStream_t st);
+                             int clamp_pred, float* loss_out, hipStream_t st);
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
                        float eps, int64_t step, hipStream_t st);
 

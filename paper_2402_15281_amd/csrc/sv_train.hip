@@ -1,8 +1,8 @@
 // Training step of the swept-volume network on samples (x, q0, q1, delta) produced by
 // the exact check (paper Sec. IV-C: training tuples; Sec. V: Adam with PyTorch's
 // default constants).  Loss: mean over the batch of |y - clamp(delta)|, clamp to
-// [-sigma, sigma] (targets only: a clamped prediction would have no gradient beyond
-// sigma, where Adam's first updates leave a wide network).  BF16 hidden layers on
+// [-sigma, sigma] on the targets only, or mean |clamp(y) - clamp(delta)| (clamp_pred;
+// DeepSDF's form: no gradient where |y| >= sigma).  BF16 hidden layers on
 // MFMA with FP32 accumulation, FP32 first and output layers, FP32 master weights,
 // FP32 Adam state.
 //
@@ -52,6 +52,7 @@ struct TrainArgs {
   const __bf16* packed;   // forward operands, layers 2..L
   const __bf16* packedT;  // backward operands, layers 2..L
   float* grad;            // [n_params]
+  int clamp_pred;         // 1: the loss clamps the prediction as well as the target
 };
 
 // Parameter offsets of the flat vector (see sv_mlp in sv.h), 1-based layer l.
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_fwd(TrainArgs a
   }
 }
 
-// dy of 256 rows per block and the block's sum of |y - clamp(delta)| (fixed-order tree)
+// dy of 256 rows per block and the block's sum of the clamped L1 terms (fixed-order tree)
 // into part[block]; k_train_loss_sum adds the partials in a fixed order.
 __global__ __launch_bounds__(256) void k_train_loss(TrainArgs a, float sigma, float* __restrict__ part) {
   __shared__ float red[256];
@@ -252,9 +253,11 @@ __global__ __launch_bounds__(256) void k_train_loss(TrainArgs a, float sigma, fl
   if (b < a.B) {
     const float yv = a.y[b];
     const float d = a.samples[(size_t)a.idx[b] * (in_dim + 1) + in_dim];
-    const float r = yv - fminf(fmaxf(d, -sigma), sigma);
+    const bool live = !a.clamp_pred || fabsf(yv) < sigma;   // d clamp(y) / dy
+    const float yc = a.clamp_pred ? fminf(fmaxf(yv, -sigma), sigma) : yv;
+    const float r = yc - fminf(fmaxf(d, -sigma), sigma);
     s = fabsf(r);
-    g = (r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f)) / (float)a.B;
+    g = live ? (r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f)) / (float)a.B : 0.f;
   }
   a.dy[b] = g;
   red[threadIdx.x] = s;
@@ -655,8 +658,8 @@ size_t train_part_w1_elems(const MlpArgs& n, int64_t Bp) {
 hipError_t launch_train_step(const MlpArgs& net, const float* samples, const int* idx, int B, int Bp, __bf16* aT,
                              __bf16* dzT, float* h0T, float* y, float* dy, const __bf16* packed,
                              const __bf16* packedT, float* grad, float* part_w, float* part_w1, float sigma,
-                             float* loss_out, hipStream_t st) {
-  TrainArgs a{net, samples, idx, B, Bp, aT, dzT, h0T, y, dy, packed, packedT, grad};
+                             int clamp_pred, float* loss_out, hipStream_t st) {
+  TrainArgs a{net, samples, idx, B, Bp, aT, dzT, h0T, y, dy, packed, packedT, grad, clamp_pred};
   switch (net.width) {
     case 128: return launch_train_t<128>(a, part_w, part_w1, sigma, loss_out, st);
     case 256: return launch_train_t<256>(a, part_w, part_w1, sigma, loss_out, st);

@@ -41,17 +41,33 @@ class DataRecipe:
 
 @dataclass
 class TrainRecipe:
+    """Adam at lr (Sec. V: PyTorch's defaults) for `epochs` passes over the rows.
+
+    schedule: "constant", or "plateau": the learning rate is multiplied by
+    plateau_factor after plateau_patience epochs without a new best held-out loss
+    (the paper's ReduceLROnPlateau with factor 0.1 and patience 10 over 200 epochs,
+    Sec. V; needs validation rows).  keep_best: end with the weights of the epoch
+    with the best held-out loss (the paper tests the checkpoint with the best
+    validation loss).  clamp_pred: clamp the predictions in the loss as well as the
+    targets (sv_train_hparams.clamp_pred)."""
     epochs: int = 20
     batch: int = 65536
     lr: float = 1e-3
     clamp_sigma: float = 0.1
     seed: int = 7
+    schedule: str = "constant"
+    plateau_factor: float = 0.1
+    plateau_patience: int = 10
+    keep_best: bool = False
+    clamp_pred: bool = False
 
 
 @dataclass
 class TrainLog:
     epoch_loss: list = field(default_factory=list)
     val_mae: list = field(default_factory=list)
+    lr: list = field(default_factory=list)
+    best_epoch: int = -1
     steps: int = 0
     seconds: float = 0.0
     n_short: int = 0
@@ -219,24 +235,42 @@ def train(mlp, samples, recipe: TrainRecipe, val_rows=None, log=None, device="cu
         # to the device is queued behind the running steps instead of waiting for them
         return torch.from_numpy(svgen.permutation(recipe.seed * 7919 + ep, n)).pin_memory()
 
+    if recipe.schedule not in ("constant", "plateau"):
+        raise ValueError(f"unknown schedule {recipe.schedule!r}")
+    if (recipe.schedule == "plateau" or recipe.keep_best) and val_rows is None:
+        raise ValueError("the plateau schedule and keep_best need validation rows")
+    lr = recipe.lr
+    best, since_best, best_params = math.inf, 0, None
     order = epoch_order(0)
     for ep in range(recipe.epochs):
         perm = order.to(device, non_blocking=True)
         ep_loss = torch.zeros(1, dtype=torch.float32, device=device)
+        tl.lr.append(lr)
         for s in range(steps_per_epoch):
             idx = perm[s * recipe.batch:(s + 1) * recipe.batch]
             step += 1
-            sv.sv_train_step(mlp, m, v, step, samples, idx, lr=recipe.lr, clamp_sigma=recipe.clamp_sigma,
-                             loss_out=loss, ws=ws)
+            sv.sv_train_step(mlp, m, v, step, samples, idx, lr=lr, clamp_sigma=recipe.clamp_sigma,
+                             loss_out=loss, ws=ws, clamp_pred=recipe.clamp_pred)
             ep_loss += loss * idx.shape[0]
         if ep + 1 < recipe.epochs:
             order = epoch_order(ep + 1)       # on the host while the GPU runs this epoch
         tl.epoch_loss.append(float(ep_loss.item()) / n)
         if val_rows is not None:
             tl.val_mae.append(val_mae(mlp, val_rows, recipe.clamp_sigma))
+            if tl.val_mae[-1] < best:
+                best, since_best, tl.best_epoch = tl.val_mae[-1], 0, ep
+                if recipe.keep_best:
+                    best_params = mlp.params.clone()
+            else:
+                since_best += 1
+                if recipe.schedule == "plateau" and since_best > recipe.plateau_patience:
+                    lr *= recipe.plateau_factor
+                    since_best = 0
         if log:
-            log(f"epoch {ep + 1}/{recipe.epochs}: loss {tl.epoch_loss[-1]:.5f}"
+            log(f"epoch {ep + 1}/{recipe.epochs}: lr {tl.lr[-1]:.1e}, loss {tl.epoch_loss[-1]:.5f}"
                 + (f", val clamped MAE {tl.val_mae[-1] * 1e3:.2f} mm" if val_rows is not None else ""))
+    if best_params is not None:
+        mlp.params.copy_(best_params)
     torch.cuda.synchronize()
     tl.steps = step
     tl.seconds = time.perf_counter() - t0

@@ -32,17 +32,12 @@ def sv():
     return _binding
 
 
-class culling:
-    """Context: exact-check culling on or off (both the per-call and the batched pass)."""
-
-    def __init__(self, sv, on):
-        self.sv, self.on = sv, on
-
-    def __enter__(self):
-        self.sv.sv_set_exact_culling(self.on)
-
-    def __exit__(self, *exc):
-        self.sv.sv_set_exact_culling(True)
+def tile(sv, **fields):
+    """The default launch shape with some fields replaced (cull=0: the unculled kernel)."""
+    t = sv.sv_default_tile()
+    for k, v in fields.items():
+        setattr(t, k, v)
+    return t
 
 
 def make_batch(sv, arm, specs, seed):
@@ -69,11 +64,11 @@ def results(reqs):
             for _, _, o in reqs.requests]
 
 
-def per_request(sv, robot, reqs, eps=EPS):
+def per_request(sv, robot, reqs, eps=EPS, unculled=False):
     out = []
     for m, c, _ in reqs.requests:
         o = sv.DeviceResults(m.n)
-        sv.sv_check_motions(robot, m, c, o, eps)
+        sv.sv_check_motions(robot, m, c, o, eps, unculled=unculled)
         out.append(o)
     torch.cuda.synchronize()
     return [(o.min_dist.cpu().numpy(), o.argmin.cpu().numpy(), o.verdict.cpu().numpy()) for o in out]
@@ -137,12 +132,12 @@ def test_every_launch_shape_bitwise(sv, ppl):
     caps = reqs.caps(max_band=8)
     ref = per_request(sv, robot, reqs)
     ws = sv.workspace(sv.sv_batch_workspace_size(robot, caps))
-    with culling(sv, False):
-        for threads in (64, 128, 256):
-            for bpc, tpi in ((1, 1), (3, 2), (8, 64), (32, 5)):
-                poison(reqs)
-                sv.sv_check_requests(robot, reqs, caps, EPS, tile=sv.sv_tile(ppl, threads, bpc, tpi), ws=ws)
-                assert_bitwise(results(reqs), ref)
+    for threads in (64, 128, 256):
+        for bpc, tpi in ((1, 1), (3, 2), (8, 64), (32, 5)):
+            poison(reqs)
+            sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws,
+                                 tile=tile(sv, cull=0, ppl=ppl, threads=threads, blocks_per_cu=bpc, tiles_per_item=tpi))
+            assert_bitwise(results(reqs), ref)
 
 
 CULL_MIX = [(40, 20000, 64, "spline"), (3, 9000, 17, "linear"), (0, 3000, 64, "spline"), (25, 0, 48, "linear"),
@@ -161,15 +156,16 @@ def test_culled_batch_equals_unculled(sv, specs):
     caps = reqs.caps(max_band=16)
     ws = sv.workspace(sv.sv_batch_workspace_size(robot, caps))
     status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
-    with culling(sv, False):
+    poison(reqs)
+    sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, status=status, tile=tile(sv, cull=0))
+    dense = results(reqs)
+    assert int(status.item()) == 0
+    assert_bitwise(dense, per_request(sv, robot, reqs, unculled=True))
+    shapes = [None, None, tile(sv, cull_div_linear=16, cull_div_spline=32, cull_gangs=2),
+              tile(sv, cull_div_linear=64, cull_div_spline=128, cull_gangs=16, cull_blocks_per_cu=1)]
+    for shape in shapes:   # the default twice (workspace reuse), then extreme sample blocks and gangs
         poison(reqs)
-        sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, status=status)
-        dense = results(reqs)
-        assert int(status.item()) == 0
-        assert_bitwise(dense, per_request(sv, robot, reqs))
-    for rep in range(2):
-        poison(reqs)
-        sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, status=status)
+        sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, status=status, tile=shape)
         assert_bitwise(results(reqs), dense)
         assert int(status.item()) == 0
     assert_bitwise(per_request(sv, robot, reqs), dense)
@@ -204,11 +200,10 @@ def test_total_points_capacity(sv):
 
 @pytest.mark.parametrize("culled", [True, False], ids=["culled", "unculled"])
 def test_graph_capture_and_replay_with_new_contents(sv, culled):
-    with culling(sv, culled):
-        graph_replay_case(sv)
+    graph_replay_case(sv, tile(sv, cull=int(culled)))
 
 
-def graph_replay_case(sv):
+def graph_replay_case(sv, shape):
     arm = svgen.make_arm(1)
     robot = sv.make_robot(arm)
     specs = [(5, 800, 48, "spline"), (1, 3000, 48, "linear"), (9, 150, 48, "spline")]
@@ -217,14 +212,15 @@ def graph_replay_case(sv):
     ws = sv.workspace(sv.sv_batch_workspace_size(robot, caps))
     ticks = torch.zeros(reqs.n + 1, dtype=torch.int64, device="cuda")
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
-    sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, done_ticks=ticks, status=status)   # warm-up, eager
+    sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, done_ticks=ticks, status=status, tile=shape)   # eager
     eager = results(reqs)
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
         with torch.cuda.graph(g, stream=s):
-            sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, done_ticks=ticks, status=status, stream=s)
+            sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, done_ticks=ticks, status=status, stream=s,
+                                 tile=shape)
     torch.cuda.current_stream().wait_stream(s)
     for rep in range(3):
         poison(reqs)
@@ -286,8 +282,13 @@ def test_status_word_and_host_checks(sv):
         sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, n_req=caps.max_requests + 1)
     assert e.value.status == -2
     with pytest.raises(sv.SvError) as e:
-        sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, tile=sv.sv_tile(3, 256, 8, 4))
+        sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, tile=tile(sv, ppl=3))
     assert e.value.status == -1
+    for bad in (dict(cull=2), dict(cull_gangs=3), dict(cull_gangs=32), dict(cull_div_linear=48),
+                dict(cull_div_spline=16), dict(cull_blocks_per_cu=9), dict(cull_blocks_per_cu=-1)):
+        with pytest.raises(sv.SvError) as e:
+            sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, tile=tile(sv, **bad))
+        assert e.value.status == -1, bad
     with pytest.raises(sv.SvError) as e:
         sv.sv_check_requests(robot, reqs, caps, EPS, ws=torch.empty(64, dtype=torch.uint8, device="cuda"))
     assert e.value.status == -3
@@ -340,9 +341,16 @@ def test_requests_workload_full_size(sv, orc):
     got = results(reqs)
     assert int(status.item()) == 0
     assert_bitwise(got, per_request(sv, robot, reqs))
-    with culling(sv, False):
+    poison(reqs)
+    sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, status=status, tile=tile(sv, cull=0))
+    assert_bitwise(results(reqs), got)
+    # the culled pass under other launch shapes (gangs, blocks, sample-block divisors)
+    for fields in (dict(cull_gangs=1, cull_blocks_per_cu=1), dict(cull_gangs=16, cull_div_linear=16,
+                                                                   cull_div_spline=128),
+                   dict(cull_gangs=4, cull_blocks_per_cu=2, cull_div_linear=64, cull_div_spline=32)):
         poison(reqs)
-        sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, status=status)
+        sv.sv_check_requests(robot, reqs, caps, EPS, ws=ws, status=status, tile=tile(sv, **fields))
+        assert int(status.item()) == 0
         assert_bitwise(results(reqs), got)
     order = np.argsort([r.motions.n * r.cloud.shape[0] for r in rq])
     for ri in order[:3]:

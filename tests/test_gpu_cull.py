@@ -26,16 +26,13 @@ def sv():
 
 
 def check(sv, arm, motions, pts, eps, cull, mlp=None, screen=0, tau=0.0):
-    sv.sv_set_exact_culling(cull)
-    try:
-        dm, dc = sv.DeviceMotions(motions), sv.DeviceCloud(pts)
-        out = sv.DeviceResults(dm.n)
-        ws = sv.sv_check_motions(sv.make_robot(arm), dm, dc, out, eps, mlp=mlp, screen=screen, tau=tau)
-        torch.cuda.synchronize()
-        return (out.min_dist.cpu().numpy(), out.argmin.cpu().numpy(), out.verdict.cpu().numpy(),
-                sv.executed_tests(ws))
-    finally:
-        sv.sv_set_exact_culling(True)
+    dm, dc = sv.DeviceMotions(motions), sv.DeviceCloud(pts)
+    out = sv.DeviceResults(dm.n)
+    ws = sv.sv_check_motions(sv.make_robot(arm), dm, dc, out, eps, mlp=mlp, screen=screen, tau=tau,
+                             unculled=not cull)
+    torch.cuda.synchronize()
+    return (out.min_dist.cpu().numpy(), out.argmin.cpu().numpy(), out.verdict.cpu().numpy(),
+            sv.executed_tests(ws))
 
 
 def assert_same(a, b):

@@ -2,9 +2,10 @@
 
 Workload: 512 linear motions x 20,000 bin points (10.24M pairs), T = 256, eps = 1 cm,
 tau = 3 cm, with the 15 -> 8 x 512 -> 1 softplus network trained on the GPU by the
-library's own kernels on a short schedule (1M rows from the exact check, 4 epochs of
-65,536-row batches), so that its predictions send a realistic share of points to the
-exact check instead of all or none.
+library's own kernels on a short schedule (2.5M rows from the exact check, 16 epochs of
+65,536-row batches, about 610 steps), so that its predictions send a realistic share of
+points to the exact check instead of all or none (4 epochs over 1M rows, 61 steps, left
+every prediction below tau).
 
 Checks:
   - certified screening: the verdicts of all 512 motions equal the exact check's
@@ -43,9 +44,9 @@ def setup(sv):
     motions = svgen.make_motions(arm, w["n_motions"], w["T"], w["motion_seed"])
     pts = svgen.bin_cloud(w["n_points"], w["cloud_seed"])
     shape = w["mlp"]
-    samples, _ = tr.make_dataset(arm, tr.DataRecipe(n_motions=2000, chunk=2000), seed=501)
+    samples, _ = tr.make_dataset(arm, tr.DataRecipe(n_motions=5000, chunk=2500), seed=501)
     mlp = sv.DeviceMLP(tr.init_params(svgen.MLPSpec(*shape), 502), *shape)
-    tr.train(mlp, samples, tr.TrainRecipe(epochs=4, batch=65536))
+    tr.train(mlp, samples, tr.TrainRecipe(epochs=16, batch=65536))
     del samples
     return w, arm, motions, pts, shape, mlp
 

@@ -10,7 +10,6 @@ certified confirmation, FP64 band recheck) can be captured once and replayed.  B
 - after new motions and points are copied into the captured buffers, a replay equals
   an eager call on the new contents bit for bit.
 """
-import contextlib
 
 import numpy as np
 import pytest
@@ -28,15 +27,6 @@ def sv():
     from paper_2402_15281_amd import _binding
     assert torch.cuda.is_available()
     return _binding
-
-
-@contextlib.contextmanager
-def culling(sv, on):
-    sv.sv_set_exact_culling(on)
-    try:
-        yield
-    finally:
-        sv.sv_set_exact_culling(True)
 
 
 def results(out):
@@ -69,44 +59,44 @@ def test_check_motions_graph_replay(sv, mode):
     if mode == "certified":
         spec = svgen.MLPSpec(15, 256, 4)
         mlp, screen = sv.DeviceMLP(svgen.mlp_init(spec, 1302), 15, 256, 4), sv.SV_SCREEN_CERTIFIED
-    with culling(sv, mode != "dense"):
-        ws = sv.workspace(sv.sv_workspace_size(sv.SV_OP_CHECK, robot, dm, dc, mlp))
+    ws = sv.workspace(sv.sv_workspace_size(sv.SV_OP_CHECK, robot, dm, dc, mlp))
 
-        def call(stream=None):
-            sv.sv_check_motions(robot, dm, dc, out, EPS, mlp=mlp, screen=screen, tau=TAU, ws=ws, stream=stream)
+    def call(stream=None):
+        sv.sv_check_motions(robot, dm, dc, out, EPS, mlp=mlp, screen=screen, tau=TAU, ws=ws, stream=stream,
+                            unculled=mode == "dense")
 
-        call()   # eager warm-up and reference
-        torch.cuda.synchronize()
-        eager = results(out)
-        g = torch.cuda.CUDAGraph()
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            with torch.cuda.graph(g, stream=s):
-                call(s)
-        torch.cuda.current_stream().wait_stream(s)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            poison(out, mlp is not None)
-            torch.cuda.synchronize()
-            g.replay()
-            torch.cuda.synchronize()
-            assert_same(results(out), eager)
-            _ = torch.randn(1000, device="cuda").sum().item()   # unrelated eager work between replays
-        # new contents in the captured buffers
-        mo2 = svgen.make_motions(arm, 24, 64, 1310)
-        dm.q0.copy_(torch.as_tensor(mo2.q0, dtype=torch.float32))
-        dm.q1.copy_(torch.as_tensor(mo2.q1, dtype=torch.float32))
-        dc.xyz.copy_(sv.DeviceCloud(svgen.bin_cloud(2500, 1311)).xyz)
+    call()   # eager warm-up and reference
+    torch.cuda.synchronize()
+    eager = results(out)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            call(s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for _ in range(3):
         poison(out, mlp is not None)
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        replayed = results(out)
-        poison(out, mlp is not None)
-        call()
-        torch.cuda.synchronize()
-        fresh = results(out)
-        assert_same(replayed, fresh)
-        assert not np.array_equal(replayed[0], eager[0])
-        print(f"{mode}: {int(fresh[2].sum())} of {dm.n} motions colliding after the new contents")
+        assert_same(results(out), eager)
+        _ = torch.randn(1000, device="cuda").sum().item()   # unrelated eager work between replays
+    # new contents in the captured buffers
+    mo2 = svgen.make_motions(arm, 24, 64, 1310)
+    dm.q0.copy_(torch.as_tensor(mo2.q0, dtype=torch.float32))
+    dm.q1.copy_(torch.as_tensor(mo2.q1, dtype=torch.float32))
+    dc.xyz.copy_(sv.DeviceCloud(svgen.bin_cloud(2500, 1311)).xyz)
+    poison(out, mlp is not None)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    replayed = results(out)
+    poison(out, mlp is not None)
+    call()
+    torch.cuda.synchronize()
+    fresh = results(out)
+    assert_same(replayed, fresh)
+    assert not np.array_equal(replayed[0], eager[0])
+    print(f"{mode}: {int(fresh[2].sum())} of {dm.n} motions colliding after the new contents")

@@ -109,12 +109,15 @@ def many_rows(sv):
     return out
 
 
-@pytest.mark.parametrize("shape,B,sigma", [((15, 128, 3), 200, 0.1), ((15, 256, 2), 512, 10.0),
-                                           ((15, 512, 4), 300, 0.1), ((15, 512, 8), 640, 10.0),
-                                           ((15, 128, 1), 100, 10.0), ((15, 512, 8), 4096, 0.1),
-                                           ((15, 512, 8), 5000, 0.1), ((15, 512, 8), 65536, 0.1),
-                                           ((15, 256, 3), 65536, 10.0)])
-def test_train_gradient_matches_oracle(sv, many_rows, shape, B, sigma):
+# clamp_pred cases: sigma = 7 mm sits inside the spread of the initial predictions of the
+# 15 -> 3 x 256 -> 1 network (|y| from about 4 to 10 mm), so part of the batch lies in the
+# clamp's dead zone
+@pytest.mark.parametrize("shape,B,sigma,clamp_pred", [
+    ((15, 128, 3), 200, 0.1, False), ((15, 256, 2), 512, 10.0, False), ((15, 512, 4), 300, 0.1, False),
+    ((15, 512, 8), 640, 10.0, False), ((15, 128, 1), 100, 10.0, False), ((15, 512, 8), 4096, 0.1, False),
+    ((15, 512, 8), 5000, 0.1, False), ((15, 512, 8), 65536, 0.1, False), ((15, 256, 3), 65536, 10.0, False),
+    ((15, 256, 3), 640, 0.007, True), ((15, 256, 3), 5000, 0.007, True)])
+def test_train_gradient_matches_oracle(sv, many_rows, shape, B, sigma, clamp_pred):
     from paper_2402_15281_amd import train as tr
     arm = svgen.make_arm(1)
     if B <= 1200:
@@ -131,13 +134,18 @@ def test_train_gradient_matches_oracle(sv, many_rows, shape, B, sigma):
     g = torch.zeros(n, device="cuda")
     loss = torch.zeros(1, device="cuda")
     sv.sv_train_step(mlp, m, v, 1, out, torch.as_tensor(idx, device="cuda"), lr=0.0, clamp_sigma=sigma,
-                     loss_out=loss, grad_out=g)
+                     loss_out=loss, grad_out=g, clamp_pred=clamp_pred)
     torch.cuda.synchronize()
     X = rows[idx, :15]
     t = rows[idx, 15]
     # the loss's sign and clamp decisions are taken on the BF16-rounding predictions
     decide = om.forward_bf16(flat.astype(np.float64), *shape, X)
-    ref_loss, ref_g = om.loss_and_grad(flat.astype(np.float64), *shape, X, t, sigma, decide=decide)
+    if clamp_pred:
+        dead = float(np.mean(np.abs(decide) >= sigma))
+        print(f"predictions in the clamp's dead zone: {dead:.3f}")
+        assert 0.05 < dead < 0.95
+    ref_loss, ref_g = om.loss_and_grad(flat.astype(np.float64), *shape, X, t, sigma, decide=decide,
+                                       clamp_pred=clamp_pred)
     gg = g.cpu().numpy().astype(np.float64)
     assert abs(loss.item() - ref_loss) <= 1e-2 * ref_loss
     for a, b in zip(_split(gg, shape), _split(ref_g, shape)):
@@ -183,9 +191,10 @@ def test_train_gradient_matches_central_differences(sv):
 
     h = 2e-3
     off = 0
-    checked = 0
+    checked = expected = 0
     for nw, nb in _blocks(shape):
         for size in (nw, nb):
+            expected += min(3, size)                  # the output bias block has one entry
             blk = gg[off:off + size]
             scale = np.max(np.abs(blk))
             for j in np.argsort(-np.abs(blk))[:3]:
@@ -201,7 +210,7 @@ def test_train_gradient_matches_central_differences(sv):
                 assert abs(gg[i] - fd) <= 5e-2 * scale, (i, gg[i], fd, scale)
                 checked += 1
             off += size
-    assert checked == 3 * 2 * len(_blocks(shape))
+    assert checked == expected == 3 * (2 * len(_blocks(shape)) - 1) + 1
 
 
 def test_train_adam_update_and_determinism(sv):

@@ -141,6 +141,46 @@ def test_clamp_acts_on_targets_only():
     assert g_lo[-1] == pytest.approx(np.mean(np.sign(y + 0.01)), abs=1e-15)
 
 
+def test_both_sides_clamp_matches_autograd():
+    """DeepSDF's form, |clamp(y) - clamp(t)|, against torch autograd through torch.clamp
+    on both sides (predictions spread beyond sigma so that some have no gradient)."""
+    shape = (15, 32, 3)
+    flat = svgen.mlp_init(svgen.MLPSpec(*shape), 4).astype(np.float64)
+    flat[-1] = 0.0
+    flat[-33:-1] *= 8.0
+    X, t = _batch(25, B=96)
+    sigma = 0.1
+    flat[-1] = -np.median(om.forward(flat, *shape, X)[0])   # centred: part of the batch beyond sigma
+    y, _ = om.forward(flat, *shape, X)
+    assert 10 < np.sum(np.abs(y) >= sigma) < 86
+    loss, g = om.loss_and_grad(flat, *shape, X, t, sigma, clamp_pred=True)
+    net = torch_net(flat, *shape)
+    pred = net(torch.tensor(X))[:, 0]
+    L = torch.mean(torch.abs(torch.clamp(pred, -sigma, sigma) - torch.clamp(torch.tensor(t), -sigma, sigma)))
+    L.backward()
+    ref = torch.cat([torch.cat([m.weight.grad.reshape(-1), m.bias.grad]) for m in net
+                     if isinstance(m, torch.nn.Linear)]).numpy()
+    assert loss == pytest.approx(L.item(), rel=1e-14)
+    np.testing.assert_allclose(g, ref, rtol=1e-10, atol=1e-14)
+
+
+def test_both_sides_clamp_dead_zone():
+    """Every prediction beyond sigma: the loss is the clamped gap and the gradient is
+    zero; the target-only form still has one."""
+    shape = (15, 16, 2)
+    flat = svgen.mlp_init(svgen.MLPSpec(*shape), 9).astype(np.float64)
+    flat[-1] = 5.0                                   # b_out: every prediction far above sigma
+    X, _ = _batch(10, B=16)
+    y, _ = om.forward(flat, *shape, X)
+    assert np.all(y > 1.0)
+    t = np.linspace(-0.2, 0.2, 16)
+    l2, g2 = om.loss_and_grad(flat, *shape, X, t, 0.1, clamp_pred=True)
+    assert l2 == pytest.approx(np.mean(0.1 - np.clip(t, -0.1, 0.1)), rel=1e-14)
+    assert not np.any(g2)
+    _, g1 = om.loss_and_grad(flat, *shape, X, t, 0.1)
+    assert g1[-1] == pytest.approx(1.0, abs=1e-15)
+
+
 def test_adam_matches_torch():
     rng = np.random.default_rng(11)
     p0 = rng.normal(size=50)

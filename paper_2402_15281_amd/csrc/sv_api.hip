@@ -149,7 +149,6 @@ struct CheckWs {
   unsigned long long* keys;
   int* band;          // motions in the certified band (FP64 recheck)
   int* band_count;
-  CapEntry64* table64;
   unsigned long long* keys64;
   __bf16* packed;     // BF16 hidden-layer weights
   int* plist;         // [M][N] points sent to the exact check
@@ -189,7 +188,6 @@ CheckWs carve_check(void* ws, const sv_robot& r, const sv_motions& m, const sv_c
   w.keys = cv.take<unsigned long long>(m.n);
   w.band = cv.take<int>(m.n);
   w.band_count = cv.take<int>(1);
-  w.table64 = cv.take<CapEntry64>(entries);
   w.keys64 = cv.take<unsigned long long>(m.n);
   if (mlp) {
     w.packed = cv.take<__bf16>(mlp_packed_elems(to_args(*mlp)));
@@ -486,7 +484,7 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
     }
   }
   SV_TRY("finalize", launch_finalize(w.keys, M, mlist, mcount, eps, kCertBand, *out, w.band, w.band_count, st));
-  SV_TRY("recheck64", launch_recheck64(*robot, ma, ca, w.band, w.band_count, w.table64, w.keys64, eps, *out, st));
+  SV_TRY("recheck64", launch_recheck64(*robot, ma, ca, w.band, w.band_count, w.keys64, eps, *out, st));
 #undef SV_TRY
   return SV_OK;
 }

@@ -11,7 +11,7 @@
 //   k_exact        per (motion, point tile): min over capsules and samples, FP32 VALU;
 //                  optional per-point output and per-motion (distance, index) min keys
 //   k_finalize     keys -> min distance, argmin, verdict; certified-band list
-//   k_fk64_table / k_exact64 / k_finalize64: FP64 recheck of the band list
+//   k_exact64 / k_finalize64: FP64 recheck of the band list (FK in LDS, no table)
 #include "sv_geom_common.h"
 
 namespace sv {
@@ -152,32 +152,47 @@ __global__ void k_screen_decide(unsigned long long* __restrict__ keys, int64_t M
 }
 
 // --------------------------------------------------------- FP64 recheck
-// Grid-stride over (slot, t) for the slots listed by k_finalize.
-__global__ __launch_bounds__(256) void k_fk64_table(Robot64 rb, MotionArgs mo, const int* __restrict__ list,
-                                                    const int* __restrict__ count, CapEntry64* __restrict__ table) {
-  const int64_t work = (int64_t)(*count) * mo.T;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < work; g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t slot = g / mo.T;
-    const int t = (int)(g - slot * mo.T);
-    const int64_t m = list[slot];
-    write_entries64(rb, mo.kind, mo.q0 + m * rb.dof, mo.q1 + m * rb.dof, mo.via ? mo.via + m * 2 * rb.dof : nullptr,
-                    t, mo.T, table + (size_t)slot * rb.n_caps * mo.T + t, mo.T);
-  }
-}
+constexpr int kFk64Chunk = 32;   // samples placed in LDS per stage
 
-// Grid-stride over (slot, tile of 256 points); per-slot min of the FP64 distance.
-__global__ __launch_bounds__(256) void k_exact64(const CapEntry64* __restrict__ table, int T, int K,
-                                                 CloudArgs c, int tiles, const int* __restrict__ count,
+// Grid-stride over (slot, tile of 256 points) of the motions listed by k_finalize: per
+// slot the min over the tile of the FP64 swept distance.  The block places the listed
+// motion's capsules in FP64 for kFk64Chunk samples at a time in LDS (one thread per
+// sample) and every thread folds them into its point's per-capsule minimum of squared
+// distances (kept in LDS, so that the FK's registers are free); the minimum is exact in
+// any order, so the result is that of a full FP64 table, without one in memory.
+__global__ __launch_bounds__(256) void k_exact64(Robot64 rb, MotionArgs mo, const int* __restrict__ list,
+                                                 const int* __restrict__ count, CloudArgs c, int tiles,
                                                  unsigned long long* __restrict__ keys64) {
-  const int64_t work = (int64_t)(*count) * tiles;
+  __shared__ CapEntry64 ent[SV_MAX_CAPS * kFk64Chunk];   // [k][t - t0]
+  __shared__ double m2[SV_MAX_CAPS][256];                // [k][thread]
   __shared__ unsigned long long wmin[4];
+  const int K = rb.n_caps, T = mo.T, dof = rb.dof;
+  const int64_t work = (int64_t)(*count) * tiles;
   for (int64_t w = blockIdx.x; w < work; w += gridDim.x) {
     const int64_t slot = w / tiles;
     const int tile = (int)(w - slot * tiles);
+    const int64_t m = list[slot];
     const int i = tile * 256 + threadIdx.x;
+    const bool valid = i < c.n;
+    const double x = valid ? (double)c.x[i] : 0.0, y = valid ? (double)c.y[i] : 0.0,
+                 z = valid ? (double)c.z[i] : 0.0;
+    for (int k = 0; k < K; ++k) m2[k][threadIdx.x] = INFINITY;
+    for (int t0 = 0; t0 < T; t0 += kFk64Chunk) {
+      const int nt = min(kFk64Chunk, T - t0);
+      __syncthreads();   // the previous stage (or item) is consumed
+      if ((int)threadIdx.x < nt)
+        write_entries64(rb, mo.kind, mo.q0 + m * dof, mo.q1 + m * dof, mo.via ? mo.via + m * 2 * dof : nullptr,
+                        t0 + (int)threadIdx.x, T, ent + threadIdx.x, kFk64Chunk);
+      __syncthreads();
+      for (int k = 0; k < K; ++k) {
+        double v = m2[k][threadIdx.x];
+        for (int t = 0; t < nt; ++t) v = fmin(v, seg_d2_64(ent[k * kFk64Chunk + t], x, y, z));
+        m2[k][threadIdx.x] = v;
+      }
+    }
     double best = INFINITY;
-    if (i < c.n) best = swept_min64(table + (size_t)slot * K * T, T, T, K, c.x[i], c.y[i], c.z[i]);
-    unsigned long long key = i < c.n ? ord_f64(best) : kKeyEmpty;
+    for (int k = 0; k < K; ++k) best = fmin(best, sqrt(m2[k][threadIdx.x]) - ent[k * kFk64Chunk].r);
+    unsigned long long key = valid ? ord_f64(best) : kKeyEmpty;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       const unsigned long long o = __shfl_xor(key, off, 64);
@@ -190,7 +205,6 @@ __global__ __launch_bounds__(256) void k_exact64(const CapEntry64* __restrict__ 
       for (int q = 1; q < 4; ++q) k2 = wmin[q] < k2 ? wmin[q] : k2;
       if (k2 != kKeyEmpty) atomicMin(keys64 + slot, k2);
     }
-    __syncthreads();
   }
 }
 
@@ -665,19 +679,15 @@ hipError_t launch_screen_decide(unsigned long long* keys, int64_t M, const int* 
 }
 
 hipError_t launch_recheck64(const sv_robot& rb, const MotionArgs& m, const CloudArgs& c, const int* list,
-                            const int* count, CapEntry64* table64, unsigned long long* keys64, float eps,
-                            sv_results out, hipStream_t st) {
+                            const int* count, unsigned long long* keys64, float eps, sv_results out,
+                            hipStream_t st) {
   if (m.n == 0) return hipSuccess;
   hipError_t e = launch_fill_u64(keys64, m.n, kKeyEmpty, st);
   if (e != hipSuccess) return e;
-  const int64_t fk_work = m.n * m.T;
-  hipLaunchKernelGGL(k_fk64_table, dim3((unsigned)std::min<int64_t>(grid_for(fk_work, 256), 1024)), dim3(256), 0, st,
-                     robot_to_dev<double>(rb), m, list, count, table64);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   const int tiles = (c.n + 255) / 256;
   if (tiles > 0) {
-    hipLaunchKernelGGL(k_exact64, dim3((unsigned)std::min<int64_t>(m.n * tiles, 2048)), dim3(256), 0, st, table64,
-                       m.T, rb.n_caps, c, tiles, count, keys64);
+    hipLaunchKernelGGL(k_exact64, dim3((unsigned)std::min<int64_t>(m.n * tiles, 2048)), dim3(256), 0, st,
+                       robot_to_dev<double>(rb), m, list, count, c, tiles, keys64);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_finalize64, dim3(4), dim3(256), 0, st, list, count, keys64, eps, out);

@@ -198,8 +198,8 @@ struct SearchHdr {
   unsigned long long next_item;  // head of the work queue
 };
 
-// Workspace of a search over M motions: per-position / per-motion arrays [M], the
-// capsule table [M][K][T] and its FP64 counterpart for the band recheck.
+// Workspace of a search over M motions: per-position / per-motion arrays [M] and the
+// capsule table [M][K][T].
 struct SearchWs {
   SearchHdr* hdr;
   int *order, *remaining;
@@ -207,7 +207,6 @@ struct SearchWs {
   float* dist_pos;
   CapEntry* table;
   int *band_list, *band_pos;
-  CapEntry64* table64;
   unsigned long long* keys64;
   float* d64;
   uint8_t* v64;
@@ -310,7 +309,7 @@ hipError_t launch_finalize(const unsigned long long* keys, int64_t M, const int*
 hipError_t launch_screen_decide(unsigned long long* keys, int64_t M, const int* pcount, float eps, float band,
                                 int certified, sv_results out, int* full, int* full_count, hipStream_t st);
 hipError_t launch_recheck64(const sv_robot& rb, const MotionArgs& m, const CloudArgs& c, const int* list,
-                            const int* count, CapEntry64* table64, unsigned long long* keys64, float eps,
+                            const int* count, unsigned long long* keys64, float eps,
                             sv_results out, hipStream_t st);
 
 ExactShape default_exact_shape();

@@ -205,7 +205,6 @@ SearchWs carve_search(void* ws, const sv_robot& rb, int64_t M, int T, size_t* by
   w.table = cv.take<CapEntry>((size_t)M * K * T);
   w.band_list = cv.take<int>((size_t)M);
   w.band_pos = cv.take<int>((size_t)M);
-  w.table64 = cv.take<CapEntry64>((size_t)M * K * T);
   w.keys64 = cv.take<unsigned long long>((size_t)M);
   w.d64 = cv.take<float>((size_t)M);
   w.v64 = cv.take<uint8_t>((size_t)M);
@@ -239,7 +238,7 @@ hipError_t launch_search(const sv_robot& rb, const MotionArgs& mo, const CloudAr
     hipLaunchKernelGGL((k_search_exact<kSearchP, kSearchNT>), dim3(blocks), dim3(kSearchNT), 0, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const sv_results r64{w.d64, nullptr, w.v64, nullptr};
-    if ((e = launch_recheck64(rb, mo, c, w.band_list, &w.hdr->band_count, w.table64, w.keys64, eps, r64, st)) !=
+    if ((e = launch_recheck64(rb, mo, c, w.band_list, &w.hdr->band_count, w.keys64, eps, r64, st)) !=
         hipSuccess)
       return e;
   }

@@ -43,10 +43,11 @@ class DataRecipe:
 class TrainRecipe:
     """Adam at lr (Sec. V: PyTorch's defaults) for `epochs` passes over the rows.
 
-    schedule: "constant", or "plateau": the learning rate is multiplied by
+    schedule: "constant"; "plateau": the learning rate is multiplied by
     plateau_factor after plateau_patience epochs without a new best held-out loss
     (the paper's ReduceLROnPlateau with factor 0.1 and patience 10 over 200 epochs,
-    Sec. V; needs validation rows).  keep_best: end with the weights of the epoch
+    Sec. V; needs validation rows); "cosine": lr (1 + cos(pi s / S)) / 2 at step s of
+    S.  keep_best: end with the weights of the epoch
     with the best held-out loss (the paper tests the checkpoint with the best
     validation loss).  clamp_pred: clamp the predictions in the loss as well as the
     targets (sv_train_hparams.clamp_pred)."""
@@ -235,7 +236,7 @@ def train(mlp, samples, recipe: TrainRecipe, val_rows=None, log=None, device="cu
         # to the device is queued behind the running steps instead of waiting for them
         return torch.from_numpy(svgen.permutation(recipe.seed * 7919 + ep, n)).pin_memory()
 
-    if recipe.schedule not in ("constant", "plateau"):
+    if recipe.schedule not in ("constant", "plateau", "cosine"):
         raise ValueError(f"unknown schedule {recipe.schedule!r}")
     if (recipe.schedule == "plateau" or recipe.keep_best) and val_rows is None:
         raise ValueError("the plateau schedule and keep_best need validation rows")
@@ -249,6 +250,8 @@ def train(mlp, samples, recipe: TrainRecipe, val_rows=None, log=None, device="cu
         for s in range(steps_per_epoch):
             idx = perm[s * recipe.batch:(s + 1) * recipe.batch]
             step += 1
+            if recipe.schedule == "cosine":
+                lr = recipe.lr * 0.5 * (1.0 + math.cos(math.pi * (step - 1) / (recipe.epochs * steps_per_epoch)))
             sv.sv_train_step(mlp, m, v, step, samples, idx, lr=lr, clamp_sigma=recipe.clamp_sigma,
                              loss_out=loss, ws=ws, clamp_pred=recipe.clamp_pred)
             ep_loss += loss * idx.shape[0]

@@ -52,7 +52,7 @@ def test_host_side_validation(b):
     assert b.lib.sv_workspace_size(1, ctypes.byref(r), None, 0, ctypes.byref(m), ctypes.byref(c), ctypes.byref(n)) == -1
     m = b.sv_motions(0, 16, 4, 1, 1, None)
     assert b.lib.sv_workspace_size(1, ctypes.byref(r), None, 0, ctypes.byref(m), ctypes.byref(c), ctypes.byref(n)) == 0
-    assert n.value >= 4 * 7 * 16 * (32 + 64)
+    assert n.value >= 4 * 7 * 16 * 32                                   # at least the FP32 capsule table
 
 
 def test_oracle_and_library_share_no_code():

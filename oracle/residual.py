@@ -106,3 +106,80 @@ def forward_bf16(flat, in_dim, width, n_blocks, X, bn_eps):
         y = h + batchnorm(np.maximum(z, 0.0), blk, bn_eps)
         h = y if i + 1 == n_blocks else round_bf16(y)
     return h @ net["w_out"] + net["b_out"]
+
+
+# ---------------------------------------------------------------- training
+# BatchNorm in its training form (Sec. IV-A names BatchNorm layers; Sec. V trains with
+# PyTorch): each block normalises with the statistics of the batch,
+#     mu_B = mean over the batch of a,  v_B = mean over the batch of (a - mu_B)^2,
+#     BN(a) = gamma (a - mu_B) / sqrt(v_B + eps) + beta,
+# and afterwards moves its running statistics towards them with momentum m:
+#     mu <- (1 - m) mu + m mu_B,  var <- (1 - m) var + m v_B B / (B - 1)
+# (PyTorch's rule: the running variance takes the unbiased batch variance).
+
+
+def forward_train(flat, in_dim, width, n_blocks, X, bn_eps):
+    """delta_hat [B] with batch-statistic BatchNorm, and what the backward pass needs."""
+    net = unpack(flat, in_dim, width, n_blocks)
+    X = np.asarray(X, np.float64)
+    h = X @ net["W0"].T + net["b0"]
+    cache = {"X": X, "h": [h], "a": [], "n": [], "mu": [], "v": []}
+    for blk in net["blocks"]:
+        z = np.concatenate([h, X], axis=1) @ np.concatenate([blk["Wh"], blk["Wx"]], axis=1).T + blk["c"]
+        a = np.maximum(z, 0.0)
+        mu = a.mean(axis=0)
+        v = ((a - mu) ** 2).mean(axis=0)
+        n = (a - mu) / np.sqrt(v + bn_eps)
+        h = h + blk["gamma"] * n + blk["beta"]
+        for k, val in (("a", a), ("n", n), ("mu", mu), ("v", v), ("h", h)):
+            cache[k].append(val)
+    y = h @ net["w_out"] + net["b_out"]
+    return y, cache
+
+
+def loss_and_grad_train(flat, in_dim, width, n_blocks, X, target, sigma, bn_eps, decide=None):
+    """Target-clamped L1 loss (oracle.mlp.clamped_l1) of the batch-statistic forward pass
+    and its gradient w.r.t. the flat vector, by backpropagation.  The running-statistic
+    entries (mu, var) get zero gradient: they are not trained but averaged
+    (running_update).  `decide`: the predictions the loss's sign decisions are taken on.
+
+    BatchNorm backward, with n = (a - mu_B) / s, s = sqrt(v_B + eps), g = dL/dh_b:
+      dgamma = sum g n,  dbeta = sum g,
+      da = gamma / s (g - mean(g) - n mean(g n))      (means over the batch);
+    ReLU passes da where z > 0 (a > 0); the skip passes g to h_{b-1} unchanged.
+    """
+    net = unpack(flat, in_dim, width, n_blocks)
+    y, c = forward_train(flat, in_dim, width, n_blocks, X, bn_eps)
+    B = y.shape[0]
+    tc = np.clip(np.asarray(target, np.float64), -sigma, sigma)
+    loss = float(np.mean(np.abs(y - tc)))
+    yd = y if decide is None else np.asarray(decide, np.float64)
+    dy = np.sign(yd - tc) / B
+    grads = {"w_out": c["h"][-1].T @ dy, "b_out": dy.sum(), "blocks": [None] * n_blocks}
+    g = dy[:, None] * net["w_out"][None, :]
+    for i in range(n_blocks - 1, -1, -1):
+        blk = net["blocks"][i]
+        n, a = c["n"][i], c["a"][i]
+        s = np.sqrt(c["v"][i] + bn_eps)
+        dgamma, dbeta = (g * n).sum(axis=0), g.sum(axis=0)
+        da = blk["gamma"] / s * (g - g.mean(axis=0) - n * (g * n).mean(axis=0))
+        dz = da * (a > 0)
+        hp = c["h"][i]
+        grads["blocks"][i] = {"Wh": dz.T @ hp, "Wx": dz.T @ c["X"], "c": dz.sum(axis=0), "gamma": dgamma,
+                              "beta": dbeta, "mu": np.zeros(width), "var": np.zeros(width)}
+        g = g + dz @ blk["Wh"]
+    grads["W0"] = g.T @ c["X"]
+    grads["b0"] = g.sum(axis=0)
+    return loss, pack(grads)
+
+
+def running_update(flat, in_dim, width, n_blocks, X, bn_eps, momentum=0.1):
+    """The flat vector with every block's running statistics moved towards this batch's
+    (after a training forward pass on X)."""
+    net = unpack(flat, in_dim, width, n_blocks)
+    _, c = forward_train(flat, in_dim, width, n_blocks, X, bn_eps)
+    B = np.asarray(X).shape[0]
+    for blk, mu, v in zip(net["blocks"], c["mu"], c["v"]):
+        blk["mu"] = (1 - momentum) * blk["mu"] + momentum * mu
+        blk["var"] = (1 - momentum) * blk["var"] + momentum * v * B / (B - 1)
+    return pack(net)

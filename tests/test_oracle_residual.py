@@ -120,3 +120,93 @@ def test_bf16_emulation_close_to_fp64():
     err = np.abs(yb - y) / (1.0 + np.abs(y))
     assert err.max() < 2e-2
     assert err.mean() < 5e-3
+
+
+# ---------------------------------------------------------------- training form
+def _torch_grads(m):
+    """Gradients of the torch model in the flat layout (running statistics: zero)."""
+    parts = [m.first.weight.grad.reshape(-1), m.first.bias.grad]
+    W = m.first.weight.shape[0]
+    for lin, bn in zip(m.lin, m.bn):
+        g = lin.weight.grad
+        parts += [g[:, :W].reshape(-1), g[:, W:].reshape(-1), lin.bias.grad, bn.weight.grad, bn.bias.grad,
+                  torch.zeros(W, dtype=torch.float64), torch.zeros(W, dtype=torch.float64)]
+    parts += [m.last.weight.grad.reshape(-1), m.last.bias.grad]
+    return torch.cat(parts).numpy()
+
+
+@pytest.mark.parametrize("width,n_blocks,B", [(32, 3, 96), (64, 1, 40), (16, 5, 200)])
+def test_training_pass_matches_torch_batchnorm(width, n_blocks, B):
+    """Loss, gradient and running statistics of the batch-statistic forward pass against
+    torch's layers in training mode (nn.BatchNorm1d normalising with the batch's
+    statistics, momentum 0.1), with autograd in FP64."""
+    eps = 1e-5
+    flat = svgen.res_init(svgen.ResSpec(IN, width, n_blocks), 31).astype(np.float64)
+    X = rows(B, 32)
+    t = np.random.default_rng(33).uniform(-0.15, 0.3, B)
+    sigma = 0.1
+    loss, g = ores.loss_and_grad_train(flat, IN, width, n_blocks, X, t, sigma, eps)
+    m = torch_model(flat, IN, width, n_blocks, eps).train()
+    pred = m(torch.tensor(X))
+    L = torch.mean(torch.abs(pred - torch.clamp(torch.tensor(t), -sigma, sigma)))
+    L.backward()
+    assert loss == pytest.approx(L.item(), rel=1e-13)
+    np.testing.assert_allclose(g, _torch_grads(m), rtol=1e-9, atol=1e-13)
+    upd = ores.running_update(flat, IN, width, n_blocks, X, eps)
+    net = ores.unpack(upd, IN, width, n_blocks)
+    for blk, bn in zip(net["blocks"], m.bn):
+        np.testing.assert_allclose(blk["mu"], bn.running_mean.numpy(), rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(blk["var"], bn.running_var.numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_training_forward_normalises_each_block():
+    """After a block's BatchNorm in training form, gamma = 1 and beta = 0 leave every
+    feature with batch mean 0 and batch variance v / (v + eps) (v its raw variance);
+    with gamma = 0 the block adds beta only."""
+    width, n_blocks, B, eps = 24, 2, 64, 1e-5
+    flat = svgen.res_init(svgen.ResSpec(IN, width, n_blocks), 41).astype(np.float64)
+    net = ores.unpack(flat, IN, width, n_blocks)
+    for blk in net["blocks"]:
+        blk["gamma"][:] = 1.0
+        blk["beta"][:] = 0.0
+    X = rows(B, 42)
+    _, c = ores.forward_train(ores.pack(net), IN, width, n_blocks, X, eps)
+    for i in range(n_blocks):
+        d = c["h"][i + 1] - c["h"][i]
+        np.testing.assert_allclose(d.mean(axis=0), 0.0, atol=1e-12)
+        np.testing.assert_allclose(d.var(axis=0), c["v"][i] / (c["v"][i] + eps), rtol=1e-10)
+    for blk in net["blocks"]:
+        blk["gamma"][:] = 0.0
+        blk["beta"][:] = 0.25
+    _, c = ores.forward_train(ores.pack(net), IN, width, n_blocks, X, eps)
+    for i in range(n_blocks):
+        np.testing.assert_allclose(c["h"][i + 1] - c["h"][i], 0.25, rtol=0, atol=1e-15)
+
+
+def test_training_gradient_matches_central_differences():
+    """FP64 central differences of the batch-statistic loss (targets far from the
+    predictions, so the loss is smooth in theta)."""
+    width, n_blocks, B, eps = 8, 2, 30, 1e-5
+    flat = svgen.res_init(svgen.ResSpec(IN, width, n_blocks), 51).astype(np.float64)
+    X = rows(B, 52)
+    y, _ = ores.forward_train(flat, IN, width, n_blocks, X, eps)
+    t = y + np.where(np.arange(B) % 2 == 0, 0.5, -0.5)
+    _, g = ores.loss_and_grad_train(flat, IN, width, n_blocks, X, t, 10.0, eps)
+    net = ores.unpack(flat, IN, width, n_blocks)
+    skip = set()   # running statistics have zero gradient by definition
+    off = IN * width + width
+    for _ in range(n_blocks):
+        base = off + width * width + width * IN + 3 * width
+        skip |= set(range(base, base + 2 * width))
+        off += width * width + width * IN + 5 * width
+    rng = np.random.default_rng(53)
+    idx = [i for i in rng.choice(flat.size, 120, replace=False) if i not in skip]
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(flat)
+        e[i] = h
+        lp = np.mean(np.abs(ores.forward_train(flat + e, IN, width, n_blocks, X, eps)[0] - t))
+        lm = np.mean(np.abs(ores.forward_train(flat - e, IN, width, n_blocks, X, eps)[0] - t))
+        assert g[i] == pytest.approx((lp - lm) / (2 * h), rel=1e-5, abs=1e-9), i
+    assert len(idx) > 60
+    assert not any(g[i] for i in skip)

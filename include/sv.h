@@ -210,6 +210,23 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
                      const sv_motions* motions, const sv_cloud* cloud, sv_results* out, void* ws,
                      size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): sv_check_motions without a workspace
+ * argument.  Its scratch memory is a static device array of SV_STATIC_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on, from the first call with that device
+ * current until the process ends; the call itself allocates and frees nothing and
+ * records no profiler events.  Arguments, results and arithmetic are those of
+ * sv_check_motions (the same kernels).  A check whose workspace (sv_workspace_size,
+ * SV_OP_CHECK) exceeds SV_STATIC_SCRATCH_BYTES returns SV_ERR_WORKSPACE and launches
+ * nothing; the exact and the screened check of 512 motions at T = 256 against 20,000
+ * points with a 15 -> 8 x 512 -> 1 network fit (32 and 76 MiB).  Every call on one GPU
+ * uses that GPU's one array and leaves its contents behind (each call initialises what
+ * it reads): calls that overlap in time on one GPU -- other streams, other threads --
+ * race and give wrong results, so the caller must order them. */
+#define SV_STATIC_SCRATCH_BYTES ((size_t)96 << 20)
+int sv_check_motions_static(const sv_robot* robot, const sv_mlp* mlp, int screen, float eps, float tau,
+                            const sv_motions* motions, const sv_cloud* cloud, sv_results* out, void* stream);
+
 /* ---- continuous certification (Sec. III, eq. (3)) ---------------------------------
  * The swept volume is a union over the continuous path parameter s in [0, 1]; the
  * exact check evaluates it at the T samples s_t, so its distance is an upper bound of

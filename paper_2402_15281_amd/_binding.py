@@ -126,6 +126,9 @@ def _load():
                                      ctypes.c_float,
                                      ctypes.POINTER(sv_motions), ctypes.POINTER(sv_cloud),
                                      ctypes.POINTER(sv_results), P, ctypes.c_size_t, P]
+    lib.sv_check_motions_static.argtypes = [ctypes.POINTER(sv_robot), ctypes.POINTER(sv_mlp), ctypes.c_int,
+                                            ctypes.c_float, ctypes.c_float, ctypes.POINTER(sv_motions),
+                                            ctypes.POINTER(sv_cloud), ctypes.POINTER(sv_results), P]
     lib.sv_profile_enable.argtypes = [ctypes.c_int]
     lib.sv_profile_reset.argtypes = []
     lib.sv_profile_reset.restype = None
@@ -161,7 +164,7 @@ def _load():
                "sv_profile_read", "sv_make_samples", "sv_make_samples_workspace_size", "sv_nn_predict",
                "sv_train_step", "sv_train_workspace_size", "sv_batch_workspace_size", "sv_check_requests",
                "sv_tile_candidates", "sv_default_tile", "sv_wall_clock_hz", "sv_nn_min", "sv_nn_min_workspace_size",
-               "sv_first_free", "sv_first_free_workspace_size", "sv_continuous_gap",
+               "sv_first_free", "sv_first_free_workspace_size", "sv_continuous_gap", "sv_check_motions_static",
                "sv_make_samples_paper", "sv_make_samples_paper_workspace_size"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
@@ -357,6 +360,17 @@ def sv_check_motions(robot: sv_robot, motions: DeviceMotions, cloud: DeviceCloud
     _check(lib.sv_check_motions(ctypes.byref(robot), mref, mode, float(eps), float(tau), ctypes.byref(md),
                                 ctypes.byref(cd), ctypes.byref(rd), _ptr(ws), ws.numel(), _stream(stream)))
     return ws
+
+
+def sv_check_motions_static(robot: sv_robot, motions: DeviceMotions, cloud: DeviceCloud, out: DeviceResults,
+                            eps: float, mlp: DeviceMLP = None, screen: int = SV_SCREEN_NONE, tau: float = 0.0,
+                            stream=None, unculled: bool = False):
+    """sv_check_motions on the library's static scratch memory (no workspace, no allocation)."""
+    md, cd, rd = motions.desc(), cloud.desc(), out.desc()
+    keep, mref = _mlp_ref(mlp)
+    mode = int(screen) | (SV_CHECK_UNCULLED if unculled else 0)
+    _check(lib.sv_check_motions_static(ctypes.byref(robot), mref, mode, float(eps), float(tau), ctypes.byref(md),
+                                       ctypes.byref(cd), ctypes.byref(rd), _stream(stream)))
 
 
 def executed_tests(ws: torch.Tensor) -> int:

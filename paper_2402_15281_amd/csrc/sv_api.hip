@@ -39,6 +39,7 @@ struct ProfRec {
   hipEvent_t a, b;
 };
 thread_local bool t_prof_on = false;
+thread_local bool t_prof_suspended = false;   // within a call that may not create events
 thread_local std::vector<ProfRec> t_prof_pending;
 thread_local std::map<std::string, std::pair<double, int64_t>> t_prof_acc;
 
@@ -47,7 +48,7 @@ struct ProfScope {
   ProfRec rec{nullptr, nullptr, nullptr};
   hipStream_t st;
   ProfScope(const char* name, hipStream_t s) : st(s) {
-    if (!t_prof_on) return;
+    if (!t_prof_on || t_prof_suspended) return;
     if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess) return;
     rec.name = name;
     (void)hipEventRecord(rec.a, st);
@@ -271,6 +272,48 @@ std::vector<sv_tile> tile_candidates() {
 }  // namespace
 }  // namespace sv
 
+// Scratch memory of sv_check_motions_static: one copy on every GPU the library runs on,
+// held until the process ends.  Host code never uses this name for the memory (on the
+// host it is only a stand-in): it takes the device address that hipGetSymbolAddress
+// returns for the current device, once per device (static_scratch).
+static __device__ __align__(256) unsigned char scratch[SV_STATIC_SCRATCH_BYTES];
+
+namespace sv {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, resolved on the first call
+// with that device current and kept.
+int static_scratch(void** p) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(SV_ERR_UNSUPPORTED, "device index %d >= %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(SV_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *p = g_scratch_ptr[dev];
+  return SV_OK;
+}
+
+// Suspends the thread's profiler for the scope (it would create HIP events).
+struct ProfSuspend {
+  bool was;
+  ProfSuspend() : was(t_prof_suspended) { t_prof_suspended = true; }
+  ~ProfSuspend() { t_prof_suspended = was; }
+};
+
+}  // namespace
+}  // namespace sv
+
 using namespace sv;
 
 extern "C" {
@@ -487,6 +530,22 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
   SV_TRY("recheck64", launch_recheck64(*robot, ma, ca, w.band, w.band_count, w.keys64, eps, *out, st));
 #undef SV_TRY
   return SV_OK;
+}
+
+int sv_check_motions_static(const sv_robot* robot, const sv_mlp* mlp, int screen, float eps, float tau,
+                            const sv_motions* motions, const sv_cloud* cloud, sv_results* out, void* stream) {
+  int s;
+  if ((s = check_robot(robot)) || (s = check_motions(motions, robot->dof)) || (s = check_cloud(cloud))) return s;
+  const bool screened = (screen & ~SV_CHECK_UNCULLED) != SV_SCREEN_NONE;
+  if (screened && mlp && (s = check_mlp(mlp, SV_BF16, robot->dof))) return s;
+  const size_t need = carve_check(nullptr, *robot, *motions, *cloud, screened ? mlp : nullptr).bytes;
+  if (need > SV_STATIC_SCRATCH_BYTES)
+    return fail(SV_ERR_WORKSPACE, "this check needs %zu bytes of scratch; the static scratch holds %zu", need,
+                (size_t)SV_STATIC_SCRATCH_BYTES);
+  void* ptr = nullptr;
+  if ((s = static_scratch(&ptr))) return s;
+  ProfSuspend no_events;
+  return sv_check_motions(robot, mlp, screen, eps, tau, motions, cloud, out, ptr, SV_STATIC_SCRATCH_BYTES, stream);
 }
 
 // ---- training data, row prediction, training step --------------------------------

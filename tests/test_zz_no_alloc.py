@@ -1,0 +1,75 @@
+"""sv_check_motions_static (the check on the library's static scratch memory, for
+callers that cannot allocate) against sv_check_motions with a caller workspace, through
+the C ABI: bit-identical results on two calls in a row, the second on a smaller input
+(the scratch keeps the first call's contents), exact and screened; a call whose
+workspace exceeds the scratch is rejected on the host and writes nothing."""
+import numpy as np
+import pytest
+import torch
+
+import svgen
+
+pytestmark = pytest.mark.gpu
+
+EPS, TAU = 0.01, 0.03
+
+
+@pytest.fixture(scope="module")
+def sv():
+    from paper_2402_15281_amd import _binding
+    assert torch.cuda.is_available()
+    return _binding
+
+
+def run(sv, fn, robot, motions, pts, mlp, screen):
+    dm, dc = sv.DeviceMotions(motions), sv.DeviceCloud(pts)
+    out = sv.DeviceResults(dm.n)
+    out.min_dist.fill_(float("nan"))
+    out.argmin.fill_(-7)
+    out.verdict.fill_(9)
+    out.n_fallback.fill_(-3)
+    fn(robot, dm, dc, out, EPS, mlp=mlp, screen=screen, tau=TAU)
+    torch.cuda.synchronize()
+    return (out.min_dist.cpu().numpy().view(np.int32).copy(), out.argmin.cpu().numpy().copy(),
+            out.verdict.cpu().numpy().copy(), out.n_fallback.cpu().numpy().copy())
+
+
+@pytest.mark.parametrize("screened", [False, True], ids=["exact", "certified"])
+def test_static_scratch_matches_workspace_call(sv, screened):
+    arm = svgen.make_arm(1)
+    robot = sv.make_robot(arm)
+    mlp, screen = None, sv.SV_SCREEN_NONE
+    if screened:
+        spec = svgen.MLPSpec(15, 256, 4)
+        mlp, screen = sv.DeviceMLP(svgen.mlp_init(spec, 1402), 15, 256, 4), sv.SV_SCREEN_CERTIFIED
+    cases = [(svgen.make_motions(arm, 96, 128, 1400), svgen.bin_cloud(12000, 1401)),   # first, larger
+             (svgen.make_motions(arm, 13, 37, 1403), svgen.bin_cloud(700, 1404))]      # then smaller
+    for motions, pts in cases:
+        ref = run(sv, sv.sv_check_motions, robot, motions, pts, mlp, screen)
+        got = run(sv, sv.sv_check_motions_static, robot, motions, pts, mlp, screen)
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(a, b)
+        assert np.all((ref[2] == 0) | (ref[2] == 1))
+
+
+def test_static_scratch_full_benchmark_size_and_limit(sv):
+    """512 motions x 20,000 bin points at T = 256 fits; T = 1024 (a 112 MiB capsule
+    table) does not and is rejected before any launch."""
+    arm = svgen.make_arm(1)
+    robot = sv.make_robot(arm)
+    w = svgen.WORKLOADS["bin20k"]
+    motions = svgen.make_motions(arm, w["n_motions"], w["T"], w["motion_seed"])
+    pts = svgen.bin_cloud(w["n_points"], w["cloud_seed"])
+    ref = run(sv, sv.sv_check_motions, robot, motions, pts, None, sv.SV_SCREEN_NONE)
+    got = run(sv, sv.sv_check_motions_static, robot, motions, pts, None, sv.SV_SCREEN_NONE)
+    for a, b in zip(got, ref):
+        np.testing.assert_array_equal(a, b)
+    big = svgen.Motions(motions.q0, motions.q1, 1024)
+    dm, dc = sv.DeviceMotions(big), sv.DeviceCloud(pts)
+    out = sv.DeviceResults(dm.n)
+    out.verdict.fill_(9)
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_check_motions_static(robot, dm, dc, out, EPS)
+    assert e.value.status == -3
+    torch.cuda.synchronize()
+    assert bool((out.verdict == 9).all())

@@ -459,9 +459,17 @@ def box_world_search(sv, torch, np, arm, train_epochs, reps=3):
     mlp = sv.DeviceMLP(tr.init_params(spec, w["mlp_seed"]), *w["mlp"])
     tlog = tr.train(mlp, samples, tr.TrainRecipe(epochs=train_epochs, batch=16384))
     ev = tr.evaluate(mlp, val)
-    del samples
     log(f"box world: network {w['mlp']} trained in {time.perf_counter() - t0:.1f} s, val clamped MAE "
         f"{ev['mae_clamped'] * 1e3:.1f} mm")
+    # the paper's residual network of the same size (Sec. V-B: 5 blocks of 512), trained on
+    # the same rows with batch-statistic BatchNorm, evaluated with its running statistics
+    rspec = svgen.ResSpec(*w["mlp"])
+    rnet = sv.DeviceMLP(tr.init_params_res(rspec, w["mlp_seed"]), *w["mlp"], kind=1, bn_eps=1e-5)
+    rlog = tr.train(rnet, samples, tr.TrainRecipe(epochs=train_epochs, batch=16384))
+    rev = tr.evaluate(rnet, val)
+    del samples
+    log(f"box world: residual network {w['mlp']} trained in {rlog.seconds:.1f} s ({rlog.steps} steps), val clamped "
+        f"MAE {rev['mae_clamped'] * 1e3:.1f} mm")
     robot = sv.make_robot(arm)
     eps = w["eps"]
     res = sv.search_result_tensor()
@@ -472,6 +480,7 @@ def box_world_search(sv, torch, np, arm, train_epochs, reps=3):
         d_hat = torch.empty(dm.n, device="cuda")
         ws_s = sv.sv_first_free(robot, dm, dc, eps, res)
         ws_n = sv.sv_nn_min(mlp, dm, dc, d_hat)
+        ws_r = sv.sv_nn_min(rnet, dm, dc, d_hat)
         out = sv.DeviceResults(dm.n)
         sv.sv_check_motions(robot, dm, dc, out, eps)
         torch.cuda.synchronize()
@@ -484,8 +493,12 @@ def box_world_search(sv, torch, np, arm, train_epochs, reps=3):
             sv.sv_nn_min(mlp, dm, dc, d_hat, ws=ws_n)
             sv.sv_first_free(robot, dm, dc, eps, res, d_hat=d_hat, ws=ws_s)
 
+        def guided_res():
+            sv.sv_nn_min(rnet, dm, dc, d_hat, ws=ws_r)
+            sv.sv_first_free(robot, dm, dc, eps, res, d_hat=d_hat, ws=ws_s)
+
         rec_ = {"free_fraction": free}
-        for name, fn in (("plain", plain), ("guided", guided)):
+        for name, fn in (("plain", plain), ("guided", guided), ("guided_residual", guided_res)):
             fn()
             torch.cuda.synchronize()
             ms = []
@@ -509,15 +522,22 @@ def box_world_search(sv, torch, np, arm, train_epochs, reps=3):
            "network": {"shape": list(w["mlp"]), "train_epochs": train_epochs, "train_batch": 16384,
                        "train_rows": rec.n_motions * (rec.n_uniform + rec.n_near), "train_seconds": tlog.seconds,
                        "val_clamped_mae_m": ev["mae_clamped"], "val_near_surface_mae_m": ev["mae_near"]},
-           "answers_free": all(r[k]["answer_free"] for r in rows for k in ("plain", "guided"))}
-    for k in ("plain", "guided"):
+           "network_residual": {"shape": list(w["mlp"]), "kind": "the paper's residual network (ReLU, BatchNorm "
+                                "with batch statistics in training, running statistics in inference, skip and "
+                                "jump connections)", "train_epochs": train_epochs, "train_batch": 16384,
+                                "train_seconds": rlog.seconds, "ms_per_step": rlog.seconds / rlog.steps * 1e3,
+                                "val_clamped_mae_m": rev["mae_clamped"], "val_near_surface_mae_m": rev["mae_near"]},
+           "answers_free": all(r[k]["answer_free"] for r in rows for k in ("plain", "guided", "guided_residual"))}
+    for k in ("plain", "guided", "guided_residual"):
         out[k] = {"ms_mean": stat(k, "ms")[0], "ms_std": stat(k, "ms")[1],
                   "n_exact_mean": stat(k, "n_exact")[0], "n_exact_std": stat(k, "n_exact")[1],
                   "n_nn_mean": stat(k, "n_nn")[0], "n_exact_run_mean": stat(k, "n_exact_run")[0],
                   "found_fraction": float(np.mean([r[k]["found"] for r in rows]))}
     log(f"box world: plain {out['plain']['ms_mean']:.3f} ms, {out['plain']['n_exact_mean']:.2f} exact checks; "
         f"guided {out['guided']['ms_mean']:.3f} ms, {out['guided']['n_exact_mean']:.2f} exact checks, "
-        f"{out['guided']['n_nn_mean']:.2f} network checks; free fraction {out['free_fraction_mean']:.3f}")
+        f"{out['guided']['n_nn_mean']:.2f} network checks; guided by the residual network "
+        f"{out['guided_residual']['ms_mean']:.3f} ms, {out['guided_residual']['n_exact_mean']:.2f} exact checks; free "
+        f"fraction {out['free_fraction_mean']:.3f}")
     return out
 
 

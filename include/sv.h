@@ -128,7 +128,7 @@ typedef struct {
                           or 1024 (training: up to 512) */
   int32_t n_hidden;    /* L >= 1: softplus layers (SV_NET_MLP) or blocks (SV_NET_RESIDUAL) */
   const float* params; /* dev FP32, flat, in the order given above */
-  int32_t kind;        /* SV_NET_MLP or SV_NET_RESIDUAL; training supports SV_NET_MLP only */
+  int32_t kind;        /* SV_NET_MLP or SV_NET_RESIDUAL */
   float bn_eps;        /* SV_NET_RESIDUAL: the BatchNorm epsilon (> 0) */
 } sv_mlp;
 
@@ -464,7 +464,13 @@ typedef struct {
 
 /* One training step of the BF16 network (mlp->width 128, 256 or 512): forward pass of
  * the batch rows samples[batch_idx[i]], i < batch, clamped-L1 loss, backward pass,
- * Adam update.  mlp->params holds the FP32 master weights and is updated in place
+ * Adam update.
+ * SV_NET_RESIDUAL (the paper's network, Sec. IV-A; target-only clamp, in_dim <= 16): its
+ * BatchNorm layers normalise with the statistics of the batch (mean and biased variance
+ * over the batch rows, as PyTorch's layers do in training), the gradient flows through
+ * them, and after the step every block's running statistics move towards the batch's
+ * with momentum 0.1 (mu <- 0.9 mu + 0.1 mean, var <- 0.9 var + 0.1 var_B B / (B - 1)).
+ * Their entries of the gradient are zero and Adam leaves them alone.  mlp->params holds the FP32 master weights and is updated in place
  * (it must point to writable device memory); adam_m, adam_v: dev [n_params] FP32
  * Adam moments (zero before the first step).  Hidden layers run in BF16 on MFMA
  * with FP32 accumulation; gradient reductions are in fixed order, so a step is

@@ -183,3 +183,58 @@ def running_update(flat, in_dim, width, n_blocks, X, bn_eps, momentum=0.1):
         blk["mu"] = (1 - momentum) * blk["mu"] + momentum * mu
         blk["var"] = (1 - momentum) * blk["var"] + momentum * v * B / (B - 1)
     return pack(net)
+
+
+def loss_and_grad_train_bf16(flat, in_dim, width, n_blocks, X, target, sigma, bn_eps, rounding=True):
+    """Debugging aid and error gauge: loss_and_grad_train with the BF16 training path's
+    rounding points, otherwise FP64 (rounding=False gives loss_and_grad_train exactly).
+
+    Rounded to BF16 (round to nearest even): the block weights Wh_b, Wx_b; the network
+    input as the sum of its BF16 rounding and the BF16 rounding of the remainder; h_0 and
+    every block input h_b (b < L; h_L stays unrounded); a_b = relu(z_b) (the batch
+    statistics are taken on the rounded values); dz_b; g_0 = dL/dh_0 (W_0 and b_0 sums).
+    The BatchNorm backward amplifies the forward roundings (its gradient is a small
+    remainder of large terms), so the distance of this emulation from the FP64 gradient
+    measures what the BF16 path can reach.
+    """
+    R = round_bf16 if rounding else (lambda v: np.asarray(v, np.float64))
+    net = unpack(flat, in_dim, width, n_blocks)
+    X = np.asarray(X, np.float64)
+    if rounding:
+        x_hi = round_bf16(X)
+        Xs = x_hi + round_bf16(X.astype(np.float32) - x_hi.astype(np.float32))
+    else:
+        Xs = X
+    h = R(X @ net["W0"].T + net["b0"])
+    hs, As, ns, invs = [h], [], [], []
+    for i, blk in enumerate(net["blocks"]):
+        z = h @ R(blk["Wh"]).T + Xs @ R(blk["Wx"]).T + blk["c"]
+        a = R(np.maximum(z, 0.0))
+        mu = a.mean(axis=0)
+        inv = 1.0 / np.sqrt(((a - mu) ** 2).mean(axis=0) + bn_eps)
+        n = (a - mu) * inv
+        hn = h + blk["gamma"] * n + blk["beta"]
+        h = hn if i + 1 == n_blocks else R(hn)
+        hs.append(h)
+        As.append(a)
+        ns.append(n)
+        invs.append(inv)
+    y = h @ net["w_out"] + net["b_out"]
+    B = y.shape[0]
+    tc = np.clip(np.asarray(target, np.float64), -sigma, sigma)
+    loss = float(np.mean(np.abs(y - tc)))
+    dy = np.sign(y - tc) / B
+    grads = {"w_out": h.T @ dy, "b_out": dy.sum(), "blocks": [None] * n_blocks}
+    g = dy[:, None] * net["w_out"][None, :]
+    for i in range(n_blocks - 1, -1, -1):
+        blk = net["blocks"][i]
+        n = ns[i]
+        dgamma, dbeta = (g * n).sum(axis=0), g.sum(axis=0)
+        dz = R(blk["gamma"] * invs[i] * (g - g.mean(axis=0) - n * (g * n).mean(axis=0)) * (As[i] > 0))
+        grads["blocks"][i] = {"Wh": dz.T @ hs[i], "Wx": dz.T @ X, "c": dz.sum(axis=0), "gamma": dgamma,
+                              "beta": dbeta, "mu": np.zeros(width), "var": np.zeros(width)}
+        g = g + dz @ R(blk["Wh"])
+    g0 = R(g)
+    grads["W0"] = g0.T @ X
+    grads["b0"] = g0.sum(axis=0)
+    return loss, pack(grads)

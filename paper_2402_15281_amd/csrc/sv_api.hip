@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "sv_internal.h"
+#include "sv_mlp_common.h"
 
 namespace sv {
 namespace {
@@ -580,7 +581,38 @@ struct TrainWs {
 };
 size_t n_params(const sv_mlp& n) {
   const size_t W = n.width;
+  if (n.kind == SV_NET_RESIDUAL) return res_block_base(n.width, n.in_dim, n.n_hidden) + W + 1;
   return W * n.in_dim + W + (size_t)(n.n_hidden - 1) * (W * W + W) + W + 1;
+}
+struct TrainResWs {
+  ResTrainWs r;
+  float* grad;
+  size_t bytes;
+};
+TrainResWs carve_train_res(void* ws, const sv_mlp& mlp, int64_t B) {
+  const MlpArgs na = to_args(mlp);
+  const int64_t Bp = train_rows_padded(B);
+  const size_t W = mlp.width, L = mlp.n_hidden, slab = W * (size_t)Bp, tiles = (size_t)Bp / 64;
+  Carver cv(ws);
+  TrainResWs w{};
+  w.r.packed = cv.take<__bf16>(mlp_packed_elems(na));
+  w.r.packedT = cv.take<__bf16>(L * W * W);
+  w.r.xT = cv.take<float>((size_t)mlp.in_dim * Bp);
+  w.r.hT = cv.take<__bf16>(L * slab);
+  w.r.aT = cv.take<__bf16>(L * slab);
+  w.r.dzT = cv.take<__bf16>((L + 1) * slab);
+  w.r.g = cv.take<float>(slab);
+  w.r.part = cv.take<float>(tiles * 2 * W);
+  w.r.stats = cv.take<float>(L * 3 * W);
+  w.r.bsum = cv.take<float>(2 * W);
+  w.r.y = cv.take<float>(Bp);
+  w.r.dy = cv.take<float>(Bp);
+  w.r.pout = cv.take<float>(tiles * (W + 2));
+  w.r.part_w = cv.take<float>(train_res_part_w_elems(na));
+  w.r.part_w1 = cv.take<float>(train_res_part_w1_elems(na));
+  w.grad = cv.take<float>(n_params(mlp));
+  w.bytes = cv.off;
+  return w;
 }
 TrainWs carve_train(void* ws, const sv_mlp& mlp, int64_t B) {
   const MlpArgs na = to_args(mlp);
@@ -600,6 +632,9 @@ TrainWs carve_train(void* ws, const sv_mlp& mlp, int64_t B) {
   w.part_w1 = cv.take<float>(train_part_w1_elems(na, Bp));
   w.bytes = cv.off;
   return w;
+}
+size_t train_bytes(const sv_mlp& mlp, int64_t B) {
+  return mlp.kind == SV_NET_RESIDUAL ? carve_train_res(nullptr, mlp, B).bytes : carve_train(nullptr, mlp, B).bytes;
 }
 }  // namespace
 
@@ -736,10 +771,9 @@ int sv_train_workspace_size(const sv_mlp* mlp, int64_t batch, size_t* bytes) {
   int s;
   if (!bytes) return fail(SV_ERR_ARG, "bytes is NULL");
   if ((s = check_mlp(mlp, SV_BF16, 0))) return s;
-  if (mlp->kind != SV_NET_MLP) return fail(SV_ERR_UNSUPPORTED, "training supports SV_NET_MLP networks only");
   if (mlp->width > kTrainMaxWidth) return fail(SV_ERR_UNSUPPORTED, "training width %d > %d", mlp->width, kTrainMaxWidth);
   if (batch < 1 || batch > (1 << 24)) return fail(SV_ERR_SHAPE, "batch %lld outside 1..2^24", (long long)batch);
-  *bytes = carve_train(nullptr, *mlp, batch).bytes;
+  *bytes = train_bytes(*mlp, batch);
   return SV_OK;
 }
 
@@ -748,7 +782,6 @@ int sv_train_step(const sv_mlp* mlp, float* adam_m, float* adam_v, const sv_trai
                   void* ws, size_t ws_bytes, void* stream) {
   int s;
   if ((s = check_mlp(mlp, SV_BF16, 0))) return s;
-  if (mlp->kind != SV_NET_MLP) return fail(SV_ERR_UNSUPPORTED, "training supports SV_NET_MLP networks only");
   if (mlp->width > kTrainMaxWidth) return fail(SV_ERR_UNSUPPORTED, "training width %d > %d", mlp->width, kTrainMaxWidth);
   if (!hp) return fail(SV_ERR_ARG, "hparams is NULL");
   if (hp->step < 1) return fail(SV_ERR_ARG, "Adam step must be >= 1");
@@ -758,6 +791,29 @@ int sv_train_step(const sv_mlp* mlp, float* adam_m, float* adam_v, const sv_trai
   if (batch < 1 || batch > (1 << 24)) return fail(SV_ERR_SHAPE, "batch %lld outside 1..2^24", (long long)batch);
   if (n_samples < 1) return fail(SV_ERR_SHAPE, "no samples");
   if (!adam_m || !adam_v || !samples || !batch_idx) return fail(SV_ERR_ARG, "NULL device pointer");
+  if (mlp->kind == SV_NET_RESIDUAL) {
+    if (hp->clamp_pred) return fail(SV_ERR_UNSUPPORTED, "the residual network trains with the target-only clamp");
+    const TrainResWs w0 = carve_train_res(nullptr, *mlp, batch);
+    if (!ws || ws_bytes < w0.bytes)
+      return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", w0.bytes, ws_bytes);
+    const TrainResWs w = carve_train_res(ws, *mlp, batch);
+    hipStream_t st = (hipStream_t)stream;
+    const MlpArgs na = to_args(*mlp);
+    float* grad = grad_out ? grad_out : w.grad;
+    hipError_t e;
+    {
+      ProfScope ps("train_grad", st);
+      e = launch_train_step_res(na, samples, batch_idx, (int)batch, (int)train_rows_padded(batch), w.r,
+                                hp->clamp_sigma, grad, loss_out, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "residual train step");
+    ProfScope ps("adam", st);
+    e = launch_bn_running(na, w.r, (int)batch, const_cast<float*>(mlp->params), st);
+    if (e == hipSuccess)
+      e = launch_adam(const_cast<float*>(mlp->params), adam_m, adam_v, grad, (int64_t)n_params(*mlp), hp->lr,
+                      hp->beta1, hp->beta2, hp->adam_eps, hp->step, st);
+    return e == hipSuccess ? SV_OK : hip_fail(e, "adam");
+  }
   const TrainWs w0 = carve_train(nullptr, *mlp, batch);
   if (!ws || ws_bytes < w0.bytes) return fail(SV_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", w0.bytes, ws_bytes);
   const TrainWs w = carve_train(ws, *mlp, batch);

@@ -337,6 +337,24 @@ hipError_t launch_train_step(const MlpArgs& net, const float* samples, const int
                              __bf16* dzT, float* h0T, float* y, float* dy, const __bf16* packed,
                              const __bf16* packedT, float* grad, float* part_w, float* part_w1, float sigma,
                              int clamp_pred, float* loss_out, hipStream_t st);
+// Training of the residual network (SV_NET_RESIDUAL) with batch-statistic BatchNorm:
+// buffers of one step (Bp rows; slabs of W x Bp values in the tiled layout of aT).
+struct ResTrainWs {
+  __bf16 *packed, *packedT;   // forward operands (mlp_packed_elems), Wh_b^T [L][W][W]
+  float* xT;                  // [in_dim][Bp]
+  __bf16 *hT, *aT, *dzT;      // [L], [L] and [L + 1] slabs
+  float *g, *part, *stats, *bsum, *y, *dy, *pout;   // [slab], [Bp/64][2][W], [L][3][W], [2][W], [Bp], [Bp], [Bp/64][W+2]
+  float *part_w, *part_w1;    // dW splits
+};
+size_t train_res_part_w_elems(const MlpArgs& n);
+size_t train_res_part_w1_elems(const MlpArgs& n);
+// Forward, loss, backward and gradient of one batch; grad[n_params] (running-statistic
+// entries zero), loss_out (optional).  Leaves the batch statistics in w.stats.
+hipError_t launch_train_step_res(const MlpArgs& net, const float* samples, const int* idx, int B, int Bp,
+                                 const ResTrainWs& w, float sigma, float* grad, float* loss_out, hipStream_t st);
+// Moves every block's running statistics in params towards the batch statistics of
+// the last launch_train_step_res (momentum 0.1, unbiased variance).
+hipError_t launch_bn_running(const MlpArgs& net, const ResTrainWs& w, int B, float* params, hipStream_t st);
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
                        float eps, int64_t step, hipStream_t st);
 

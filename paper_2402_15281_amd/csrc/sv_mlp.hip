@@ -404,13 +404,6 @@ __global__ __launch_bounds__(mlp_threads<W>(), mlp_blocks_per_cu<W>()) void k_ml
 // on the BF16 block input, and stores the result in BF16 in place.  The last block's
 // FP32 result feeds the output layer.
 
-// Parameter offsets of block b (0-based) in the flat vector.
-__host__ __device__ inline size_t res_block_stride(int W, int in_dim) {
-  return (size_t)W * W + (size_t)W * in_dim + 5 * (size_t)W;
-}
-__host__ __device__ inline size_t res_block_base(int W, int in_dim, int b) {
-  return (size_t)W * in_dim + W + (size_t)b * res_block_stride(W, in_dim);
-}
 
 template <int W, int kMode>
 __global__ __launch_bounds__(mlp_threads<W>(), mlp_blocks_per_cu<W>()) void k_res_bf16(MlpArgs net, MotionArgs mo, CloudArgs c, int tiles,

@@ -123,6 +123,16 @@ __device__ __forceinline__ void layer_mfma_fb(const __bf16* __restrict__ Wp, con
   layer_mfma_k<W, W + kLdsPad, FB, RB, D>(Wp, Hin, wf, wr, lane, bias, acc);
 }
 
+// Parameter offsets of the residual network's block b (0-based) in the flat vector:
+// Wh [W][W], Wx [W][in_dim], c, gamma, beta, mu, var [W] each; the output layer follows
+// the last block, at res_block_base(W, in_dim, n_blocks).
+__host__ __device__ inline size_t res_block_stride(int W, int in_dim) {
+  return (size_t)W * W + (size_t)W * in_dim + 5 * (size_t)W;
+}
+__host__ __device__ inline size_t res_block_base(int W, int in_dim, int b) {
+  return (size_t)W * in_dim + W + (size_t)b * res_block_stride(W, in_dim);
+}
+
 // Packing of a W x W weight matrix M (row-major, FP32) into MFMA A-operand order:
 // element (fb, ks, lane, e) = M[fb*32 + lane%32][ks*16 + 8*(lane/32) + e], or of
 // M's transpose when `transpose` is set.  o indexes the packed array of one layer.

@@ -195,6 +195,23 @@ def init_params(spec: svgen.MLPSpec, seed: int) -> np.ndarray:
     return flat
 
 
+def init_params_res(spec: svgen.ResSpec, seed: int) -> np.ndarray:
+    """Seeded initialisation of the residual network for training: linear layers
+    uniform(+-1/sqrt(fan_in)) as svgen.res_init draws them, BatchNorm layers as PyTorch
+    creates them (gamma 1, beta 0, running mean 0, running variance 1), the output layer
+    scaled by 0.1 as in init_params."""
+    flat = svgen.res_init(spec, seed)
+    W, i = spec.width, spec.in_dim
+    for b in range(spec.n_blocks):
+        base = W * i + W + b * (W * W + W * i + 5 * W) + W * W + W * i
+        flat[base + W:base + 2 * W] = 1.0        # gamma
+        flat[base + 2 * W:base + 3 * W] = 0.0    # beta
+        flat[base + 3 * W:base + 4 * W] = 0.0    # running mean
+        flat[base + 4 * W:base + 5 * W] = 1.0    # running variance
+    flat[-(W + 1):] *= np.float32(0.1)
+    return flat
+
+
 def predict(mlp, rows, precision=sv.SV_BF16):
     out = torch.empty(rows.shape[0], dtype=torch.float32, device=rows.device)
     sv.sv_nn_predict(mlp, precision, rows, out)

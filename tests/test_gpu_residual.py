@@ -138,8 +138,12 @@ def test_residual_min_and_screening_modes(sv, orc):
 
 def test_residual_host_checks(sv):
     flat, dnet = device_net(sv, 128, 2, 600)
-    with pytest.raises(sv.SvError) as e:
-        sv.sv_train_workspace_size(dnet, 256)
+    assert sv.sv_train_workspace_size(dnet, 256) > 0        # the residual network trains (test_gpu_train_residual)
+    n = flat.size
+    rows = torch.zeros(256, IN + 1, device="cuda")
+    with pytest.raises(sv.SvError) as e:                    # ... with the target-only clamp
+        sv.sv_train_step(dnet, torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"), 1, rows,
+                         torch.arange(256, dtype=torch.int32, device="cuda"), clamp_pred=True)
     assert e.value.status == -4
     bad = sv.DeviceMLP(flat, IN, 128, 2, kind=sv.SV_NET_RESIDUAL, bn_eps=0.0)
     m = svgen.make_motions(svgen.make_arm(1), 1, 8, 601)

@@ -210,3 +210,22 @@ def test_training_gradient_matches_central_differences():
         assert g[i] == pytest.approx((lp - lm) / (2 * h), rel=1e-5, abs=1e-9), i
     assert len(idx) > 60
     assert not any(g[i] for i in skip)
+
+
+def test_training_bf16_emulation_reduces_to_fp64():
+    """Without rounding the emulation is the FP64 training gradient; with it, the
+    gradient moves by a measurable amount that stays within 10% (the BatchNorm backward
+    amplifies the forward roundings of relative size 2^-9)."""
+    width, n_blocks, B, eps = 64, 2, 200, 1e-5
+    flat = svgen.res_init(svgen.ResSpec(IN, width, n_blocks), 61).astype(np.float64)
+    X = rows(B, 62)
+    y, _ = ores.forward_train(flat, IN, width, n_blocks, X, eps)
+    t = y + np.where(np.arange(B) % 2 == 0, 0.5, -0.5)
+    l0, g0 = ores.loss_and_grad_train(flat, IN, width, n_blocks, X, t, 10.0, eps)
+    l1, g1 = ores.loss_and_grad_train_bf16(flat, IN, width, n_blocks, X, t, 10.0, eps, rounding=False)
+    assert l1 == pytest.approx(l0, rel=1e-14)
+    np.testing.assert_allclose(g1, g0, rtol=1e-10, atol=1e-15)
+    l2, g2 = ores.loss_and_grad_train_bf16(flat, IN, width, n_blocks, X, t, 10.0, eps)
+    assert abs(l2 - l0) < 1e-2 * l0
+    rel = np.linalg.norm(g2 - g0) / np.linalg.norm(g0)
+    assert 1e-4 < rel < 0.1, rel

@@ -609,7 +609,7 @@ TrainResWs carve_train_res(void* ws, const sv_mlp& mlp, int64_t B) {
   w.r.dy = cv.take<float>(Bp);
   w.r.pout = cv.take<float>(tiles * (W + 2));
   w.r.part_w = cv.take<float>(train_res_part_w_elems(na));
-  w.r.part_w1 = cv.take<float>(train_res_part_w1_elems(na));
+  w.r.part_w1 = cv.take<float>(train_res_part_w1_elems(na, Bp));
   w.grad = cv.take<float>(n_params(mlp));
   w.bytes = cv.off;
   return w;

@@ -347,7 +347,7 @@ struct ResTrainWs {
   float *part_w, *part_w1;    // dW splits
 };
 size_t train_res_part_w_elems(const MlpArgs& n);
-size_t train_res_part_w1_elems(const MlpArgs& n);
+size_t train_res_part_w1_elems(const MlpArgs& n, int64_t Bp);
 // Forward, loss, backward and gradient of one batch; grad[n_params] (running-statistic
 // entries zero), loss_out (optional).  Leaves the batch statistics in w.stats.
 hipError_t launch_train_step_res(const MlpArgs& net, const float* samples, const int* idx, int B, int Bp,

@@ -23,10 +23,12 @@
 //   k_grad_w          dW_l = dz_l^T a_{l-1} for l >= 2 (MFMA, split over the batch; both
 //                     operands staged in LDS)
 //   k_grad_reduce     fixed-order sum of the splits
-//   k_grad_rows       w_out and b_out gradients (one block per output)
-//   k_grad_w1         dW_1 = dz_1^T h0 and db_1 in FP32 (lanes along the batch, split over
-//                     the batch) + fixed-order sum (db_l for l >= 2 is summed by k_grad_w
-//                     from its staged dz rows)
+//   k_grad_out        w_out and b_out gradients (blocks stream runs of tiles) + fixed-order
+//                     sum of the blocks' partials
+//   k_grad_w1         dW_1 = dz_1^T h0 and db_1 on MFMA (the FP32 input as BF16 high and
+//                     low parts, a column of ones for the bias; split over the batch) +
+//                     fixed-order sum (db_l for l >= 2 is summed by k_grad_w from its
+//                     staged dz rows)
 //   k_adam            Adam update of the FP32 masters
 #include <math.h>
 
@@ -37,7 +39,8 @@ namespace sv {
 namespace {
 
 constexpr int kRows = kTileRows;
-constexpr int kSplitW = 16;       // batch splits of the dW GEMM
+constexpr int kSplitW = 9;        // batch splits of the dW GEMM (8 x 512: 7 layers x 9 x 4 tiles = 252 blocks, one round on 256 CUs)
+constexpr int kGwXcd = 1;         // 1: the tiles of one (layer, split) on one XCD
 
 struct TrainArgs {
   MlpArgs net;
@@ -128,6 +131,39 @@ __device__ __forceinline__ void load_tile_T(const __bf16* inT, __bf16* H, int r0
       bf16x8 o;
 #pragma unroll
       for (int f = 0; f < 8; ++f) o[f] = in[f][r];
+      *reinterpret_cast<bf16x8*>(H + (8 * rg + r) * LD + 8 * fg) = o;
+    }
+  }
+}
+
+// load_tile_T in two halves: the global loads into registers (issued before the
+// layer's MFMA loop, so that they are in flight during it), then the transposed LDS
+// writes.
+template <int W, int NT>
+__device__ __forceinline__ void fetch_tile_T(const __bf16* inT, int r0, bf16x8 (&in)[W / 64 / (NT / 64)][8]) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rg = lane >> 3;
+#pragma unroll
+  for (int q = 0; q < W / 64 / NW; ++q) {
+    const int fg = 8 * (w + q * NW) + (lane & 7);
+#pragma unroll
+    for (int f = 0; f < 8; ++f) in[q][f] = *reinterpret_cast<const bf16x8*>(inT + tix(W, 8 * fg + f, r0 + 8 * rg));
+  }
+}
+template <int W, int NT, int LD = W + kLdsPad>
+__device__ __forceinline__ void put_tile_T(const bf16x8 (&in)[W / 64 / (NT / 64)][8], __bf16* H) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rg = lane >> 3;
+#pragma unroll
+  for (int q = 0; q < W / 64 / NW; ++q) {
+    const int fg = 8 * (w + q * NW) + (lane & 7);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      bf16x8 o;
+#pragma unroll
+      for (int f = 0; f < 8; ++f) o[f] = in[q][f][r];
       *reinterpret_cast<bf16x8*>(H + (8 * rg + r) * LD + 8 * fg) = o;
     }
   }
@@ -316,12 +352,12 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_bwd(TrainArgs a
   __syncthreads();
   for (int l = L; l >= 2; --l) {
     // dh_{l-1}[r][k] = sum_f dz_l[r][f] W_l[f][k]: A operand = W_l^T packed
+    bf16x8 pre[W / 64 / (NT / 64)][8];   // the activations of layer l - 1, in flight during the MFMAs
+    fetch_tile_T<W, NT>(a.aT + (size_t)(l - 2) * W * a.Bp, r0, pre);
     f32x16 acc[kTFB][kTRB];
     layer_mfma_fb<W, kTFB, kTRB, 2>(a.packedT + (size_t)(l - 2) * W * W, H, wid, 0, lane, nullptr, acc);
     __syncthreads();   // every wave has read the tile (and copied it out)
-    // the activations of layer l - 1 into the free tile, then dz_{l-1} over them in place:
-    // each lane reads and writes the same (row, 4 features) pieces
-    load_tile_T<W, NT>(a.aT + (size_t)(l - 2) * W * a.Bp, H, r0);
+    put_tile_T<W, NT>(pre, H);   // into the free tile, then dz_{l-1} over them in place
     __syncthreads();
 #pragma unroll
     for (int fb = 0; fb < kTFB; ++fb)
@@ -344,96 +380,181 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_bwd(TrainArgs a
 }
 
 // Partial dW_l[f][k] = sum over one batch split of dz_l[f][b] a_{l-1}[k][b], l >= 2.
-// Both operands are batch-contiguous rows ([feature][batch]); a lane's MFMA fragment is
-// 16 bytes of one row, so reading fragments straight from memory touches a cache line
-// per lane and re-fetches each line once per k-step.  Instead a block stages chunks of
-// kGwChunk batch rows of its TF dz rows and TK a rows in LDS with coalesced 16-byte
-// loads (a row's chunk is one 128-byte line), prefetching the next chunk into registers
-// during the MFMAs, and its 4 waves read fragments from LDS: wave (wf, wk) owns rows
-// (TF / 2) wf .. and columns (TK / 2) wk .. as (TF / 64) x (TK / 64) MFMA tiles of
-// 32 x 32.  At W >= 256 the block tile is 256 x 256 (each dz and activation row read by
-// two blocks; 256 accumulator registers per lane, one wave per SIMD): 1.71 ms per
-// training step, against 1.81 for 128 x 256 tiles in 128-row chunks and 2.22 for
-// 128 x 256 in 64-row chunks with two blocks per CU.
-constexpr int kGwChunk = 64;                   // batch rows per LDS stage
-constexpr int kGwLd = kGwChunk + kLdsPad;      // LDS row stride (elements)
+// Both operands are batch-contiguous rows ([feature][batch]), so a block (a TF x TK tile
+// of dW_l) stages chunks of kGwChunk batch rows of its TF dz rows and TK activation
+// rows in LDS and its 4 waves read the MFMA fragments from there: wave (wf, wk) owns
+// rows (TF / 2) wf .. and columns (TK / 2) wk .. as (TF / 64) x (TK / 64) tiles of
+// 32 x 32.  At W >= 256 the block tile is 256 x 256 (256 accumulator registers per
+// lane, one wave per SIMD, one block per CU).  The kernel is bound by the bytes in
+// flight per CU: the chunks are moved by direct-to-LDS loads (global_load_lds_dwordx4,
+// no registers), kGwStages LDS buffers deep, so that kGwStages - 1 chunks are in flight
+// while the MFMAs run on one.  A chunk row is 64 contiguous bytes (4 segments of 16);
+// the DMA writes each wave's 64 segments to 1 KB of consecutive LDS, so the swizzle
+// that keeps the fragment reads free of bank conflicts is applied on the global side:
+// LDS slot s' of row r holds segment s' ^ ((r >> 1) & 3).  Each buffer is its own LDS
+// variable and the loop is unrolled over them, so that the compiler can tell the
+// buffers apart and waits only as the explicit vmcnt waits say.
+constexpr int kGwChunk = 32;                   // batch rows per LDS stage (two MFMA k-steps)
+constexpr int kGwStages = 4;                   // LDS buffers
+constexpr int kGwStageElems = 512 * kGwChunk;  // (TF + TK) rows at most
+__shared__ __align__(16) __bf16 gw_buf0[kGwStageElems];
+__shared__ __align__(16) __bf16 gw_buf1[kGwStageElems];
+__shared__ __align__(16) __bf16 gw_buf2[kGwStageElems];
+__shared__ __align__(16) __bf16 gw_buf3[kGwStageElems];
+template <int B>
+__device__ __forceinline__ __bf16* gw_buf() {
+  return B == 0 ? gw_buf0 : B == 1 ? gw_buf1 : B == 2 ? gw_buf2 : gw_buf3;
+}
+__device__ __forceinline__ int gw_slot(int r, int seg) { return seg ^ ((r >> 1) & 3); }
 
 template <int W>
 constexpr int gw_tk() { return W >= 256 ? 256 : W; }   // output columns per block
 template <int W>
 constexpr int gw_tf() { return W >= 256 ? 256 : W; }   // output rows per block
 
+// Block -> (column tile tk, row tile tf, split s, layer l).  The tiles of one (layer,
+// split) read the same dz and activation rows; the 4 (at W = 512) are given block
+// indices 8 apart, which the dispatcher deals to the same XCD, so that the rows one
+// tile fetches are found in that XCD's L2 by the others.  Blocks past the last whole
+// group of 8 (layer, split) pairs keep the plain order.
+template <int W>
+__device__ __forceinline__ void gw_coords(int b, int nblocks, int* tk, int* tf, int* s, int* l) {
+  constexpr int NT = (W / gw_tk<W>()) * (W / gw_tf<W>());   // tiles per (layer, split)
+  int g, t;
+  if (kGwXcd && NT > 1 && b < nblocks / (8 * NT) * (8 * NT)) {
+    const int sg = b / (8 * NT), r = b - sg * 8 * NT;
+    g = sg * 8 + (r & 7);
+    t = r >> 3;
+  } else {
+    g = b / NT;
+    t = b - g * NT;
+  }
+  *tk = t % (W / gw_tk<W>());
+  *tf = t / (W / gw_tk<W>());
+  *s = g % kSplitW;
+  *l = g / kSplitW + 2;
+}
+
+// vmcnt(n) for the waits of k_grad_w (n loads of this wave still in flight).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+template <int W>
+struct GwCtx {
+  static constexpr int TF = gw_tf<W>(), TK = gw_tk<W>();
+  static constexpr int NQ = (TF + TK) * (kGwChunk / 8) / 256;   // 16-byte loads per thread and chunk
+  const __bf16* dz;
+  const __bf16* ap;
+  int f0, k0, b_begin, nch, tid, wid, lane;
+  int off[NQ];   // element offset of this thread's q-th segment from its chunk's start
+};
+
+// The direct-to-LDS loads of chunk c (batch rows b_begin + kGwChunk c ..) into buffer B.
+template <int W, int B>
+__device__ __forceinline__ void gw_issue(const GwCtx<W>& x, int c) {
+  using C = GwCtx<W>;
+  const int b = x.b_begin + kGwChunk * c;          // a multiple of 32: the chunk lies in one 64-row tile
+  const size_t base = (size_t)(b >> 6) * W * 64 + (b & 63);
+#pragma unroll
+  for (int q = 0; q < C::NQ; ++q) {
+    // rows 64 q + tid / 4: the first TF are dz rows (q < NQ / 2 when TF == TK)
+    const __bf16* src = (64 * q < C::TF ? x.dz : x.ap) + base + x.off[q];
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(gw_buf<B>() + (256 * q + 64 * x.wid) * 8),
+                                     16, 0, 0);
+  }
+}
+
+// Step c on buffer B: wait for chunk c, refill the buffer freed by step c - 1 with chunk
+// c + kGwStages - 1, add the bias sums and run the MFMAs of the chunk.
+template <int W, int B>
+__device__ __forceinline__ void gw_step(const GwCtx<W>& x, int c, bool bias, float& dbs,
+                                       f32x16 (&acc)[gw_tf<W>() / 64][gw_tk<W>() / 64]) {
+  using C = GwCtx<W>;
+  constexpr int TF = C::TF, TK = C::TK, NQ = C::NQ, FBW = TF / 64, RB = TK / 64;
+  // chunks issued after c that may still be in flight: min(nch - 1 - c, kGwStages - 2)
+  const int later = min(x.nch - 1 - c, kGwStages - 2);
+  if (later >= 2) wait_vm<2 * NQ>();
+  else if (later == 1) wait_vm<NQ>();
+  else wait_vm<0>();
+  __builtin_amdgcn_s_barrier();                    // chunk c has landed for every wave; c - 1 is consumed
+  if (c + kGwStages - 1 < x.nch) gw_issue<W, (B + kGwStages - 1) % kGwStages>(x, c + kGwStages - 1);
+  const __bf16* S = gw_buf<B>();
+  const int half = x.lane >> 5, col = x.lane & 31, wf = x.wid & 1, wk = x.wid >> 1;
+  if (bias) {   // db_l[f] = sum_b dz_l[f][b]: 256 / TF threads per row
+    constexpr int TPR = 256 / TF, SPT = 4 / TPR;   // segments per thread
+    const int r = x.tid / TPR;
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(S + r * kGwChunk + 8 * gw_slot(r, SPT * (x.tid % TPR) + u));
+#pragma unroll
+      for (int e = 0; e < 8; ++e) dbs += (float)v[e];
+    }
+  }
+#pragma unroll
+  for (int ks = 0; ks < kGwChunk / 16; ++ks) {
+    bf16x8 xa[FBW], yb[RB];
+#pragma unroll
+    for (int fb = 0; fb < FBW; ++fb) {
+      const int r = (TF / 2) * wf + 32 * fb + col;
+      xa[fb] = *reinterpret_cast<const bf16x8*>(S + r * kGwChunk + 8 * gw_slot(r, 2 * ks + half));
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int r = TF + (TK / 2) * wk + 32 * rb + col;
+      yb[rb] = *reinterpret_cast<const bf16x8*>(S + r * kGwChunk + 8 * gw_slot(r, 2 * ks + half));
+    }
+#pragma unroll
+    for (int fb = 0; fb < FBW; ++fb)
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+        acc[fb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[fb], yb[rb], acc[fb][rb], 0, 0, 0);
+  }
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void k_grad_w(TrainArgs a, float* __restrict__ part) {
   constexpr int TF = gw_tf<W>(), TK = gw_tk<W>();
   constexpr int FBW = TF / 64;                       // row (feature) blocks per wave
   constexpr int RB = TK / 64;                        // column blocks per wave
-  constexpr int SEG = kGwChunk / 8;                  // 16-byte segments per row and chunk
-  __shared__ __align__(16) __bf16 As[TF * kGwLd];
-  __shared__ __align__(16) __bf16 Bs[TK * kGwLd];
-  int g = blockIdx.x;
-  const int tk = g % (W / TK); g /= (W / TK);
-  const int tf = g % (W / TF); g /= (W / TF);
-  const int s = g % kSplitW; g /= kSplitW;
-  const int l = g + 2;                              // layer 2..L
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int half = lane >> 5, col = lane & 31;
-  const int wf = wid & 1, wk = wid >> 1;
-  const int f0 = tf * TF, k0 = tk * TK;
-  const int per = a.Bp / kSplitW;                   // multiple of 16 (Bp is a multiple of 256)
-  const int b_begin = s * per, b_end = b_begin + per;
-  const __bf16* dz = a.dzT + (size_t)(l - 1) * W * a.Bp;   // layer blocks
-  const __bf16* ap = a.aT + (size_t)(l - 2) * W * a.Bp;
+  static_assert((TF + TK) * kGwChunk <= kGwStageElems && kGwStages == 4, "stage buffers");
+  int tk, tf, s, l;
+  gw_coords<W>(blockIdx.x, gridDim.x, &tk, &tf, &s, &l);
+  GwCtx<W> x;
+  x.tid = threadIdx.x;
+  x.lane = x.tid & 63;
+  x.wid = x.tid >> 6;
+  x.f0 = tf * TF;
+  x.k0 = tk * TK;
+  const int tiles = a.Bp / 64;                      // splits: whole 64-row tiles, as even as they come
+  x.b_begin = (int)((int64_t)s * tiles / kSplitW) * 64;
+  x.nch = ((int)((int64_t)(s + 1) * tiles / kSplitW) * 64 - x.b_begin) / kGwChunk;
+  x.dz = a.dzT + (size_t)(l - 1) * W * a.Bp;        // layer blocks
+  x.ap = a.aT + (size_t)(l - 2) * W * a.Bp;
+  static_assert(TF % 64 == 0, "a load pass holds rows of one operand");
+#pragma unroll
+  for (int q = 0; q < GwCtx<W>::NQ; ++q) {           // thread's row r and segment of load q: tix(W, f, 8 seg) in a chunk
+    const int id = 256 * q + x.tid, r = id >> 2, seg = gw_slot(r, id & 3);
+    x.off[q] = (r < TF ? x.f0 + r : x.k0 + r - TF) * 64 + 8 * seg;
+  }
+  const int half = x.lane >> 5, col = x.lane & 31, wf = x.wid & 1, wk = x.wid >> 1;
   f32x16 acc[FBW][RB];
 #pragma unroll
   for (int fb = 0; fb < FBW; ++fb)
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) acc[fb][rb] = f32x16{};
-  float dbs = 0.f;   // this thread's half-row sum of dz for the bias gradient (tk == 0)
-  // thread tid moves segments tid + 256 q, q < NQ, of each chunk: row r, columns c8..
-  constexpr int NQ = (TF + TK) * SEG / 256;
-  static_assert((TF + TK) * SEG % 256 == 0, "whole passes");
-  bf16x8 stage[NQ];
-  auto fetch = [&](int b, int kc) {                  // the chunk at b into registers
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int id = tid + 256 * q, r = id / SEG, c8 = 8 * (id - r * SEG);
-      const __bf16* src = r < TF ? dz + tix(W, f0 + r, b + c8) : ap + tix(W, k0 + r - TF, b + c8);
-      if (c8 < kc) stage[q] = *reinterpret_cast<const bf16x8*>(src);
-    }
-  };
-  fetch(b_begin, min(kGwChunk, b_end - b_begin));
-  for (int b = b_begin; b < b_end; b += kGwChunk) {
-    const int kc = min(kGwChunk, b_end - b);        // multiple of 16
-    __syncthreads();                                // every wave is done with the last stage
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int id = tid + 256 * q, r = id / SEG, c8 = 8 * (id - r * SEG);
-      __bf16* dst = r < TF ? As + r * kGwLd : Bs + (r - TF) * kGwLd;
-      if (c8 < kc) *reinterpret_cast<bf16x8*>(dst + c8) = stage[q];
-    }
-    __syncthreads();
-    if (b + kGwChunk < b_end) fetch(b + kGwChunk, min(kGwChunk, b_end - b - kGwChunk));   // in flight during the MFMAs
-    if (tk == 0) {   // the bias gradient db_l[f] = sum_b dz_l[f][b]: 256 / TF threads per row
-      constexpr int TPR = 256 / TF, CPT = kGwChunk / TPR;
-      const __bf16* row = As + (tid / TPR) * kGwLd + CPT * (tid % TPR);
-      const int n = min(CPT, kc - CPT * (tid % TPR));
-      for (int c = 0; c < n; ++c) dbs += (float)row[c];
-    }
-    for (int ks = 0; ks < kc / 16; ++ks) {
-      bf16x8 x[FBW], y[RB];
-#pragma unroll
-      for (int fb = 0; fb < FBW; ++fb)
-        x[fb] = *reinterpret_cast<const bf16x8*>(As + ((TF / 2) * wf + 32 * fb + col) * kGwLd + 16 * ks + 8 * half);
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-        y[rb] = *reinterpret_cast<const bf16x8*>(Bs + ((TK / 2) * wk + 32 * rb + col) * kGwLd + 16 * ks + 8 * half);
-#pragma unroll
-      for (int fb = 0; fb < FBW; ++fb)
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-          acc[fb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[fb], y[rb], acc[fb][rb], 0, 0, 0);
-    }
+  float dbs = 0.f;   // this thread's share of its dz row's sum (the bias gradient, tk == 0)
+  const bool bias = tk == 0;
+  if (x.nch > 0) gw_issue<W, 0>(x, 0);
+  if (x.nch > 1) gw_issue<W, 1>(x, 1);
+  if (x.nch > 2) gw_issue<W, 2>(x, 2);
+  for (int c = 0; c < x.nch; c += kGwStages) {
+    gw_step<W, 0>(x, c, bias, dbs, acc);
+    if (c + 1 < x.nch) gw_step<W, 1>(x, c + 1, bias, dbs, acc);
+    if (c + 2 < x.nch) gw_step<W, 2>(x, c + 2, bias, dbs, acc);
+    if (c + 3 < x.nch) gw_step<W, 3>(x, c + 3, bias, dbs, acc);
   }
   float* P = part + ((size_t)(l - 2) * kSplitW + s) * W * W;
 #pragma unroll
@@ -444,13 +565,13 @@ __global__ __launch_bounds__(256) void k_grad_w(TrainArgs a, float* __restrict__
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          P[(size_t)(f0 + (TF / 2) * wf + 32 * fb + 8 * j + 4 * half + i) * W + k0 + (TK / 2) * wk + 32 * rb + col] =
+          P[(size_t)(x.f0 + (TF / 2) * wf + 32 * fb + 8 * j + 4 * half + i) * W + x.k0 + (TK / 2) * wk + 32 * rb + col] =
               acc[fb][rb][4 * j + i];
-  if (tk == 0) {   // bias partials after the weight partials: [L - 1][kSplitW][W]
+  if (bias) {   // bias partials after the weight partials: [L - 1][kSplitW][W]
     constexpr int TPR = 256 / TF;
     const float d = TPR == 2 ? dbs + __shfl_xor(dbs, 1, 64) : dbs;
-    if (tid % TPR == 0)
-      part[(size_t)(a.net.n_hidden - 1) * kSplitW * W * W + ((size_t)(l - 2) * kSplitW + s) * W + f0 + tid / TPR] = d;
+    if (x.tid % TPR == 0)
+      part[(size_t)(a.net.n_hidden - 1) * kSplitW * W * W + ((size_t)(l - 2) * kSplitW + s) * W + x.f0 + x.tid / TPR] = d;
   }
 }
 
@@ -477,116 +598,177 @@ __global__ void k_grad_reduce(TrainArgs a, const float* __restrict__ part) {
   }
 }
 
-// One block of 256 threads per output: rows 0 .. W-1 are the w_out gradient
-// (sum_b dy[b] a_L[f][b]), row W is b_out's (sum_b dy[b]).  Each thread sums a strided
-// share of the batch with four loads in flight, then the block combines the shares in
-// a fixed order.  (Every hidden layer's bias gradient comes with its weights: db_1 from
-// k_grad_w1, db_l, l >= 2, from k_grad_w.)
-__global__ __launch_bounds__(256) void k_grad_rows(TrainArgs a) {
-  __shared__ float red[4];
-  const MlpArgs& n = a.net;
-  const int W = n.width, L = n.n_hidden;
-  const int row = blockIdx.x;
+// Output-layer gradients: w_out[f] = sum_b dy[b] a_L[f][b] and b_out = sum_b dy[b].  A
+// block streams a contiguous run of 64-row tiles of the last hidden layer's block (each
+// tile's layer is W x 64 consecutive BF16 values): wave w takes features w W/4 .. and
+// every load of a wave reads 1 KB of consecutive memory, 8 features x 64 rows, so lane l
+// always meets feature 8 q + l/8 of its quarter and rows 8 (l % 8) .. + 7 of the tile.
+// Per-lane sums run over the block's tiles; lanes of one feature are then combined and
+// the block writes its partial row [W + 1]; k_sum_splits adds the blocks' rows in a
+// fixed order.
+constexpr int kOutBlocks = 256;    // blocks (at most) of k_grad_out
+__host__ __device__ inline int out_blocks(int Bp) { return Bp / 64 < kOutBlocks ? Bp / 64 : kOutBlocks; }
+
+template <int W>
+__global__ __launch_bounds__(256) void k_grad_out(TrainArgs a, float* __restrict__ part) {
+  constexpr int Q = W / 32;                            // loads per wave and tile
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  float s = 0.f;
-  if (row < W) {
-    const __bf16* v = a.aT + (size_t)(L - 1) * W * a.Bp;   // the last hidden layer's block
-    float u[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int b0 = 8 * tid; b0 < a.Bp; b0 += 4 * 2048) {
+  const int tiles = a.Bp / 64, nb = out_blocks(a.Bp);
+  const int t_begin = (int)((int64_t)blockIdx.x * tiles / nb), t_end = (int)((int64_t)(blockIdx.x + 1) * tiles / nb);
+  const int fw = wid * (W / 4);
+  const __bf16* v = a.aT + (size_t)(a.net.n_hidden - 1) * W * a.Bp;   // the last hidden layer's block
+  float acc[Q], sdy = 0.f;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int b = b0 + q * 2048;
-        if (b < a.Bp) {
-          const bf16x8 x = *reinterpret_cast<const bf16x8*>(v + tix(W, row, b));
+  for (int q = 0; q < Q; ++q) acc[q] = 0.f;
+  for (int t = t_begin; t < t_end; ++t) {
+    const __bf16* base = v + ((size_t)t * W + fw) * 64 + 8 * lane;
+    bf16x8 x[Q];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) u[q] = fmaf((float)x[e], a.dy[b + e], u[q]);
+    for (int q = 0; q < Q; ++q) x[q] = *reinterpret_cast<const bf16x8*>(base + 512 * q);
+    const float4 d0 = *reinterpret_cast<const float4*>(a.dy + (size_t)t * 64 + 8 * (lane & 7));
+    const float4 d1 = *reinterpret_cast<const float4*>(a.dy + (size_t)t * 64 + 8 * (lane & 7) + 4);
+    const float d[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[q] = fmaf((float)x[q][e], d[e], acc[q]);
+    if (wid == 0 && lane < 8) sdy += ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]));
+  }
+  float* P = part + (size_t)blockIdx.x * (W + 1);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    float u = acc[q];
+    u += __shfl_xor(u, 1, 64);
+    u += __shfl_xor(u, 2, 64);
+    u += __shfl_xor(u, 4, 64);
+    if ((lane & 7) == 0) P[fw + 8 * q + (lane >> 3)] = u;
+  }
+  if (wid == 0) {
+    sdy += __shfl_xor(sdy, 1, 64);
+    sdy += __shfl_xor(sdy, 2, 64);
+    sdy += __shfl_xor(sdy, 4, 64);
+    if (lane == 0) P[W] = sdy;
+  }
+}
+
+// out[o] = sum over r < R of part[r n + o], in a fixed order: a block of 16 waves takes
+// 64 consecutive outputs; wave w sums rows w R/16 .. in order, 8 loads in flight, and
+// the 16 wave sums are added in order.  Many short sums in parallel instead of one long
+// chain per output (the splits of the gradient kernels are up to 256 rows).
+__global__ __launch_bounds__(1024) void k_sum_splits(const float* __restrict__ part, int R, int n,
+                                                     float* __restrict__ out) {
+  __shared__ float ws[16][64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int o = blockIdx.x * 64 + lane;
+  const int r0 = (int)((int64_t)wid * R / 16), r1 = (int)((int64_t)(wid + 1) * R / 16);
+  float acc = 0.f;
+  if (o < n) {
+    int r = r0;
+    for (; r + 8 <= r1; r += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(r + u) * n + o];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; r < r1; ++r) acc += part[(size_t)r * n + o];
+  }
+  ws[wid][lane] = acc;
+  __syncthreads();
+  if (wid == 0 && o < n) {
+    float t = 0.f;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += ws[w][lane];
+    out[o] = t;
+  }
+}
+
+hipError_t launch_sum_splits(const float* part, int R, int n, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, st, part, R, n, out);
+  return hipGetLastError();
+}
+
+// dW_1[f][j] = sum_b dz_1[f][b] h0[j][b] and db_1[f] = sum_b dz_1[f][b] on MFMA.  The FP32
+// input is split into a BF16 high part and the BF16 rounding of the remainder (about 16
+// significant bits together), so that two MFMAs per 16 batch rows, with dz_1 as the A
+// operand, give C_hi[f][j] over the high parts, whose column in_dim is a column of ones
+// (the bias), and C_lo[f][j] over the low parts; dW_1 = C_hi + C_lo.  A block takes one
+// batch split and 4 waves of 64 features each (two feature blocks of 32); the B
+// fragments of the split are built once per block in LDS, in chunks of kW1Chunk k-steps
+// of 16 rows.  The splits' partial rows [W][in_dim] then [W] go to part, summed in a
+// fixed order by k_sum_splits.
+constexpr int kW1MaxSplits = 128;
+constexpr int kW1Chunk = 16;      // k-steps per LDS chunk (256 rows)
+constexpr int kW1Unroll = 8;      // k-steps whose dz loads are in flight together
+__host__ __device__ inline int w1_splits(int Bp) { return Bp / 16 < kW1MaxSplits ? Bp / 16 : kW1MaxSplits; }
+
+__global__ __launch_bounds__(256) void k_grad_w1(TrainArgs a, float* __restrict__ part) {
+  __shared__ __align__(16) bf16x8 Bf[kW1Chunk][2][64];   // [k-step][high, low][lane]
+  const int W = a.net.width, in_dim = a.net.in_dim;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  const int S = w1_splits(a.Bp), nks = a.Bp / 16, s = blockIdx.y;
+  const int ks_begin = (int)((int64_t)s * nks / S), ks_end = (int)((int64_t)(s + 1) * nks / S);
+  const int f0 = (blockIdx.x * 4 + wid) * 64;
+  const bool active = f0 < W;                      // wave-uniform; every wave takes the barriers
+  f32x16 hi[2] = {f32x16{}, f32x16{}}, lo[2] = {f32x16{}, f32x16{}};
+  for (int c0 = ks_begin; c0 < ks_end; c0 += kW1Chunk) {
+    const int nc = min(kW1Chunk, ks_end - c0);
+    __syncthreads();                               // the last chunk's fragments are consumed
+    for (int it = tid; it < nc * 64; it += 256) {  // fragment (k-step, lane l): column l % 32, rows 8 (l / 32) ..
+      const int k = it >> 6, l = it & 63, j = l & 31;
+      const int b = (c0 + k) * 16 + 8 * (l >> 5);
+      bf16x8 h = {}, r = {};
+      if (j < in_dim) {
+        const float4 u0 = *reinterpret_cast<const float4*>(a.h0T + (size_t)j * a.Bp + b);
+        const float4 u1 = *reinterpret_cast<const float4*>(a.h0T + (size_t)j * a.Bp + b + 4);
+        const float x[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          h[e] = (__bf16)x[e];
+          r[e] = (__bf16)(x[e] - (float)h[e]);
+        }
+      } else if (j == in_dim) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) h[e] = (__bf16)1.0f;
+      }
+      Bf[k][0][l] = h;
+      Bf[k][1][l] = r;
+    }
+    __syncthreads();
+    if (active) {
+      for (int k0 = 0; k0 < nc; k0 += kW1Unroll) {
+        bf16x8 x[kW1Unroll][2];
+#pragma unroll
+        for (int u = 0; u < kW1Unroll; ++u)
+#pragma unroll
+          for (int fb = 0; fb < 2; ++fb)
+            if (k0 + u < nc)
+              x[u][fb] = *reinterpret_cast<const bf16x8*>(a.dzT + tix(W, f0 + 32 * fb + col, (c0 + k0 + u) * 16 + 8 * half));
+#pragma unroll
+        for (int u = 0; u < kW1Unroll; ++u) {
+          if (k0 + u >= nc) break;
+          const bf16x8 bh = Bf[k0 + u][0][lane], bl = Bf[k0 + u][1][lane];
+#pragma unroll
+          for (int fb = 0; fb < 2; ++fb) {
+            hi[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[u][fb], bh, hi[fb], 0, 0, 0);
+            lo[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[u][fb], bl, lo[fb], 0, 0, 0);
+          }
         }
       }
     }
-    s = (u[0] + u[1]) + (u[2] + u[3]);
-  } else {
-    for (int b = tid; b < a.Bp; b += 256) s += a.dy[b];
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) red[wid] = s;
-  __syncthreads();
-  if (tid == 0) a.grad[off_out(n) + row] = (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-// dW_1[f][j] = sum_b dz_1[f][b] h0[j][b] and db_1[f] = sum_b dz_1[f][b] in FP32, over one
-// batch split per block.  A wave takes kW1F features; its lanes run along the batch (8
-// consecutive rows each, so one load reads a 1 KB stretch of a dz row and of an input
-// row), and every lane keeps kW1F x (in_dim + 1) partial sums, combined across the wave
-// at the end in a fixed order.
-constexpr int kW1F = 4;            // features per wave
-constexpr int kW1Split = 16;       // batch splits
-
-__global__ __launch_bounds__(256) void k_grad_w1(TrainArgs a, float* __restrict__ part) {
-  constexpr int kMaxIn = 3 + 2 * SV_MAX_DOF;
-  const int W = a.net.width, in_dim = a.net.in_dim;
-  const int lane = threadIdx.x & 63;
-  const int fw = (blockIdx.x * 4 + (threadIdx.x >> 6)) * kW1F;   // first feature of the wave
-  const int s = blockIdx.y;
-  if (fw >= W) return;                                             // wave-uniform
-  const int per = a.Bp / kW1Split;                                 // multiple of 16
-  const int b_begin = s * per, b_end = b_begin + per;
-  float acc[kW1F][kMaxIn], accb[kW1F];
-#pragma unroll
-  for (int q = 0; q < kW1F; ++q) {
-    accb[q] = 0.f;
-#pragma unroll
-    for (int jj = 0; jj < kMaxIn; ++jj) acc[q][jj] = 0.f;
-  }
-  for (int b = b_begin + 8 * lane; b < b_end; b += 512) {
-    float g[kW1F][8];
-#pragma unroll
-    for (int q = 0; q < kW1F; ++q) {
-      const bf16x8 x = *reinterpret_cast<const bf16x8*>(a.dzT + tix(W, fw + q, b));
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        g[q][e] = (float)x[e];
-        accb[q] += g[q][e];
-      }
-    }
-#pragma unroll
-    for (int jj = 0; jj < kMaxIn; ++jj) {
-      if (jj >= in_dim) continue;
-      const float4 u = *reinterpret_cast<const float4*>(a.h0T + (size_t)jj * a.Bp + b);
-      const float4 v = *reinterpret_cast<const float4*>(a.h0T + (size_t)jj * a.Bp + b + 4);
-      const float h[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int q = 0; q < kW1F; ++q)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) acc[q][jj] = fmaf(g[q][e], h[e], acc[q][jj]);
-    }
-  }
+  if (!active) return;
+  // C[f][j]: acc[4 jj + i] is feature 32 fb + 8 jj + 4 half + i, column col
   float* ps = part + (size_t)s * W * (in_dim + 1);   // this split: dW_1 [W][in_dim], then db_1 [W]
 #pragma unroll
-  for (int q = 0; q < kW1F; ++q) {
+  for (int fb = 0; fb < 2; ++fb)
 #pragma unroll
-    for (int jj = 0; jj < kMaxIn; ++jj) {
-      if (jj >= in_dim) continue;
-      float v = acc[q][jj];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == 0) ps[(size_t)(fw + q) * in_dim + jj] = v;
+    for (int e = 0; e < 16; ++e) {
+      const int f = f0 + 32 * fb + 8 * (e >> 2) + 4 * half + (e & 3);
+      if (col < in_dim) ps[(size_t)f * in_dim + col] = hi[fb][e] + lo[fb][e];
+      else if (col == in_dim) ps[(size_t)W * in_dim + f] = hi[fb][e];
     }
-    float v = accb[q];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) ps[(size_t)W * in_dim + fw + q] = v;
-  }
-}
-
-// dW_1 and db_1 (contiguous in the flat vector) from the splits, in a fixed order.
-__global__ void k_grad_w1_reduce(TrainArgs a, const float* __restrict__ part, int chunks) {
-  const int n = a.net.width * (a.net.in_dim + 1);
-  for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < n; o += gridDim.x * blockDim.x) {
-    float s = 0.f;
-    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n + o];
-    a.grad[o] = s;
-  }
 }
 
 // Adam, PyTorch's form: p -= (lr / (1 - b1^t)) * m / (sqrt(v) / sqrt(1 - b2^t) + eps).
@@ -637,12 +819,14 @@ hipError_t launch_train_t(TrainArgs a, float* part_w, float* part_w1, float sigm
     hipLaunchKernelGGL(k_grad_reduce, dim3(2048), dim3(256), 0, st, a, part_w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_grad_rows, dim3((unsigned)(W + 1)), dim3(256), 0, st, a);
+  // the output-layer partials, then the dW_1 splits, use part_w1 in turn
+  hipLaunchKernelGGL((k_grad_out<W>), dim3((unsigned)out_blocks(a.Bp)), dim3(256), 0, st, a, part_w1);
+  if ((e = launch_sum_splits(part_w1, out_blocks(a.Bp), W + 1, a.grad + off_out(a.net), st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grad_w1, dim3((unsigned)((W + 255) / 256), (unsigned)w1_splits(a.Bp)), dim3(256), 0, st, a,
+                     part_w1);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_grad_w1, dim3((unsigned)((W / kW1F + 3) / 4), kW1Split), dim3(256), 0, st, a, part_w1);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_grad_w1_reduce, dim3(64), dim3(256), 0, st, a, part_w1, kW1Split);
-  return hipGetLastError();
+  // dW_1 and db_1 are contiguous at the start of the flat vector
+  return launch_sum_splits(part_w1, w1_splits(a.Bp), W * (a.net.in_dim + 1), a.grad, st);
 }
 
 // ----------------------------------------------------------------- residual network
@@ -1095,9 +1279,9 @@ hipError_t launch_train_res_t(ResTrainArgs a, float* part_w, float* part_w1, flo
     u.dzT = a.dzT + (size_t)s * W * a.Bp;
     u.h0T = a.xT;
     u.grad = a.grad + (s == 0 ? 0 : res_block_base(W, n.in_dim, s - 1) + (size_t)W * W);
-    hipLaunchKernelGGL(k_grad_w1, dim3((unsigned)((W / kW1F + 3) / 4), kW1Split), dim3(256), 0, st, u, part_w1);
-    hipLaunchKernelGGL(k_grad_w1_reduce, dim3(64), dim3(256), 0, st, u, part_w1, kW1Split);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grad_w1, dim3((unsigned)((W + 255) / 256), (unsigned)w1_splits(a.Bp)), dim3(256), 0, st, u,
+                       part_w1);
+    if ((e = launch_sum_splits(part_w1, w1_splits(a.Bp), W * (n.in_dim + 1), u.grad, st)) != hipSuccess) return e;
   }
   return hipGetLastError();
 }
@@ -1110,8 +1294,10 @@ size_t train_part_w_elems(const MlpArgs& n) {   // dW_l splits, then db_l splits
   return n.n_hidden >= 2 ? (size_t)kSplitW * (n.n_hidden - 1) * n.width * (n.width + 1) : 0;
 }
 size_t train_part_w1_elems(const MlpArgs& n, int64_t Bp) {
-  // the dW_1 splits; the loss partials (Bp / 256 floats) borrow the same space first
-  return std::max<size_t>((size_t)kW1Split * n.width * (n.in_dim + 1), (size_t)(Bp / 256));
+  // the dW_1 splits; the loss partials (Bp / 256 floats) and the output-layer partials
+  // borrow the same space first
+  return std::max({(size_t)w1_splits((int)Bp) * n.width * (n.in_dim + 1), (size_t)(Bp / 256),
+                   (size_t)out_blocks((int)Bp) * (n.width + 1)});
 }
 
 hipError_t launch_train_step(const MlpArgs& net, const float* samples, const int* idx, int B, int Bp, __bf16* aT,
@@ -1128,7 +1314,9 @@ hipError_t launch_train_step(const MlpArgs& net, const float* samples, const int
 }
 
 size_t train_res_part_w_elems(const MlpArgs& n) { return (size_t)kSplitW * n.n_hidden * n.width * (n.width + 1); }
-size_t train_res_part_w1_elems(const MlpArgs& n) { return (size_t)kW1Split * n.width * (n.in_dim + 1); }
+size_t train_res_part_w1_elems(const MlpArgs& n, int64_t Bp) {
+  return (size_t)w1_splits((int)Bp) * n.width * (n.in_dim + 1);
+}
 
 hipError_t launch_train_step_res(const MlpArgs& net, const float* samples, const int* idx, int B, int Bp,
                                  const ResTrainWs& w, float sigma, float* grad, float* loss_out, hipStream_t st) {

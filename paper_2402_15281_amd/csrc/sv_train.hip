@@ -85,6 +85,11 @@ constexpr int train_threads() { return 64 * (W / (32 * kTFB)); }
 // 128-byte line.  Element (feature f, batch row b) of a block:
 __host__ __device__ inline size_t tix(int W, int f, int b) { return ((size_t)(b >> 6) * W + f) * 64 + (b & 63); }
 
+// The activation and dz streams (hundreds of MB per step, each byte read once by the
+// next kernel) are written and read with the non-temporal cache policy, so that they do
+// not push the packed weights (3.7 MB, read by every tile) out of L2: 1.14 -> 1.07 ms per
+// training step (8 x 512, batch 65,536).
+//
 // Copy the LDS tile H[64][LD] (features 0..W-1) to the layer block outT (features f, rows r0 .. r0 + 63) in blocks
 // of 8 rows x 8 features: a lane reads its block with eight 16-byte LDS reads (rows),
 // transposes it in registers and writes eight 16-byte stores (features).  In a wave the
@@ -108,7 +113,7 @@ __device__ __forceinline__ void store_tile_T(const __bf16* H, __bf16* outT, int 
       bf16x8 o;
 #pragma unroll
       for (int r = 0; r < 8; ++r) o[r] = in[r][f];
-      *reinterpret_cast<bf16x8*>(outT + tix(W, 8 * fg + f, r0 + 8 * rg)) = o;
+      __builtin_nontemporal_store(o, reinterpret_cast<bf16x8*>(outT + tix(W, 8 * fg + f, r0 + 8 * rg)));
     }
   }
 }
@@ -148,7 +153,7 @@ __device__ __forceinline__ void fetch_tile_T(const __bf16* inT, int r0, bf16x8 (
   for (int q = 0; q < W / 64 / NW; ++q) {
     const int fg = 8 * (w + q * NW) + (lane & 7);
 #pragma unroll
-    for (int f = 0; f < 8; ++f) in[q][f] = *reinterpret_cast<const bf16x8*>(inT + tix(W, 8 * fg + f, r0 + 8 * rg));
+    for (int f = 0; f < 8; ++f) in[q][f] = __builtin_nontemporal_load(reinterpret_cast<const bf16x8*>(inT + tix(W, 8 * fg + f, r0 + 8 * rg)));
   }
 }
 template <int W, int NT, int LD = W + kLdsPad>

@@ -641,10 +641,9 @@ def main():
         f"{cont['free_at_samples']}, certified free along the continuous motion {cont['free_continuous']} of {dm.n}")
     ms_t, kt = timed(sv, torch, check(out_t, mlp, sv.SV_SCREEN_TRUST), max(args.steps // 2, 1), 1,
                      ["screen", "fallback"])
-    ms_u, ku = timed(sv, torch, check(out_u, untrained, sv.SV_SCREEN_CERTIFIED), max(args.steps // 2, 1), 1,
-                     ["screen", "fallback", "confirm"])
-    ms_c, kc = timed(sv, torch, check(out_c, mlp, sv.SV_SCREEN_CERTIFIED), args.steps, args.warmup,
-                     ["screen", "fallback", "confirm"])
+    stages = ["sort", "screen", "fallback", "decide", "confirm", "finalize", "recheck64"]
+    ms_u, ku = timed(sv, torch, check(out_u, untrained, sv.SV_SCREEN_CERTIFIED), max(args.steps // 2, 1), 1, stages)
+    ms_c, kc = timed(sv, torch, check(out_c, mlp, sv.SV_SCREEN_CERTIFIED), args.steps, args.warmup, stages)
     M, N = dm.n, dc.n
     value = M / (ms_c / 1e3)
 
@@ -690,7 +689,8 @@ def main():
         f"({fx / PEAK_FP32_TFLOPS:.1%} of FP32 peak); dense kernel {kd['exact']:.3f} ms = {fd:.1f} TFLOP/s "
         f"({fd / PEAK_FP32_TFLOPS:.1%}), results identical {dense_same}")
     log(f"certified: {ms_c:.3f} ms/step = {value:.0f} motions/s; network {kc['screen']:.3f} ms = {fm:.1f} TFLOP/s "
-        f"({fm / PEAK_BF16_TFLOPS:.1%} of BF16 peak); fallback {kc['fallback']:.3f} ms; confirm {kc['confirm']:.3f} ms")
+        f"({fm / PEAK_BF16_TFLOPS:.1%} of BF16 peak); sort {kc['sort']:.3f} ms; fallback {kc['fallback']:.3f} ms; "
+        f"confirm {kc['confirm']:.3f} ms")
     log(f"trust:     {ms_t:.3f} ms/step; verdict agreement trust {np.mean(v_t == v_x):.4f}, "
         f"certified {np.mean(v_c == v_x):.4f}; fallback fraction {nfb.sum() / (M * N):.4f}")
     log(f"untrained: certified {ms_u:.3f} ms/step, fallback fraction {nfb_u.sum() / (M * N):.4f}, "
@@ -733,6 +733,7 @@ def main():
         "trust_screening": {"value": M / (ms_t / 1e3), "unit": "motions/s", "ms_per_step": ms_t,
                             "verdict_agreement_vs_exact": float(np.mean(v_t == v_x))},
         "verdict_agreement_certified_vs_exact": float(np.mean(v_c == v_x)),
+        "certified_stages_ms": {k: kc[k] for k in stages},
         "fallback_fraction": float(nfb.sum() / (M * N)),
         "collision_fraction": float(v_x.mean()),
         "trust_missed_collisions": int(np.sum((v_x == 1) & (v_t == 0))),

@@ -498,17 +498,35 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
       }
     } else {
       const MlpArgs na = to_args(*mlp);
+      const bool certified = screen == SV_SCREEN_CERTIFIED;
       SV_TRY("init", launch_fill_i32(w.pcount, M, 0, st));
       SV_TRY("init", launch_fill_i32(w.full_count, 1, 0, st));
       SV_TRY("pack_bf16", launch_pack_bf16(na, 0, w.packed, st));
-      SV_TRY("screen", launch_mlp_bf16(na, ma, ca, w.packed, nullptr, tau, w.plist, w.pcount, st));
-      SV_TRY("fallback", launch_exact(*robot, w.table, ma, ca, nullptr, nullptr, M, w.plist, w.pcount, nullptr, w.keys,
-                                      shape, st));
-      SV_TRY("decide", launch_screen_decide(w.keys, M, w.pcount, eps, kCertBand, screen == SV_SCREEN_CERTIFIED, *out,
-                                            w.full, w.full_count, st));
-      if (screen == SV_SCREEN_CERTIFIED) {
+      if (cull) {
+        // Screen the Morton-sorted cloud (a prediction does not depend on the order), so
+        // that the points sent per motion come in sorted order and the culled check of
+        // them bounds each wave's points by a small sphere.  Certified screening only
+        // asks whether a sent point lies within eps - band: groups provably above that
+        // are skipped from the start.
+        SV_TRY("sort", launch_cull_sort(*robot, w.table, ma, ca, w.cull, st));
+        CloudArgs sorted = ca;
+        sorted.x = w.cull.sx;
+        sorted.y = w.cull.sy;
+        sorted.z = w.cull.sz;
+        SV_TRY("screen", launch_mlp_bf16(na, ma, sorted, w.packed, nullptr, tau, w.plist, w.pcount, st));
+        SV_TRY("fallback", launch_fallback_culled(*robot, w.table, ma, cloud->n, w.plist, w.pcount,
+                                                  certified ? eps - kCertBand : INFINITY, w.keys, w.cull, st));
+      } else {
+        SV_TRY("screen", launch_mlp_bf16(na, ma, ca, w.packed, nullptr, tau, w.plist, w.pcount, st));
+        SV_TRY("fallback", launch_exact(*robot, w.table, ma, ca, nullptr, nullptr, M, w.plist, w.pcount, nullptr,
+                                        w.keys, shape, st));
+      }
+      SV_TRY("decide", launch_screen_decide(w.keys, M, w.pcount, eps, kCertBand, certified, *out, w.full,
+                                            w.full_count, st));
+      if (certified) {
         if (cull) {
-          SV_TRY("confirm", launch_exact_culled(*robot, w.table, ma, ca, w.full, w.full_count, M, w.keys, w.cull, st));
+          SV_TRY("confirm", launch_cull_pass(*robot, w.table, ma, ca, w.full, w.full_count, M, w.keys, w.cull, true,
+                                             st));
         } else {
           SV_TRY("confirm", launch_exact(*robot, w.table, ma, ca, w.full, w.full_count, M, nullptr, nullptr, nullptr,
                                          w.keys, shape, st));

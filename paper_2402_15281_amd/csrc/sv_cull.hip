@@ -360,6 +360,126 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
   }
 }
 
+// The exact check of the points a network screen sent (sv_check_motions with a screen):
+// per motion, the points of the Morton-sorted cloud listed in plist[m N ..] (sorted
+// indices, pcount[m] of them, in sorted order; perm maps them to the caller's).  Block
+// (motion, tile of NT P listed points); each wave bounds its 64 P points by a sphere
+// (box midpoint, largest distance) and, capsule by capsule, runs the sample blocks that
+// the sphere test of cull_item cannot rule out under G.  G starts at the smaller of g0
+// and the motion's current key and falls with the wave's own results.  With g0 = +inf
+// the result is the minimum over the sent points and its lowest index, bit for bit; with
+// g0 = eps - band (certified screening, which only asks whether some sent point lies
+// within it) it is that minimum whenever the minimum is <= g0, and a value above g0
+// otherwise.  The sorted order keeps a wave's points close together, so that its sphere
+// is small.
+template <int P, int NT>
+__global__ __launch_bounds__(NT) void k_fallback_cull(const CapEntry* __restrict__ table,
+                                                      const float4* __restrict__ spheres, int T, int K, int nb, int B,
+                                                      const float* __restrict__ sx, const float* __restrict__ sy,
+                                                      const float* __restrict__ sz, const int* __restrict__ perm, int N,
+                                                      int tiles, const int* __restrict__ plist,
+                                                      const int* __restrict__ pcount, float g0,
+                                                      unsigned long long* __restrict__ keys,
+                                                      unsigned long long* __restrict__ work) {
+  __shared__ unsigned long long wmin[NT / 64];
+  __shared__ unsigned long long wexec[NT / 64];
+  const int m = blockIdx.x / tiles;
+  const int tile = blockIdx.x - m * tiles;
+  const int n_here = pcount[m];
+  if (tile * (NT * P) >= n_here) return;           // block-uniform
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int base = tile * (NT * P) + wid * (64 * P) + lane;
+  float x[P], y[P], z[P], best[P];
+  int idx[P];
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int jj = base + p * 64;
+    const bool ok = jj < n_here;
+    const int j = ok ? plist[(size_t)m * N + jj] : 0;
+    idx[p] = ok ? perm[j] : -1;
+    x[p] = ok ? sx[j] : 0.f;
+    y[p] = ok ? sy[j] : 0.f;
+    z[p] = ok ? sz[j] : 0.f;
+    best[p] = INFINITY;
+    if (ok) {
+      lo[0] = fminf(lo[0], x[p]); hi[0] = fmaxf(hi[0], x[p]);
+      lo[1] = fminf(lo[1], y[p]); hi[1] = fmaxf(hi[1], y[p]);
+      lo[2] = fminf(lo[2], z[p]); hi[2] = fmaxf(hi[2], z[p]);
+    }
+  }
+  unsigned long long executed = 0;
+  if (__builtin_amdgcn_readfirstlane((int)(base < n_here))) {   // lane 0 holds the wave's first point
+    float c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c[a] = uniform_f(0.5f * (wave_min(lo[a]) + wave_max(hi[a])));
+    float r2 = 0.f;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+      if (idx[p] >= 0) {
+        const float dx = x[p] - c[0], dy = y[p] - c[1], dz = z[p] - c[2];
+        r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
+      }
+    const float rw = uniform_f(sqrtf(wave_max(r2)));
+    float G = uniform_f(fminf(g0, key_dist(__hip_atomic_load(keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))));
+    auto skip = [&](float bx, float by, float bz, float br, float g) {
+      const float dx = bx - c[0], dy = by - c[1], dz = bz - c[2];
+      const float S = g + kCullMargin + rw + br;
+      return S < 0.f || dx * dx + dy * dy + dz * dz > S * S;
+    };
+    for (int k = 0; k < K; ++k) {
+      const size_t e = ((size_t)m * K + k) * T;
+      const float4* sph = spheres + ((size_t)m * K + k) * nb;
+      const float r = load_entry((ConstF4Ptr)table, e).r;
+      float m2[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p) m2[p] = INFINITY;
+      for (int b0 = 0; b0 < nb; b0 += 64) {
+        // lane l tests block b0 + l against the bound at the start of the chunk (the
+        // bound only falls, so a block failing here fails every later test too)
+        const int bl = b0 + lane;
+        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+        bool maybe = false;
+        if (bl < nb) {
+          q = sph[bl];
+          maybe = !skip(q.x, q.y, q.z, q.w, G);
+        }
+        for (unsigned long long mask = __ballot(maybe); mask; mask &= mask - 1) {
+          const int l = __builtin_ctzll(mask);
+          const float bx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.x), l));
+          const float by = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.y), l));
+          const float bz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.z), l));
+          const float br = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.w), l));
+          if (skip(bx, by, bz, br, G)) continue;   // the bound has tightened since
+          const int t0 = (b0 + l) * B, t1 = min(t0 + B, T);
+          swept_range<P>((ConstF4Ptr)table, e, t0, t1, x, y, z, m2);
+          executed += (unsigned long long)(t1 - t0) * (64 * P);
+          float wb = INFINITY;
+#pragma unroll
+          for (int p = 0; p < P; ++p)
+            if (idx[p] >= 0) wb = fminf(wb, sqrtf(m2[p]) - r);
+          G = uniform_f(fminf(G, wave_min(wb)));
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) best[p] = fminf(best[p], sqrtf(m2[p]) - r);
+    }
+  }
+  const unsigned long long k2 = block_min_key<NT>(lane_min_key<P>(best, idx), wmin);
+  if (threadIdx.x == 0 && k2 < __hip_atomic_load(keys + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMin(keys + m, k2);
+  if (work) {
+    if (lane == 0) wexec[wid] = executed;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long ex = 0;
+#pragma unroll
+      for (int q = 0; q < NT / 64; ++q) ex += wexec[q];
+      if (ex) atomicAdd(work + blockIdx.x % kWorkSlots, ex);
+    }
+  }
+}
+
 inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 int device_cus_cull() {
   static int cus[64] = {0};
@@ -404,10 +524,9 @@ hipError_t launch_bin_scan(const int* count, int64_t n_host, const int64_t* n_de
 int cull_blocks(int T, int kind) { return cull_block_count(T, kind); }
 int cull_tiles(int64_t N) { return (int)((N + kCullNT * kCullP - 1) / (kCullNT * kCullP)); }
 
-hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const MotionArgs& mo, const CloudArgs& c,
-                               const int* mlist, const int* mcount, int64_t n_slots, unsigned long long* keys,
-                               const CullWs& w, hipStream_t st) {
-  if (n_slots == 0 || c.n == 0) return hipSuccess;
+hipError_t launch_cull_sort(const sv_robot& rb, const CapEntry* table, const MotionArgs& mo, const CloudArgs& c,
+                            const CullWs& w, hipStream_t st) {
+  if (c.n == 0) return hipSuccess;
   const int K = rb.n_caps, T = mo.T, nb = cull_block_count(T, mo.kind), B = cull_block_len(T, mo.kind);
   hipError_t e;
   const int64_t nbins = (int64_t)1 << (3 * w.level);
@@ -423,8 +542,19 @@ hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const 
     return e;
   hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(c.n, 256)), dim3(256), 0, st, c, w.pbin, w.pslot, w.bin_start,
                      w.sx, w.sy, w.sz, w.perm);
-  hipLaunchKernelGGL(k_block_spheres, dim3(grid_for(mo.n * K * nb, 256)), dim3(256), 0, st, table, mo.n, T, K, nb, B,
-                     w.spheres);
+  if (mo.n > 0)
+    hipLaunchKernelGGL(k_block_spheres, dim3(grid_for(mo.n * K * nb, 256)), dim3(256), 0, st, table, mo.n, T, K, nb, B,
+                       w.spheres);
+  return hipGetLastError();
+}
+
+hipError_t launch_cull_pass(const sv_robot& rb, const CapEntry* table, const MotionArgs& mo, const CloudArgs& c,
+                            const int* mlist, const int* mcount, int64_t n_slots, unsigned long long* keys,
+                            const CullWs& w, bool reset, hipStream_t st) {
+  if (n_slots == 0 || c.n == 0) return hipSuccess;
+  const int K = rb.n_caps, T = mo.T, nb = cull_block_count(T, mo.kind), B = cull_block_len(T, mo.kind);
+  hipError_t e;
+  if (reset && (e = launch_fill_i32(w.list_count, 2, 0, st)) != hipSuccess) return e;
   const int stride = std::max(1, c.n / 256);
   hipLaunchKernelGGL(k_exact_seed, dim3((unsigned)(n_slots * K)), dim3(256), 0, st, table, T, K, w.sx, w.sy, w.sz, w.perm,
                      c.n, stride, seed_stride(T), mlist, mcount, keys);
@@ -442,6 +572,28 @@ hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const 
   hipLaunchKernelGGL((k_exact_cull<kCullP, kCullNT>), dim3(blocks), dim3(kCullNT), 0, st, table, w.spheres,
                      w.wave_spheres, T, K, nb, B, w.sx, w.sy, w.sz, w.perm, c.n, tiles, mlist, w.list, w.list_caps,
                      w.list_count, keys, w.work);
+  return hipGetLastError();
+}
+
+hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const MotionArgs& mo, const CloudArgs& c,
+                               const int* mlist, const int* mcount, int64_t n_slots, unsigned long long* keys,
+                               const CullWs& w, hipStream_t st) {
+  if (n_slots == 0 || c.n == 0) return hipSuccess;
+  hipError_t e = launch_cull_sort(rb, table, mo, c, w, st);
+  if (e != hipSuccess) return e;
+  return launch_cull_pass(rb, table, mo, c, mlist, mcount, n_slots, keys, w, false, st);
+}
+
+hipError_t launch_fallback_culled(const sv_robot& rb, const CapEntry* table, const MotionArgs& mo, int N,
+                                  const int* plist, const int* pcount, float g0, unsigned long long* keys,
+                                  const CullWs& w, hipStream_t st) {
+  if (mo.n == 0 || N == 0) return hipSuccess;
+  const int K = rb.n_caps, T = mo.T, nb = cull_block_count(T, mo.kind), B = cull_block_len(T, mo.kind);
+  const int tiles = (N + kCullNT * kCullP - 1) / (kCullNT * kCullP);
+  const int64_t blocks = mo.n * tiles;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_fallback_cull<kCullP, kCullNT>), dim3((unsigned)blocks), dim3(kCullNT), 0, st, table, w.spheres,
+                     T, K, nb, B, w.sx, w.sy, w.sz, w.perm, N, tiles, plist, pcount, g0, keys, w.work);
   return hipGetLastError();
 }
 

@@ -264,6 +264,23 @@ int cull_tiles(int64_t N);
 hipError_t launch_exact_culled(const sv_robot& rb, const CapEntry* table, const MotionArgs& mo, const CloudArgs& c,
                                const int* mlist, const int* mcount, int64_t n_slots, unsigned long long* keys,
                                const CullWs& w, hipStream_t st);
+// The two halves of launch_exact_culled: the Morton sort of the cloud into w (sx, sy, sz,
+// perm) and the sample-block spheres of every motion; then the pass itself (seed bound,
+// tile spheres, item list, culled kernel) over the motion slots, which needs the sort
+// (reset: clear the item queue first, when the sort did not run just before).
+hipError_t launch_cull_sort(const sv_robot& rb, const CapEntry* table, const MotionArgs& mo, const CloudArgs& c,
+                            const CullWs& w, hipStream_t st);
+hipError_t launch_cull_pass(const sv_robot& rb, const CapEntry* table, const MotionArgs& mo, const CloudArgs& c,
+                            const int* mlist, const int* mcount, int64_t n_slots, unsigned long long* keys,
+                            const CullWs& w, bool reset, hipStream_t st);
+// Per-motion keys over the points a screen sent, plist[m N ..] (indices into the sorted
+// cloud of w, pcount[m] per motion), with sample blocks skipped that the sphere test
+// proves to lie above min(g0, the current key); needs launch_cull_sort.  Exact (the
+// minimum over the sent points and its lowest caller index) whenever that minimum is
+// <= g0; g0 = +inf makes it exact always.
+hipError_t launch_fallback_culled(const sv_robot& rb, const CapEntry* table, const MotionArgs& mo, int N,
+                                  const int* plist, const int* pcount, float g0, unsigned long long* keys,
+                                  const CullWs& w, hipStream_t st);
 
 // ---- launchers (sv_geom.hip) ------------------------------------------------------
 // Paper-style training samples (Sec. IV-C): workspace arrays [M][n_uniform] (u*),

@@ -3,7 +3,8 @@
 Skipped test groups are proven to exceed the motion's minimum, so min_dist, argmin
 and verdict must be bit-identical with culling on and off: on the bin-picking
 workload (linear and spline motions), with duplicated points (exact ties), tiny and
-ragged clouds, and in certified screening (whose confirmation pass is culled).  The
+ragged clouds, and in screening (the check of the sent points and certified
+screening's confirmation pass are culled).  The
 sample blocks follow T and the motion kind (2 to 16 samples: about T / 32 for linear
 motions, T / 64 for splines), so the cases span every block length regime, including
 the largest block count below T = 1024 (a spline at T = 256: 64 blocks of 4).  The
@@ -89,3 +90,41 @@ def test_culled_confirmation_in_certified_screening(sv):
     assert_same(on, off)
     ex = check(sv, arm, motions, pts, 0.01, False)
     np.testing.assert_array_equal(on[2], ex[2])
+
+
+@pytest.mark.parametrize("T,M,N,q", [(64, 40, 4000, 0.3), (33, 24, 2100, 0.6), (256, 8, 1500, 0.1)])
+def test_culled_fallback_of_screening(sv, T, M, N, q):
+    """The exact check of the points a screen sends runs culled over the Morton-sorted
+    cloud (from min(eps - band, current minimum) in certified mode, from the current
+    minimum in trust mode).  Both modes must give the unculled kernels' results bit for
+    bit: minima over the sent points and their lowest caller indices (every sent point
+    duplicated once: exact ties), verdicts and fallback counts.  tau is the q quantile of
+    the predictions, so that a share of the points is sent and some motions have a
+    witness and some do not."""
+    arm = svgen.make_arm(1)
+    motions = svgen.make_motions(arm, M, T, 430 + T)
+    base = svgen.bin_cloud(N // 2, 431 + T)
+    pts = np.concatenate([base, base[: N - N // 2]])
+    mlp = sv.DeviceMLP(svgen.mlp_init(svgen.MLPSpec(15, 128, 3), 432), 15, 128, 3)
+    dm, dc = sv.DeviceMotions(motions), sv.DeviceCloud(pts)
+    pred = torch.empty(M, pts.shape[0], device="cuda")
+    sv.sv_nn_sdf(mlp, sv.SV_BF16, dm, dc, pred)
+    tau = float(torch.quantile(pred.flatten()[:1 << 20], q).item())
+    robot = sv.make_robot(arm)
+    for mode in (sv.SV_SCREEN_TRUST, sv.SV_SCREEN_CERTIFIED):
+        res = []
+        for unculled in (False, True):
+            out = sv.DeviceResults(dm.n)
+            sv.sv_check_motions(robot, dm, dc, out, 0.01, mlp=mlp, screen=mode, tau=tau, unculled=unculled)
+            torch.cuda.synchronize()
+            res.append((out.min_dist.cpu().numpy(), out.argmin.cpu().numpy(), out.verdict.cpu().numpy(),
+                        out.n_fallback.cpu().numpy()))
+        on, off = res
+        assert_same(on, off)
+        np.testing.assert_array_equal(on[3], off[3])
+        sent = on[3] > 0
+        print(f"T={T} M={M} N={N} mode {mode}: {sent.sum()} motions with sent points, "
+              f"{int((on[2] == 1).sum())} colliding, fallback fraction {on[3].sum() / (M * pts.shape[0]):.3f}")
+        assert sent.any()
+    ex = check(sv, arm, motions, pts, 0.01, False)
+    np.testing.assert_array_equal(on[2], ex[2])   # certified verdicts are the exact check's

@@ -656,15 +656,14 @@ __global__ __launch_bounds__(256) void k_grad_out(TrainArgs a, float* __restrict
   }
 }
 
-// out[o] = sum over r < R of part[r n + o], in a fixed order: a block of 16 waves takes
-// 64 consecutive outputs; wave w sums rows w R/16 .. in order, 8 loads in flight, and
-// the 16 wave sums are added in order.  Many short sums in parallel instead of one long
-// chain per output (the splits of the gradient kernels are up to 256 rows).
-__global__ __launch_bounds__(1024) void k_sum_splits(const float* __restrict__ part, int R, int n,
-                                                     float* __restrict__ out) {
-  __shared__ float ws[16][64];
+// sum over r < R of part[r n + o], in a fixed order, valid in wave 0: a block of 16
+// waves takes 64 consecutive outputs (o = block * 64 + lane); wave w sums rows w R/16 ..
+// in order, 8 loads in flight, and the 16 wave sums are added in order.  Many short sums
+// in parallel instead of one long chain per output (the splits of the gradient kernels
+// are up to 256 rows).  ws: [16][64] floats of LDS; one barrier.
+__device__ __forceinline__ float split_sum_64(const float* __restrict__ part, int R, int n, int o,
+                                              float (*ws)[64]) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int o = blockIdx.x * 64 + lane;
   const int r0 = (int)((int64_t)wid * R / 16), r1 = (int)((int64_t)(wid + 1) * R / 16);
   float acc = 0.f;
   if (o < n) {
@@ -680,12 +679,21 @@ __global__ __launch_bounds__(1024) void k_sum_splits(const float* __restrict__ p
   }
   ws[wid][lane] = acc;
   __syncthreads();
-  if (wid == 0 && o < n) {
-    float t = 0.f;
+  float t = 0.f;
+  if (wid == 0) {
 #pragma unroll
     for (int w = 0; w < 16; ++w) t += ws[w][lane];
-    out[o] = t;
   }
+  return t;
+}
+
+// out[o] = sum over r < R of part[r n + o] (split_sum_64).
+__global__ __launch_bounds__(1024) void k_sum_splits(const float* __restrict__ part, int R, int n,
+                                                     float* __restrict__ out) {
+  __shared__ float ws[16][64];
+  const int o = blockIdx.x * 64 + (threadIdx.x & 63);
+  const float t = split_sum_64(part, R, n, o, ws);
+  if (threadIdx.x < 64 && o < n) out[o] = t;
 }
 
 hipError_t launch_sum_splits(const float* part, int R, int n, float* out, hipStream_t st) {
@@ -983,18 +991,20 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_rt_fwd(ResTrainArgs a
   }
 }
 
-// Batch sums per feature from the per-tile sums in a.part: 64 features per block, four
-// thread groups over the tiles, combined in FP64 in a fixed order.
+// Batch sums per feature from the per-tile sums in a.part: 64 features per block, 16
+// thread groups over consecutive runs of tiles, combined in FP64 in a fixed order.
 // mode 0 (forward, block b): stats[b] = (mean, 1 / sqrt(var + eps), var) of a_b.
 // mode 1 (backward, block b): bsum = (sum g, sum g n); the gradients of beta_b and gamma_b.
-__global__ __launch_bounds__(256) void k_rt_stats(ResTrainArgs a, int b, int mode) {
-  __shared__ double red[2][4][64];
+constexpr int kStatGroups = 16;
+__global__ __launch_bounds__(64 * kStatGroups) void k_rt_stats(ResTrainArgs a, int b, int mode) {
+  __shared__ double red[2][kStatGroups][64];
   const int W = a.net.width, tiles = a.Bp / kRows;
   const int fl = threadIdx.x & 63, tg = threadIdx.x >> 6;
   const int f = blockIdx.x * 64 + fl;
+  const int t0 = (int)((int64_t)tg * tiles / kStatGroups), t1 = (int)((int64_t)(tg + 1) * tiles / kStatGroups);
   double s0 = 0.0, s1 = 0.0;
   if (f < W)
-    for (int t = tg; t < tiles; t += 4) {
+    for (int t = t0; t < t1; ++t) {
       s0 += a.part[((size_t)t * 2) * W + f];
       s1 += a.part[((size_t)t * 2 + 1) * W + f];
     }
@@ -1002,8 +1012,12 @@ __global__ __launch_bounds__(256) void k_rt_stats(ResTrainArgs a, int b, int mod
   red[1][tg][fl] = s1;
   __syncthreads();
   if (tg != 0 || f >= W) return;
-  const double S0 = (red[0][0][fl] + red[0][1][fl]) + (red[0][2][fl] + red[0][3][fl]);
-  const double S1 = (red[1][0][fl] + red[1][1][fl]) + (red[1][2][fl] + red[1][3][fl]);
+  double S0 = 0.0, S1 = 0.0;
+#pragma unroll
+  for (int q = 0; q < kStatGroups; ++q) {
+    S0 += red[0][q][fl];
+    S1 += red[1][q][fl];
+  }
   if (mode == 0) {
     const double mu = S0 / a.B, v = fmax(S1 / a.B - mu * mu, 0.0);
     float* st = a.stats + (size_t)(b - 1) * 3 * W;
@@ -1088,14 +1102,15 @@ __global__ __launch_bounds__(256) void k_rt_out(ResTrainArgs a) {
   }
 }
 
-// The output layer's gradient and the loss from the per-tile partials, in a fixed order.
-__global__ void k_rt_out_reduce(ResTrainArgs a, float* __restrict__ loss_out) {
+// The output layer's gradient and the loss from the per-tile partials [tiles][W + 2], in
+// a fixed order (split_sum_64: 16 waves over runs of tiles per 64 outputs).
+__global__ __launch_bounds__(1024) void k_rt_out_reduce(ResTrainArgs a, float* __restrict__ loss_out) {
+  __shared__ float ws[16][64];
   const int W = a.net.width, tiles = a.Bp / kRows;
-  float* gout = a.grad + res_block_base(W, a.net.in_dim, a.net.n_hidden);
-  for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < W + 2; o += gridDim.x * blockDim.x) {
-    float s = 0.f;
-    for (int t = 0; t < tiles; ++t) s += a.pout[(size_t)t * (W + 2) + o];
-    if (o <= W) gout[o] = s;
+  const int o = blockIdx.x * 64 + (threadIdx.x & 63);
+  const float s = split_sum_64(a.pout, tiles, W + 2, o, ws);
+  if (threadIdx.x < 64 && o < W + 2) {
+    if (o <= W) a.grad[res_block_base(W, a.net.in_dim, a.net.n_hidden) + o] = s;
     else if (loss_out) *loss_out = s / (float)a.B;
   }
 }
@@ -1253,15 +1268,15 @@ hipError_t launch_train_res_t(ResTrainArgs a, float* part_w, float* part_w1, flo
   const unsigned sgrid = (unsigned)((W + 63) / 64);
   for (int b = 1; b <= L; ++b) {
     hipLaunchKernelGGL((k_rt_fwd<W>), dim3(tiles), dim3(train_threads<W>()), lds_f, st, a, b);
-    hipLaunchKernelGGL(k_rt_stats, dim3(sgrid), dim3(256), 0, st, a, b, 0);
+    hipLaunchKernelGGL(k_rt_stats, dim3(sgrid), dim3(64 * kStatGroups), 0, st, a, b, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL((k_rt_out<W>), dim3(tiles), dim3(256), lds_o, st, a);
-  hipLaunchKernelGGL(k_rt_out_reduce, dim3((W + 2 + 255) / 256), dim3(256), 0, st, a, loss_out);
+  hipLaunchKernelGGL(k_rt_out_reduce, dim3((W + 2 + 63) / 64), dim3(1024), 0, st, a, loss_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   for (int b = L; b >= 1; --b) {
     if (b < L) hipLaunchKernelGGL((k_rt_bstats<W>), dim3(tiles), dim3(256), 0, st, a, b);
-    hipLaunchKernelGGL(k_rt_stats, dim3(sgrid), dim3(256), 0, st, a, b, 1);
+    hipLaunchKernelGGL(k_rt_stats, dim3(sgrid), dim3(64 * kStatGroups), 0, st, a, b, 1);
     hipLaunchKernelGGL((k_rt_bwd<W>), dim3(tiles), dim3(train_threads<W>()), lds_b, st, a, b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

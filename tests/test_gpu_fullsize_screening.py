@@ -101,3 +101,23 @@ def test_fullsize_fallback_set_follows_predictions(sv, setup):
     lo, hi = int(np.sum(yb < tau - bar)), int(np.sum(yb < tau + bar))
     print(f"motion {m}: {int(nf[0])} points sent, emulation band [{lo}, {hi}]")
     assert lo <= nf[0] <= hi
+
+
+def test_trained_network_gain(sv, setup):
+    """What the trained network gains over the method without it: with the same seeded
+    weights before training, certified screening gives the same verdicts (the exact
+    check's) but sends (nearly) every pair to the exact check; the trained network sends
+    a fraction of them."""
+    from paper_2402_15281_amd import train as tr
+    w, arm, motions, pts, shape, mlp = setup
+    eps, tau = w["eps"], w["tau"]
+    untrained = sv.DeviceMLP(tr.init_params(svgen.MLPSpec(*shape), 502), *shape)
+    ex = _check(sv, arm, motions, pts, None, sv.SV_SCREEN_NONE, eps, tau)
+    _, _, uvd, unf = _check(sv, arm, motions, pts, untrained, sv.SV_SCREEN_CERTIFIED, eps, tau)
+    _, _, cvd, cnf = _check(sv, arm, motions, pts, mlp, sv.SV_SCREEN_CERTIFIED, eps, tau)
+    np.testing.assert_array_equal(uvd, ex[2])
+    np.testing.assert_array_equal(cvd, ex[2])
+    pairs = motions.n * pts.shape[0]
+    fu, ft = unf.sum() / pairs, cnf.sum() / pairs
+    print(f"fallback fraction: untrained {fu:.3f}, trained {ft:.3f}")
+    assert ft < 0.5 * fu, (ft, fu)

@@ -558,7 +558,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         log("this benchmark runs on exactly one GPU: the collision check is measured on one MI355X; "
-            "multi-GPU sharding is described in DESIGN.md but not built")
+            "sharding across GPUs is not built")
         sys.exit(2)
 
     import numpy as np

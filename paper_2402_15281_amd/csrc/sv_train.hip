@@ -396,9 +396,11 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_bwd(TrainArgs a
 // while the MFMAs run on one.  A chunk row is 64 contiguous bytes (4 segments of 16);
 // the DMA writes each wave's 64 segments to 1 KB of consecutive LDS, so the swizzle
 // that keeps the fragment reads free of bank conflicts is applied on the global side:
-// LDS slot s' of row r holds segment s' ^ ((r >> 1) & 3).  Each buffer is its own LDS
-// variable and the loop is unrolled over them, so that the compiler can tell the
-// buffers apart and waits only as the explicit vmcnt waits say.
+// LDS slot s' of row r holds segment s' ^ ((r >> 1) & 3).  The waits are explicit vmcnt
+// counts with raw barriers (a __syncthreads would wait for every load in flight); each
+// buffer is its own LDS variable and the loop is unrolled over them, so that the
+// compiler can tell the buffers apart (it still adds a full wait before one of the four
+// buffers' reads).
 constexpr int kGwChunk = 32;                   // batch rows per LDS stage (two MFMA k-steps)
 constexpr int kGwStages = 4;                   // LDS buffers
 constexpr int kGwStageElems = 512 * kGwChunk;  // (TF + TK) rows at most

@@ -248,10 +248,14 @@ def train(mlp, samples, recipe: TrainRecipe, val_rows=None, log=None, device="cu
     step = 0
     t0 = time.perf_counter()
 
+    # The seeded sample order of each epoch, drawn on the device in stream order: a host
+    # permutation of 10M rows (about 0.2 s) outlasts a whole epoch of steps (0.17 s at
+    # 1.1 ms per step) and left the GPU waiting at every epoch boundary.
+    gen = torch.Generator(device=device)
+    gen.manual_seed(recipe.seed)
+
     def epoch_order(ep):
-        # the seeded sample order of one epoch, staged in pinned memory so that its copy
-        # to the device is queued behind the running steps instead of waiting for them
-        return torch.from_numpy(svgen.permutation(recipe.seed * 7919 + ep, n)).pin_memory()
+        return torch.randperm(n, generator=gen, device=device, dtype=torch.int32)
 
     if recipe.schedule not in ("constant", "plateau", "cosine"):
         raise ValueError(f"unknown schedule {recipe.schedule!r}")
@@ -261,7 +265,7 @@ def train(mlp, samples, recipe: TrainRecipe, val_rows=None, log=None, device="cu
     best, since_best, best_params = math.inf, 0, None
     order = epoch_order(0)
     for ep in range(recipe.epochs):
-        perm = order.to(device, non_blocking=True)
+        perm = order
         ep_loss = torch.zeros(1, dtype=torch.float32, device=device)
         tl.lr.append(lr)
         for s in range(steps_per_epoch):
@@ -271,9 +275,9 @@ def train(mlp, samples, recipe: TrainRecipe, val_rows=None, log=None, device="cu
                 lr = recipe.lr * 0.5 * (1.0 + math.cos(math.pi * (step - 1) / (recipe.epochs * steps_per_epoch)))
             sv.sv_train_step(mlp, m, v, step, samples, idx, lr=lr, clamp_sigma=recipe.clamp_sigma,
                              loss_out=loss, ws=ws, clamp_pred=recipe.clamp_pred)
-            ep_loss += loss * idx.shape[0]
+            ep_loss.add_(loss, alpha=idx.shape[0])
         if ep + 1 < recipe.epochs:
-            order = epoch_order(ep + 1)       # on the host while the GPU runs this epoch
+            order = epoch_order(ep + 1)
         tl.epoch_loss.append(float(ep_loss.item()) / n)
         if val_rows is not None:
             tl.val_mae.append(val_mae(mlp, val_rows, recipe.clamp_sigma))

@@ -434,6 +434,7 @@ __global__ __launch_bounds__(NT) void k_fallback_cull(const CapEntry* __restrict
       float m2[P];
 #pragma unroll
       for (int p = 0; p < P; ++p) m2[p] = INFINITY;
+      int nrun = 0;
       for (int b0 = 0; b0 < nb; b0 += 64) {
         // lane l tests block b0 + l against the bound at the start of the chunk (the
         // bound only falls, so a block failing here fails every later test too)
@@ -452,13 +453,14 @@ __global__ __launch_bounds__(NT) void k_fallback_cull(const CapEntry* __restrict
           const float br = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.w), l));
           if (skip(bx, by, bz, br, G)) continue;   // the bound has tightened since
           const int t0 = (b0 + l) * B, t1 = min(t0 + B, T);
-          swept_range<P>((ConstF4Ptr)table, e, t0, t1, x, y, z, m2);
+          swept_block<P>((ConstF4Ptr)table, e, t0, t1, x, y, z, m2);
           executed += (unsigned long long)(t1 - t0) * (64 * P);
-          float wb = INFINITY;
+          if (++nrun % kBoundEvery) continue;   // as in cull_item
+          float mm = INFINITY;
 #pragma unroll
           for (int p = 0; p < P; ++p)
-            if (idx[p] >= 0) wb = fminf(wb, sqrtf(m2[p]) - r);
-          G = uniform_f(fminf(G, wave_min(wb)));
+            if (idx[p] >= 0) mm = fminf(mm, m2[p]);
+          G = uniform_f(fminf(G, sqrtf(wave_min(mm)) - r));
         }
       }
 #pragma unroll

@@ -254,6 +254,35 @@ __device__ __forceinline__ void swept_range(ConstF4Ptr tab, size_t e, int t0, in
   }
 }
 
+// swept_range for the culled passes' sample blocks (2 to 16 samples, one block per
+// call): the entries of four samples are loaded before any of their tests, so that one
+// latency of the scalar loads covers four tests per point (with the sparser bound
+// updates of the culled passes: 0.562 -> 0.528 ms per culled pass at T = 256 and 1.40 ->
+// 1.17 ms at T = 1,024 on bin20k; eight samples at a time measured slower).
+// The same squared distances as swept_range, so the minima are bit-identical.
+template <int P>
+__device__ __forceinline__ void swept_block(ConstF4Ptr tab, size_t e, int t0, int t1, const float (&x)[P],
+                                            const float (&y)[P], const float (&z)[P], float (&m2)[P]) {
+  int t = t0;
+  for (; t + 3 < t1; t += 4) {
+    CapEntry q[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = load_entry(tab, e + t + i);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      float d[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) d[i] = seg_d2(q[i], x[p], y[p], z[p]);
+      m2[p] = fminf(m2[p], fminf(fminf(d[0], d[1]), fminf(d[2], d[3])));
+    }
+  }
+  for (; t < t1; ++t) {
+    const CapEntry a = load_entry(tab, e + t);
+#pragma unroll
+    for (int p = 0; p < P; ++p) m2[p] = fminf(m2[p], seg_d2(a, x[p], y[p], z[p]));
+  }
+}
+
 // Per lane: best[p] = min over capsules k of (sqrt(min over samples t of the squared
 // distance from point p to segment k at t) - r_k), for the motion whose table entries
 // start at entry e0 and run [K][T].

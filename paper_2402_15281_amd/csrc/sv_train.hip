@@ -949,18 +949,33 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_rt_fwd(ResTrainArgs a
     __syncthreads();
     store_tile_T<W, NT, LD>(H, a.hT, r0);
   } else {        // h_{b-1} = h_{b-2} + gamma (a_{b-1} - mu) inv + beta, rounded to BF16
-    load_tile_T<W, NT, LD>(a.hT + (size_t)(b - 2) * slab, H, r0);
-    __syncthreads();
+    // In 8 x 8 blocks (rows 8 rg.., features 8 fg..; the lane order of fetch_tile_T):
+    // h_{b-2} and a_{b-1} come in with 16-byte loads, h_{b-1} goes out feature-major with
+    // 16-byte stores and into the LDS tile by the transposed writes.
+    constexpr int NQ = W / 64 / NW;
     const float* q = rt_block(a, b - 1) + (size_t)W * W + (size_t)W * in_dim + W;   // gamma, beta
     const float* st = a.stats + (size_t)(b - 2) * 3 * W;
-    const __bf16* ap = a.aT + (size_t)(b - 2) * slab;
-    for (int f = wid; f < W; f += NW) {   // lane = row: one 128-byte line of a per feature
-      const float av = (float)ap[tix(W, f, r0 + lane)];
-      __bf16* hp = H + lane * LD + f;
-      *hp = (__bf16)((float)*hp + fmaf(q[f] * st[W + f], av - st[f], q[W + f]));
+    bf16x8 hv[NQ][8], av[NQ][8];
+    fetch_tile_T<W, NT>(a.hT + (size_t)(b - 2) * slab, r0, hv);
+    fetch_tile_T<W, NT>(a.aT + (size_t)(b - 2) * slab, r0, av);
+    const int rg = lane >> 3;
+    __bf16* hout = a.hT + (size_t)(b - 1) * slab;
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq) {
+      const int fg = 8 * (wid + qq * NW) + (lane & 7);
+#pragma unroll
+      for (int f = 0; f < 8; ++f) {
+        const int ff = 8 * fg + f;
+        const float gi = q[ff] * st[W + ff], mu = st[ff], be = q[W + ff];
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = (__bf16)((float)hv[qq][f][e] + fmaf(gi, (float)av[qq][f][e] - mu, be));
+        hv[qq][f] = o;
+        __builtin_nontemporal_store(o, reinterpret_cast<bf16x8*>(hout + tix(W, ff, r0 + 8 * rg)));
+      }
     }
+    put_tile_T<W, NT, LD>(hv, H);
     __syncthreads();
-    store_tile_T<W, NT, LD>(H, a.hT + (size_t)(b - 1) * slab, r0);
   }
   f32x16 acc[kTFB][kTRB];
   layer_mfma_k<K, LD, kTFB, kTRB, 2>(a.packed + (size_t)(b - 1) * W * K, H, wid, 0, lane,
@@ -1005,11 +1020,27 @@ __global__ __launch_bounds__(64 * kStatGroups) void k_rt_stats(ResTrainArgs a, i
   const int f = blockIdx.x * 64 + fl;
   const int t0 = (int)((int64_t)tg * tiles / kStatGroups), t1 = (int)((int64_t)(tg + 1) * tiles / kStatGroups);
   double s0 = 0.0, s1 = 0.0;
-  if (f < W)
-    for (int t = t0; t < t1; ++t) {
+  if (f < W) {
+    // tiles in order; eight tiles' loads in flight before their adds
+    int t = t0;
+    for (; t + 8 <= t1; t += 8) {
+      float v0[8], v1[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        v0[u] = a.part[((size_t)(t + u) * 2) * W + f];
+        v1[u] = a.part[((size_t)(t + u) * 2 + 1) * W + f];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s0 += v0[u];
+        s1 += v1[u];
+      }
+    }
+    for (; t < t1; ++t) {
       s0 += a.part[((size_t)t * 2) * W + f];
       s1 += a.part[((size_t)t * 2 + 1) * W + f];
     }
+  }
   red[0][tg][fl] = s0;
   red[1][tg][fl] = s1;
   __syncthreads();
@@ -1035,14 +1066,13 @@ __global__ __launch_bounds__(64 * kStatGroups) void k_rt_stats(ResTrainArgs a, i
   }
 }
 
-// h_L = h_{L-1} + gamma_L (a_L - mu) inv + beta_L in FP32 (kept in LDS), the prediction,
-// the loss terms and dy of the tile's rows, then per feature: the tile's sums of dy h_L
-// (the w_out gradient) and, for the last block's BatchNorm backward with g = dy w_out,
-// of g and g n_L.
+// h_L = h_{L-1} + gamma_L (a_L - mu) inv + beta_L in FP32, the prediction, the loss
+// terms and dy of the tile's rows, then per feature: the tile's sums of dy h_L (the
+// w_out gradient; h_L formed again from the same operands, which is cheaper than an FP32
+// tile in LDS that would hold the kernel to one block per CU) and, for the last block's
+// BatchNorm backward with g = dy w_out, of g and g n_L.
 template <int W>
 __global__ __launch_bounds__(256) void k_rt_out(ResTrainArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  float (*hs)[W + 1] = reinterpret_cast<float (*)[W + 1]>(smem);
   __shared__ float ys[4][kRows];
   __shared__ float dys[kRows], ls[kRows];
   const MlpArgs& n = a.net;
@@ -1055,12 +1085,25 @@ __global__ __launch_bounds__(256) void k_rt_out(ResTrainArgs a) {
   const float* wout = rt_block(a, L + 1);
   const __bf16* hp = a.hT + (size_t)(L - 1) * slab;
   const __bf16* ap = a.aT + (size_t)(L - 1) * slab;
+  // Prediction partials: wave w sums wout[f] h_L[r][f] over f = w, w + 4, ... in order
+  // for row r = lane.  h_L is formed in chunks of 64 features: 16-byte loads of h_{L-1}
+  // and a_L (8 rows of one feature), FP32 results into hs[row][feature] (row stride 65:
+  // conflict-free), then each wave reads its features of the chunk.
+  __shared__ float hs[kRows][65];
   float yp = 0.f;
-  for (int f = wid; f < W; f += 4) {   // lane = row
-    const size_t o = tix(W, f, r0 + lane);
-    const float h = (float)hp[o] + fmaf(q[f] * st[W + f], (float)ap[o] - st[f], q[W + f]);
-    hs[lane][f] = h;
-    yp = fmaf(wout[f], h, yp);
+  for (int c0 = 0; c0 < W; c0 += 64) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int sgi = tid + 256 * u, fc = sgi >> 3, rg = sgi & 7, f = c0 + fc;
+      const size_t o = tix(W, f, r0 + 8 * rg);
+      const bf16x8 hv = *reinterpret_cast<const bf16x8*>(hp + o), av = *reinterpret_cast<const bf16x8*>(ap + o);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) hs[8 * rg + e][fc] = (float)hv[e] + fmaf(q[f] * st[W + f], (float)av[e] - st[f], q[W + f]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int fc = wid; fc < 64; fc += 4) yp = fmaf(wout[c0 + fc], hs[lane][fc], yp);
+    __syncthreads();
   }
   ys[wid][lane] = yp;
   __syncthreads();
@@ -1083,12 +1126,14 @@ __global__ __launch_bounds__(256) void k_rt_out(ResTrainArgs a) {
   for (int f = tid; f < W; f += 256) {
     float sh = 0.f, sn = 0.f;
     const bf16x8* arow = reinterpret_cast<const bf16x8*>(ap + tix(W, f, r0));
+    const bf16x8* hrow = reinterpret_cast<const bf16x8*>(hp + tix(W, f, r0));
     for (int c = 0; c < kRows / 8; ++c) {
-      const bf16x8 av = arow[c];
+      const bf16x8 av = arow[c], hv = hrow[c];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int r = 8 * c + e;
-        sh = fmaf(dys[r], hs[r][f], sh);
+        const float h = (float)hv[e] + fmaf(q[f] * st[W + f], (float)av[e] - st[f], q[W + f]);
+        sh = fmaf(dys[r], h, sh);
         sn = fmaf(dys[r], ((float)av[e] - st[f]) * st[W + f], sn);
       }
     }
@@ -1127,10 +1172,18 @@ __global__ __launch_bounds__(256) void k_rt_bstats(ResTrainArgs a, int b) {
     const float4* grow = reinterpret_cast<const float4*>(a.g + tix(W, f, r0));
     const bf16x8* arow = reinterpret_cast<const bf16x8*>(ap + tix(W, f, r0));
     float s = 0.f, sn = 0.f;
+    // the feature's 64 rows of g and a_b, all loads in flight before the sums (in row order)
+    float4 gq[kRows / 4];
+    bf16x8 aq[kRows / 8];
+#pragma unroll
+    for (int c = 0; c < kRows / 4; ++c) gq[c] = grow[c];
+#pragma unroll
+    for (int c = 0; c < kRows / 8; ++c) aq[c] = arow[c];
+#pragma unroll
     for (int c = 0; c < kRows / 8; ++c) {
-      const float4 g0 = grow[2 * c], g1 = grow[2 * c + 1];
+      const float4 g0 = gq[2 * c], g1 = gq[2 * c + 1];
       const float gv[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
-      const bf16x8 av = arow[c];
+      const bf16x8 av = aq[c];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         s += gv[e];
@@ -1163,19 +1216,56 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_rt_bwd(ResTrainArgs a
   const __bf16* ap = a.aT + (size_t)(b - 1) * slab;
   __bf16* dzs = a.dzT + (size_t)b * slab;
   const float invB = 1.f / (float)a.B;
-  const bool valid = r0 + lane < a.B;
-  const float dyr = b == L ? a.dy[r0 + lane] : 0.f;
-  for (int f = wid; f < W; f += NW) {   // lane = row
-    const size_t o = tix(W, f, r0 + lane);
-    const float gv = b == L ? dyr * wout[f] : a.g[o];
-    const float av = (float)ap[o];
-    const float nn = (av - st[f]) * st[W + f];
-    const float dz = (valid && av > 0.f)
-                         ? gamma[f] * st[W + f] * (gv - a.bsum[f] * invB - nn * (a.bsum[W + f] * invB))
-                         : 0.f;
-    const __bf16 d16 = (__bf16)dz;
-    H[lane * LD + f] = d16;
-    dzs[o] = d16;
+  // dz_b in 8 x 8 blocks (rows 8 rg.., features 8 fg..; the lane order of fetch_tile_T):
+  // a_b, g (FP32) and dz_b move as 16-byte pieces of feature rows, dz_b goes into the
+  // LDS tile by transposed writes.
+  constexpr int NQ = W / 64 / NW;
+  const int rg = lane >> 3;
+  float dyv[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) dyv[e] = 0.f;
+  if (b == L) {
+    const float4 d0 = *reinterpret_cast<const float4*>(a.dy + r0 + 8 * rg);
+    const float4 d1 = *reinterpret_cast<const float4*>(a.dy + r0 + 8 * rg + 4);
+    dyv[0] = d0.x; dyv[1] = d0.y; dyv[2] = d0.z; dyv[3] = d0.w;
+    dyv[4] = d1.x; dyv[5] = d1.y; dyv[6] = d1.z; dyv[7] = d1.w;
+  }
+#pragma unroll
+  for (int qq = 0; qq < NQ; ++qq) {
+    const int fg = 8 * (wid + qq * NW) + (lane & 7);
+    bf16x8 av[8], dz16[8];
+#pragma unroll
+    for (int f = 0; f < 8; ++f) av[f] = *reinterpret_cast<const bf16x8*>(ap + tix(W, 8 * fg + f, r0 + 8 * rg));
+#pragma unroll
+    for (int f = 0; f < 8; ++f) {
+      const int ff = 8 * fg + f;
+      const size_t o = tix(W, ff, r0 + 8 * rg);
+      float gl[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (b < L) {
+        const float4 g0 = *reinterpret_cast<const float4*>(a.g + o);
+        const float4 g1 = *reinterpret_cast<const float4*>(a.g + o + 4);
+        gl[0] = g0.x; gl[1] = g0.y; gl[2] = g0.z; gl[3] = g0.w;
+        gl[4] = g1.x; gl[5] = g1.y; gl[6] = g1.z; gl[7] = g1.w;
+      }
+      const float gm = gamma[ff], iv = st[W + ff], mu = st[ff], s0 = a.bsum[ff], s1 = a.bsum[W + ff], wo = wout[ff];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool valid = r0 + 8 * rg + e < a.B;
+        const float gv = b == L ? dyv[e] * wo : gl[e];
+        const float avf = (float)av[f][e];
+        const float nn = (avf - mu) * iv;
+        const float dz = (valid && avf > 0.f) ? gm * iv * (gv - s0 * invB - nn * (s1 * invB)) : 0.f;
+        dz16[f][e] = (__bf16)dz;
+      }
+      *reinterpret_cast<bf16x8*>(dzs + o) = dz16[f];
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      bf16x8 t;
+#pragma unroll
+      for (int f = 0; f < 8; ++f) t[f] = dz16[f][r];
+      *reinterpret_cast<bf16x8*>(H + (8 * rg + r) * LD + 8 * fg) = t;
+    }
   }
   __syncthreads();
   f32x16 acc[kTFB][kTRB];
@@ -1251,16 +1341,13 @@ hipError_t launch_train_res_t(ResTrainArgs a, float* part_w, float* part_w1, flo
   const unsigned tiles = (unsigned)(a.Bp / kRows);
   const size_t lds_f = (size_t)kRows * (W + kResXCols + kLdsPad) * sizeof(__bf16);
   const size_t lds_b = (size_t)kRows * (W + kLdsPad) * sizeof(__bf16);
-  const size_t lds_o = (size_t)kRows * (W + 1) * sizeof(float);
   static bool attr = false;
   hipError_t e;
   if (!attr) {
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rt_fwd<W>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f)) != hipSuccess ||
         (e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rt_bwd<W>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_b)) != hipSuccess ||
-        (e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rt_out<W>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_o)) != hipSuccess)
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_b)) != hipSuccess)
       return e;
     attr = true;
   }
@@ -1273,7 +1360,7 @@ hipError_t launch_train_res_t(ResTrainArgs a, float* part_w, float* part_w1, flo
     hipLaunchKernelGGL(k_rt_stats, dim3(sgrid), dim3(64 * kStatGroups), 0, st, a, b, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_rt_out<W>), dim3(tiles), dim3(256), lds_o, st, a);
+  hipLaunchKernelGGL((k_rt_out<W>), dim3(tiles), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_rt_out_reduce, dim3((W + 2 + 63) / 64), dim3(1024), 0, st, a, loss_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   for (int b = L; b >= 1; --b) {

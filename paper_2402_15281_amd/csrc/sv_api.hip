@@ -842,8 +842,7 @@ int sv_train_step(const sv_mlp* mlp, float* adam_m, float* adam_v, const sv_trai
   hipError_t e;
   {
     ProfScope ps("pack_bf16", st);
-    e = launch_pack_bf16(na, 0, w.packed, st);
-    if (e == hipSuccess) e = launch_pack_bf16(na, 1, w.packedT, st);
+    e = launch_pack_bf16_both(na, w.packed, w.packedT, st);
   }
   if (e != hipSuccess) return hip_fail(e, "pack weights");
   {

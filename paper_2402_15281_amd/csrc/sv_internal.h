@@ -339,6 +339,8 @@ hipError_t launch_mlp_f32(const MlpArgs& net, const MotionArgs& mo, const CloudA
 // Hidden-layer weights (layers 2..L) to BF16 in MFMA A-operand order; transpose = 1
 // packs W_l^T (the backward pass's operand).
 hipError_t launch_pack_bf16(const MlpArgs& net, int transpose, __bf16* packed, hipStream_t st);
+// W_l and W_l^T of the softplus network in one launch (training).
+hipError_t launch_pack_bf16_both(const MlpArgs& net, __bf16* packed, __bf16* packedT, hipStream_t st);
 // Network on n independent rows rows[i][0:in_dim] (row_stride floats apart); bf16
 // selects the BF16 kernel (packed weights required) over the FP32 one.
 hipError_t launch_mlp_rows(const MlpArgs& net, int bf16, const __bf16* packed, const float* rows, int64_t row_stride,

@@ -126,16 +126,37 @@ __global__ __launch_bounds__(256) void k_mlp_f32(MlpArgs net, MotionArgs mo, Clo
 // k-step ks (16 inputs): 64 lanes x 8 BF16 = the A operand of one MFMA, where lane ln
 // holds W_l[fb*32 + ln%32][ks*16 + 8*(ln/32) + e], e = 0..7.
 // With `transpose`, W_l^T is packed instead (the operand of the backward pass).
-__global__ void k_pack_bf16(MlpArgs net, int transpose, __bf16* __restrict__ packed) {
+__global__ void k_pack_bf16(MlpArgs net, __bf16* __restrict__ packed, __bf16* __restrict__ packedT) {
+  // One lane part (8 BF16 values, 16 bytes) of each operand per thread: for row r and
+  // inputs k .. k + 7 of that part, W_l[r][k .. k + 7] (two 16-byte loads) goes to
+  // `packed` and W_l[k .. k + 7][r] (W_l^T's part at the same position) to `packedT`,
+  // each when its pointer is set.  W is a power of two (128 .. 1024), so the position
+  // splits by shifts.
   const int W = net.width;
-  const int64_t per_layer = (int64_t)W * W;
+  const int lw = 31 - __builtin_clz(W);
+  const int64_t per_layer = (int64_t)1 << (2 * lw - 3);      // parts per layer
   const int64_t total = per_layer * (net.n_hidden - 1);
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-    const int l = (int)(g / per_layer);               // 0-based hidden-layer index (layer l+2 of 1..L)
-    int row, colk;
-    packed_coords(g - (int64_t)l * per_layer, W, transpose != 0, &row, &colk);
-    const float* Wl = net.params + (size_t)W * net.in_dim + W + (size_t)l * (per_layer + W);
-    packed[g] = (__bf16)Wl[(size_t)row * W + colk];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(c >> (2 * lw - 3));                  // 0-based hidden-layer index (layer l+2 of 1..L)
+    const int64_t cl = c & (per_layer - 1);
+    const int ln = (int)(cl & 63);
+    const int64_t blk = cl >> 6;
+    const int ks = (int)(blk & ((W >> 4) - 1)), fb = (int)(blk >> (lw - 4));
+    const int r = fb * 32 + (ln & 31), k = ks * 16 + 8 * (ln >> 5);
+    const float* Wl = net.params + (size_t)W * net.in_dim + W + (size_t)l * ((size_t)W * W + W);
+    if (packed) {
+      const float4 u = *reinterpret_cast<const float4*>(Wl + (size_t)r * W + k);
+      const float4 v = *reinterpret_cast<const float4*>(Wl + (size_t)r * W + k + 4);
+      const bf16x8 o = {(__bf16)u.x, (__bf16)u.y, (__bf16)u.z, (__bf16)u.w,
+                        (__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w};
+      *reinterpret_cast<bf16x8*>(packed + 8 * c) = o;
+    }
+    if (packedT) {
+      bf16x8 t;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) t[e] = (__bf16)Wl[(size_t)(k + e) * W + r];
+      *reinterpret_cast<bf16x8*>(packedT + 8 * c) = t;
+    }
   }
 }
 
@@ -704,8 +725,17 @@ hipError_t launch_pack_bf16(const MlpArgs& net, int transpose, __bf16* packed, h
   }
   const int64_t total = (int64_t)mlp_packed_elems(net);
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)std::min<int64_t>(grid_for(total, 256), 4096)), dim3(256), 0, st, net,
-                     transpose, packed);
+  hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)std::min<int64_t>(grid_for(total / 8, 256), 4096)), dim3(256), 0, st,
+                     net, transpose ? nullptr : packed, transpose ? packed : nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_bf16_both(const MlpArgs& net, __bf16* packed, __bf16* packedT, hipStream_t st) {
+  if (net.kind == SV_NET_RESIDUAL) return hipErrorInvalidValue;
+  const int64_t total = (int64_t)mlp_packed_elems(net);
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)std::min<int64_t>(grid_for(total / 8, 256), 4096)), dim3(256), 0, st,
+                     net, packed, packedT);
   return hipGetLastError();
 }
 

@@ -14,11 +14,11 @@
 //   h0T[j][b]     FP32 network input, feature-major
 //   y[b], dy[b]   FP32 prediction and d loss / d y
 // Kernels, in launch order:
-//   k_pack_bf16 (x2)  W_l and W_l^T in MFMA operand order (sv_mlp.hip)
-//   k_train_fwd       per 64-row tile: all layers, activations to aT, y (the inference
-//                     kernel's tile shape, one in-place LDS tile, two blocks per CU)
-//   k_train_loss      dy and per-block loss partials; k_train_loss_sum: the loss
-//                     (fixed-order reductions)
+//   k_pack_bf16       W_l and W_l^T in MFMA operand order, one launch (sv_mlp.hip)
+//   k_train_fwd       per 64-row tile: all layers, activations to aT, y, dy and the
+//                     tile's sum of the loss terms (the inference kernel's tile shape,
+//                     one in-place LDS tile, two blocks per CU)
+//   k_train_loss_sum  the loss (fixed-order sum of the tiles' sums)
 //   k_train_bwd       per 64-row tile: dz of every layer via W_l^T MFMA, to dzT
 //   k_grad_w          dW_l = dz_l^T a_{l-1} for l >= 2 (MFMA, split over the batch; both
 //                     operands staged in LDS)
@@ -56,6 +56,8 @@ struct TrainArgs {
   const __bf16* packedT;  // backward operands, layers 2..L
   float* grad;            // [n_params]
   int clamp_pred;         // 1: the loss clamps the prediction as well as the target
+  float sigma;            // the loss clamp
+  float* loss_part;       // [Bp / 64] the forward's per-tile sums of the loss terms
 };
 
 // Parameter offsets of the flat vector (see sv_mlp in sv.h), 1-based layer l.
@@ -276,41 +278,31 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_fwd(TrainArgs a
     }
   }
   __syncthreads();
-  if (tid < kRows) {
+  if (tid < kRows) {   // wave 0: row r0 + lane
     float yv = wout[W];
 #pragma unroll
     for (int w = 0; w < NW; ++w) yv += part[w][tid];
-    a.y[r0 + tid] = yv;
+    const int b = r0 + tid;
+    a.y[b] = yv;
+    // the loss term and dy of the row; rows past the batch carry neither
+    float s = 0.f, g = 0.f;
+    if (b < a.B) {
+      const float sg = a.sigma;
+      const float d = a.samples[(size_t)a.idx[b] * (in_dim + 1) + in_dim];
+      const bool live = !a.clamp_pred || fabsf(yv) < sg;   // d clamp(y) / dy
+      const float yc = a.clamp_pred ? fminf(fmaxf(yv, -sg), sg) : yv;
+      const float r = yc - fminf(fmaxf(d, -sg), sg);
+      s = fabsf(r);
+      g = live ? (r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f)) / (float)a.B : 0.f;
+    }
+    a.dy[b] = g;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);   // fixed order
+    if (tid == 0) a.loss_part[blockIdx.x] = s;
   }
 }
 
-// dy of 256 rows per block and the block's sum of the clamped L1 terms (fixed-order tree)
-// into part[block]; k_train_loss_sum adds the partials in a fixed order.
-__global__ __launch_bounds__(256) void k_train_loss(TrainArgs a, float sigma, float* __restrict__ part) {
-  __shared__ float red[256];
-  const int in_dim = a.net.in_dim;
-  const int b = blockIdx.x * 256 + threadIdx.x;   // < Bp
-  float s = 0.f, g = 0.f;
-  if (b < a.B) {
-    const float yv = a.y[b];
-    const float d = a.samples[(size_t)a.idx[b] * (in_dim + 1) + in_dim];
-    const bool live = !a.clamp_pred || fabsf(yv) < sigma;   // d clamp(y) / dy
-    const float yc = a.clamp_pred ? fminf(fmaxf(yv, -sigma), sigma) : yv;
-    const float r = yc - fminf(fmaxf(d, -sigma), sigma);
-    s = fabsf(r);
-    g = live ? (r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f)) / (float)a.B : 0.f;
-  }
-  a.dy[b] = g;
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
-
-// The mean clamped-L1 loss from the n block partials, in a fixed order (one block).
+// The loss: the sum of the forward's per-tile sums in a fixed order, / B.
 __global__ __launch_bounds__(1024) void k_train_loss_sum(TrainArgs a, const float* __restrict__ part, int n,
                                                          float* __restrict__ loss_out) {
   __shared__ float red[1024];
@@ -818,11 +810,13 @@ hipError_t launch_train_t(TrainArgs a, float* part_w, float* part_w1, float sigm
   static bool fwd_attr = false, bwd_attr = false;
   if ((e = set_lds_attr<W>(reinterpret_cast<const void*>(&k_train_fwd<W>), &fwd_attr)) != hipSuccess) return e;
   if ((e = set_lds_attr<W>(reinterpret_cast<const void*>(&k_train_bwd<W>), &bwd_attr)) != hipSuccess) return e;
+  // the forward writes dy and the per-tile loss sums; those borrow part_w1, which
+  // k_grad_w1 fills only later in the step
+  a.sigma = sigma;
+  a.loss_part = part_w1;
   hipLaunchKernelGGL((k_train_fwd<W>), dim3(tiles), dim3(train_threads<W>()), lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // the loss partials borrow part_w1, which k_grad_w1 fills only later in the step
-  hipLaunchKernelGGL(k_train_loss, dim3((unsigned)(a.Bp / 256)), dim3(256), 0, st, a, sigma, part_w1);
-  hipLaunchKernelGGL(k_train_loss_sum, dim3(1), dim3(1024), 0, st, a, part_w1, a.Bp / 256, loss_out);
+  hipLaunchKernelGGL(k_train_loss_sum, dim3(1), dim3(1024), 0, st, a, part_w1, a.Bp / 64, loss_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((k_train_bwd<W>), dim3(tiles), dim3(train_threads<W>()), lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1403,9 +1397,9 @@ size_t train_part_w_elems(const MlpArgs& n) {   // dW_l splits, then db_l splits
   return n.n_hidden >= 2 ? (size_t)kSplitW * (n.n_hidden - 1) * n.width * (n.width + 1) : 0;
 }
 size_t train_part_w1_elems(const MlpArgs& n, int64_t Bp) {
-  // the dW_1 splits; the loss partials (Bp / 256 floats) and the output-layer partials
+  // the dW_1 splits; the loss partials (Bp / 64 floats) and the output-layer partials
   // borrow the same space first
-  return std::max({(size_t)w1_splits((int)Bp) * n.width * (n.in_dim + 1), (size_t)(Bp / 256),
+  return std::max({(size_t)w1_splits((int)Bp) * n.width * (n.in_dim + 1), (size_t)(Bp / 64),
                    (size_t)out_blocks((int)Bp) * (n.width + 1)});
 }
 

@@ -1156,36 +1156,55 @@ __global__ __launch_bounds__(1024) void k_rt_out_reduce(ResTrainArgs a, float* _
   }
 }
 
-// Per-tile sums of g = dL/dh_b and g n_b (b < L): one thread per feature, 64 rows each.
+// Per-tile sums of g = dL/dh_b and g n_b (b < L), each feature's 64 rows summed in row
+// order by one lane.  A wave stages 32 features at a time in LDS (the tile's g and a_b
+// of 32 consecutive features are 8 KB and 4 KB of consecutive memory: 16-byte loads,
+// consecutive lanes on consecutive pieces), so that the loads are coalesced; lane f then
+// reads its feature's rows from LDS (row stride 65: conflict-free).
 template <int W>
 __global__ __launch_bounds__(256) void k_rt_bstats(ResTrainArgs a, int b) {
+  constexpr int kF = 32;   // features per wave and pass
+  __shared__ float gs[4][kF][kRows + 1], as[4][kF][kRows + 1];
   const int tile = blockIdx.x, r0 = tile * kRows;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const float* st = a.stats + (size_t)(b - 1) * 3 * W;
   const __bf16* ap = a.aT + (size_t)(b - 1) * W * a.Bp;
-  for (int f = threadIdx.x; f < W; f += 256) {
-    const float4* grow = reinterpret_cast<const float4*>(a.g + tix(W, f, r0));
-    const bf16x8* arow = reinterpret_cast<const bf16x8*>(ap + tix(W, f, r0));
-    float s = 0.f, sn = 0.f;
-    // the feature's 64 rows of g and a_b, all loads in flight before the sums (in row order)
-    float4 gq[kRows / 4];
-    bf16x8 aq[kRows / 8];
+  float (*G)[kRows + 1] = gs[wid];
+  float (*A)[kRows + 1] = as[wid];
+  for (int f0 = kF * wid; f0 < W; f0 += 4 * kF) {
+    const float4* g4 = reinterpret_cast<const float4*>(a.g + tix(W, f0, r0));   // kF x 64 floats
+    const bf16x8* a8 = reinterpret_cast<const bf16x8*>(ap + tix(W, f0, r0));    // kF x 64 BF16
+    float4 gq[kF * kRows / 4 / 64];
+    bf16x8 aq[kF * kRows / 8 / 64];
 #pragma unroll
-    for (int c = 0; c < kRows / 4; ++c) gq[c] = grow[c];
+    for (int u = 0; u < kF * kRows / 4 / 64; ++u) gq[u] = g4[lane + 64 * u];
 #pragma unroll
-    for (int c = 0; c < kRows / 8; ++c) aq[c] = arow[c];
+    for (int u = 0; u < kF * kRows / 8 / 64; ++u) aq[u] = a8[lane + 64 * u];
 #pragma unroll
-    for (int c = 0; c < kRows / 8; ++c) {
-      const float4 g0 = gq[2 * c], g1 = gq[2 * c + 1];
-      const float gv[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
-      const bf16x8 av = aq[c];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        s += gv[e];
-        sn = fmaf(gv[e], ((float)av[e] - st[f]) * st[W + f], sn);
-      }
+    for (int u = 0; u < kF * kRows / 4 / 64; ++u) {
+      const int q = lane + 64 * u, f = q >> 4, r = 4 * (q & 15);
+      G[f][r] = gq[u].x; G[f][r + 1] = gq[u].y; G[f][r + 2] = gq[u].z; G[f][r + 3] = gq[u].w;
     }
-    a.part[((size_t)tile * 2) * W + f] = s;
-    a.part[((size_t)tile * 2 + 1) * W + f] = sn;
+#pragma unroll
+    for (int u = 0; u < kF * kRows / 8 / 64; ++u) {
+      const int q = lane + 64 * u, f = q >> 3, r = 8 * (q & 7);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) A[f][r + e] = (float)aq[u][e];
+    }
+    __builtin_amdgcn_wave_barrier();   // the wave's LDS writes come before its reads
+    if (lane < kF) {
+      const int f = f0 + lane;
+      const float mu = st[f], iv = st[W + f];
+      float s = 0.f, sn = 0.f;
+      for (int r = 0; r < kRows; ++r) {
+        const float gv = G[lane][r];
+        s += gv;
+        sn = fmaf(gv, (A[lane][r] - mu) * iv, sn);
+      }
+      a.part[((size_t)tile * 2) * W + f] = s;
+      a.part[((size_t)tile * 2 + 1) * W + f] = sn;
+    }
+    __builtin_amdgcn_wave_barrier();   // reads done before the next pass overwrites
   }
 }
 
@@ -1264,23 +1283,52 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_rt_bwd(ResTrainArgs a
   __syncthreads();
   f32x16 acc[kTFB][kTRB];
   layer_mfma_fb<W, kTFB, kTRB, 2>(a.packedT + (size_t)(b - 1) * W * W, H, wid, 0, lane, nullptr, acc);
+  // g <- g + dz_b Wh_b in two halves of 32 rows through the LDS tile, which is free after
+  // the loop: the accumulators go in row-major FP32 ([32][W + 4], 16-byte writes), then
+  // a thread updates 8 consecutive rows of one feature with 16-byte accesses of g
+  // (instead of one 4-byte access per accumulator).
+  constexpr int TS = W + 4;
+  static_assert(32 * TS * sizeof(float) <= kRows * LD * sizeof(__bf16), "half a tile in FP32 fits the LDS tile");
+  float* T = reinterpret_cast<float*>(smem);
 #pragma unroll
-  for (int fb = 0; fb < kTFB; ++fb)
+  for (int rb = 0; rb < kTRB; ++rb) {
+    __syncthreads();   // the tile (rb = 0) or the previous half (rb = 1) has been read
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int fb = 0; fb < kTFB; ++fb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = 32 * (kTFB * wid + fb) + 8 * j + 4 * half + i;
-#pragma unroll
-        for (int rb = 0; rb < kTRB; ++rb) {
-          const int r = 32 * rb + col;
-          const size_t o = tix(W, k, r0 + r);
-          const float gb = b == L ? a.dy[r0 + r] * wout[k] : a.g[o];
-          const float gn = gb + acc[fb][rb][4 * j + i];
-          if (b > 1) a.g[o] = gn;
-          else a.dzT[o] = (__bf16)gn;
-        }
+      for (int j = 0; j < 4; ++j) {
+        const int k = 32 * (kTFB * wid + fb) + 8 * j + 4 * half;
+        *reinterpret_cast<float4*>(T + col * TS + k) =
+            make_float4(acc[fb][rb][4 * j], acc[fb][rb][4 * j + 1], acc[fb][rb][4 * j + 2], acc[fb][rb][4 * j + 3]);
       }
+    __syncthreads();
+    for (int task = tid; task < 4 * W; task += NT) {   // (feature k, rows 32 rb + 8 rr ..)
+      const int k = task >> 2, rr = task & 3;
+      const int rl = 32 * rb + 8 * rr;
+      const size_t o = tix(W, k, r0 + rl);
+      float gv[8];
+      if (b == L) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) gv[e] = a.dy[r0 + rl + e] * wout[k];
+      } else {
+        const float4 g0 = *reinterpret_cast<const float4*>(a.g + o);
+        const float4 g1 = *reinterpret_cast<const float4*>(a.g + o + 4);
+        gv[0] = g0.x; gv[1] = g0.y; gv[2] = g0.z; gv[3] = g0.w;
+        gv[4] = g1.x; gv[5] = g1.y; gv[6] = g1.z; gv[7] = g1.w;
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) gv[e] = gv[e] + T[(8 * rr + e) * TS + k];
+      if (b > 1) {
+        *reinterpret_cast<float4*>(a.g + o) = make_float4(gv[0], gv[1], gv[2], gv[3]);
+        *reinterpret_cast<float4*>(a.g + o + 4) = make_float4(gv[4], gv[5], gv[6], gv[7]);
+      } else {
+        bf16x8 d;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) d[e] = (__bf16)gv[e];
+        *reinterpret_cast<bf16x8*>(a.dzT + o) = d;
+      }
+    }
+  }
 }
 
 // Wh_b^T of every block in MFMA A-operand order (packed_coords, transposed).

@@ -328,23 +328,30 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_bwd(TrainArgs a
   const int r0 = blockIdx.x * kRows;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
-  for (int f = tid; f < W; f += NT) {   // dz_L = dy * w_out * sigma(z_L)
-    const float wo = n.params[off_out(n) + f];
-    const __bf16* aL = a.aT + (size_t)(L - 1) * W * a.Bp + tix(W, f, r0);
-    __bf16* dzL = a.dzT + (size_t)(L - 1) * W * a.Bp + tix(W, f, r0);
+  {   // dz_L = dy * w_out * sigma(z_L), in the 8 x 8 blocks of fetch_tile_T (16-byte loads
+      // and stores of feature rows, transposed writes into the LDS tile)
+    constexpr int NQ = W / 64 / (NT / 64);
+    const int rg = lane >> 3;
+    bf16x8 av[NQ][8];
+    fetch_tile_T<W, NT>(a.aT + (size_t)(L - 1) * W * a.Bp, r0, av);
+    const float4 d0 = *reinterpret_cast<const float4*>(a.dy + r0 + 8 * rg);
+    const float4 d1 = *reinterpret_cast<const float4*>(a.dy + r0 + 8 * rg + 4);
+    const float dyv[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+    __bf16* dzL = a.dzT + (size_t)(L - 1) * W * a.Bp;
 #pragma unroll
-    for (int c = 0; c < kRows / 8; ++c) {
-      const bf16x8 av = *reinterpret_cast<const bf16x8*>(aL + 8 * c);
-      bf16x8 out;
+    for (int q = 0; q < NQ; ++q) {
+      const int fg = 8 * (wid + q * (NT / 64)) + (lane & 7);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int r = 8 * c + e;
-        const float g = a.dy[r0 + r] * wo * softplus_grad_from_out((float)av[e]);
-        out[e] = (__bf16)g;
-        H[r * LD + f] = out[e];
+      for (int f = 0; f < 8; ++f) {
+        const float wo = n.params[off_out(n) + 8 * fg + f];
+        bf16x8 out;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) out[e] = (__bf16)(dyv[e] * wo * softplus_grad_from_out((float)av[q][f][e]));
+        av[q][f] = out;
+        __builtin_nontemporal_store(out, reinterpret_cast<bf16x8*>(dzL + tix(W, 8 * fg + f, r0 + 8 * rg)));
       }
-      *reinterpret_cast<bf16x8*>(dzL + 8 * c) = out;
     }
+    put_tile_T<W, NT>(av, H);
   }
   __syncthreads();
   for (int l = L; l >= 2; --l) {
@@ -715,6 +722,10 @@ __global__ __launch_bounds__(256) void k_grad_w1(TrainArgs a, float* __restrict_
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
   const int S = w1_splits(a.Bp), nks = a.Bp / 16, s = blockIdx.y;
+  // blockIdx.z: the dz slot (the residual network's W_0 and its blocks' Wx_b, c_b, one
+  // launch; a single slot for the softplus network), each with its own partials
+  const __bf16* dz = a.dzT + (size_t)blockIdx.z * W * a.Bp;
+  part += (size_t)blockIdx.z * S * W * (in_dim + 1);
   const int ks_begin = (int)((int64_t)s * nks / S), ks_end = (int)((int64_t)(s + 1) * nks / S);
   const int f0 = (blockIdx.x * 4 + wid) * 64;
   const bool active = f0 < W;                      // wave-uniform; every wave takes the barriers
@@ -751,7 +762,7 @@ __global__ __launch_bounds__(256) void k_grad_w1(TrainArgs a, float* __restrict_
 #pragma unroll
           for (int fb = 0; fb < 2; ++fb)
             if (k0 + u < nc)
-              x[u][fb] = *reinterpret_cast<const bf16x8*>(a.dzT + tix(W, f0 + 32 * fb + col, (c0 + k0 + u) * 16 + 8 * half));
+              x[u][fb] = *reinterpret_cast<const bf16x8*>(dz + tix(W, f0 + 32 * fb + col, (c0 + k0 + u) * 16 + 8 * half));
 #pragma unroll
         for (int u = 0; u < kW1Unroll; ++u) {
           if (k0 + u >= nc) break;
@@ -1331,6 +1342,17 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_rt_bwd(ResTrainArgs a
   }
 }
 
+// The sums of the dW_1 splits of every dz slot (k_grad_w1 with one slot per blockIdx.z):
+// slot 0 into W_0 and b_0, slot b into block b's Wx_b and c_b (split_sum_64).
+__global__ __launch_bounds__(1024) void k_rt_sum_w1(ResTrainArgs a, const float* __restrict__ part, int R) {
+  __shared__ float ws[16][64];
+  const int W = a.net.width, in_dim = a.net.in_dim, nw1 = W * (in_dim + 1), s = blockIdx.y;
+  const int o = blockIdx.x * 64 + (threadIdx.x & 63);
+  const float t = split_sum_64(part + (size_t)s * R * nw1, R, nw1, o, ws);
+  float* out = a.grad + (s == 0 ? 0 : res_block_base(W, in_dim, s - 1) + (size_t)W * W);
+  if (threadIdx.x < 64 && o < nw1) out[o] = t;
+}
+
 // Wh_b^T of every block in MFMA A-operand order (packed_coords, transposed).
 __global__ void k_pack_resT(MlpArgs net, __bf16* __restrict__ packedT) {
   const int W = net.width;
@@ -1424,15 +1446,18 @@ hipError_t launch_train_res_t(ResTrainArgs a, float* part_w, float* part_w1, flo
   hipLaunchKernelGGL((k_grad_w<W>), dim3(gw_blocks), dim3(256), 0, st, t, part_w);
   hipLaunchKernelGGL(k_rt_grad_reduce, dim3(2048), dim3(256), 0, st, a, part_w);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // W_0 and b_0 (dz slot 0 = g_0), Wx_b and c_b (slot b) against the FP32 input
-  for (int s = 0; s <= L; ++s) {
+  // W_0 and b_0 (dz slot 0 = g_0), Wx_b and c_b (slot b) against the FP32 input: all
+  // L + 1 slots in one launch, then their fixed-order sums in one launch
+  {
     TrainArgs u = t;
-    u.dzT = a.dzT + (size_t)s * W * a.Bp;
+    u.dzT = a.dzT;
     u.h0T = a.xT;
-    u.grad = a.grad + (s == 0 ? 0 : res_block_base(W, n.in_dim, s - 1) + (size_t)W * W);
-    hipLaunchKernelGGL(k_grad_w1, dim3((unsigned)((W + 255) / 256), (unsigned)w1_splits(a.Bp)), dim3(256), 0, st, u,
-                       part_w1);
-    if ((e = launch_sum_splits(part_w1, w1_splits(a.Bp), W * (n.in_dim + 1), u.grad, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grad_w1, dim3((unsigned)((W + 255) / 256), (unsigned)w1_splits(a.Bp), (unsigned)(L + 1)),
+                       dim3(256), 0, st, u, part_w1);
+    const int nw1 = W * (n.in_dim + 1);
+    hipLaunchKernelGGL(k_rt_sum_w1, dim3((unsigned)((nw1 + 63) / 64), (unsigned)(L + 1)), dim3(1024), 0, st, a,
+                       part_w1, w1_splits(a.Bp));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipGetLastError();
 }
@@ -1465,8 +1490,8 @@ hipError_t launch_train_step(const MlpArgs& net, const float* samples, const int
 }
 
 size_t train_res_part_w_elems(const MlpArgs& n) { return (size_t)kSplitW * n.n_hidden * n.width * (n.width + 1); }
-size_t train_res_part_w1_elems(const MlpArgs& n, int64_t Bp) {
-  return (size_t)w1_splits((int)Bp) * n.width * (n.in_dim + 1);
+size_t train_res_part_w1_elems(const MlpArgs& n, int64_t Bp) {   // one region per dz slot
+  return (size_t)w1_splits((int)Bp) * n.width * (n.in_dim + 1) * (n.n_hidden + 1);
 }
 
 hipError_t launch_train_step_res(const MlpArgs& net, const float* samples, const int* idx, int B, int Bp,

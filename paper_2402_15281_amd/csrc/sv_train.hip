@@ -199,9 +199,14 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_fwd(TrainArgs a
     if (j < in_dim) {
       const int b = min(r0 + r, a.B - 1);
       v = a.samples[(size_t)a.idx[b] * (in_dim + 1) + j];
-      a.h0T[(size_t)j * a.Bp + r0 + r] = v;
     }
     h0s[r][j] = v;
+  }
+  __syncthreads();
+  // the inputs feature-major for the dW_1 kernel: consecutive threads on consecutive rows
+  for (int e = tid; e < kRows * in_dim; e += NT) {
+    const int j = e / kRows, r = e - j * kRows;
+    a.h0T[(size_t)j * a.Bp + r0 + r] = h0s[r][j];
   }
   // Layer 1 in FP32, FPT features per thread.  Inputs and weights past in_dim are zero,
   // so the fixed-length chain adds exact zeros after the in_dim real terms.
@@ -214,7 +219,6 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_fwd(TrainArgs a
 #pragma unroll
     for (int j = 0; j < kInPad; ++j) w[q][j] = j < in_dim ? w1[j] : 0.f;
   }
-  __syncthreads();
 #pragma unroll 2
   for (int r = 0; r < kRows; ++r) {
     float h[kInPad];
@@ -920,13 +924,15 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_rt_fwd(ResTrainArgs a
   for (int e = tid; e < kRows * kInPad; e += NT) {
     const int r = e / kInPad, j = e - r * kInPad;
     float v = 0.f;
-    if (j < in_dim) {
-      v = a.samples[(size_t)a.idx[min(r0 + r, a.B - 1)] * (in_dim + 1) + j];
-      if (b == 1) a.xT[(size_t)j * a.Bp + r0 + r] = v;
-    }
+    if (j < in_dim) v = a.samples[(size_t)a.idx[min(r0 + r, a.B - 1)] * (in_dim + 1) + j];
     xs[r][j] = v;
   }
   __syncthreads();
+  if (b == 1)   // the input feature-major for the input-column gradients: consecutive threads on consecutive rows
+    for (int e = tid; e < kRows * in_dim; e += NT) {
+      const int j = e / kRows, r = e - j * kRows;
+      a.xT[(size_t)j * a.Bp + r0 + r] = xs[r][j];
+    }
   // the network input as BF16 high and low parts, columns W .. W + 2 in_dim - 1
   for (int e = tid; e < kRows * kResXCols; e += NT) {
     const int r = e / kResXCols, j = e - r * kResXCols;

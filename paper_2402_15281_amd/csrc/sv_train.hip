@@ -1134,23 +1134,35 @@ __global__ __launch_bounds__(256) void k_rt_out(ResTrainArgs a) {
   float* po = a.pout + (size_t)tile * (W + 2);
   float sdy = 0.f;
   for (int r = 0; r < kRows; ++r) sdy += dys[r];
-  for (int f = tid; f < W; f += 256) {
-    float sh = 0.f, sn = 0.f;
-    const bf16x8* arow = reinterpret_cast<const bf16x8*>(ap + tix(W, f, r0));
-    const bf16x8* hrow = reinterpret_cast<const bf16x8*>(hp + tix(W, f, r0));
-    for (int c = 0; c < kRows / 8; ++c) {
-      const bf16x8 av = arow[c], hv = hrow[c];
+  // Per feature, in row order: sum dy h_L and sum dy n_L.  The same chunks of 64 features
+  // as above (coalesced loads; h_L and n_L into LDS), then wave 0's lane f sums feature
+  // c0 + f.
+  __shared__ float ns[kRows][65];
+  for (int c0 = 0; c0 < W; c0 += 64) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int sgi = tid + 256 * u, fc = sgi >> 3, rg = sgi & 7, f = c0 + fc;
+      const size_t o = tix(W, f, r0 + 8 * rg);
+      const bf16x8 hv = *reinterpret_cast<const bf16x8*>(hp + o), av = *reinterpret_cast<const bf16x8*>(ap + o);
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int r = 8 * c + e;
-        const float h = (float)hv[e] + fmaf(q[f] * st[W + f], (float)av[e] - st[f], q[W + f]);
-        sh = fmaf(dys[r], h, sh);
-        sn = fmaf(dys[r], ((float)av[e] - st[f]) * st[W + f], sn);
+        hs[8 * rg + e][fc] = (float)hv[e] + fmaf(q[f] * st[W + f], (float)av[e] - st[f], q[W + f]);
+        ns[8 * rg + e][fc] = ((float)av[e] - st[f]) * st[W + f];
       }
     }
-    po[f] = sh;
-    a.part[((size_t)tile * 2) * W + f] = wout[f] * sdy;
-    a.part[((size_t)tile * 2 + 1) * W + f] = wout[f] * sn;
+    __syncthreads();
+    if (wid == 0) {
+      const int f = c0 + lane;
+      float sh = 0.f, sn = 0.f;
+      for (int r = 0; r < kRows; ++r) {
+        sh = fmaf(dys[r], hs[r][lane], sh);
+        sn = fmaf(dys[r], ns[r][lane], sn);
+      }
+      po[f] = sh;
+      a.part[((size_t)tile * 2) * W + f] = wout[f] * sdy;
+      a.part[((size_t)tile * 2 + 1) * W + f] = wout[f] * sn;
+    }
+    __syncthreads();
   }
   if (tid == 0) {
     float sl = 0.f;

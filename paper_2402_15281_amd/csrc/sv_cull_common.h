@@ -290,8 +290,9 @@ __device__ __forceinline__ unsigned long long cull_item(ConstF4Ptr tab, size_t e
         executed += (unsigned long long)(t1 - t0) * (64 * P);
         if (++nrun % kBoundEvery) continue;
         // Tighten the bound with this wave's points: the square root of the smallest
-        // squared distance (min commutes with the monotone sqrt and - r, so this is the
-        // smallest sqrt(m2) - r).  A bound not yet tightened is still an upper bound.
+        // squared distance, minus r (sqrt and - r do not decrease, so this is the
+        // smallest sqrt(m2) - r; kCullMargin covers a last-place difference of the
+        // hardware square root).  A bound not yet tightened is still an upper bound.
         float mm = INFINITY;
 #pragma unroll
         for (int p = 0; p < P; ++p)

@@ -36,6 +36,7 @@ METRIC = "motions checked/sec @20k-pt cloud: NN+fallback vs exact GPU; verdict a
 PEAK_FP32_TFLOPS = 157.3          # MI355X vector FP32: 256 CUs x 2.4 GHz x 256 flop/clk
 PEAK_BF16_TFLOPS = 2516.6         # MI355X dense BF16 MFMA: 256 CUs x 2.4 GHz x 4096 flop/clk
 FLOP_PER_SEGMENT_TEST = 21        # per (point, sample, capsule): sub 3, dot 5, scale 1, residual 6, norm 5, min 1
+FLOP_EXECUTED_PER_TEST = 20       # the kernels' own: the scale by 1/|AB|^2 is in the table entry (H = AB/|AB|^2)
 
 
 def log(*a):
@@ -728,6 +729,8 @@ def main():
                                                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                                                     "frac": fd / PEAK_FP32_TFLOPS, "kernel_ms": kd["exact"],
                                                     "flop_per_launch": flop_exact,
+                                                    "frac_by_executed_flop": fd * FLOP_EXECUTED_PER_TEST
+                                                    / FLOP_PER_SEGMENT_TEST / PEAK_FP32_TFLOPS,
                                                     "traffic": profiled_traffic("k_exact_bin20k_traffic.md",
                                                                                 GEOM_SOURCES)}}},
         "trust_screening": {"value": M / (ms_t / 1e3), "unit": "motions/s", "ms_per_step": ms_t,

@@ -219,7 +219,7 @@ int sv_check_motions(const sv_robot* robot, const sv_mlp* mlp, int screen, float
  * sv_check_motions (the same kernels).  A check whose workspace (sv_workspace_size,
  * SV_OP_CHECK) exceeds SV_STATIC_SCRATCH_BYTES returns SV_ERR_WORKSPACE and launches
  * nothing; the exact and the screened check of 512 motions at T = 256 against 20,000
- * points with a 15 -> 8 x 512 -> 1 network fit (32 and 76 MiB).  Every call on one GPU
+ * points with a 15 -> 8 x 512 -> 1 network fit (46 and 88 MiB).  Every call on one GPU
  * uses that GPU's one array and leaves its contents behind (each call initialises what
  * it reads): calls that overlap in time on one GPU -- other streams, other threads --
  * race and give wrong results, so the caller must order them. */

@@ -130,20 +130,20 @@ typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(4))) const vf4* ConstF4Ptr;
 
 __device__ __forceinline__ CapEntry load_entry(ConstF4Ptr p, size_t idx) {
-  const vf4 lo = p[2 * idx], hi = p[2 * idx + 1];
+  const vf4 lo = p[3 * idx], mid = p[3 * idx + 1], hi = p[3 * idx + 2];
   CapEntry e;
-  e.ax = lo.x; e.ay = lo.y; e.az = lo.z; e.inv_l2 = lo.w;
-  e.bx = hi.x; e.by = hi.y; e.bz = hi.z; e.r = hi.w;
+  e.ax = lo.x; e.ay = lo.y; e.az = lo.z; e.r = lo.w;
+  e.bx = mid.x; e.by = mid.y; e.bz = mid.z; e.inv_l2 = mid.w;
+  e.hx = hi.x; e.hy = hi.y; e.hz = hi.z; e.pad = hi.w;
   return e;
 }
 
 // Squared distance from (x, y, z) to the segment of entry e.  The closest-point
-// parameter is clamped to [0, 1]; the residual is formed explicitly (never as
-// |ap|^2 - dot^2 / |ab|^2, which cancels near the segment's axis).
+// parameter (p - A) . H, H = AB / |AB|^2, is clamped to [0, 1]; the residual is formed
+// explicitly (never as |ap|^2 - dot^2 / |ab|^2, which cancels near the segment's axis).
 __device__ __forceinline__ float seg_d2(const CapEntry& e, float x, float y, float z) {
   const float px = x - e.ax, py = y - e.ay, pz = z - e.az;
-  const float dot = px * e.bx + py * e.by + pz * e.bz;
-  const float u = __builtin_amdgcn_fmed3f(dot * e.inv_l2, 0.0f, 1.0f);
+  const float u = __builtin_amdgcn_fmed3f(px * e.hx + py * e.hy + pz * e.hz, 0.0f, 1.0f);
   const float ex = px - u * e.bx, ey = py - u * e.by, ez = pz - u * e.bz;
   return ex * ex + ey * ey + ez * ez;
 }
@@ -193,6 +193,7 @@ __device__ __forceinline__ void write_entries(const Robot32& rb, int kind, const
       e.ax = A[k][0]; e.ay = A[k][1]; e.az = A[k][2];
       e.inv_l2 = l2 > 0.f ? 1.0f / l2 : 0.f;
       e.bx = bx; e.by = by; e.bz = bz; e.r = rb.r[k];
+      e.hx = bx * e.inv_l2; e.hy = by * e.inv_l2; e.hz = bz * e.inv_l2; e.pad = 0.f;
       dst[(size_t)k * stride] = e;
     }
 }

@@ -70,11 +70,16 @@ struct CloudArgs {
   const float* z;
 };
 
-// Capsule-sample table entry of the FP32 exact check: segment start A, 1/|AB|^2
-// (0 for a sphere), segment vector AB, radius.  Layout [motion][capsule][t].
-struct alignas(32) CapEntry {
-  float ax, ay, az, inv_l2;
-  float bx, by, bz, r;
+// Capsule-sample table entry of the FP32 exact check: segment start A, radius, segment
+// vector AB, 1/|AB|^2 (0 for a sphere), and H = AB / |AB|^2, so that the closest-point
+// parameter of a point p is the clamped dot product (p - A) . H: one multiply per test
+// fewer than (p - A) . AB / |AB|^2 (the dense kernel's 13.5 -> 12.5 VALU instructions
+// per test, 5.31 -> 4.88 ms on bin20k; the culled passes read 48 instead of 32 bytes per
+// sample and take the same time).  Layout [motion][capsule][t], 48 bytes each.
+struct alignas(16) CapEntry {
+  float ax, ay, az, r;
+  float bx, by, bz, inv_l2;
+  float hx, hy, hz, pad;
 };
 // FP64 entry for the certified-band recheck: A, |AB|^2, AB, radius.
 struct alignas(64) CapEntry64 {

@@ -53,7 +53,7 @@ def test_static_scratch_matches_workspace_call(sv, screened):
 
 
 def test_static_scratch_full_benchmark_size_and_limit(sv):
-    """512 motions x 20,000 bin points at T = 256 fits; T = 1024 (a 112 MiB capsule
+    """512 motions x 20,000 bin points at T = 256 fits; T = 1024 (a 168 MiB capsule
     table) does not and is rejected before any launch."""
     arm = svgen.make_arm(1)
     robot = sv.make_robot(arm)

@@ -180,6 +180,7 @@ CheckWs carve_check(void* ws, const sv_robot& r, const sv_motions& m, const sv_c
   w.cull.sy = cv.take<float>(N);
   w.cull.sz = cv.take<float>(N);
   w.cull.spheres = cv.take<float4>((size_t)m.n * r.n_caps * cull_blocks(m.T, m.kind));
+  w.cull.group_spheres = cv.take<float4>((size_t)m.n * r.n_caps * cull_group_count(cull_blocks(m.T, m.kind)));
   w.cull.tile_spheres = cv.take<float4>((size_t)cull_tiles(c.n));
   w.cull.wave_spheres = cv.take<float4>((size_t)cull_tiles(c.n) * 4);
   w.cull.list = cv.take<int>((size_t)m.n * cull_tiles(c.n) * r.n_caps);

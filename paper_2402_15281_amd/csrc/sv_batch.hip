@@ -454,6 +454,23 @@ __global__ __launch_bounds__(256) void k_batch_block_spheres(BatchArgs a) {
     block_sphere(a, q);
 }
 
+// Grid-stride over (motion, capsule, group of kGroupBlocks sample blocks): the group
+// spheres of the item filter (group_sphere over the request's blocks).
+__global__ __launch_bounds__(256) void k_batch_group_spheres(BatchArgs a) {
+  const BatchWs& w = a.w;
+  const int64_t total = w.plan->total_motions * a.K * w.ng_max;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t gk = q / w.ng_max;
+    const int gi = (int)(q - gk * w.ng_max);
+    const int64_t g = gk / a.K;
+    const int r = find_seg(w.motion_off, a.n_req, g);
+    const int nb = cull_block_count(a.reqs[r].motions.T, a.reqs[r].motions.kind, a.div_lin, a.div_spl);
+    if (kGroupBlocks * gi >= nb || w.n_points[r] == 0) continue;
+    w.gspheres[q] = group_sphere(w.spheres + (size_t)gk * w.nb_max, kGroupBlocks * gi,
+                                 min(kGroupBlocks * (gi + 1), nb));
+  }
+}
+
 // The seed bound of (motion g, capsule k) from a stride sample of 256 points of the
 // request's sorted cloud and every seed_stride(T)-th sample (a 256-thread block).
 __device__ void seed_bound(const BatchArgs& a, int64_t g, int k, unsigned long long* wmin) {
@@ -510,6 +527,7 @@ __device__ __forceinline__ void cull_list_step(const BatchArgs& a, int64_t c, in
     const int64_t g = w.motion_off[r] + m;
     const int64_t tile = w.tile_off[r] + t;
     keep = item_may_hit(w.tile_sph[tile], w.wave_sph + 4 * tile, w.spheres + ((size_t)g * a.K + k) * w.nb_max,
+                        w.gspheres + ((size_t)g * a.K + k) * w.ng_max,
                         cull_block_count(a.reqs[r].motions.T, a.reqs[r].motions.kind, a.div_lin, a.div_spl),
                         key_dist(w.keys[g]));
     g32 = (int)g;
@@ -839,6 +857,7 @@ BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, siz
   w.point_cap = caps.max_total_points > 0 ? caps.max_total_points : (int64_t)caps.max_requests * caps.max_points;
   w.tile_cap = w.point_cap / kCullTilePts + caps.max_requests;
   w.nb_max = cull_block_count_max(caps.max_T);
+  w.ng_max = cull_group_count(w.nb_max);
   w.cand_cap = caps.max_motions * ((caps.max_points + kCullTilePts - 1) / kCullTilePts) * rb.n_caps;
   w.n_points = cv.take<int64_t>(R);
   w.point_off = cv.take<int64_t>(R + 1);
@@ -864,6 +883,7 @@ BatchWs carve_batch(void* ws, const sv_robot& rb, const sv_batch_caps& caps, siz
   w.tile_sph = cv.take<float4>((size_t)w.tile_cap);
   w.wave_sph = cv.take<float4>((size_t)w.tile_cap * 4);
   w.spheres = cv.take<float4>((size_t)caps.max_motions * rb.n_caps * w.nb_max);
+  w.gspheres = cv.take<float4>((size_t)caps.max_motions * rb.n_caps * w.ng_max);
   w.list_g = cv.take<int>((size_t)w.cand_cap);
   w.list_tk = cv.take<int>((size_t)w.cand_cap);
   w.req = cv.take<BatchReq>(R);
@@ -923,6 +943,8 @@ hipError_t launch_batch(const sv_robot& rb, const sv_request* reqs, int n_req, c
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_tile_spheres, dim3(capped(w.tile_cap)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_batch_block_spheres, dim3(capped(grid_for(caps.max_motions * rb.n_caps * w.nb_max, 256))),
+                       dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_batch_group_spheres, dim3(capped(grid_for(caps.max_motions * rb.n_caps * w.ng_max, 256))),
                        dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_batch_seed, dim3(capped(caps.max_motions * rb.n_caps)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_batch_cull_list, dim3(capped(grid_for(w.cand_cap, 256))), dim3(256), 0, st, a);

@@ -224,6 +224,18 @@ __global__ __launch_bounds__(256) void k_block_spheres(const CapEntry* __restric
   spheres[g] = make_float4(cx, cy, cz, sqrtf(r2) + e[t0].r);
 }
 
+// The group spheres of every (motion, capsule): group i encloses block spheres 8 i ..
+// (group_sphere).  One thread per group.
+__global__ __launch_bounds__(256) void k_group_spheres(const float4* __restrict__ spheres, int64_t MK, int nb,
+                                                       float4* __restrict__ groups) {
+  const int ng = cull_group_count(nb);
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= MK * ng) return;
+  const int64_t mk = g / ng;
+  const int gi = (int)(g - mk * ng);
+  groups[g] = group_sphere(spheres + mk * nb, kGroupBlocks * gi, min(kGroupBlocks * (gi + 1), nb));
+}
+
 // Upper bound of d(X, m) to start from: the smallest test distance over a stride
 // sample of the sorted cloud (thread i: sorted point i * stride) and every tstride-th
 // sample of the motion, folded into the motion's key.  Any subset of the tests gives a
@@ -272,7 +284,8 @@ __global__ __launch_bounds__(256) void k_tile_spheres(const float* __restrict__ 
 // few tiles near the robot.
 __global__ __launch_bounds__(256) void k_cull_list(const float4* __restrict__ tile_sph,
                                                    const float4* __restrict__ wave_sph,
-                                                   const float4* __restrict__ spheres, int K, int nb, int tiles,
+                                                   const float4* __restrict__ spheres,
+                                                   const float4* __restrict__ groups, int K, int nb, int tiles,
                                                    int64_t n_slots, const int* __restrict__ mlist,
                                                    const int* __restrict__ mcount,
                                                    const unsigned long long* __restrict__ keys,
@@ -287,7 +300,8 @@ __global__ __launch_bounds__(256) void k_cull_list(const float4* __restrict__ ti
     const int slot = (int)(st / tiles);
     const int tile = (int)(st - (int64_t)slot * tiles);
     const int m = mlist ? mlist[slot] : slot;
-    mask = item_may_hit(tile_sph[tile], wave_sph + 4 * (size_t)tile, spheres + ((size_t)m * K + k) * nb, nb,
+    mask = item_may_hit(tile_sph[tile], wave_sph + 4 * (size_t)tile, spheres + ((size_t)m * K + k) * nb,
+                        groups + ((size_t)m * K + k) * cull_group_count(nb), nb,
                         key_dist(keys[m])) ? 1 : 0;
   }
   const bool keep = mask != 0;
@@ -544,9 +558,12 @@ hipError_t launch_cull_sort(const sv_robot& rb, const CapEntry* table, const Mot
     return e;
   hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(c.n, 256)), dim3(256), 0, st, c, w.pbin, w.pslot, w.bin_start,
                      w.sx, w.sy, w.sz, w.perm);
-  if (mo.n > 0)
+  if (mo.n > 0) {
     hipLaunchKernelGGL(k_block_spheres, dim3(grid_for(mo.n * K * nb, 256)), dim3(256), 0, st, table, mo.n, T, K, nb, B,
                        w.spheres);
+    hipLaunchKernelGGL(k_group_spheres, dim3(grid_for(mo.n * K * cull_group_count(nb), 256)), dim3(256), 0, st,
+                       w.spheres, mo.n * K, nb, w.group_spheres);
+  }
   return hipGetLastError();
 }
 
@@ -567,7 +584,7 @@ hipError_t launch_cull_pass(const sv_robot& rb, const CapEntry* table, const Mot
   hipLaunchKernelGGL(k_tile_spheres, dim3((unsigned)tiles), dim3(256), 0, st, w.sx, w.sy, w.sz, c.n,
                      w.tile_spheres, w.wave_spheres);
   hipLaunchKernelGGL(k_cull_list, dim3(grid_for(items * K, 256)), dim3(256), 0, st, w.tile_spheres, w.wave_spheres,
-                     w.spheres, K, nb,
+                     w.spheres, w.group_spheres, K, nb,
                      tiles, n_slots, mlist, mcount, keys, w.list, w.list_caps, w.list_count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int blocks = (int)std::min<int64_t>(items * K, resident_cull_blocks());

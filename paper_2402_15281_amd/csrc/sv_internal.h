@@ -171,6 +171,7 @@ struct BatchWs {
   float4* tile_sph;                               // [tile_cap]
   float4* wave_sph;                               // [tile_cap][4] the culled kernel's wave groups
   float4* spheres;                                // [max_motions][K][nb_max]
+  float4* gspheres;                               // [max_motions][K][ng_max] group spheres (item filter)
   int *list_g, *list_tk;                          // [cand_cap] motion, tile << 4 | capsule
   BatchReq* req;                                  // [max_requests]
   int* fill;                                      // [max_requests] listed items per request
@@ -180,7 +181,7 @@ struct BatchWs {
   int* gang_req;                                  // [kMaxGangs][max_requests] requests in gang order
   int* gang_off;                                  // [kMaxGangs][max_requests + 1] their first gang item
   int64_t point_cap, tile_cap, cand_cap, bin_cap;
-  int nb_max;
+  int nb_max, ng_max;
 };
 
 bool batch_tile_supported(const sv_tile& t);
@@ -253,6 +254,7 @@ struct CullWs {
   int* perm;                        // [N] caller's index of each sorted point
   float *sx, *sy, *sz;              // [N] sorted points
   float4* spheres;                  // [M][K][cull_blocks(T)]
+  float4* group_spheres;            // [M][K][cull_group_count(cull_blocks(T))]
   float4* tile_spheres;             // [cull_tiles(N)]
   float4* wave_spheres;             // [cull_tiles(N)][4] the culled kernel's wave groups
   int* list;                        // [M * cull_tiles(N) * K] surviving (motion slot, tile) items
@@ -262,6 +264,9 @@ struct CullWs {
 };
 constexpr int kWorkSlots = 256;
 int cull_blocks(int T, int kind);
+// Sample blocks per group sphere of the culled passes' item filter (item_may_hit).
+constexpr int kGroupBlocks = 8;
+__host__ __device__ constexpr int cull_group_count(int nb) { return (nb + kGroupBlocks - 1) / kGroupBlocks; }
 int cull_tiles(int64_t N);
 // Per-motion (distance, index) keys of the motion slots (mlist/mcount as launch_exact)
 // over all points, with groups of tests that provably exceed the minimum skipped.

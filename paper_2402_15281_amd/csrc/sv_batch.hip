@@ -310,38 +310,89 @@ __global__ __launch_bounds__(NT) void k_batch_exact(BatchArgs a) {
 // order, so small requests complete first.  Every request carries a token in
 // remaining[] besides its listed items; the last of them to retire finalizes it.
 
-// Grid-stride over the points of all requests: per-request bounds (order-preserving
-// keys), one atomic per wave and axis when the wave's points share a request.
+// Per-request bounds of the points (order-preserving keys).  Each block takes one
+// contiguous run of the concatenated points, each thread keeps running bounds per
+// request, and a block whose final runs share one request reduces them and issues one
+// atomic per bound (per wave, the atomics of a 200,000-point request had queued on its six
+// words: 0.65 ms of the 64-request batch).
 __global__ __launch_bounds__(256) void k_batch_bounds(BatchArgs a) {
+  __shared__ unsigned red[4][6];
+  __shared__ int rlo[4], rhi[4];
   const BatchWs& w = a.w;
   const int64_t total = w.plan->total_points;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = base + threadIdx.x;
-    const bool ok = i < total;
-    const int r = ok ? find_seg(w.point_off, a.n_req, i) : -1;
-    float v[3] = {0.f, 0.f, 0.f};
-    if (ok) {
-      const sv_cloud cl = a.reqs[r].cloud;
-      const int64_t j = i - w.point_off[r];
-      v[0] = cl.x[j]; v[1] = cl.y[j]; v[2] = cl.z[j];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // one contiguous run of points per block, so that a block's points mostly share a request
+  const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t c0 = (int64_t)blockIdx.x * chunk, c1 = min(c0 + chunk, total);
+  int rc = -1;
+  unsigned b[6];
+  auto reset = [&]() {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      b[q] = ord_f32(INFINITY);
+      b[3 + q] = ord_f32(-INFINITY);
     }
-    const int r0 = __builtin_amdgcn_readfirstlane(r);
-    const bool same = __ballot(ok && r != r0) == 0 && r0 >= 0;
-    if (same) {
+  };
+  auto flush = [&]() {
+    if (rc < 0) return;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const float lo = wave_min(ok ? v[q] : INFINITY), hi = wave_max(ok ? v[q] : -INFINITY);
-        if ((threadIdx.x & 63) == 0) {
-          atomicMin(w.bounds + 6 * r0 + q, ord_f32(lo));
-          atomicMax(w.bounds + 6 * r0 + 3 + q, ord_f32(hi));
-        }
-      }
-    } else if (ok) {
+    for (int q = 0; q < 3; ++q) {
+      atomicMin(w.bounds + 6 * rc + q, b[q]);
+      atomicMax(w.bounds + 6 * rc + 3 + q, b[3 + q]);
+    }
+  };
+  reset();
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+    const int r = find_seg(w.point_off, a.n_req, i);
+    if (r != rc) {   // a request boundary inside the thread's run
+      flush();
+      reset();
+      rc = r;
+    }
+    const sv_cloud cl = a.reqs[r].cloud;
+    const int64_t j = i - w.point_off[r];
+    const float v[3] = {cl.x[j], cl.y[j], cl.z[j]};
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        atomicMin(w.bounds + 6 * r + q, ord_f32(v[q]));
-        atomicMax(w.bounds + 6 * r + 3 + q, ord_f32(v[q]));
-      }
+    for (int q = 0; q < 3; ++q) {
+      b[q] = min(b[q], ord_f32(v[q]));
+      b[3 + q] = max(b[3 + q], ord_f32(v[q]));
+    }
+  }
+  // the block's final runs: one set of atomics if they all belong to one request
+  int mn = rc < 0 ? 0x7fffffff : rc, mx = rc;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mn = min(mn, __shfl_xor(mn, off, 64));
+    mx = max(mx, __shfl_xor(mx, off, 64));
+  }
+  if (lane == 0) {
+    rlo[wid] = mn;
+    rhi[wid] = mx;
+  }
+  __syncthreads();
+  const int bmn = min(min(rlo[0], rlo[1]), min(rlo[2], rlo[3]));
+  const int bmx = max(max(rhi[0], rhi[1]), max(rhi[2], rhi[3]));
+  if (bmx < 0) return;                     // no points in this block
+  if (bmn != bmx) {                        // several requests: each thread its own
+    flush();
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    unsigned x = b[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned y = __shfl_xor(x, off, 64);
+      x = q < 3 ? min(x, y) : max(x, y);
+    }
+    if (lane == 0) red[wid][q] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      atomicMin(w.bounds + 6 * bmx + q, min(min(red[0][q], red[1][q]), min(red[2][q], red[3][q])));
+      atomicMax(w.bounds + 6 * bmx + 3 + q, max(max(red[0][3 + q], red[1][3 + q]), max(red[2][3 + q], red[3][3 + q])));
     }
   }
 }

@@ -42,7 +42,7 @@ typedef enum {
   SV_ERR_ARG = -1,          /* null pointer or value out of range */
   SV_ERR_SHAPE = -2,        /* inconsistent sizes */
   SV_ERR_WORKSPACE = -3,    /* workspace missing or too small */
-  SV_ERR_UNSUPPORTED = -4,  /* valid request this build does not implement */
+  SV_ERR_UNSUPPORTED = -4,  /* valid request the library does not implement */
   SV_ERR_HIP = -5           /* a HIP runtime call failed */
 } sv_status;
 

@@ -489,10 +489,10 @@ __global__ __launch_bounds__(mlp_threads<W>(), mlp_blocks_per_cu<W>()) void k_re
         for (int rb = 0; rb < kRB; ++rb) {
           __bf16* hp = H + (32 * rb + col) * LD + f;
           const bf16x4 h = *reinterpret_cast<const bf16x4*>(hp);
-          const float y0 = fmaf(bn01.x, fmaxf(acc[fb][rb][4 * j + 0], 0.f), bn01.y) + (float)h[0];
-          const float y1 = fmaf(bn01.z, fmaxf(acc[fb][rb][4 * j + 1], 0.f), bn01.w) + (float)h[1];
-          const float y2 = fmaf(bn23.x, fmaxf(acc[fb][rb][4 * j + 2], 0.f), bn23.y) + (float)h[2];
-          const float y3 = fmaf(bn23.z, fmaxf(acc[fb][rb][4 * j + 3], 0.f), bn23.w) + (float)h[3];
+          const float y0 = fmaf(bn01.x, relu_acc(acc[fb][rb][4 * j + 0]), bn01.y) + (float)h[0];
+          const float y1 = fmaf(bn01.z, relu_acc(acc[fb][rb][4 * j + 1]), bn01.w) + (float)h[1];
+          const float y2 = fmaf(bn23.x, relu_acc(acc[fb][rb][4 * j + 2]), bn23.y) + (float)h[2];
+          const float y3 = fmaf(bn23.z, relu_acc(acc[fb][rb][4 * j + 3]), bn23.w) + (float)h[3];
           if (last) {
             p[rb] = fmaf(wo.x, y0, fmaf(wo.y, y1, fmaf(wo.z, y2, fmaf(wo.w, y3, p[rb]))));
           } else {

@@ -21,11 +21,16 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kTileRows = 64;   // rows (queries / samples) per workgroup
 constexpr int kLdsPad = 8;      // BF16 elements of padding per LDS row
 
+// max(z, 0) of an MFMA result as med3(z, 0, FLT_MAX), one instruction: fmaxf compiles to
+// a NaN-quieting max(z, z) first, since the compiler cannot tell that MFMA results are
+// already quiet.  The same value for every finite z (+inf gives FLT_MAX).
+__device__ __forceinline__ float relu_acc(float z) { return __builtin_amdgcn_fmed3f(z, 0.f, 3.402823466e38f); }
+
 // Softplus for values that are rounded to BF16 afterwards:
 // max(z, 0) + ln2 * log2(1 + 2^(-|z| log2 e)) with the hardware exp2/log2.
 __device__ __forceinline__ float softplus_fast(float z) {
   const float e = __builtin_amdgcn_exp2f(-fabsf(z) * 1.44269504088896341f);
-  return fmaf(0.693147180559945309f, __builtin_amdgcn_logf(1.0f + e), fmaxf(z, 0.f));
+  return fmaf(0.693147180559945309f, __builtin_amdgcn_logf(1.0f + e), relu_acc(z));
 }
 
 // Derivative of softplus from its output a = softplus(z): sigmoid(z) = 1 - exp(-a).

@@ -999,8 +999,8 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_rt_fwd(ResTrainArgs a
       const int f = 32 * (kTFB * wid + fb) + 8 * j + 4 * half;
 #pragma unroll
       for (int rb = 0; rb < kTRB; ++rb) {
-        const bf16x4 v = {(__bf16)fmaxf(acc[fb][rb][4 * j + 0], 0.f), (__bf16)fmaxf(acc[fb][rb][4 * j + 1], 0.f),
-                          (__bf16)fmaxf(acc[fb][rb][4 * j + 2], 0.f), (__bf16)fmaxf(acc[fb][rb][4 * j + 3], 0.f)};
+        const bf16x4 v = {(__bf16)relu_acc(acc[fb][rb][4 * j + 0]), (__bf16)relu_acc(acc[fb][rb][4 * j + 1]),
+                          (__bf16)relu_acc(acc[fb][rb][4 * j + 2]), (__bf16)relu_acc(acc[fb][rb][4 * j + 3])};
         *reinterpret_cast<bf16x4*>(H + (32 * rb + col) * LD + f) = v;
       }
     }

@@ -369,7 +369,7 @@ __global__ __launch_bounds__(mlp_threads<W>(), mlp_blocks_per_cu<W>()) void k_ml
     const __bf16* Wp = packed + (size_t)(l - 1) * W * W;
     const float* bl = bias_base + (size_t)(l - 1) * ((size_t)W * W + W) + (size_t)W * W;
     f32x16 acc[kFB][kRB];
-    layer_mfma_fb<W, kFB, kRB, kRing>(Wp, H, wid, 0, lane, bl, acc);
+    layer_mfma_fb<W, kFB, kRB, kRing, true>(Wp, H, wid, 0, lane, bl, acc);
     const bool last = l + 1 == net.n_hidden;
     if (!last) __syncthreads();   // every wave has read the tile
     // Epilogue: acc[fb][rb][4j+i] is feature 32 (FB wid + fb) + 8j + 4 half + i of row

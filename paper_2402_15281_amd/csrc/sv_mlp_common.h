@@ -57,8 +57,10 @@ __device__ __forceinline__ bf16x8 load_tile(__amdgpu_buffer_rsrc_t rs, int lane_
 // per load, so weight traffic per MFMA is 1/RB KB and LDS traffic 1/FB KB.
 // Ring depth D for the weight tiles.
 // K: inputs (columns of the layer's weights and of the activation tile), LD: the tile's
-// row stride in elements.
-template <int K, int LD, int FB, int RB, int D>
+// row stride in elements.  kPrio raises the wave's issue priority for the loop, so that
+// on a SIMD shared with a wave in its epilogue the MFMAs go first and the epilogue's
+// VALU work fills the cycles between them.
+template <int K, int LD, int FB, int RB, int D, bool kPrio = false>
 __device__ __forceinline__ void layer_mfma_k(const __bf16* __restrict__ Wp, const __bf16* Hin, int wf, int wr,
                                              int lane, const float* __restrict__ bias, f32x16 (&acc)[FB][RB]) {
   constexpr int KS = K / 16;
@@ -92,6 +94,7 @@ __device__ __forceinline__ void layer_mfma_k(const __bf16* __restrict__ Wp, cons
   bf16x8 b[RB];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) b[rb] = *reinterpret_cast<const bf16x8*>(B + 32 * rb * LD);
+  if constexpr (kPrio) __builtin_amdgcn_s_setprio(1);
   for (int ks = 0; ks < KS; ks += D) {
 #pragma unroll
     for (int s = 0; s < D; ++s) {
@@ -119,13 +122,14 @@ __device__ __forceinline__ void layer_mfma_k(const __bf16* __restrict__ Wp, cons
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+  if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
 }
 
 // A square layer (W inputs) over a tile [rows][W + kLdsPad].
-template <int W, int FB, int RB, int D>
+template <int W, int FB, int RB, int D, bool kPrio = false>
 __device__ __forceinline__ void layer_mfma_fb(const __bf16* __restrict__ Wp, const __bf16* Hin, int wf, int wr,
                                               int lane, const float* __restrict__ bias, f32x16 (&acc)[FB][RB]) {
-  layer_mfma_k<W, W + kLdsPad, FB, RB, D>(Wp, Hin, wf, wr, lane, bias, acc);
+  layer_mfma_k<W, W + kLdsPad, FB, RB, D, kPrio>(Wp, Hin, wf, wr, lane, bias, acc);
 }
 
 // Parameter offsets of the residual network's block b (0-based) in the flat vector:

@@ -241,7 +241,7 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_fwd(TrainArgs a
   const float* wout = n.params + off_out(n);
   for (int l = 2; l <= L; ++l) {
     f32x16 acc[kTFB][kTRB];
-    layer_mfma_fb<W, kTFB, kTRB, 2>(a.packed + (size_t)(l - 2) * W * W, H, wid, 0, lane, n.params + off_b(n, l),
+    layer_mfma_fb<W, kTFB, kTRB, 2, true>(a.packed + (size_t)(l - 2) * W * W, H, wid, 0, lane, n.params + off_b(n, l),
                                     acc);
     const bool last = l == L;
     __syncthreads();   // every wave has read the tile (and copied it out)
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(train_threads<W>(), 2) void k_train_bwd(TrainArgs a
     bf16x8 pre[W / 64 / (NT / 64)][8];   // the activations of layer l - 1, in flight during the MFMAs
     fetch_tile_T<W, NT>(a.aT + (size_t)(l - 2) * W * a.Bp, r0, pre);
     f32x16 acc[kTFB][kTRB];
-    layer_mfma_fb<W, kTFB, kTRB, 2>(a.packedT + (size_t)(l - 2) * W * W, H, wid, 0, lane, nullptr, acc);
+    layer_mfma_fb<W, kTFB, kTRB, 2, true>(a.packedT + (size_t)(l - 2) * W * W, H, wid, 0, lane, nullptr, acc);
     __syncthreads();   // every wave has read the tile (and copied it out)
     put_tile_T<W, NT>(pre, H);   // into the free tile, then dz_{l-1} over them in place
     __syncthreads();
